@@ -249,8 +249,15 @@ def nonlinear_substep(u: np.ndarray, theta: np.ndarray, interior: np.ndarray) ->
     w = u.copy()
     sel = interior & (theta != 0.0)
     t = theta[sel]
-    e = np.exp(-u[sel])
-    w[sel] = np.log((np.cosh(t) + e * np.sinh(t)) / (e * np.cosh(t) + np.sinh(t)))
+    us = u[sel]
+    # Same ratio; for u < 0 numerator and denominator are multiplied by e^{u}
+    # so that e^{-u} never overflows double (|u| > 709 occurs in AOS runs).
+    pos = us >= 0.0
+    e = np.exp(-np.abs(us))           # e^{-u} for u >= 0, e^{u} for u < 0
+    ch, sh = np.cosh(t), np.sinh(t)
+    num = np.where(pos, ch + e * sh, e * ch + sh)
+    den = np.where(pos, e * ch + sh, ch + e * sh)
+    w[sel] = np.log(num / den)
     return w
 
 

@@ -256,7 +256,7 @@ def _N(u, theta):
 @pytest.mark.parametrize("theta", [1e-4, 0.05, 0.7, 3.0])
 def test_nonlinear_closed_form_tanh(theta):
     # integral of dw / sinh w = ln |tanh(w/2)|  =>  tanh(w1/2) = e^{-2 theta} tanh(w0/2)
-    u = np.linspace(-30, 30, 241)
+    u = np.concatenate([np.linspace(-30, 30, 241), [-5000.0, -800.0, 800.0, 5000.0]])
     w = _N(u, theta)
     ref = 2.0 * np.arctanh(np.exp(-2 * theta) * np.tanh(u / 2))
     assert np.allclose(w, ref, rtol=1e-11, atol=1e-12)
