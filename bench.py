@@ -1,0 +1,179 @@
+"""Benchmark: LOD grid-point-updates/s of the full RE+V solve on one MI355X.
+
+One "step" is one complete solve of the 2000-atom globular workload
+(161^3 nodes, h = 0.5 A): setup, solvated and vacuum LODIE2 loops at
+dt = 0.2 (20 steps) and dt = 0.1 (40 steps), FP64 energy reductions and the
+Richardson + vacuum combination.  Inputs are resident in device memory
+before the timed region (atoms are copied in by the solve itself, 80 kB).
+
+Prints one JSON line.  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f32x|f64]
+                    [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LOD grid-point-updates/s at ≤1e-3 kcal/mol energy err; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def _sweep_source_sha():
+    p = os.path.join(ROOT, "paper_1410_2788_amd", "csrc", "sweep_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(kernel_class: str, precision: str):
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the current sweep source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d.get(f"{kernel_class}:{precision}")
+        if e and e.get("source_sha") == _sweep_source_sha():
+            return e.get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+    return None
+
+
+def cpu_baseline(workload, n_steps_meas: int = 2):
+    """The FP64 oracle on the host: setup of both media plus a few LODIE2
+    steps, extrapolated to the full solve's step count."""
+    import threadpoolctl
+
+    import oracle
+    w = workload
+    p = w.params
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        pb_m = oracle.make_problem(w.molecule, w.grid, p, "solvated")
+        pb_v = oracle.make_problem(w.molecule, w.grid, p, "vacuum")
+        t_setup = time.perf_counter() - t0
+        u = pb_m.u0.copy()
+        t1 = time.perf_counter()
+        for _ in range(n_steps_meas):
+            u = oracle.lod_step(u, pb_m, p.dt, p.alpha, "LODIE2")
+        t_step = (time.perf_counter() - t1) / n_steps_meas
+    steps = p.n_steps * (3 if p.richardson else 1) * (2 if p.vacuum else 1)
+    pts = w.grid.interior_points
+    est = t_setup + steps * t_step
+    return {"value": steps * pts / est, "unit": "grid-point-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"{w.name}: setup of both media ({t_setup:.1f} s) + {n_steps_meas} "
+                       f"solvated LODIE2 steps ({t_step:.2f} s/step), extrapolated to the "
+                       f"{steps} steps of one solve; numpy FP64, 1 thread"),
+            "seconds_measured": t_setup + n_steps_meas * t_step}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f32x", "f64"])
+    ap.add_argument("--scheme", default="LODIE2", choices=["LODIE2", "LODIE1", "AOSIE2", "AOSIE1"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="skip the per-kernel event timing in the timed region")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1410_2788_amd import inputs, npb
+
+    w = inputs.globular_2000(precision=args.precision, scheme=args.scheme)
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "globular_2000_161.json")))
+    solver = npb.Solver(w.molecule, w.grid, w.params, device=0)
+    print(f"[bench] {w.name} precision={args.precision} scheme={args.scheme} "
+          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        solver.run()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    if not args.no_timing:
+        npb.npb_ctx_set_timing(solver.ctx, True)
+    lat = []
+    results = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        r = solver.run()
+        lat.append((time.perf_counter() - t) * 1e3)
+        results.append(r)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ktimes = npb.npb_ctx_get_kernel_times(solver.ctx) if not args.no_timing else None
+    npb.npb_ctx_set_timing(solver.ctx, False)
+
+    # accuracy gate: the FP64 oracle's energies for this workload
+    tol = max(1e-3, 1e-5 * abs(ref["dG"]))
+    errs = [abs(r["dG"] - ref["dG"]) for r in results if args.scheme == "LODIE2"]
+    ok = [e <= tol for e in errs] if errs else [False] * len(results)
+    per_solve = results[0]["grid_point_updates"]
+    ms_per_step = total_ms / args.steps
+    good = sum(ok)
+    value = per_solve * good / (total_ms * 1e-3)
+
+    roof = None
+    if ktimes:
+        cls = max(("sweep_x", "sweep_y", "sweep_z"), key=lambda c: ktimes[c]["ms"])
+        kt = ktimes[cls]
+        avg_ms = kt["ms"] / max(kt["count"], 1)
+        bpl = kt["bytes"] / max(kt["count"], 1)
+        ach = bpl / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": _traffic(cls, args.precision),
+                "kernel": f"npb::sweep_{cls[-1]}_kernel", "avg_launch_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": bpl,
+                "per_class": {c: {"launches": ktimes[c]["count"],
+                                  "avg_us": round(ktimes[c]["ms"] / max(ktimes[c]["count"], 1) * 1e3, 2),
+                                  "GBps": round(ktimes[c]["bytes"] / max(ktimes[c]["ms"], 1e-12) / 1e6, 1)}
+                              for c in ("sweep_x", "sweep_y", "sweep_z", "init", "setup", "energy")}}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid-point-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f32x": "f32-storage/f64-solve", "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.grid.nx, w.grid.ny, w.grid.nz], "h": w.grid.h,
+                   "atoms": w.molecule.n_atoms, "scheme": args.scheme, "richardson": True,
+                   "vacuum": True, "dt": [w.params.dt, w.params.dt / 2],
+                   "steps_per_solve": results[0]["steps_done"],
+                   "grid_point_updates_per_solve": per_solve},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "device_ms_median": float(np.median([r["device_ms"] for r in results]))},
+        "energy": {"dG": results[0]["dG"], "oracle_dG": ref["dG"],
+                   "abs_err": errs[0] if errs else None, "tolerance": tol,
+                   "solves_within_tolerance": good},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(inputs.globular_2000(precision="f64"))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

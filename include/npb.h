@@ -1,0 +1,202 @@
+/*
+ * npb.h - C ABI of the MI355X pseudo-transient nonlinear Poisson-Boltzmann
+ * solver (LOD / AOS time splitting, Wilson & Zhao).
+ *
+ * Problem statement (Sec. 2.1, Eqs. (NPB), (RhoEq), (DebyeHuckel),
+ * (BoundaryCond); Sec. 2.2, Eq. (TimeDepNPB)): point charges q_j at r_j
+ * with radii R_j define the solute (union of balls, eps_in inside, eps_out
+ * and the modified Debye-Hueckel parameter kbar^2 outside).  The solver
+ * integrates  alpha du/dt = div(eps grad u) - kbar^2 sinh(u) + rho  on a
+ * uniform grid with Dirichlet data on the outer shell, for a fixed number of
+ * pseudo-time steps of size dt, and returns the dimensionless potential u
+ * (as phi = kT u in kcal/mol/e) and the electrostatic solvation energy.
+ *
+ * Conventions used by every entry point
+ *   - Grid arrays are [nz][ny][nx], x fastest; node (i,j,k) sits at
+ *     origin + h (i, j, k).  The outer layer of nodes is the Dirichlet set.
+ *   - Host pointers are borrowed for the duration of the call only.
+ *   - Device pointers are caller-owned; the library never frees them.
+ *   - "stream" is a hipStream_t passed as void* (0 = the null stream).
+ *   - Functions return npb_status; on failure npb_last_error() gives a
+ *     thread-local message.  No C++ exception crosses this boundary.
+ *   - A context is bound to one device; calls on one context must not run
+ *     concurrently from several host threads.
+ */
+#ifndef NPB_H
+#define NPB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NPB_ABI_VERSION 1
+
+typedef enum npb_status {
+  NPB_OK = 0,
+  NPB_EINVAL = 1,     /* bad argument: n < 5, h <= 0, eps <= 0, kbar^2 < 0,
+                         alpha <= 0, dt <= 0, n_steps < 1, unknown scheme or
+                         precision, null pointer, workspace too small      */
+  NPB_ERANGE = 2,     /* an atom's trilinear 8-node stencil touches the
+                         Dirichlet shell (or leaves the grid)              */
+  NPB_ENOMEM = 3,     /* host-side allocation failed                       */
+  NPB_EDEVICE = 4,    /* a HIP runtime call failed                         */
+  NPB_EDIVERGED = 5,  /* a result is not finite                            */
+  NPB_EBUSY = 6       /* admission refused (serving)                       */
+} npb_status;
+
+typedef enum npb_scheme {
+  NPB_LODIE2 = 0,  /* source, x, y, z sweeps, nonlinear (Sec. 3.1, last paragraph) */
+  NPB_LODIE1 = 1,  /* nonlinear, x, y, z sweeps, source (Eqs. (LODIE1_1)-(LODIE1_5)) */
+  NPB_AOSIE2 = 2,  /* additive, source split 1/3 per direction (Eqs. (AOSIE2_2)-(AOSIE2_4)) */
+  NPB_AOSIE1 = 3   /* additive, source on x only (Eqs. (AOSIE1_1)-(AOSIE1_5)) */
+} npb_scheme;
+
+typedef enum npb_precision {
+  NPB_FP64 = 0,    /* sweeps, sub-steps and field storage in double */
+  NPB_FP32 = 1,    /* sweeps, sub-steps and field storage in float; setup,
+                      energies, differences and Richardson stay double */
+  NPB_FP32X = 2    /* field stored in float (FP32 traffic), line solves and
+                      sub-steps computed in double */
+} npb_precision;
+
+/* Molecule: n_atoms atoms; xyz[3*i+d] in Angstrom, q[i] in e, radius[i]
+ * in Angstrom.  Host pointers, read during the call only. */
+typedef struct npb_molecule {
+  int32_t n_atoms;
+  const double* xyz;
+  const double* q;
+  const double* radius;
+} npb_molecule;
+
+/* Uniform grid: nx*ny*nz nodes, spacing h (Angstrom), origin = position of
+ * node (0,0,0).  Each n must be at least 5. */
+typedef struct npb_grid {
+  int32_t nx, ny, nz;
+  int32_t pad_;
+  double h;
+  double origin[3];
+} npb_grid;
+
+/* Run parameters.
+ *   eps_in, eps_out : dielectric inside / outside the solute (Sec. 2.1)
+ *   kappa_bar_sq    : kbar^2 in the solvent, Angstrom^-2 (Eq. (DebyeHuckel));
+ *                     npb_kappa_bar_sq() converts an ionic strength
+ *   temperature_K   : sets kT = 0.592183 T/298 kcal/mol and the Bjerrum
+ *                     length 332.06371/kT Angstrom
+ *   alpha, dt       : scaling parameter and step of Eq. (TimeDepNPB)
+ *   n_steps         : steps at dt (the dt/2 level of Richardson runs 2 n_steps)
+ *   scheme          : npb_scheme
+ *   precision       : npb_precision
+ *   richardson      : 1 = run dt and dt/2 and combine (Sec. 4.3, Eq. (rich))
+ *   vacuum          : 1 = also solve the uniform-eps_in, kbar = 0 problem by
+ *                     the same scheme and report the solvation energy
+ *                     (Sec. 4.3, Eq. (deltaG3)); 0 = solvated potential only
+ *   field_select    : which potential d_field_out receives: 0 = solvated,
+ *                     1 = vacuum (needs vacuum = 1)                          */
+typedef struct npb_params {
+  double eps_in, eps_out, kappa_bar_sq, temperature_K, alpha, dt;
+  int32_t n_steps;
+  int32_t scheme;
+  int32_t precision;
+  int32_t richardson;
+  int32_t vacuum;
+  int32_t field_select;
+  int32_t reserved[2];
+} npb_params;
+
+/* Results, all energies in kcal/mol.
+ *   G_m[l], G_0[l]  : (1/2) sum_p Q_p phi_p over the trilinear charge nodes
+ *                     for the solvated / vacuum potential at level l
+ *                     (l = 0: dt, n steps; l = 1: dt/2, 2 n steps)
+ *   dG_plain        : G_m[0] - G_0[0]  (Eq. (deltaG3) at dt)
+ *   dG              : with Richardson, (2 G_m[1] - G_m[0]) - (2 G_0[1] - G_0[0])
+ *                     (Eq. (deltaG3) applied to Eq. (rich)); else dG_plain.
+ *                     NaN when vacuum = 0.
+ *   All differences and combinations are formed in double on the device.
+ *   grid_point_updates : interior nodes times executed steps, all loops
+ *   device_ms       : device time from the first setup kernel to the
+ *                     energies being ready
+ *   n_charge_nodes  : distinct nodes carrying trilinear charge
+ *   finite          : 1 if every reported energy is finite             */
+typedef struct npb_result {
+  double dG;
+  double dG_plain;
+  double G_m[2];
+  double G_0[2];
+  double grid_point_updates;
+  double device_ms;
+  int32_t steps_done;
+  int32_t n_charge_nodes;
+  int32_t finite;
+  int32_t reserved;
+} npb_result;
+
+typedef struct npb_ctx npb_ctx;
+
+/* Per-kernel timing gathered while timing is enabled (npb_ctx_set_timing):
+ * launches and summed device milliseconds for each kernel class, measured
+ * with HIP events recorded on the solve's stream around each launch. */
+typedef struct npb_kernel_times {
+  int64_t count[8];
+  double ms[8];
+  double bytes[8];   /* algorithmic bytes moved by those launches */
+} npb_kernel_times;
+
+enum npb_kernel_class {
+  NPB_K_SWEEP_X = 0, NPB_K_SWEEP_Y = 1, NPB_K_SWEEP_Z = 2,
+  NPB_K_SETUP = 3, NPB_K_INIT = 4, NPB_K_ENERGY = 5, NPB_K_OTHER = 6
+};
+
+/* Returns NPB_ABI_VERSION.  Pure. */
+int npb_abi_version(void);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* npb_last_error(void);
+
+/* kbar^2 in Angstrom^-2 for a 1:1 salt of ionic strength ionic_molar (mol/L)
+ * at temperature T (K): 8.486902807 (298/T) I (Sec. 2.1).  Pure. */
+double npb_kappa_bar_sq(double ionic_molar, double temperature_K);
+
+/* Create a context on HIP device `device` (allocates a few pinned staging
+ * bytes and events).  *out receives the context; destroy with
+ * npb_ctx_destroy. */
+npb_status npb_ctx_create(int device, npb_ctx** out);
+void npb_ctx_destroy(npb_ctx* ctx);
+
+/* Enable (1) or disable (0) per-kernel event timing; enabling clears the
+ * accumulated times. */
+npb_status npb_ctx_set_timing(npb_ctx* ctx, int enable);
+npb_status npb_ctx_get_kernel_times(npb_ctx* ctx, npb_kernel_times* out);
+
+/* Host-only checks of a problem: the same argument and stencil checks that
+ * npb_solve performs before touching the device.  Returns NPB_OK,
+ * NPB_EINVAL or NPB_ERANGE. */
+npb_status npb_validate(const npb_molecule* mol, const npb_grid* grid,
+                        const npb_params* params);
+
+/* Bytes of device workspace npb_solve needs for this problem (a 256-byte
+ * aligned block the caller allocates, e.g. a uint8 tensor).  Pure host. */
+npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
+                               const npb_params* params, size_t* bytes);
+
+/* Solve one problem.  Enqueues setup (solute mask, trilinear charges,
+ * boundary data), the time loops, the FP64 energy reductions and
+ * combinations on `stream`, then waits for that stream and fills *out.
+ *   d_ws, ws_bytes : device workspace, at least npb_workspace_bytes
+ *   d_field_out    : NULL, or a device array of nx*ny*nz doubles that
+ *                    receives phi = kT u (kcal/mol/e) of the selected medium,
+ *                    Richardson-combined when richardson = 1
+ * Errors: EINVAL, ERANGE (before any device work), EDEVICE, EDIVERGED (the
+ * energies are still written to *out). */
+npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                     const npb_params* params, void* d_ws, size_t ws_bytes,
+                     double* d_field_out, void* stream, npb_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NPB_H */

@@ -1,0 +1,471 @@
+// Per-solve setup on the device: solute mask, trilinear charges, source
+// density, per-line source lists and Dirichlet boundary data.
+//
+// All of it is deterministic: the charge at a node is summed in atom order
+// (a stable sort of the 8 N_a stencil entries by node), so repeated solves
+// give bit-identical inputs to the time loop.  FP64 throughout; expression
+// order follows the definitions so that contraction into fused
+// multiply-adds is switched off where a predicate or a weight is formed.
+#include "npb_internal.h"
+
+namespace npb {
+
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t step = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += step) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// Solute region = union of atomic balls, a node on a sphere counts as
+// solute (Sec. 2.1: eps_m on/inside the surface).  One block per atom walks
+// the atom's bounding box of nodes.
+__global__ __launch_bounds__(256) void mask_raster_kernel(SetupArgs a, uint8_t* mask) {
+#pragma clang fp contract(off)
+  const int at = blockIdx.x;
+  const int na = a.n_atoms;
+  const double c[3] = {a.atoms[at], a.atoms[na + at], a.atoms[2 * na + at]};
+  const double R = a.atoms[4 * na + at];
+  const double o[3] = {a.ox, a.oy, a.oz};
+  const int n[3] = {a.nx, a.ny, a.nz};
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (int)floor((c[d] - R - o[d]) / a.h) - 1;
+    hi[d] = (int)ceil((c[d] + R - o[d]) / a.h) + 1;
+    if (lo[d] < 0) lo[d] = 0;
+    if (hi[d] > n[d] - 1) hi[d] = n[d] - 1;
+    if (lo[d] > hi[d]) return;
+  }
+  const int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
+  const long long tot = (long long)bx * by * bz;
+  const double R2 = R * R;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    int i = lo[0] + (int)(e % bx);
+    int j = lo[1] + (int)((e / bx) % by);
+    int k = lo[2] + (int)(e / ((long long)bx * by));
+    double X = (double)i * a.h;
+    X = a.ox + X;
+    double Y = (double)j * a.h;
+    Y = a.oy + Y;
+    double Z = (double)k * a.h;
+    Z = a.oz + Z;
+    double dx = X - c[0], dy = Y - c[1], dz = Z - c[2];
+    double d2 = dx * dx + dy * dy;
+    d2 = d2 + dz * dz;
+    if (d2 <= R2) mask[((long long)k * a.ny + j) * a.nx + i] = 1;
+  }
+}
+
+hipError_t launch_mask_raster(const SetupArgs& a, uint8_t* mask, hipStream_t st) {
+  if (a.n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(mask_raster_kernel, dim3(a.n_atoms), dim3(256), 0, st, a, mask);
+  return hipGetLastError();
+}
+
+// Trilinear stencil of each atom (Sec. 3.1: Q by trilinear interpolation):
+// g = (r - origin)/h, i0 = floor(g), f = g - i0; corner weights w = f or
+// 1 - f per axis, product in x, y, z order; entry value q * w.
+__global__ void stencil_kernel(SetupArgs a, int* key, int* id, double* val, int* err) {
+#pragma clang fp contract(off)
+  const int at = blockIdx.x * blockDim.x + threadIdx.x;
+  const int na = a.n_atoms;
+  if (at >= na) return;
+  const double o[3] = {a.ox, a.oy, a.oz};
+  const int n[3] = {a.nx, a.ny, a.nz};
+  int i0[3];
+  double f[3];
+  bool bad = false;
+  for (int d = 0; d < 3; ++d) {
+    double g = (a.atoms[d * na + at] - o[d]) / a.h;
+    double fl = floor(g);
+    i0[d] = (int)fl;
+    f[d] = g - fl;
+    if (i0[d] < 1 || i0[d] + 1 > n[d] - 2) bad = true;
+  }
+  if (bad) {
+    atomicOr(err, 1);
+    for (int c = 0; c < 8; ++c) {
+      key[8 * at + c] = 0;
+      id[8 * at + c] = 8 * at + c;
+      val[8 * at + c] = 0.0;
+    }
+    return;
+  }
+  const double q = a.atoms[3 * na + at];
+  for (int cz = 0; cz < 2; ++cz) {
+    double wz = cz ? f[2] : 1.0 - f[2];
+    for (int cy = 0; cy < 2; ++cy) {
+      double wy = cy ? f[1] : 1.0 - f[1];
+      for (int cx = 0; cx < 2; ++cx) {
+        double wx = cx ? f[0] : 1.0 - f[0];
+        double w = wx * wy;
+        w = w * wz;
+        int c = cz * 4 + cy * 2 + cx;
+        key[8 * at + c] = ((i0[2] + cz) * a.ny + (i0[1] + cy)) * a.nx + (i0[0] + cx);
+        id[8 * at + c] = 8 * at + c;
+        val[8 * at + c] = q * w;
+      }
+    }
+  }
+}
+
+hipError_t launch_stencil(const SetupArgs& a, int* key, int* id, double* val, int* err,
+                          hipStream_t st) {
+  if (a.n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(stencil_kernel, dim3((a.n_atoms + 127) / 128), dim3(128), 0, st, a, key,
+                     id, val, err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits, 256 items per block
+
+__global__ __launch_bounds__(256) void radix_count_kernel(const int* key, int n, int shift,
+                                                          int nblocks, int* hist) {
+  __shared__ int h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  int i = blockIdx.x * 256 + tid;
+  if (i < n) atomicAdd(&h[(key[i] >> shift) & 255], 1);
+  __syncthreads();
+  hist[tid * nblocks + blockIdx.x] = h[tid];
+}
+
+__global__ __launch_bounds__(256) void radix_scatter_kernel(const int* kin, const int* iin,
+                                                            int* kout, int* iout, int n,
+                                                            int shift, int nblocks,
+                                                            const int* hist) {
+  __shared__ int dg[256];
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x * 256 + tid;
+  int k = 0, id = 0, d = 256;
+  if (i < n) {
+    k = kin[i];
+    id = iin[i];
+    d = (k >> shift) & 255;
+  }
+  dg[tid] = d;
+  __syncthreads();
+  if (i < n) {
+    int r = 0;
+    for (int j = 0; j < tid; ++j) r += (dg[j] == d);
+    int pos = hist[d * nblocks + blockIdx.x] + r;
+    kout[pos] = k;
+    iout[pos] = id;
+  }
+}
+
+// single-block exclusive scan of n ints in place; *total = sum
+__global__ __launch_bounds__(1024) void scan_kernel(int* data, int n, int* total) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b = tid * per;
+  const int e = min(b + per, n);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += data[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - s;
+  for (int i = b; i < e; ++i) {
+    int v = data[i];
+    data[i] = run;
+    run += v;
+  }
+  if (tid == 1023 && total) *total = part[1023];
+}
+
+hipError_t launch_exclusive_scan(int* data, int n, int* total, hipStream_t st) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, data, n, total);
+  return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(int* key_a, int* id_a, int* key_b, int* id_b, int* hist, int n,
+                            long long key_limit, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int nblocks = (n + 255) / 256;
+  int passes = 0;
+  while (passes < 4 && (key_limit >> (8 * passes)) > 0) ++passes;
+  if (passes & 1) ++passes;  // an even count leaves the result in (key_a, id_a)
+  int *ka = key_a, *ia = id_a, *kb = key_b, *ib = id_b;
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    hipLaunchKernelGGL(radix_count_kernel, dim3(nblocks), dim3(256), 0, st, ka, n, shift,
+                       nblocks, hist);
+    hipError_t e = launch_exclusive_scan(hist, 256 * nblocks, nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(256), 0, st, ka, ia, kb, ib, n,
+                       shift, nblocks, hist);
+    int* t = ka;
+    ka = kb;
+    kb = t;
+    t = ia;
+    ia = ib;
+    ib = t;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// merge equal nodes: charge = sum of entry values in atom order, from 0
+
+__global__ void heads_kernel(const int* key, int n, int* heads) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) heads[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+__global__ void merge_kernel(const int* key, const int* id, const double* val, const int* uid,
+                             int n, int* q_idx, double* q_val, double* q_rho, double pref) {
+#pragma clang fp contract(off)
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (i != 0 && key[i] == key[i - 1]) return;
+  double s = 0.0;
+  int j = i;
+  do {
+    s += val[id[j]];
+    ++j;
+  } while (j < n && key[j] == key[i]);
+  int u = uid[i];
+  q_idx[u] = key[i];
+  q_val[u] = s;
+  q_rho[u] = pref * s;
+}
+
+hipError_t launch_merge_charges(const int* key, const int* id, const double* val, int* heads,
+                                int n, int* nq_dev, int* q_idx, double* q_val, double* q_rho,
+                                double rho_pref, hipStream_t st) {
+  if (n <= 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(nq_dev), 1, 0u, st);
+  int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(heads_kernel, dim3(nb), dim3(256), 0, st, key, n, heads);
+  hipError_t e = launch_exclusive_scan(heads, n, nq_dev, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(merge_kernel, dim3(nb), dim3(256), 0, st, key, id, val, heads, n, q_idx,
+                     q_val, q_rho, rho_pref);
+  return hipGetLastError();
+}
+
+// ptr[l] = first entry whose key >= l * keys_per_line (binary search), l = 0..n_lines
+__global__ void line_ptr_kernel(const int* keys, const int* n_dev, int n_lines,
+                                int keys_per_line, int* ptr) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l > n_lines) return;
+  const int n = *n_dev;
+  const long long target = (long long)l * keys_per_line;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if ((long long)keys[mid] < target)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  ptr[l] = lo;
+}
+
+hipError_t launch_line_ptr(const int* sorted_keys, const int* n_dev, int /*cap*/, int n_lines,
+                           int keys_per_line, int* ptr, hipStream_t st) {
+  hipLaunchKernelGGL(line_ptr_kernel, dim3((n_lines + 1 + 255) / 256), dim3(256), 0, st,
+                     sorted_keys, n_dev, n_lines, keys_per_line, ptr);
+  return hipGetLastError();
+}
+
+// keys ordering the charge list by y-lines ((z, x, y)) or z-lines ((y, x, z));
+// entries past the list end get the sentinel nx*ny*nz
+__global__ void axis_keys_kernel(const int* q_idx, const int* nq_dev, int cap, int nx, int ny,
+                                 int nz, int axis, int* key, int* id) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cap) return;
+  const int nq = *nq_dev;
+  int kk = nx * ny * nz;
+  if (k < nq) {
+    int lin = q_idx[k];
+    int x = lin % nx;
+    int t = lin / nx;
+    int y = t % ny;
+    int z = t / ny;
+    kk = (axis == 1) ? (z * nx + x) * ny + y : (y * nx + x) * nz + z;
+  }
+  key[k] = kk;
+  id[k] = k;
+}
+
+hipError_t launch_axis_keys(const int* q_idx, const int* nq_dev, int cap, int nx, int ny, int nz,
+                            int axis, int* key, int* id, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axis_keys_kernel, dim3((cap + 255) / 256), dim3(256), 0, st, q_idx, nq_dev,
+                     cap, nx, ny, nz, axis, key, id);
+  return hipGetLastError();
+}
+
+__global__ void gather_entries_kernel(const int* id, const int* nq_dev, int cap, const int* q_idx,
+                                      const double* q_rho, int* lin_out, double* rho_out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap || i >= *nq_dev) return;
+  lin_out[i] = q_idx[id[i]];
+  rho_out[i] = q_rho[id[i]];
+}
+
+hipError_t launch_gather_entries(const int* id, const int* nq_dev, int cap, const int* q_idx,
+                                 const double* q_rho, int* lin_out, double* rho_out,
+                                 hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_entries_kernel, dim3((cap + 255) / 256), dim3(256), 0, st, id, nq_dev,
+                     cap, q_idx, q_rho, lin_out, rho_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dirichlet data on the outer shell (Eq. (BoundaryCond)):
+//   u = l_B sum_i q_i exp(-kappa d) / (eps d),  kappa = kbar / sqrt(eps)
+// Shell enumeration: face z = 0 (ny*nx), face z = nz-1 (ny*nx), then per
+// interior z the ring y = 0 (nx), y = ny-1 (nx), and x = 0, nx-1 for each
+// interior y.
+
+__device__ __forceinline__ void shell_node(long long s, int nx, int ny, int nz, int& i, int& j,
+                                           int& k) {
+  const long long nxy = (long long)nx * ny;
+  const long long ring = 2LL * nx + 2LL * (ny - 2);
+  if (s < nxy) {
+    k = 0;
+    j = (int)(s / nx);
+    i = (int)(s % nx);
+  } else if (s < 2 * nxy) {
+    long long t = s - nxy;
+    k = nz - 1;
+    j = (int)(t / nx);
+    i = (int)(t % nx);
+  } else {
+    long long t = s - 2 * nxy;
+    k = 1 + (int)(t / ring);
+    int r = (int)(t % ring);
+    if (r < nx) {
+      j = 0;
+      i = r;
+    } else if (r < 2 * nx) {
+      j = ny - 1;
+      i = r - nx;
+    } else {
+      int r2 = r - 2 * nx;
+      j = 1 + r2 / 2;
+      i = (r2 & 1) ? nx - 1 : 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void boundary_kernel(SetupArgs a, double eps, double kappa,
+                                                       double lB, double* bc, long long nshell) {
+#pragma clang fp contract(off)
+  __shared__ double sx[256], sy[256], sz[256], sq[256];
+  const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = s < nshell;
+  double X = 0, Y = 0, Z = 0;
+  if (valid) {
+    int i, j, k;
+    shell_node(s, a.nx, a.ny, a.nz, i, j, k);
+    X = a.ox + (double)i * a.h;
+    Y = a.oy + (double)j * a.h;
+    Z = a.oz + (double)k * a.h;
+  }
+  const int na = a.n_atoms;
+  double acc = 0.0;
+  for (int t0 = 0; t0 < na; t0 += 256) {
+    int t = t0 + threadIdx.x;
+    if (t < na) {
+      sx[threadIdx.x] = a.atoms[t];
+      sy[threadIdx.x] = a.atoms[na + t];
+      sz[threadIdx.x] = a.atoms[2 * na + t];
+      sq[threadIdx.x] = a.atoms[3 * na + t];
+    }
+    __syncthreads();
+    const int cnt = min(256, na - t0);
+    if (valid) {
+      if (kappa == 0.0) {
+        for (int jj = 0; jj < cnt; ++jj) {
+          double dx = X - sx[jj], dy = Y - sy[jj], dz = Z - sz[jj];
+          double d = sqrt(dx * dx + dy * dy + dz * dz);
+          acc += sq[jj] / (eps * d);
+        }
+      } else {
+        for (int jj = 0; jj < cnt; ++jj) {
+          double dx = X - sx[jj], dy = Y - sy[jj], dz = Z - sz[jj];
+          double d = sqrt(dx * dx + dy * dy + dz * dz);
+          acc += sq[jj] * exp(-kappa * d) / (eps * d);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (valid) bc[s] = lB * acc;
+}
+
+hipError_t launch_boundary(const SetupArgs& a, double eps, double kappa, double lB, double* bc,
+                           hipStream_t st) {
+  const long long ns = shell_count(a.nx, a.ny, a.nz);
+  hipLaunchKernelGGL(boundary_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, a,
+                     eps, kappa, lB, bc, ns);
+  return hipGetLastError();
+}
+
+// Face class of every (chunk, line) of one sweep direction: 0 if all nodes
+// from the chunk's left neighbour to its right neighbour are solvent, 2 if
+// all are solute, 1 otherwise (and for chunks that reach the line end).
+// Lines are enumerated as the sweep kernels do.
+__global__ void chunk_class_kernel(const uint8_t* mask, int nx, int ny, int nz, int dir, int M,
+                                   int P, uint8_t* out) {
+  const int nxi = nx - 2, nyi = ny - 2;
+  const long long nlines = (dir == 0) ? (long long)nyi * (nz - 2)
+                                      : (long long)nxi * ((dir == 1 ? nz : ny) - 2);
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nlines * P) return;
+  const int p = (int)(idx / nlines);
+  const long long l = idx - (long long)p * nlines;
+  long long base, stride;
+  int n;
+  if (dir == 0) {
+    int y = 1 + (int)(l % nyi), z = 1 + (int)(l / nyi);
+    base = ((long long)z * ny + y) * nx;
+    stride = 1;
+    n = nx;
+  } else {
+    int x = 1 + (int)(l % nxi), o = 1 + (int)(l / nxi);
+    base = (dir == 1) ? ((long long)o * ny * nx + x) : ((long long)o * nx + x);
+    stride = (dir == 1) ? nx : (long long)nx * ny;
+    n = (dir == 1) ? ny : nz;
+  }
+  const int j0 = p * M, j1 = p * M + M + 1;
+  uint8_t c = 1;
+  if (j1 <= n - 1) {
+    const uint8_t v0 = mask[base + (long long)j0 * stride];
+    bool same = true;
+    for (int j = j0 + 1; j <= j1; ++j) same = same && (mask[base + (long long)j * stride] == v0);
+    if (same) c = v0 ? 2 : 0;
+  }
+  out[idx] = c;
+}
+
+hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int ny, int nz, int dir, int M, int P,
+                                uint8_t* out, hipStream_t st) {
+  const long long nlines = (dir == 0) ? (long long)(ny - 2) * (nz - 2)
+                                      : (long long)(nx - 2) * ((dir == 1 ? nz : ny) - 2);
+  const long long tot = nlines * P;
+  hipLaunchKernelGGL(chunk_class_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     mask, nx, ny, nz, dir, M, P, out);
+  return hipGetLastError();
+}
+
+}  // namespace npb

@@ -1,0 +1,261 @@
+"""Python binding of libnpb.so: the C ABI of include/npb.h, one function per
+entry point with the same name, plus `solve`, which allocates the device
+workspace (a torch uint8 tensor) and the optional field, and marshals a
+seeded workload into the C structs.  Every step of the computation runs in
+the HIP library; this module only moves arguments.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import threading
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnpb.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "npb.h")
+
+NPB_OK, NPB_EINVAL, NPB_ERANGE, NPB_ENOMEM, NPB_EDEVICE, NPB_EDIVERGED, NPB_EBUSY = range(7)
+STATUS_NAMES = {0: "NPB_OK", 1: "NPB_EINVAL", 2: "NPB_ERANGE", 3: "NPB_ENOMEM",
+                4: "NPB_EDEVICE", 5: "NPB_EDIVERGED", 6: "NPB_EBUSY"}
+SCHEMES = {"LODIE2": 0, "LODIE1": 1, "AOSIE2": 2, "AOSIE1": 3}
+PRECISIONS = {"f64": 0, "f32": 1, "f32x": 2}
+KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other"]
+
+
+class npb_molecule(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("xyz", C.POINTER(C.c_double)),
+                ("q", C.POINTER(C.c_double)), ("radius", C.POINTER(C.c_double))]
+
+
+class npb_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad_", C.c_int32),
+                ("h", C.c_double), ("origin", C.c_double * 3)]
+
+
+class npb_params(C.Structure):
+    _fields_ = [("eps_in", C.c_double), ("eps_out", C.c_double), ("kappa_bar_sq", C.c_double),
+                ("temperature_K", C.c_double), ("alpha", C.c_double), ("dt", C.c_double),
+                ("n_steps", C.c_int32), ("scheme", C.c_int32), ("precision", C.c_int32),
+                ("richardson", C.c_int32), ("vacuum", C.c_int32), ("field_select", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
+
+
+class npb_result(C.Structure):
+    _fields_ = [("dG", C.c_double), ("dG_plain", C.c_double), ("G_m", C.c_double * 2),
+                ("G_0", C.c_double * 2), ("grid_point_updates", C.c_double),
+                ("device_ms", C.c_double), ("steps_done", C.c_int32),
+                ("n_charge_nodes", C.c_int32), ("finite", C.c_int32), ("reserved", C.c_int32)]
+
+
+class npb_kernel_times(C.Structure):
+    _fields_ = [("count", C.c_int64 * 8), ("ms", C.c_double * 8), ("bytes", C.c_double * 8)]
+
+
+class NPBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnpb.so; raises if it has not been built (no fallback)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_1410_2788_amd.build`")
+        # torch ships its own HIP runtime with the same soname as ROCm's;
+        # loading torch first makes libnpb bind to that one, so the process
+        # holds a single HIP runtime (two would each claim the device).
+        import torch  # noqa: F401
+        lib = C.CDLL(path)
+        P = C.POINTER
+        lib.npb_abi_version.restype = C.c_int
+        lib.npb_last_error.restype = C.c_char_p
+        lib.npb_kappa_bar_sq.restype = C.c_double
+        lib.npb_kappa_bar_sq.argtypes = [C.c_double, C.c_double]
+        lib.npb_ctx_create.restype = C.c_int
+        lib.npb_ctx_create.argtypes = [C.c_int, P(C.c_void_p)]
+        lib.npb_ctx_destroy.restype = None
+        lib.npb_ctx_destroy.argtypes = [C.c_void_p]
+        lib.npb_ctx_set_timing.restype = C.c_int
+        lib.npb_ctx_set_timing.argtypes = [C.c_void_p, C.c_int]
+        lib.npb_ctx_get_kernel_times.restype = C.c_int
+        lib.npb_ctx_get_kernel_times.argtypes = [C.c_void_p, P(npb_kernel_times)]
+        lib.npb_validate.restype = C.c_int
+        lib.npb_validate.argtypes = [P(npb_molecule), P(npb_grid), P(npb_params)]
+        lib.npb_workspace_bytes.restype = C.c_int
+        lib.npb_workspace_bytes.argtypes = [P(npb_molecule), P(npb_grid), P(npb_params),
+                                            P(C.c_size_t)]
+        lib.npb_solve.restype = C.c_int
+        lib.npb_solve.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
+                                  C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, P(npb_result)]
+        _lib = lib
+        return lib
+
+
+def header_functions(path: str = HEADER_PATH):
+    """Names of the functions include/npb.h declares."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"\b(npb_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != NPB_OK:
+        raise NPBError(status, npb_last_error())
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+
+def npb_abi_version() -> int:
+    return load_library().npb_abi_version()
+
+
+def npb_last_error() -> str:
+    return load_library().npb_last_error().decode()
+
+
+def npb_kappa_bar_sq(ionic_molar: float, temperature_K: float) -> float:
+    return load_library().npb_kappa_bar_sq(ionic_molar, temperature_K)
+
+
+def npb_ctx_create(device: int = 0) -> C.c_void_p:
+    ctx = C.c_void_p()
+    _check(load_library().npb_ctx_create(device, C.byref(ctx)))
+    return ctx
+
+
+def npb_ctx_destroy(ctx) -> None:
+    load_library().npb_ctx_destroy(ctx)
+
+
+def npb_ctx_set_timing(ctx, enable: bool) -> None:
+    _check(load_library().npb_ctx_set_timing(ctx, 1 if enable else 0))
+
+
+def npb_ctx_get_kernel_times(ctx) -> dict:
+    t = npb_kernel_times()
+    _check(load_library().npb_ctx_get_kernel_times(ctx, C.byref(t)))
+    return {name: {"count": int(t.count[i]), "ms": float(t.ms[i]), "bytes": float(t.bytes[i])}
+            for i, name in enumerate(KERNEL_CLASSES)}
+
+
+def npb_validate(mol: npb_molecule, grid: npb_grid, params: npb_params) -> int:
+    """Returns the status code (does not raise)."""
+    return load_library().npb_validate(C.byref(mol), C.byref(grid), C.byref(params))
+
+
+def npb_workspace_bytes(mol: npb_molecule, grid: npb_grid, params: npb_params) -> int:
+    n = C.c_size_t()
+    _check(load_library().npb_workspace_bytes(C.byref(mol), C.byref(grid), C.byref(params),
+                                              C.byref(n)))
+    return int(n.value)
+
+
+def npb_solve(ctx, mol: npb_molecule, grid: npb_grid, params: npb_params, d_ws: int,
+              ws_bytes: int, d_field_out: Optional[int], stream: int) -> npb_result:
+    res = npb_result()
+    st = load_library().npb_solve(ctx, C.byref(mol), C.byref(grid), C.byref(params),
+                                  C.c_void_p(d_ws), ws_bytes,
+                                  C.c_void_p(d_field_out) if d_field_out else None,
+                                  C.c_void_p(stream), C.byref(res))
+    if st != NPB_OK:
+        err = NPBError(st, npb_last_error())
+        err.result = res
+        raise err
+    return res
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+
+class Molecule:
+    """Keeps the numpy arrays alive while the C struct points at them."""
+
+    def __init__(self, xyz, q, radius):
+        self.xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        self.q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1))
+        self.radius = np.ascontiguousarray(np.asarray(radius, dtype=np.float64).reshape(-1))
+        dp = C.POINTER(C.c_double)
+        self.c = npb_molecule(self.q.shape[0], self.xyz.ctypes.data_as(dp),
+                              self.q.ctypes.data_as(dp), self.radius.ctypes.data_as(dp))
+
+
+def make_grid(g) -> npb_grid:
+    o = (C.c_double * 3)(*[float(v) for v in g.origin])
+    return npb_grid(int(g.nx), int(g.ny), int(g.nz), 0, float(g.h), o)
+
+
+def make_params(p, field_select: int = 0) -> npb_params:
+    kb2 = npb_kappa_bar_sq(p.ionic_molar, p.temperature_K)
+    return npb_params(float(p.eps_in), float(p.eps_out), kb2, float(p.temperature_K),
+                      float(p.alpha), float(p.dt), int(p.n_steps), SCHEMES[p.scheme],
+                      PRECISIONS[p.precision], 1 if p.richardson else 0, 1 if p.vacuum else 0,
+                      int(field_select), (C.c_int32 * 2)(0, 0))
+
+
+_ctx_cache = {}
+
+
+def context(device: int = 0):
+    if device not in _ctx_cache:
+        _ctx_cache[device] = npb_ctx_create(device)
+    return _ctx_cache[device]
+
+
+class Solver:
+    """Reusable device state for one problem shape: the workspace and the
+    optional field buffer are allocated once (torch), then `run` calls
+    npb_solve on the current torch stream."""
+
+    def __init__(self, mol, grid, params, device: int = 0, want_field: bool = False,
+                 field_select: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.mol = Molecule(mol.xyz, mol.q, mol.radius)
+        self.grid = make_grid(grid)
+        self.params = make_params(params, field_select)
+        self.ctx = context(device)
+        self.ws_bytes = npb_workspace_bytes(self.mol.c, self.grid, self.params)
+        dev = torch.device("cuda", device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.field = None
+        if want_field:
+            self.field = torch.empty((grid.nz, grid.ny, grid.nx), dtype=torch.float64, device=dev)
+
+    def run(self) -> dict:
+        torch = self.torch
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        res = npb_solve(self.ctx, self.mol.c, self.grid, self.params, self.ws.data_ptr(),
+                        self.ws_bytes, self.field.data_ptr() if self.field is not None else None,
+                        stream)
+        return result_dict(res)
+
+
+def result_dict(res: npb_result) -> dict:
+    return {"dG": res.dG, "dG_plain": res.dG_plain, "G_m": [res.G_m[0], res.G_m[1]],
+            "G_0": [res.G_0[0], res.G_0[1]], "grid_point_updates": res.grid_point_updates,
+            "device_ms": res.device_ms, "steps_done": res.steps_done,
+            "n_charge_nodes": res.n_charge_nodes, "finite": bool(res.finite)}
+
+
+def solve(mol, grid, params, device: int = 0, want_field: bool = False,
+          field_select: int = 0) -> dict:
+    """One solve; with want_field the result also holds 'phi' (numpy, FP64,
+    [nz][ny][nx], kcal/mol/e)."""
+    s = Solver(mol, grid, params, device, want_field, field_select)
+    out = s.run()
+    if want_field:
+        out["phi"] = s.field.cpu().numpy()
+    return out

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle
+on the same seeded inputs.
+
+Tolerances (see the design notes for their derivation):
+  FP64 path: field max|d phi| <= 1e-10 max|phi|; energies within
+             1e-9 relative (or 1e-8 kcal/mol absolute).
+  FP32 path: energies within max(1e-3 kcal/mol, 1e-5 |E|) for the
+             solvation energies, the stated contract; field within 2e-5 of
+             max|phi| (rounding of the FP32 field, measured margin ~10x).
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_2788_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _npb():
+    from paper_1410_2788_amd import npb
+    return npb
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _energy_close(got, ref, rel, abs_):
+    return abs(got - ref) <= max(abs_, rel * abs(ref))
+
+
+def _compare(w, field_select=0, f64_rel=1e-9, check_field=True):
+    npb = _npb()
+    want = check_field
+    _say(f"case {w.name} scheme={w.params.scheme} prec={w.params.precision} "
+         f"grid=({w.grid.nx},{w.grid.ny},{w.grid.nz}) atoms={w.molecule.n_atoms}")
+    g = npb.solve(w.molecule, w.grid, w.params, want_field=want, field_select=field_select)
+    o = oracle.solve(w.molecule, w.grid, w.params, want_fields=want)
+    keys = ["dG", "dG_plain"] if w.params.vacuum else []
+    for lv in range(2 if w.params.richardson else 1):
+        keys += [("G_m", lv)] + ([("G_0", lv)] if w.params.vacuum else [])
+    errs = {}
+    for k in keys:
+        gv = g[k[0]][k[1]] if isinstance(k, tuple) else g[k]
+        ov = o[k[0]][k[1]] if isinstance(k, tuple) else o[k]
+        errs[str(k)] = (gv, ov, gv - ov)
+    fe = None
+    if want:
+        ref = o["phi_m"] if field_select == 0 else o["phi_0"]
+        fe = float(np.max(np.abs(g["phi"] - ref)) / np.max(np.abs(ref)))
+    _say("  energies (gpu, oracle, diff):", {k: tuple(round(x, 9) for x in v) for k, v in errs.items()})
+    _say("  field rel err:", fe)
+    return g, o, errs, fe
+
+
+def _assert_f64(errs, fe, rel=1e-9):
+    for k, (gv, ov, d) in errs.items():
+        assert _energy_close(gv, ov, rel, 1e-8), (k, gv, ov)
+    if fe is not None:
+        assert fe <= 1e-10
+
+
+def _assert_f32(errs, fe, field_tol=2e-5):
+    for k, (gv, ov, d) in errs.items():
+        if k in ("dG", "dG_plain"):
+            assert _energy_close(gv, ov, 1e-5, 1e-3), (k, gv, ov)
+        else:
+            assert _energy_close(gv, ov, 1e-5, 1e-3), (k, gv, ov)
+    if fe is not None:
+        assert fe <= field_tol
+
+
+def test_abi_version_on_device():
+    npb = _npb()
+    assert npb.npb_abi_version() == 1
+    npb.context(0)
+
+
+def test_born_sphere_fp64():
+    w = inputs.born_sphere()
+    g, o, errs, fe = _compare(w)
+    _assert_f64(errs, fe)
+    assert g["n_charge_nodes"] == 8   # the node-centred ion plus 7 zero-weight stencil corners
+    assert g["steps_done"] == 200
+
+
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "AOSIE1"])
+def test_small_globular_fp64_all_schemes(scheme):
+    w = inputs.small_globular(scheme=scheme, n=41, n_atoms=120, n_steps=5)
+    g, o, errs, fe = _compare(w)
+    _assert_f64(errs, fe)
+
+
+@pytest.mark.parametrize("scheme", ["LODIE2", "AOSIE2"])
+def test_small_globular_fp32(scheme):
+    w = inputs.small_globular(scheme=scheme, n=41, n_atoms=120, n_steps=5, precision="f32")
+    g, o, errs, fe = _compare(w)
+    _assert_f32(errs, fe)
+
+
+def test_ragged_noncubic_grid_fp64_vacuum_field():
+    # several chunks per line with ragged tails on every axis
+    w = inputs.small_globular(n=43, ny=57, nz=35, n_atoms=90, n_steps=4, scheme="LODIE2")
+    g, o, errs, fe = _compare(w, field_select=1)
+    _assert_f64(errs, fe)
+
+
+def test_long_lines_many_chunks_fp64():
+    # 131 nodes: 7 chunks per y/z line, 8 chunk slots on x
+    w = inputs.small_globular(n=131, ny=21, nz=23, n_atoms=60, n_steps=2, richardson=False)
+    w.molecule.xyz[:, 1:] *= 0.25
+    g, o, errs, fe = _compare(w)
+    _assert_f64(errs, fe)
+
+
+def test_minimum_grid_single_atom_on_a_node():
+    w = inputs.Workload("tiny", inputs.single_ion(-0.7, 0.4, (0.0, 0.0, 0.0)),
+                        inputs.cubic_grid(5, 0.5),
+                        inputs.RunParams(eps_in=2.0, eps_out=80.0, ionic_molar=0.5,
+                                         temperature_K=298.0, alpha=0.5, dt=0.3, n_steps=3,
+                                         scheme="LODIE2", richardson=True, vacuum=True))
+    g, o, errs, fe = _compare(w)
+    _assert_f64(errs, fe)
+    assert g["n_charge_nodes"] == 8   # zero-weight corners are still stencil nodes
+
+
+def test_empty_molecule_gives_zero():
+    npb = _npb()
+    w = inputs.small_globular(n=21, n_atoms=4, n_steps=2)
+    empty = inputs.Molecule(np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    g = npb.solve(empty, w.grid, w.params, want_field=True)
+    assert g["dG"] == 0.0 and g["G_m"] == [0.0, 0.0] and g["n_charge_nodes"] == 0
+    assert np.all(g["phi"] == 0.0)
+
+
+def test_repeat_solves_are_bit_identical():
+    npb = _npb()
+    w = inputs.small_globular(n=41, n_atoms=150, n_steps=3, precision="f32")
+    s = npb.Solver(w.molecule, w.grid, w.params, want_field=True)
+    r1 = s.run()
+    f1 = s.field.clone()
+    r2 = s.run()
+    assert r1["dG"] == r2["dG"] and r1["G_m"] == r2["G_m"]
+    assert bool((f1 == s.field).all())
+
+
+def test_invalid_inputs_raise_before_device_work():
+    npb = _npb()
+    w = inputs.small_globular(n=21, n_atoms=4, n_steps=2)
+    bad = inputs.Molecule(np.array([[4.9, 0.0, 0.0]]), np.array([1.0]), np.array([1.0]))
+    with pytest.raises(npb.NPBError) as ei:
+        npb.solve(bad, w.grid, w.params)
+    assert ei.value.status == npb.NPB_ERANGE
+    p = inputs.RunParams(**{**w.params.__dict__, "dt": -1.0})
+    with pytest.raises(npb.NPBError) as ei:
+        npb.solve(w.molecule, w.grid, p)
+    assert ei.value.status == npb.NPB_EINVAL
+
+
+def test_globular_2000_full_size_against_stored_oracle():
+    """The benchmark workload (161^3, 2000 atoms, RE+V, 20/40 steps) in the
+    launch configuration bench.py times, against oracle energies written by
+    tests/golden/make_golden.py."""
+    path = os.path.join(GOLDEN, "globular_2000_161.json")
+    ref = json.load(open(path))
+    npb = _npb()
+    failures = []
+    for prec in ("f64", "f32x", "f32"):
+        w = inputs.globular_2000(precision=prec)
+        g = npb.solve(w.molecule, w.grid, w.params)
+        rel = 1e-9 if prec == "f64" else 1e-5
+        abs_ = 1e-7 if prec == "f64" else 1e-3
+        _say(prec, "dG err", g["dG"] - ref["dG"], "dG_plain err", g["dG_plain"] - ref["dG_plain"],
+             "G_m err", [g["G_m"][i] - ref["G_m"][i] for i in range(2)],
+             "G_0 err", [g["G_0"][i] - ref["G_0"][i] for i in range(2)],
+             "tol dG", max(abs_, rel * abs(ref["dG"])))
+        if g["n_charge_nodes"] != ref["n_charge_nodes"]:
+            failures.append((prec, "n_charge_nodes"))
+        for k in ("dG", "dG_plain"):
+            if not _energy_close(g[k], ref[k], rel, abs_):
+                failures.append((prec, k, g[k], ref[k]))
+        for k in ("G_m", "G_0"):
+            for lv in range(2):
+                if not _energy_close(g[k][lv], ref[k][lv], rel, abs_):
+                    failures.append((prec, k, lv, g[k][lv], ref[k][lv]))
+    assert not failures, failures
