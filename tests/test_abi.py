@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/npb.h declares, and its pure/host entry points
+validate arguments as documented."""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1410_2788_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def npb():
+    from paper_1410_2788_amd import npb as m
+    m.load_library()
+    return m
+
+
+def test_every_declared_function_is_exported(npb):
+    lib = ctypes.CDLL(npb.LIB_PATH)
+    names = npb.header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_kappa_helper(npb):
+    assert npb.npb_abi_version() == 1
+    g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    assert npb.npb_kappa_bar_sq(1.0, 298.0) == pytest.approx(g["kbar2_per_molar_298_inv_A2"], rel=1e-15)
+    assert npb.npb_kappa_bar_sq(0.1, 300.0) == pytest.approx(0.84303, rel=1e-5)
+
+
+def _c(npb, w):
+    m = npb.Molecule(w.molecule.xyz, w.molecule.q, w.molecule.radius)
+    return m, npb.make_grid(w.grid), npb.make_params(w.params)
+
+
+def test_validate_accepts_a_good_problem(npb):
+    w = inputs.small_globular(n=25, n_atoms=10)
+    m, g, p = _c(npb, w)
+    assert npb.npb_validate(m.c, g, p) == npb.NPB_OK
+    assert npb.npb_workspace_bytes(m.c, g, p) > 25 ** 3 * 9
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 4), ("h", 0.0), ("h", -1.0), ("eps_in", 0.0), ("eps_out", -2.0),
+    ("kappa_bar_sq", -1e-3), ("alpha", 0.0), ("dt", 0.0), ("n_steps", 0),
+    ("scheme", 7), ("precision", 5), ("field_select", 1)])
+def test_validate_rejects_bad_arguments(npb, field, value):
+    w = inputs.small_globular(n=25, n_atoms=10)
+    w.params.vacuum = field != "field_select"
+    m, g, p = _c(npb, w)
+    if field == "field_select":
+        p.vacuum = 0
+    if hasattr(g, field):
+        setattr(g, field, value)
+    else:
+        setattr(p, field, value)
+    assert npb.npb_validate(m.c, g, p) == npb.NPB_EINVAL
+    assert npb.npb_last_error() != ""
+
+
+def test_validate_rejects_stencils_touching_the_boundary(npb):
+    w = inputs.small_globular(n=25, n_atoms=10)
+    m = npb.Molecule(np.array([[5.6, 0.0, 0.0]]), np.array([1.0]), np.array([1.0]))
+    g = npb.make_grid(w.grid)
+    p = npb.make_params(w.params)
+    assert npb.npb_validate(m.c, g, p) == npb.NPB_ERANGE
+    m2 = npb.Molecule(np.array([[np.nan, 0.0, 0.0]]), np.array([1.0]), np.array([1.0]))
+    assert npb.npb_validate(m2.c, g, p) == npb.NPB_EINVAL
+
+
+def test_workspace_grows_with_the_grid(npb):
+    sizes = []
+    for n in (21, 41, 81):
+        w = inputs.small_globular(n=n, n_atoms=10)
+        m, g, p = _c(npb, w)
+        sizes.append(npb.npb_workspace_bytes(m.c, g, p))
+    assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_empty_molecule_is_valid(npb):
+    w = inputs.small_globular(n=21, n_atoms=4)
+    m = npb.Molecule(np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    assert npb.npb_validate(m.c, npb.make_grid(w.grid), npb.make_params(w.params)) == npb.NPB_OK
+
+
+def test_solve_without_context_is_rejected(npb):
+    w = inputs.small_globular(n=21, n_atoms=4)
+    m, g, p = _c(npb, w)
+    lib = npb.load_library()
+    res = npb.npb_result()
+    st = lib.npb_solve(None, ctypes.byref(m.c), ctypes.byref(g), ctypes.byref(p), None, 0, None,
+                       None, ctypes.byref(res))
+    assert st == npb.NPB_EINVAL
