@@ -15,10 +15,11 @@ namespace npb {
 // two nodal solute flags (both solvent, mixed = harmonic mean, both solute).
 template <typename T>
 struct SweepArgs {
-  T* u;                   // field, [nz][ny][nx]; read, and written in place
+  T* u;                   // field, [nz][ny][nxp]; read, and written in place
   T* acc;                 // additive-splitting accumulator (AOS modes)
-  const uint8_t* mask;    // 1 = solute node; nullptr = uniform medium
+  const uint8_t* mask;    // 1 = solute node, [nz][ny][nxp]; nullptr = uniform medium
   int nx, ny, nz;
+  int nxp;                // row pitch in elements: nx rounded up to a multiple of 4
   double re[3];           // r*eps_face for (sum of the two flags) = 0, 1, 2
   double re_uniform;      // r*eps_in for the uniform (vacuum) medium
   // exact sinh flow over theta: ka = 1 + exp(-2 theta), kb = 1 - exp(-2 theta)
@@ -36,28 +37,45 @@ struct SweepArgs {
   // face of the chunk solvent-solvent, 2 = every face solute-solute, 1 =
   // mixed; nullptr for the uniform medium (all chunks uniform)
   const uint8_t* ccls;
+  // ChunkTab<A> of this field and direction (device memory)
+  const void* tab;
   // geometry of the launch
   int M;                  // rows per chunk (compile-time in the kernel)
   int P;                  // chunks per line
-  int LW;                 // y/z: lines per block; x: lines per block
-  int S;                  // x: LDS row stride (elements)
+  int LW;                 // lines per block (x: rows, y/z: consecutive x)
+  int S;                  // LDS stride (x: per row, y/z: per node row)
 };
 
 enum SweepMode { MODE_INPLACE = 0, MODE_AOS_FIRST = 1, MODE_AOS_ADD = 2, MODE_AOS_FINISH = 3 };
 
-// Chunk lengths compiled into the sweep kernels.
-constexpr int kChunkChoices[] = {4, 8, 12, 16, 20, 24, 32};
+// Independent fields of one grid shape swept by one launch (block row
+// blockIdx.y = field): the solvated and vacuum runs at both step sizes of a
+// solve advance together.
+constexpr int kMaxFields = 4;
+template <typename T>
+struct SweepBatch {
+  SweepArgs<T> f[kMaxFields];
+};
+
+// Chunk lengths compiled into the sweep kernels (the planners keep the
+// chunk within 20 rows, where a lane's chunk still fits its registers).
+constexpr int kChunkChoices[] = {4, 8, 12, 16, 20};
 
 struct LaunchShape {
   int M, P, LW, threads, blocks;
   size_t lds;
 };
 
+// Row pitch of every field-shaped array: rows start on 16-byte boundaries,
+// so the sweeps move rows in 16-byte pieces.  Padding columns nx..nxp-1
+// hold zeros (field) or 0 (mask) and are never solved.
+inline int pitch_of(int nx) { return (nx + 3) & ~3; }
+
 // Elimination constants of a chunk whose M+1 faces all carry the same
 // coefficient re (rows a = c = -re, b = 1 + 2 re): pivot reciprocals,
 // normalised couplings and the coefficients of the chunk's reduced rows.
 // Index t = 0: solvent chunks (or the uniform medium), t = 1: solute chunks.
-constexpr int kMaxChunk = 32;
+constexpr int kMaxChunk = 20;
 template <typename A>
 struct ChunkTab {
   A inv[2][kMaxChunk];
@@ -66,25 +84,38 @@ struct ChunkTab {
   A ap[2], gp[2], re[2];
 };
 
-// number of chunks of a line per direction for a launch shape (x uses the
-// padded power-of-two count)
-inline int chunk_count(const LaunchShape& s) { return s.P; }
-
 // Pick chunk length / chunk count and the block shape for a line length.
+// plan_x: fp64 = arithmetic type is double.  plan_yz: lines along an axis of
+// n_along nodes, n_other nodes on the other transverse axis.
 LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform);
-LaunchShape plan_yz(int n_along, int n_lines, bool fp64);
+LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64_arith);
 
-// T = storage type of the field, A = arithmetic type of the line solves
+// number of interior lines of a direction (entries per chunk of its class
+// table): x lines (y, z) -> (z-1)(ny-2) + y-1; y lines (z, x) -> (z-1)(nx-2)
+// + x-1; z lines (y, x) -> (y-1)(nx-2) + x-1
+inline long long class_lines(int nx, int ny, int nz, int dir) {
+  if (dir == 0) return (long long)(ny - 2) * (nz - 2);
+  return (long long)(nx - 2) * ((dir == 1 ? nz : ny) - 2);
+}
+
+// Elimination constants for chunks of M rows whose faces all carry re_t
+// (t = 0: solvent or uniform medium, t = 1: solute), computed in double.
+template <typename A>
+void fill_chunk_tab(ChunkTab<A>& tb, double re_solvent, double re_solute, int M);
+
+// T = storage type of the field, A = arithmetic type of the line solves;
+// fields 0..nf-1 of the batch share the grid shape and the launch shape
 template <typename T, typename A>
-hipError_t launch_sweep_x(const SweepArgs<T>& a, const LaunchShape& s, hipStream_t st);
+hipError_t launch_sweep_x(const SweepBatch<T>& b, int nf, const LaunchShape& s, hipStream_t st);
 template <typename T, typename A>
-hipError_t launch_sweep_yz(const SweepArgs<T>& a, int dir, const LaunchShape& s, hipStream_t st);
+hipError_t launch_sweep_yz(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
+                           hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // setup
 
 struct SetupArgs {
-  int nx, ny, nz;
+  int nx, ny, nz, nxp;
   double h, ox, oy, oz;
   int n_atoms;
   const double* atoms;    // [5][n_atoms]: x, y, z, q, radius
@@ -105,7 +136,9 @@ hipError_t launch_merge_charges(const int* key, const int* id, const double* val
                                 double* q_rho, double rho_pref, hipStream_t st);
 hipError_t launch_line_ptr(const int* sorted_keys, const int* n_dev, int cap, int n_lines,
                            int keys_per_line, int* ptr, hipStream_t st);
-hipError_t launch_axis_keys(const int* q_idx, const int* nq_dev, int cap, int nx, int ny,
+// linear node indices are pitched (row pitch nxp); the keys order by line
+// (dense line numbering z * nx + x for y lines, y * nx + x for z lines)
+hipError_t launch_axis_keys(const int* q_idx, const int* nq_dev, int cap, int nx, int nxp, int ny,
                             int nz, int axis, int* key, int* id, hipStream_t st);
 hipError_t launch_gather_entries(const int* id, const int* nq_dev, int cap, const int* q_idx,
                                  const double* q_rho, int* lin_out, double* rho_out,
@@ -113,21 +146,23 @@ hipError_t launch_gather_entries(const int* id, const int* nq_dev, int cap, cons
 hipError_t launch_boundary(const SetupArgs& a, double eps, double kappa, double lB, double* bc,
                            hipStream_t st);
 // chunk classes of direction dir (0 = x, 1 = y, 2 = z) for chunks of M rows,
-// P per line; out[p * n_lines + line]
-hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int ny, int nz, int dir, int M, int P,
-                                uint8_t* out, hipStream_t st);
+// P per line; out[p * class_lines + line]
+hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
+                                int M, int P, uint8_t* out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // field / energy helpers
 
 template <typename T>
-hipError_t launch_field_init(T* u, const double* bc, int nx, int ny, int nz, hipStream_t st);
+hipError_t launch_field_init(T* u, const double* bc, int nx, int nxp, int ny, int nz,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_energy(const T* u, const int* q_idx, const double* q_val, const int* nq_dev,
                          int cap, double* slot, hipStream_t st);
+// dense out[nz][ny][nx] = beta * out + gamma * u (pitched u)
 template <typename T>
-hipError_t launch_field_out(double* out, const T* u, size_t n, double beta, double gamma,
-                            hipStream_t st);
+hipError_t launch_field_out(double* out, const T* u, int nx, int nxp, int ny, int nz, double beta,
+                            double gamma, hipStream_t st);
 hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum,
                           double* res, hipStream_t st);
 

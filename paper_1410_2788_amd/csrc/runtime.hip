@@ -45,19 +45,23 @@ npb_status fail(npb_status s, const std::string& msg) {
 
 namespace npb {
 
+// Dirichlet values (shell order of the boundary kernel) on the outer shell,
+// zero inside and in the padding columns
 template <typename T>
-__global__ void field_init_kernel(T* u, const double* bc, int nx, int ny, int nz) {
-  const long long n = (long long)nx * ny * nz;
+__global__ void field_init_kernel(T* u, const double* bc, int nx, int nxp, int ny, int nz) {
+  const long long n = (long long)nxp * ny * nz;
   const long long nxy = (long long)nx * ny;
   const long long ring = 2LL * nx + 2LL * (ny - 2);
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (long long)gridDim.x * blockDim.x) {
-    int i = (int)(p % nx);
-    long long t = p / nx;
+    int i = (int)(p % nxp);
+    long long t = p / nxp;
     int j = (int)(t % ny);
     int k = (int)(t / ny);
     T v = T(0);
-    if (k == 0) {
+    if (i >= nx) {
+      v = T(0);
+    } else if (k == 0) {
       v = (T)bc[(long long)j * nx + i];
     } else if (k == nz - 1) {
       v = (T)bc[nxy + (long long)j * nx + i];
@@ -77,12 +81,13 @@ __global__ void field_init_kernel(T* u, const double* bc, int nx, int ny, int nz
 }
 
 template <typename T>
-hipError_t launch_field_init(T* u, const double* bc, int nx, int ny, int nz, hipStream_t st) {
-  long long n = (long long)nx * ny * nz;
+hipError_t launch_field_init(T* u, const double* bc, int nx, int nxp, int ny, int nz,
+                             hipStream_t st) {
+  long long n = (long long)nxp * ny * nz;
   long long blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL((field_init_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, u, bc, nx,
-                     ny, nz);
+                     nxp, ny, nz);
   return hipGetLastError();
 }
 
@@ -113,21 +118,24 @@ hipError_t launch_energy(const T* u, const int* q_idx, const double* q_val, cons
 }
 
 template <typename T>
-__global__ void field_out_kernel(double* out, const T* u, long long n, double beta, double gamma) {
+__global__ void field_out_kernel(double* out, const T* u, int nx, int nxp, long long n,
+                                 double beta, double gamma) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    double v = gamma * (double)u[i];
+    const long long row = i / nx;
+    double v = gamma * (double)u[row * nxp + (i - row * nx)];
     out[i] = (beta != 0.0) ? beta * out[i] + v : v;
   }
 }
 
 template <typename T>
-hipError_t launch_field_out(double* out, const T* u, size_t n, double beta, double gamma,
-                            hipStream_t st) {
-  long long blocks = ((long long)n + 255) / 256;
+hipError_t launch_field_out(double* out, const T* u, int nx, int nxp, int ny, int nz, double beta,
+                            double gamma, hipStream_t st) {
+  const long long n = (long long)nx * ny * nz;
+  long long blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL((field_out_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, out, u,
-                     (long long)n, beta, gamma);
+  hipLaunchKernelGGL((field_out_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, out, u, nx,
+                     nxp, n, beta, gamma);
   return hipGetLastError();
 }
 
@@ -159,8 +167,10 @@ hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum
   return hipGetLastError();
 }
 
-template hipError_t launch_field_init<float>(float*, const double*, int, int, int, hipStream_t);
-template hipError_t launch_field_init<double>(double*, const double*, int, int, int, hipStream_t);
+template hipError_t launch_field_init<float>(float*, const double*, int, int, int, int,
+                                             hipStream_t);
+template hipError_t launch_field_init<double>(double*, const double*, int, int, int, int,
+                                              hipStream_t);
 
 }  // namespace npb
 
@@ -211,12 +221,33 @@ void harvest(npb_ctx* c) {
   c->pending.clear();
 }
 
+// Runs of one solve: (medium, level) pairs, the longer (dt/2) level first so
+// that the runs still stepping at any step form a prefix of the list.
+struct Run {
+  int medium;  // 0 solvated, 1 vacuum
+  int level;   // 0: dt, n steps; 1: dt/2, 2n steps
+};
+
+int make_runs(const npb_params* p, Run* runs) {
+  int nr = 0;
+  const int media = p->vacuum ? 2 : 1;
+  if (p->richardson)
+    for (int m = 0; m < media; ++m) runs[nr++] = Run{m, 1};
+  for (int m = 0; m < media; ++m) runs[nr++] = Run{m, 0};
+  return nr;
+}
+
 struct Layout {
-  size_t field, acc, mask, bc_s, bc_v, atoms, key_a, id_a, key_b, id_b, sval, hist, heads;
+  size_t field[kMaxFields], acc[kMaxFields];
+  size_t mask, bc_s, bc_v, atoms, tabs, key_a, id_a, key_b, id_b, sval, hist, heads;
   size_t q_idx, q_val, q_rho, xptr, yptr, ylin, yrho, zptr, zlin, zrho, ccls[3], slots, ints, total;
   LaunchShape shape[3];
-  int cap, nblocks;
+  Run runs[kMaxFields];
+  int n_runs, cap, nblocks;
 };
+
+// host staging (pinned): chunk tables first, then the atom planes
+constexpr size_t kTabBytes = sizeof(ChunkTab<double>);
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -224,7 +255,7 @@ bool needs_yz_sources(int scheme) { return scheme == NPB_LODIE1 || scheme == NPB
 
 Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params* p) {
   Layout L{};
-  const size_t n = (size_t)g->nx * g->ny * g->nz;
+  const size_t n = (size_t)pitch_of(g->nx) * g->ny * g->nz;  // pitched node count
   const size_t es = p->precision == NPB_FP64 ? 8 : 4;
   const int na = mol->n_atoms;
   const int cap = 8 * na;
@@ -238,12 +269,16 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
     off += align256(bytes);
     return o;
   };
-  L.field = take(n * es);
-  L.acc = take(aos ? n * es : 0);
+  L.n_runs = make_runs(p, L.runs);
+  for (int r = 0; r < kMaxFields; ++r) {
+    L.field[r] = take(r < L.n_runs ? n * es : 0);
+    L.acc[r] = take(r < L.n_runs && aos ? n * es : 0);
+  }
   L.mask = take(n);
   L.bc_s = take(ns * 8);
   L.bc_v = take(p->vacuum ? ns * 8 : 0);
   L.atoms = take((size_t)5 * na * 8);
+  L.tabs = take(kTabBytes * 3 * kMaxFields);
   L.key_a = take((size_t)cap * 4);
   L.id_a = take((size_t)cap * 4);
   L.key_b = take((size_t)cap * 4);
@@ -264,11 +299,12 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   {
     const bool f64a = p->precision != NPB_FP32;
     L.shape[0] = plan_x(g->nx, g->ny, g->nz, f64a, aos, false);
-    L.shape[1] = plan_yz(g->ny, (g->nx - 2) * (g->nz - 2), f64a);
-    L.shape[2] = plan_yz(g->nz, (g->nx - 2) * (g->ny - 2), f64a);
-    const size_t nl[3] = {(size_t)(g->ny - 2) * (g->nz - 2), (size_t)(g->nx - 2) * (g->nz - 2),
-                          (size_t)(g->nx - 2) * (g->ny - 2)};
-    for (int d = 0; d < 3; ++d) L.ccls[d] = take(nl[d] * (size_t)(L.shape[d].P > 0 ? L.shape[d].P : 1));
+    L.shape[1] = plan_yz(g->nx, g->ny, g->nz, f64a);
+    L.shape[2] = plan_yz(g->nx, g->nz, g->ny, f64a);
+    for (int d = 0; d < 3; ++d) {
+      const long long nl = class_lines(g->nx, g->ny, g->nz, d);
+      L.ccls[d] = take((size_t)nl * (size_t)(L.shape[d].P > 0 ? L.shape[d].P : 1));
+    }
   }
   L.slots = take(32 * 8);
   L.ints = take(16 * 4);
@@ -363,23 +399,66 @@ struct Solver {
     return NPB_OK;
   }
 
-  npb_status setup(const npb_molecule* mol) {
+  bool aos() const { return p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2; }
+
+  // coefficients of one run (Sec. 3: tau = dt / alpha; AOS sub-steps take
+  // 4 tau; faces carry harmonic means of the nodal permittivities)
+  struct Coefs {
+    double tau, re[3], re_uniform, t, omt, t4, omt4;
+    bool nl, vacuum;
+  };
+  Coefs coefs(const Run& r) const {
+    Coefs c{};
+    const double dt = p->dt / double(1 << r.level);
+    c.vacuum = r.medium == 1;
+    c.tau = dt / p->alpha;
+    const double rc = (aos() ? 4.0 * c.tau : c.tau) / (g->h * g->h);
+    const double ein = p->eps_in, eout = p->eps_out;
+    const double emix = 2.0 * ein * eout / (ein + eout);
+    const double eout_f = 2.0 * eout * eout / (eout + eout);
+    const double ein_f = 2.0 * ein * ein / (ein + ein);
+    c.re[0] = rc * eout_f;
+    c.re[1] = rc * emix;
+    c.re[2] = rc * ein_f;
+    c.re_uniform = rc * ein_f;
+    const double kb2 = c.vacuum ? 0.0 : p->kappa_bar_sq;
+    flow_params(kb2 * dt / (2.0 * p->alpha), c.t, c.omt);
+    flow_params(4.0 * kb2 * dt / (2.0 * p->alpha), c.t4, c.omt4);
+    c.nl = kb2 > 0.0 && !c.vacuum;
+    return c;
+  }
+
+  static size_t pinned_need(int na) { return 256 + kTabBytes * 3 * kMaxFields + (size_t)5 * na * 8; }
+
+  // atoms and chunk tables to the device through the context's pinned
+  // staging buffer
+  npb_status stage(const npb_molecule* mol) {
     const int na = mol->n_atoms;
-    const int nx = g->nx, ny = g->ny, nz = g->nz;
-    const size_t n = (size_t)nx * ny * nz;
-    // atoms as [x][y][z][q][R] planes, through pinned staging
-    const size_t abytes = (size_t)5 * na * 8;
-    if (na > 0) {
-      if (ctx->pinned_bytes < abytes + 256) {
-        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-        ctx->pinned = nullptr;
-        ctx->pinned_bytes = 0;
-        NPB_HIP(hipHostMalloc(&ctx->pinned, abytes + 256, hipHostMallocDefault));
-        ctx->pinned_bytes = abytes + 256;
+    const size_t need = pinned_need(na);
+    // the staging buffer is reused: wait for earlier copies out of it
+    NPB_HIP(hipStreamSynchronize(st));
+    if (ctx->pinned_bytes < need) {
+      if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+      ctx->pinned = nullptr;
+      ctx->pinned_bytes = 0;
+      NPB_HIP(hipHostMalloc(&ctx->pinned, need, hipHostMallocDefault));
+      ctx->pinned_bytes = need;
+    }
+    unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
+    for (int r = 0; r < L.n_runs; ++r) {
+      const Coefs c = coefs(L.runs[r]);
+      for (int d = 0; d < 3; ++d) {
+        ChunkTab<A>& tb = *reinterpret_cast<ChunkTab<A>*>(hb + 256 + kTabBytes * (3 * r + d));
+        if (c.vacuum)
+          fill_chunk_tab(tb, c.re_uniform, c.re_uniform, L.shape[d].M);
+        else
+          fill_chunk_tab(tb, c.re[0], c.re[2], L.shape[d].M);
       }
-      // the staging buffer is reused: wait for earlier copies out of it
-      NPB_HIP(hipStreamSynchronize(st));
-      double* h = reinterpret_cast<double*>(ctx->pinned);
+    }
+    NPB_HIP(hipMemcpyAsync(ws + L.tabs, hb + 256, kTabBytes * 3 * L.n_runs, hipMemcpyHostToDevice,
+                           st));
+    if (na > 0) {
+      double* h = reinterpret_cast<double*>(hb + 256 + kTabBytes * 3 * kMaxFields);
       for (int a = 0; a < na; ++a) {
         h[a] = mol->xyz[3 * a];
         h[na + a] = mol->xyz[3 * a + 1];
@@ -387,13 +466,20 @@ struct Solver {
         h[3 * na + a] = mol->q[a];
         h[4 * na + a] = mol->radius[a];
       }
-      NPB_HIP(hipMemcpyAsync(ws + L.atoms, h, abytes, hipMemcpyHostToDevice, st));
+      NPB_HIP(hipMemcpyAsync(ws + L.atoms, h, (size_t)5 * na * 8, hipMemcpyHostToDevice, st));
     }
-    sa = SetupArgs{nx, ny, nz, g->h, g->origin[0], g->origin[1], g->origin[2], na,
+    return NPB_OK;
+  }
+
+  npb_status setup(const npb_molecule* mol) {
+    const int na = mol->n_atoms;
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const int nxp = pitch_of(nx);
+    const size_t n = (size_t)nxp * ny * nz;
+    sa = SetupArgs{nx, ny, nz, nxp, g->h, g->origin[0], g->origin[1], g->origin[2], na,
                    at<double>(L.atoms)};
     int* ints = at<int>(L.ints);  // [0] nq, [1] stencil error
-    npb_status s;
-    s = timed(NPB_K_SETUP, 0, [&] {
+    return timed(NPB_K_SETUP, 0, [&] {
       hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ints), 16, 0u, st);
       if (e != hipSuccess) return e;
       e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.mask), (n + 3) / 4, 0u, st);
@@ -410,15 +496,16 @@ struct Solver {
                                at<int>(L.heads), L.cap, ints, at<int>(L.q_idx),
                                at<double>(L.q_val), at<double>(L.q_rho), pref, st);
       if (e != hipSuccess) return e;
-      e = launch_line_ptr(at<int>(L.q_idx), ints, L.cap, ny * nz, nx, at<int>(L.xptr), st);
+      e = launch_line_ptr(at<int>(L.q_idx), ints, L.cap, ny * nz, nxp, at<int>(L.xptr), st);
       if (e != hipSuccess) return e;
       if (needs_yz_sources(p->scheme) && L.cap > 0) {
         for (int axis = 1; axis <= 2; ++axis) {
-          e = launch_axis_keys(at<int>(L.q_idx), ints, L.cap, nx, ny, nz, axis, at<int>(L.key_a),
-                               at<int>(L.id_a), st);
+          e = launch_axis_keys(at<int>(L.q_idx), ints, L.cap, nx, nxp, ny, nz, axis,
+                               at<int>(L.key_a), at<int>(L.id_a), st);
           if (e != hipSuccess) return e;
           e = radix_sort_pairs(at<int>(L.key_a), at<int>(L.id_a), at<int>(L.key_b),
-                               at<int>(L.id_b), at<int>(L.hist), L.cap, (long long)n + 1, st);
+                               at<int>(L.id_b), at<int>(L.hist), L.cap,
+                               (long long)nx * ny * nz + 1, st);
           if (e != hipSuccess) return e;
           int* lin = at<int>(axis == 1 ? L.ylin : L.zlin);
           double* rho = at<double>(axis == 1 ? L.yrho : L.zrho);
@@ -443,125 +530,137 @@ struct Solver {
       if (p->vacuum) e = launch_boundary(sa, p->eps_in, 0.0, lB, at<double>(L.bc_v), st);
       if (e != hipSuccess) return e;
       for (int d = 0; d < 3 && e == hipSuccess; ++d)
-        e = launch_chunk_classes(at<uint8_t>(L.mask), nx, ny, nz, d, L.shape[d].M, L.shape[d].P,
-                                 at<uint8_t>(L.ccls[d]), st);
+        e = launch_chunk_classes(at<uint8_t>(L.mask), nx, nxp, ny, nz, d, L.shape[d].M,
+                                 L.shape[d].P, at<uint8_t>(L.ccls[d]), st);
       return e;
     });
-    return s;
   }
 
-  // one time loop of one medium at one step size
-  npb_status loop(bool vacuum, double dt, int n_steps) {
-    const int nx = g->nx, ny = g->ny, nz = g->nz;
-    const size_t n = (size_t)nx * ny * nz;
-    const double tau = dt / p->alpha;
-    const bool aos = p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2;
-    const double r = (aos ? 4.0 * tau : tau) / (g->h * g->h);
-    const double ein = p->eps_in, eout = p->eps_out;
-    const double emix = 2.0 * ein * eout / (ein + eout);
-    const double eout_f = 2.0 * eout * eout / (eout + eout);
-    const double ein_f = 2.0 * ein * ein / (ein + ein);
-    T* u = at<T>(L.field);
-    const double kb2 = vacuum ? 0.0 : p->kappa_bar_sq;
-
+  // sweep arguments of run r in direction d (scheme-specific fused work:
+  // Sec. 3.1 LODIE2 / LODIE1 orders, Sec. 3.2 AOS accumulation)
+  SweepArgs<T> sweep_args(int r, int d) {
+    const Coefs c = coefs(L.runs[r]);
     SweepArgs<T> a{};
-    a.u = u;
-    a.acc = aos ? at<T>(L.acc) : nullptr;
-    a.mask = vacuum ? nullptr : at<uint8_t>(L.mask);
-    a.nx = nx;
-    a.ny = ny;
-    a.nz = nz;
-    a.re[0] = r * eout_f;
-    a.re[1] = r * emix;
-    a.re[2] = r * ein_f;
-    a.re_uniform = r * ein_f;
-    double t, omt;
-    flow_params(kb2 * dt / (2.0 * p->alpha), t, omt);
-    double t4, omt4;
-    flow_params(4.0 * kb2 * dt / (2.0 * p->alpha), t4, omt4);
-    const bool nl = kb2 > 0.0 && !vacuum;
-
-    npb_status s = timed(NPB_K_INIT, (double)n * sizeof(T), [&] {
-      return launch_field_init<T>(u, at<double>(vacuum ? L.bc_v : L.bc_s), nx, ny, nz, st);
-    });
-    if (s != NPB_OK) return s;
-
-    // the solvated launch shapes are the ones the chunk classes were built for
-    const LaunchShape sx = vacuum ? plan_x(nx, ny, nz, sizeof(A) == 8, aos, true) : L.shape[0];
-    const LaunchShape sy = L.shape[1];
-    const LaunchShape sz = L.shape[2];
-    if (sx.M == 0 || sy.M == 0 || sz.M == 0) return fail(NPB_EINVAL, "unsupported grid shape");
-    const double pts = (double)(nx - 2) * (ny - 2) * (nz - 2);
-    const double mb = vacuum ? 0.0 : 1.0;
-    // algorithmic bytes per sweep: field read + write (+ mask) (+ accumulator)
-    const double bx = pts * (2.0 * sizeof(T) + mb + (aos ? sizeof(T) : 0.0));
-    const double by = pts * (2.0 * sizeof(T) + mb + (aos ? 2.0 * sizeof(T) : 0.0));
-    const double bz = pts * (2.0 * sizeof(T) + mb + (aos ? sizeof(T) : 0.0));
-
-    const int* ints = at<int>(L.ints);
-    (void)ints;
-    for (int step = 0; step < n_steps; ++step) {
-      SweepArgs<T> ax = a, ay = a, az = a;
-      ax.ccls = vacuum ? nullptr : at<uint8_t>(L.ccls[0]);
-      ay.ccls = vacuum ? nullptr : at<uint8_t>(L.ccls[1]);
-      az.ccls = vacuum ? nullptr : at<uint8_t>(L.ccls[2]);
-      ax.src_ptr = at<int>(L.xptr);
-      ax.src_lin = at<int>(L.q_idx);
-      ax.src_rho = at<double>(L.q_rho);
-      ay.src_ptr = at<int>(L.yptr);
-      ay.src_lin = at<int>(L.ylin);
-      ay.src_rho = at<double>(L.yrho);
-      az.src_ptr = at<int>(L.zptr);
-      az.src_lin = at<int>(L.zlin);
-      az.src_rho = at<double>(L.zrho);
-      if (p->scheme == NPB_LODIE2) {
-        ax.src_stage = 1;
-        ax.src_coef = tau;
-        if (nl) {
-          az.post_nl = 1;
-          az.post_ka = t;
-          az.post_kb = omt;
-        }
-      } else if (p->scheme == NPB_LODIE1) {
-        if (nl) {
-          ax.pre_nl = 1;
-          ax.pre_ka = t;
-          ax.pre_kb = omt;
-        }
-        az.src_stage = 2;
-        az.src_coef = tau;
+    a.u = at<T>(L.field[r]);
+    a.acc = aos() ? at<T>(L.acc[r]) : nullptr;
+    a.mask = c.vacuum ? nullptr : at<uint8_t>(L.mask);
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.nz = g->nz;
+    a.nxp = pitch_of(g->nx);
+    for (int k = 0; k < 3; ++k) a.re[k] = c.re[k];
+    a.re_uniform = c.re_uniform;
+    a.ccls = c.vacuum ? nullptr : at<uint8_t>(L.ccls[d]);
+    a.tab = ws + L.tabs + kTabBytes * (3 * r + d);
+    if (d == 0) {
+      a.src_ptr = at<int>(L.xptr);
+      a.src_lin = at<int>(L.q_idx);
+      a.src_rho = at<double>(L.q_rho);
+    } else {
+      a.src_ptr = at<int>(d == 1 ? L.yptr : L.zptr);
+      a.src_lin = at<int>(d == 1 ? L.ylin : L.zlin);
+      a.src_rho = at<double>(d == 1 ? L.yrho : L.zrho);
+    }
+    if (p->scheme == NPB_LODIE2) {
+      if (d == 0) {
+        a.src_stage = 1;
+        a.src_coef = c.tau;
+      }
+      if (d == 2 && c.nl) {
+        a.post_nl = 1;
+        a.post_ka = c.t;
+        a.post_kb = c.omt;
+      }
+    } else if (p->scheme == NPB_LODIE1) {
+      if (d == 0 && c.nl) {
+        a.pre_nl = 1;
+        a.pre_ka = c.t;
+        a.pre_kb = c.omt;
+      }
+      if (d == 2) {
+        a.src_stage = 2;
+        a.src_coef = c.tau;
+      }
+    } else {
+      const double cx = p->scheme == NPB_AOSIE2 ? 4.0 / 3.0 : 4.0;
+      const double cyz = p->scheme == NPB_AOSIE2 ? 4.0 / 3.0 : 0.0;
+      if (d == 0) {
+        a.mode = MODE_AOS_FIRST;
+        a.aos_w = c.nl ? 1 : 0;
+        a.aos_ka = c.t4;
+        a.aos_kb = c.omt4;
+        a.src_stage = 1;
+        a.src_coef = cx * c.tau;
       } else {
-        const double cx = p->scheme == NPB_AOSIE2 ? 4.0 / 3.0 : 4.0;
-        const double cyz = p->scheme == NPB_AOSIE2 ? 4.0 / 3.0 : 0.0;
-        ax.mode = MODE_AOS_FIRST;
-        ax.aos_w = nl ? 1 : 0;
-        ax.aos_ka = t4;
-        ax.aos_kb = omt4;
-        ax.src_stage = 1;
-        ax.src_coef = cx * tau;
-        ay.mode = MODE_AOS_ADD;
-        az.mode = MODE_AOS_FINISH;
+        a.mode = d == 1 ? MODE_AOS_ADD : MODE_AOS_FINISH;
         if (cyz != 0.0) {
-          ay.src_stage = 1;
-          ay.src_coef = cyz * tau;
-          az.src_stage = 1;
-          az.src_coef = cyz * tau;
+          a.src_stage = 1;
+          a.src_coef = cyz * c.tau;
         }
       }
-      s = timed(NPB_K_SWEEP_X, bx, [&] { return launch_sweep_x<T, A>(ax, sx, st); });
+    }
+    return a;
+  }
+
+  // All runs advance together: at step s the runs with more than s steps
+  // (a prefix of the run list) are swept by one launch per direction.
+  npb_status time_loop() {
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+    const int nxp = pitch_of(nx);
+    const size_t n = (size_t)nxp * ny * nz;
+    for (int r = 0; r < L.n_runs; ++r) {
+      const bool vac = L.runs[r].medium == 1;
+      npb_status s = timed(NPB_K_INIT, (double)n * sizeof(T), [&] {
+        return launch_field_init<T>(at<T>(L.field[r]), at<double>(vac ? L.bc_v : L.bc_s), nx, nxp,
+                                    ny, nz, st);
+      });
       if (s != NPB_OK) return s;
-      s = timed(NPB_K_SWEEP_Y, by, [&] { return launch_sweep_yz<T, A>(ay, 1, sy, st); });
+    }
+    if (L.shape[0].M == 0 || L.shape[1].M == 0 || L.shape[2].M == 0)
+      return fail(NPB_EINVAL, "unsupported grid shape");
+    SweepBatch<T> bx{}, by{}, bz{};
+    int steps[kMaxFields];
+    int max_steps = 0;
+    double pbytes[3][kMaxFields];
+    const double pts = (double)(nx - 2) * (ny - 2) * (nz - 2);
+    for (int r = 0; r < L.n_runs; ++r) {
+      bx.f[r] = sweep_args(r, 0);
+      by.f[r] = sweep_args(r, 1);
+      bz.f[r] = sweep_args(r, 2);
+      steps[r] = p->n_steps << L.runs[r].level;
+      if (steps[r] > max_steps) max_steps = steps[r];
+      // algorithmic bytes per sweep: field read + write (+ mask) (+ accumulator)
+      const double mb = L.runs[r].medium == 1 ? 0.0 : 1.0;
+      const double ab = aos() ? sizeof(T) : 0.0;
+      pbytes[0][r] = pts * (2.0 * sizeof(T) + mb + ab);
+      pbytes[1][r] = pts * (2.0 * sizeof(T) + mb + 2.0 * ab);
+      pbytes[2][r] = pts * (2.0 * sizeof(T) + mb + ab);
+    }
+    for (int step = 0; step < max_steps; ++step) {
+      int nf = 0;
+      double b3[3] = {0, 0, 0};
+      while (nf < L.n_runs && steps[nf] > step) {
+        for (int d = 0; d < 3; ++d) b3[d] += pbytes[d][nf];
+        ++nf;
+      }
+      npb_status s;
+      s = timed(NPB_K_SWEEP_X, b3[0], [&] { return launch_sweep_x<T, A>(bx, nf, L.shape[0], st); });
       if (s != NPB_OK) return s;
-      s = timed(NPB_K_SWEEP_Z, bz, [&] { return launch_sweep_yz<T, A>(az, 2, sz, st); });
+      s = timed(NPB_K_SWEEP_Y, b3[1],
+                [&] { return launch_sweep_yz<T, A>(by, nf, 1, L.shape[1], st); });
+      if (s != NPB_OK) return s;
+      s = timed(NPB_K_SWEEP_Z, b3[2],
+                [&] { return launch_sweep_yz<T, A>(bz, nf, 2, L.shape[2], st); });
       if (s != NPB_OK) return s;
     }
     return NPB_OK;
   }
 
-  npb_status energy(int slot_index) {
+  npb_status energy(int r) {
+    const int slot = 2 * L.runs[r].medium + L.runs[r].level;
     return timed(NPB_K_ENERGY, 0, [&] {
-      return launch_energy<T>(at<T>(L.field), at<int>(L.q_idx), at<double>(L.q_val),
-                              at<int>(L.ints), L.cap, at<double>(L.slots) + slot_index, st);
+      return launch_energy<T>(at<T>(L.field[r]), at<int>(L.q_idx), at<double>(L.q_val),
+                              at<int>(L.ints), L.cap, at<double>(L.slots) + slot, st);
     });
   }
 };
@@ -573,39 +672,40 @@ npb_status solve_t(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* g,
   Solver<T, A> S{ctx, g, p, st, reinterpret_cast<unsigned char*>(d_ws), L, {}, 0.0, 0.0};
   S.kT = thermal_energy(p->temperature_K);
   S.lB = bjerrum(p->temperature_K);
-  const size_t n = (size_t)g->nx * g->ny * g->nz;
+  npb_status s = S.stage(mol);
+  if (s != NPB_OK) return s;
   NPB_HIP(hipEventRecord(ctx->t0, st));
-  npb_status s = S.setup(mol);
+  s = S.setup(mol);
   if (s != NPB_OK) return s;
   // zero the energy slots
   s = S.timed(NPB_K_OTHER, 0, [&] {
     return launch_fill_u32(reinterpret_cast<uint32_t*>(S.ws + L.slots), 64, 0u, st);
   });
   if (s != NPB_OK) return s;
-  const int levels = p->richardson ? 2 : 1;
-  const int media = p->vacuum ? 2 : 1;
+  s = S.time_loop();
+  if (s != NPB_OK) return s;
   int steps_done = 0;
   double gpu_updates = 0.0;
   const double pts = (double)(g->nx - 2) * (g->ny - 2) * (g->nz - 2);
-  for (int m = 0; m < media; ++m) {
-    const bool vac = (m == 1);
-    for (int l = 0; l < levels; ++l) {
-      const double dt = (l == 0) ? p->dt : p->dt / 2.0;
-      const int ns = p->n_steps << l;
-      s = S.loop(vac, dt, ns);
+  for (int r = 0; r < L.n_runs; ++r) {
+    const int ns = p->n_steps << L.runs[r].level;
+    steps_done += ns;
+    gpu_updates += pts * ns;
+    s = S.energy(r);
+    if (s != NPB_OK) return s;
+  }
+  if (d_field_out) {
+    // selected medium: kT u (plain) or kT (2 u(dt/2) - u(dt)) (Richardson)
+    for (int l = 0; l < (p->richardson ? 2 : 1); ++l) {
+      int r = 0;
+      while (!(L.runs[r].medium == p->field_select && L.runs[r].level == l)) ++r;
+      const double beta = (l == 0) ? 0.0 : 1.0;
+      const double gamma = p->richardson ? (l == 0 ? -S.kT : 2.0 * S.kT) : S.kT;
+      s = S.timed(NPB_K_OTHER, 0, [&] {
+        return launch_field_out<T>(d_field_out, S.template at<T>(L.field[r]), g->nx,
+                                   pitch_of(g->nx), g->ny, g->nz, beta, gamma, st);
+      });
       if (s != NPB_OK) return s;
-      steps_done += ns;
-      gpu_updates += pts * ns;
-      s = S.energy(2 * m + l);
-      if (s != NPB_OK) return s;
-      if (d_field_out && p->field_select == m) {
-        double beta = (l == 0) ? 0.0 : 1.0;
-        double gamma = p->richardson ? (l == 0 ? -S.kT : 2.0 * S.kT) : S.kT;
-        s = S.timed(NPB_K_OTHER, 0, [&] {
-          return launch_field_out<T>(d_field_out, S.template at<T>(L.field), n, beta, gamma, st);
-        });
-        if (s != NPB_OK) return s;
-      }
     }
   }
   s = S.timed(NPB_K_OTHER, 0, [&] {
@@ -614,17 +714,8 @@ npb_status solve_t(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* g,
   });
   if (s != NPB_OK) return s;
   NPB_HIP(hipEventRecord(ctx->t1, st));
-  // results to the host
+  // results to the host (first 256 bytes of the staging buffer)
   double* hres = reinterpret_cast<double*>(ctx->pinned);
-  if (!hres || ctx->pinned_bytes < 256) {
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    ctx->pinned = nullptr;
-    ctx->pinned_bytes = 0;
-    NPB_HIP(hipStreamSynchronize(st));
-    NPB_HIP(hipHostMalloc(&ctx->pinned, 256, hipHostMallocDefault));
-    ctx->pinned_bytes = 256;
-    hres = reinterpret_cast<double*>(ctx->pinned);
-  }
   NPB_HIP(hipMemcpyAsync(hres, S.ws + L.slots + 8 * 8, 8 * 8, hipMemcpyDeviceToHost, st));
   NPB_HIP(hipMemcpyAsync(reinterpret_cast<unsigned char*>(hres) + 64, S.ws + L.ints, 8,
                          hipMemcpyDeviceToHost, st));

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void mask_raster_kernel(SetupArgs a, uint8_t* 
     double dx = X - c[0], dy = Y - c[1], dz = Z - c[2];
     double d2 = dx * dx + dy * dy;
     d2 = d2 + dz * dz;
-    if (d2 <= R2) mask[((long long)k * a.ny + j) * a.nx + i] = 1;
+    if (d2 <= R2) mask[((long long)k * a.ny + j) * a.nxp + i] = 1;
   }
 }
 
@@ -108,7 +108,7 @@ __global__ void stencil_kernel(SetupArgs a, int* key, int* id, double* val, int*
         double w = wx * wy;
         w = w * wz;
         int c = cz * 4 + cy * 2 + cx;
-        key[8 * at + c] = ((i0[2] + cz) * a.ny + (i0[1] + cy)) * a.nx + (i0[0] + cx);
+        key[8 * at + c] = ((i0[2] + cz) * a.ny + (i0[1] + cy)) * a.nxp + (i0[0] + cx);
         id[8 * at + c] = 8 * at + c;
         val[8 * at + c] = q * w;
       }
@@ -286,16 +286,16 @@ hipError_t launch_line_ptr(const int* sorted_keys, const int* n_dev, int /*cap*/
 
 // keys ordering the charge list by y-lines ((z, x, y)) or z-lines ((y, x, z));
 // entries past the list end get the sentinel nx*ny*nz
-__global__ void axis_keys_kernel(const int* q_idx, const int* nq_dev, int cap, int nx, int ny,
-                                 int nz, int axis, int* key, int* id) {
+__global__ void axis_keys_kernel(const int* q_idx, const int* nq_dev, int cap, int nx, int nxp,
+                                 int ny, int nz, int axis, int* key, int* id) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= cap) return;
   const int nq = *nq_dev;
   int kk = nx * ny * nz;
   if (k < nq) {
     int lin = q_idx[k];
-    int x = lin % nx;
-    int t = lin / nx;
+    int x = lin % nxp;
+    int t = lin / nxp;
     int y = t % ny;
     int z = t / ny;
     kk = (axis == 1) ? (z * nx + x) * ny + y : (y * nx + x) * nz + z;
@@ -304,11 +304,11 @@ __global__ void axis_keys_kernel(const int* q_idx, const int* nq_dev, int cap, i
   id[k] = k;
 }
 
-hipError_t launch_axis_keys(const int* q_idx, const int* nq_dev, int cap, int nx, int ny, int nz,
-                            int axis, int* key, int* id, hipStream_t st) {
+hipError_t launch_axis_keys(const int* q_idx, const int* nq_dev, int cap, int nx, int nxp, int ny,
+                            int nz, int axis, int* key, int* id, hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   hipLaunchKernelGGL(axis_keys_kernel, dim3((cap + 255) / 256), dim3(256), 0, st, q_idx, nq_dev,
-                     cap, nx, ny, nz, axis, key, id);
+                     cap, nx, nxp, ny, nz, axis, key, id);
   return hipGetLastError();
 }
 
@@ -424,12 +424,9 @@ hipError_t launch_boundary(const SetupArgs& a, double eps, double kappa, double 
 // Face class of every (chunk, line) of one sweep direction: 0 if all nodes
 // from the chunk's left neighbour to its right neighbour are solvent, 2 if
 // all are solute, 1 otherwise (and for chunks that reach the line end).
-// Lines are enumerated as the sweep kernels do.
-__global__ void chunk_class_kernel(const uint8_t* mask, int nx, int ny, int nz, int dir, int M,
-                                   int P, uint8_t* out) {
-  const int nxi = nx - 2, nyi = ny - 2;
-  const long long nlines = (dir == 0) ? (long long)nyi * (nz - 2)
-                                      : (long long)nxi * ((dir == 1 ? nz : ny) - 2);
+// Lines are numbered as class_lines describes.
+__global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
+                                   int M, int P, long long nlines, uint8_t* out) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nlines * P) return;
   const int p = (int)(idx / nlines);
@@ -437,14 +434,16 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int ny, int nz, 
   long long base, stride;
   int n;
   if (dir == 0) {
+    const int nyi = ny - 2;
     int y = 1 + (int)(l % nyi), z = 1 + (int)(l / nyi);
-    base = ((long long)z * ny + y) * nx;
+    base = ((long long)z * ny + y) * nxp;
     stride = 1;
     n = nx;
   } else {
+    const int nxi = nx - 2;
     int x = 1 + (int)(l % nxi), o = 1 + (int)(l / nxi);
-    base = (dir == 1) ? ((long long)o * ny * nx + x) : ((long long)o * nx + x);
-    stride = (dir == 1) ? nx : (long long)nx * ny;
+    base = (dir == 1) ? ((long long)o * ny * nxp + x) : ((long long)o * nxp + x);
+    stride = (dir == 1) ? nxp : (long long)nxp * ny;
     n = (dir == 1) ? ny : nz;
   }
   const int j0 = p * M, j1 = p * M + M + 1;
@@ -458,13 +457,12 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int ny, int nz, 
   out[idx] = c;
 }
 
-hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int ny, int nz, int dir, int M, int P,
-                                uint8_t* out, hipStream_t st) {
-  const long long nlines = (dir == 0) ? (long long)(ny - 2) * (nz - 2)
-                                      : (long long)(nx - 2) * ((dir == 1 ? nz : ny) - 2);
+hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
+                                int M, int P, uint8_t* out, hipStream_t st) {
+  const long long nlines = class_lines(nx, ny, nz, dir);
   const long long tot = nlines * P;
   hipLaunchKernelGGL(chunk_class_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                     mask, nx, ny, nz, dir, M, P, out);
+                     mask, nx, nxp, ny, nz, dir, M, P, nlines, out);
   return hipGetLastError();
 }
 

@@ -19,9 +19,10 @@
 // solute mask), which is what bounds these kernels.
 //
 //   x sweep : lines are contiguous in memory.  A block stages L whole rows
-//             in LDS with coalesced loads, lanes take (line, chunk) pairs.
-//   y/z sweep: lanes run across consecutive interior x (coalesced 128-256 B
-//             per load instruction), groups of LW lanes take one chunk each.
+//             in LDS with 16-byte loads, lanes take (line, chunk) pairs.
+//   y/z sweep: each lane holds the chunk of V adjacent x lines and moves
+//             them with one 16-byte (FP32: V = 4, FP64: V = 2) access per
+//             node row; LW lanes cover LW*V consecutive x.
 //
 // Fused pointwise work: the exact sinh flow (Eq. (ana3)), the trilinear
 // source add, and the AOS accumulation happen on values already in
@@ -222,12 +223,52 @@ __device__ __forceinline__ void put_reduced(A* R, int nl, int p, const A (&rf)[4
   }
 }
 
+// 16-byte vector access of V consecutive elements (V * sizeof(T) == 16);
+// the address must be 16-byte aligned.
+template <typename T, int V>
+struct VecIO;
+template <>
+struct VecIO<float, 4> {
+  static __device__ __forceinline__ void ld(const float* p, float (&o)[4]) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+  static __device__ __forceinline__ void st(float* p, const float (&o)[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+};
+template <>
+struct VecIO<double, 2> {
+  static __device__ __forceinline__ void ld(const double* p, double (&o)[2]) {
+    double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x; o[1] = v.y;
+  }
+  static __device__ __forceinline__ void st(double* p, const double (&o)[2]) {
+    *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
+  }
+};
+
+// solute flags of V consecutive nodes, one byte each
+template <int V>
+__device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
+  if constexpr (V == 4) return *reinterpret_cast<const uint32_t*>(p);
+  if constexpr (V == 2) return *reinterpret_cast<const uint16_t*>(p);
+  return *p;
+}
+
 // ---------------------------------------------------------------------------
-// x sweep.  Block: L lines x P chunk slots (P a power of two), L*P threads.
+// x sweep.  Block: L lines x P chunk slots (P a power of two), L*P threads;
+// lane t takes line t % L and chunk t / L.  Rows (pitch nxp, a multiple of
+// four) are moved between HBM and an odd-stride LDS tile with 16-byte
+// vector accesses; the row's boundary and padding columns are written back
+// unchanged.
 template <typename T, typename A, int M>
-__global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A> tb) {
+__global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
+  constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   extern __shared__ __align__(16) unsigned char smem[];
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const SweepArgs<T>& a = batch.f[blockIdx.y];
+  const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
+  const int nx = a.nx, ny = a.ny, nz = a.nz, nxp = a.nxp;
   const int nint = nx - 2;
   const int P = a.P, L = a.LW, S = a.S;
   const int nthreads = L * P;
@@ -253,7 +294,8 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A
     wtile = reinterpret_cast<A*>(smem + off);
     off += sizeof(A) * (size_t)L * S;
   }
-  uint8_t* mt = smem + off;
+  off = (off + 15) & ~size_t(15);
+  uint8_t* mt = smem + off;  // L rows of nxp bytes
 
   if (tid < L) {
     long long l = l0 + tid;
@@ -262,7 +304,7 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A
     if (l < nlines) {
       int y = 1 + (int)(l % nyi);
       int z = 1 + (int)(l / nyi);
-      rb = ((long long)z * ny + y) * nx;
+      rb = ((long long)z * ny + y) * nxp;
       l2 = z * ny + y;
     }
     rowbase[tid] = rb;
@@ -270,41 +312,41 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A
   }
   __syncthreads();
 
-  // coalesced row loads into LDS, kU loads in flight per thread before the
-  // first LDS store
-  const int total = L * nx;
-  const int dq = nthreads / nx, dxs = nthreads % nx;
+  // row loads: all vector loads of a thread in flight before its LDS stores
+  const int vpr = nxp / VX;  // vectors per row
+  const int nvec = L * vpr;
   {
     constexpr int kU = 8;
-    int q = tid / nx, x = tid % nx;
-    for (int e0 = tid; e0 < total; e0 += kU * nthreads) {
-      T v[kU];
-      uint8_t m[kU];
-      int o[kU];
+    for (int e0 = tid; e0 < nvec; e0 += kU * nthreads) {
+      T v[kU][VX];
+      uint32_t m[kU];
+      int q[kU], c[kU];
 #pragma unroll
       for (int j = 0; j < kU; ++j) {
         const int e = e0 + j * nthreads;
-        o[j] = -1;
-        if (e < total) {
-          long long rb = rowbase[q];
+        q[j] = -1;
+        if (e < nvec) {
+          const int qq = e / vpr;
+          const long long rb = rowbase[qq];
           if (rb >= 0) {
-            o[j] = q * S + x;
-            v[j] = a.u[rb + x];
-            m[j] = uniform ? uint8_t(0) : a.mask[rb + x];
+            q[j] = qq;
+            c[j] = (e - qq * vpr) * VX;
+            VecIO<T, VX>::ld(a.u + rb + c[j], v[j]);
+            if (!uniform) m[j] = ld_mask<VX>(a.mask + rb + c[j]);
           }
-        }
-        x += dxs;
-        q += dq;
-        if (x >= nx) {
-          x -= nx;
-          ++q;
         }
       }
 #pragma unroll
       for (int j = 0; j < kU; ++j) {
-        if (o[j] >= 0) {
-          tile[o[j]] = (A)v[j];
-          if (!uniform) mt[o[j]] = m[j];
+        if (q[j] >= 0) {
+#pragma unroll
+          for (int i = 0; i < VX; ++i) tile[q[j] * S + c[j] + i] = (A)v[j][i];
+          if (!uniform) {
+            if constexpr (VX == 4)
+              *reinterpret_cast<uint32_t*>(mt + q[j] * nxp + c[j]) = m[j];
+            else
+              *reinterpret_cast<uint16_t*>(mt + q[j] * nxp + c[j]) = (uint16_t)m[j];
+          }
         }
       }
     }
@@ -313,21 +355,16 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A
 
   // pointwise pre-operations on interior nodes: AOS W = flow(u) and the
   // LODIE1 leading nonlinear sub-step
+  const int total = L * nx;
   if (aos || a.pre_nl) {
     const A pka = (A)a.pre_ka, pkb = (A)a.pre_kb, wka = (A)a.aos_ka, wkb = (A)a.aos_kb;
-    int q = tid / nx, x = tid % nx;
     for (int e = tid; e < total; e += nthreads) {
+      const int q = e / nx, x = e - q * nx;
       if (rowbase[q] >= 0 && x >= 1 && x <= nx - 2) {
         A v = tile[q * S + x];
-        bool solvent = !uniform && mt[q * S + x] == 0;
+        bool solvent = !uniform && mt[q * nxp + x] == 0;
         if (aos) wtile[q * S + x] = (solvent && a.aos_w) ? sinh_flow(v, wka, wkb) : v;
         if (a.pre_nl && solvent) tile[q * S + x] = sinh_flow(v, pka, pkb);
-      }
-      x += dxs;
-      q += dq;
-      if (x >= nx) {
-        x -= nx;
-        ++q;
       }
     }
     __syncthreads();
@@ -344,12 +381,12 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A
     __syncthreads();
   }
 
-  // chunk elimination: lane t takes line t % L and chunk t / L
+  // chunk elimination
   const int ql = tid % L;
   const int p = tid / L;
   const bool lvalid = rowbase[ql] >= 0;
   const A* trow = tile + ql * S;
-  const uint8_t* mrow = mt + ql * S;
+  const uint8_t* mrow = mt + ql * nxp;
   const int g0 = p * M;
   A d[M];
 #pragma unroll
@@ -363,11 +400,12 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A
   const int kR = lvalid ? nint - 1 - g0 : -1;
   int cls = 1;
   if (lvalid) cls = uniform ? 0 : (a.ccls ? (int)a.ccls[(size_t)p * nlines + (l0 + ql)] : 1);
-  const bool inner = lvalid && cls != 1 && kR >= M;
-  const unsigned long long wall = __ballot(1);
-  const unsigned long long bf = __ballot(inner);
-  const unsigned long long bs = __ballot(inner && cls == 2);
-  const bool fast = (bf == wall) && (bs == 0 || bs == bf);
+  // lanes without a line follow whatever path their wave takes
+  const bool inner = cls != 1 && kR >= M;
+  const unsigned long long bv = __ballot(lvalid);
+  const unsigned long long bf = __ballot(lvalid && inner);
+  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
+  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
   const int t = (fast && bs != 0) ? 1 : 0;
   A al[M], ga[M];
   A rf[4], rl[4];
@@ -412,136 +450,183 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepArgs<T> a, ChunkTab<A
   }
   __syncthreads();
 
-  // coalesced store of the interior of each row
+  // row stores (boundary and padding columns carry their loaded values)
   T* out = aos ? a.acc : a.u;
-  {
-    int q = tid / nx, x = tid % nx;
-    for (int e = tid; e < total; e += nthreads) {
-      long long rb = rowbase[q];
-      if (rb >= 0 && x >= 1 && x <= nx - 2) out[rb + x] = (T)tile[q * S + x];
-      x += dxs;
-      q += dq;
-      if (x >= nx) {
-        x -= nx;
-        ++q;
-      }
-    }
+  for (int e = tid; e < nvec; e += nthreads) {
+    const int q = e / vpr;
+    const long long rb = rowbase[q];
+    if (rb < 0) continue;
+    const int c = (e - q * vpr) * VX;
+    T v[VX];
+#pragma unroll
+    for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c + i];
+    VecIO<T, VX>::st(out + rb + c, v);
   }
 }
 
 // ---------------------------------------------------------------------------
-// y / z sweep.  Block: LW lines (consecutive interior x, then the other
-// transverse index) x P chunks, LW*P threads; lane t takes line t % LW and
-// chunk t / LW.  VAR selects the fused work at compile time:
+// y / z sweep.  Block: one tile of TW consecutive x (x = xb .. xb+TW-1) of
+// one plane of the other transverse index o, across the whole line length
+// n; TW*P threads.  The n node rows of the tile (TW*sizeof(T) contiguous
+// bytes each) move between HBM and an LDS tile [n][TS] with 16-byte vector
+// accesses; lane t then takes line xb + t % TW and chunk t / TW, as in the
+// x sweep.  Columns outside 1..nx-2 are loaded but never solved; they are
+// stored back with the values they came with (the AOS accumulator keeps
+// its own).  VAR selects the fused work at compile time:
 //   kYzPlain   : solve only, in place
 //   kYzFlow    : solve, then the exact sinh flow on solvent nodes, in place
 //   kYzGeneral : sources before/after, flow, AOS accumulation (run-time flags)
 enum { kYzPlain = 0, kYzFlow = 1, kYzGeneral = 2 };
 
 template <typename T, typename A, int M, int VAR>
-__global__ __launch_bounds__(512) void sweep_yz_kernel(SweepArgs<T> a, ChunkTab<A> tb, int dir) {
+__global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int dir) {
+  constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   extern __shared__ __align__(16) unsigned char smem[];
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const int LW = a.LW, P = a.P;
+  const SweepArgs<T>& a = batch.f[blockIdx.y];
+  const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
+  const int nx = a.nx, ny = a.ny, nxp = a.nxp;
+  const int TW = a.LW, P = a.P, TS = a.S;
+  const int nthreads = TW * P;
   const int tid = threadIdx.x;
-  const int ql = tid % LW, p = tid / LW;
-  const int nxi = nx - 2;
-  const int n = (dir == 1) ? ny : nz;
-  const int no = (dir == 1) ? nz : ny;
+  const int n = (dir == 1) ? ny : a.nz;
   const int nint = n - 2;
-  const int nlines = nxi * (no - 2);
-  const int l = blockIdx.x * LW + ql;
-  const bool lvalid = l < nlines;
-  int x = 1, o = 1;
-  if (lvalid) {
-    o = 1 + l / nxi;
-    x = 1 + (l - (o - 1) * nxi);
-  }
+  const int ntx = (nx - 2) / TW + 1;  // tiles holding interior x
+  const int xt = blockIdx.x % ntx;
+  const int o = 1 + (int)(blockIdx.x / ntx);
+  const int xb = xt * TW;
   // element offsets fit in 32 bits (n <= 514)
-  const uint32_t stride = (dir == 1) ? (uint32_t)nx : (uint32_t)nx * (uint32_t)ny;
-  const uint32_t base = (dir == 1) ? ((uint32_t)o * (uint32_t)ny * (uint32_t)nx + (uint32_t)x)
-                                   : ((uint32_t)o * (uint32_t)nx + (uint32_t)x);
+  const uint32_t stride = (dir == 1) ? (uint32_t)nxp : (uint32_t)nxp * (uint32_t)ny;
+  const uint32_t plane = (dir == 1) ? (uint32_t)o * (uint32_t)ny * (uint32_t)nxp
+                                    : (uint32_t)o * (uint32_t)nxp;  // node (0, o, along 0)
+  const uint32_t base = plane + (uint32_t)xb;
   const bool uniform = (a.mask == nullptr);
+
+  A* red = reinterpret_cast<A*>(smem);
+  A* tile = red + (size_t)TW * 2 * P * 4;
+  uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)n * TS);  // [n][TW]
+
+  // node-row loads, every vector load of a thread in flight before its LDS
+  // stores; vectors past the row pitch are skipped
+  const int wrow = min(TW, nxp - xb);  // a multiple of 4
+  const int vpr = wrow / VX;
+  const int nvec = n * vpr;
+  {
+    constexpr int kU = 8;
+    for (int e0 = tid; e0 < nvec; e0 += kU * nthreads) {
+      T v[kU][VX];
+      uint32_t m[kU];
+      int j_[kU], c_[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nthreads;
+        j_[u] = -1;
+        if (e < nvec) {
+          const int j = e / vpr;
+          j_[u] = j;
+          c_[u] = (e - j * vpr) * VX;
+          const uint32_t pt = base + (uint32_t)j * stride + (uint32_t)c_[u];
+          VecIO<T, VX>::ld(a.u + pt, v[u]);
+          if (!uniform) m[u] = ld_mask<VX>(a.mask + pt);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (j_[u] >= 0) {
+#pragma unroll
+          for (int i = 0; i < VX; ++i) tile[j_[u] * TS + c_[u] + i] = (A)v[u][i];
+          if (!uniform) {
+            if constexpr (VX == 4)
+              *reinterpret_cast<uint32_t*>(mt + j_[u] * TW + c_[u]) = m[u];
+            else
+              *reinterpret_cast<uint16_t*>(mt + j_[u] * TW + c_[u]) = (uint16_t)m[u];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  const int ql = tid % TW;
+  const int p = tid / TW;
+  const int x = xb + ql;
+  const bool lvalid = x >= 1 && x <= nx - 2;
+
+  // trilinear source entries of this tile's lines (one thread per line)
+  auto add_sources = [&]() {
+    for (int q = tid; q < TW; q += nthreads) {
+      const int xq = xb + q;
+      if (xq < 1 || xq > nx - 2) continue;
+      const int l2 = o * nx + xq;
+      const int sb = a.src_ptr[l2], se = a.src_ptr[l2 + 1];
+      for (int e = sb; e < se; ++e) {
+        const int jj = (int)(((uint32_t)a.src_lin[e] - plane - (uint32_t)xq) / stride);
+        tile[jj * TS + q] += (A)(a.src_coef * a.src_rho[e]);
+      }
+    }
+  };
+  if (VAR == kYzGeneral && a.src_stage == 1) {
+    add_sources();
+    __syncthreads();
+  }
+
+  // chunk elimination
   const int g0 = p * M;
-  const uint32_t off0 = base + (uint32_t)(1 + g0) * stride;
-
-  const bool first = (g0 == 0);
-  const int kR = lvalid ? nint - 1 - g0 : -1;
-  int cls = 1;
-  if (lvalid) cls = uniform ? 0 : (a.ccls ? (int)a.ccls[(size_t)p * nlines + l] : 1);
-  const bool inner = lvalid && cls != 1 && kR >= M;
-  const unsigned long long wall = __ballot(1);
-  const unsigned long long bf = __ballot(inner);
-  const unsigned long long bs = __ballot(inner && cls == 2);
-  const bool fast = (bf == wall) && (bs == 0 || bs == bf);
-  const int t = (fast && bs != 0) ? 1 : 0;
-
-  A d[M], al[M], ga[M];
-  uint8_t mk[M + 2];
+  A d[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     int g = g0 + k;
-    d[k] = (lvalid && g < nint) ? (A)a.u[off0 + (uint32_t)k * stride] : A(0);
+    d[k] = (lvalid && g < nint) ? tile[(1 + g) * TS + ql] : A(0);
   }
-  A gL = A(0), gR = A(0);
-  if (lvalid && first) gL = (A)a.u[base];
-  if (!fast && lvalid && g0 <= nint - 1 && nint - 1 < g0 + M)
-    gR = (A)a.u[base + (uint32_t)(n - 1) * stride];
-
-  int sb = 0, se = 0;
-  if (VAR == kYzGeneral && a.src_stage != 0 && lvalid) {
-    int l2 = o * nx + x;
-    sb = a.src_ptr[l2];
-    se = a.src_ptr[l2 + 1];
+  const A gL = tile[ql];
+  const A gR = tile[(n - 1) * TS + ql];
+  const bool first = (g0 == 0);
+  const int kR = lvalid ? nint - 1 - g0 : -1;
+  int cls = 1;
+  if (lvalid) {
+    const long long nl = (long long)(nx - 2) * ((dir == 1 ? a.nz : ny) - 2);
+    cls = uniform ? 0
+                  : (a.ccls ? (int)a.ccls[(size_t)p * nl + (size_t)(o - 1) * (nx - 2) + (x - 1)]
+                            : 1);
   }
-  if (VAR == kYzGeneral && a.src_stage == 1) {
-    for (int e = sb; e < se; ++e) {
-      int kk = (int)(((uint32_t)a.src_lin[e] - base) / stride) - 1 - g0;
-      A v = (A)(a.src_coef * a.src_rho[e]);
-#pragma unroll
-      for (int k = 0; k < M; ++k)
-        if (kk == k) d[k] += v;
-    }
-  }
-
+  // lanes without a line follow whatever path their wave takes
+  const bool inner = cls != 1 && kR >= M;
+  const unsigned long long bv = __ballot(lvalid);
+  const unsigned long long bf = __ballot(lvalid && inner);
+  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
+  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
+  const int t = (fast && bs != 0) ? 1 : 0;
+  A al[M], ga[M];
   A rf[4], rl[4];
   if (fast) {
     const A re = tb.re[t];
     if (first) d[0] = fma(re, gL, d[0]);
     fast_eliminate<A, M>(d, tb.inv[t], tb.ga[t], tb.al[t], re, tb.ap[t], tb.gp[t], first, rf, rl);
   } else {
-    if (!uniform) {
-#pragma unroll
-      for (int k = 0; k < M + 2; ++k) {
-        int j = g0 + k;
-        mk[k] = (lvalid && j <= n - 1) ? a.mask[off0 + (uint32_t)(k - 1) * stride] : uint8_t(0);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < M + 2; ++k) mk[k] = 1;
-    }
     const A re0 = (A)(uniform ? a.re_uniform : a.re[0]);
     const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
     const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
     A reF[M + 1];
 #pragma unroll
-    for (int k = 0; k <= M; ++k) reF[k] = uniform ? re2 : pick3(mk[k] + mk[k + 1], re0, re1, re2);
+    for (int k = 0; k <= M; ++k) {
+      const int ja = g0 + k;  // face between along nodes ja and ja + 1
+      const int c = (uniform || ja + 1 > n - 1) ? 2 : (mt[ja * TW + ql] + mt[(ja + 1) * TW + ql]);
+      reF[k] = pick3(c, re0, re1, re2);
+    }
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
   }
-  A* R = reinterpret_cast<A*>(smem) + ql;
-  put_reduced(R, LW, p, rf, rl);
+  A* R = red + ql;
+  put_reduced(R, TW, p, rf, rl);
   __syncthreads();
-  if (p == 0 && lvalid) reduced_solve(R, 2 * P, LW);
+  if (p == 0 && lvalid) reduced_solve(R, 2 * P, TW);
   __syncthreads();
-  const A xf = R[(4 * (2 * p) + 3) * LW];
-  const A xl = R[(4 * (2 * p + 1) + 3) * LW];
+  const A xf = R[(4 * (2 * p) + 3) * TW];
+  const A xl = R[(4 * (2 * p + 1) + 3) * TW];
   if (fast)
     fast_finish<A, M>(d, tb.ga[t], tb.al[t], xf, xl);
   else
     chunk_finish<A, M>(d, al, ga, xf, xl);
 
-  if (!lvalid) return;
   if ((VAR == kYzFlow || (VAR == kYzGeneral && a.post_nl)) && !uniform) {
     const A ka = (A)a.post_ka, kb = (A)a.post_kb;
     if (fast) {
@@ -551,32 +636,50 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepArgs<T> a, ChunkTab<
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < M; ++k)
-        if (mk[k + 1] == 0) d[k] = sinh_flow(d[k], ka, kb);
-    }
-  }
-  if (VAR == kYzGeneral && a.src_stage == 2) {
-    for (int e = sb; e < se; ++e) {
-      int kk = (int)(((uint32_t)a.src_lin[e] - base) / stride) - 1 - g0;
-      A v = (A)(a.src_coef * a.src_rho[e]);
-#pragma unroll
-      for (int k = 0; k < M; ++k)
-        if (kk == k) d[k] += v;
+      for (int k = 0; k < M; ++k) {
+        const int g = g0 + k;
+        if (g < nint && mt[(1 + g) * TW + ql] == 0) d[k] = sinh_flow(d[k], ka, kb);
+      }
     }
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    int g = g0 + k;
-    if (g < nint) {
-      const uint32_t pt = off0 + (uint32_t)k * stride;
-      if (VAR == kYzGeneral && a.mode == MODE_AOS_ADD) {
-        a.acc[pt] = (T)((A)a.acc[pt] + A(0.25) * d[k]);
-      } else if (VAR == kYzGeneral && a.mode == MODE_AOS_FINISH) {
-        a.u[pt] = (T)((A)a.acc[pt] + A(0.25) * d[k]);
-      } else {
-        a.u[pt] = (T)d[k];
+    const int g = g0 + k;
+    if (lvalid && g < nint) tile[(1 + g) * TS + ql] = d[k];
+  }
+  __syncthreads();
+  if (VAR == kYzGeneral && a.src_stage == 2) {
+    add_sources();
+    __syncthreads();
+  }
+
+  // interior node rows back to HBM
+  const int mode = (VAR == kYzGeneral) ? a.mode : MODE_INPLACE;
+  T* out = (mode == MODE_AOS_ADD) ? a.acc : a.u;
+  const int nvi = nint * vpr;
+  for (int e = tid; e < nvi; e += nthreads) {
+    const int j = 1 + e / vpr;
+    const int c = (e - (j - 1) * vpr) * VX;
+    const uint32_t pt = base + (uint32_t)j * stride + (uint32_t)c;
+    T w[VX];
+    if (mode == MODE_AOS_ADD || mode == MODE_AOS_FINISH) {
+      T acc[VX];
+      VecIO<T, VX>::ld(a.acc + pt, acc);
+#pragma unroll
+      for (int i = 0; i < VX; ++i) {
+        const int xi = xb + c + i;
+        const A tv = tile[j * TS + c + i];
+        const bool live = xi >= 1 && xi <= nx - 2;
+        if (live)
+          w[i] = (T)((A)acc[i] + A(0.25) * tv);
+        else
+          w[i] = (mode == MODE_AOS_ADD) ? acc[i] : (T)tv;
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < VX; ++i) w[i] = (T)tile[j * TS + c + i];
     }
+    VecIO<T, VX>::st(out + pt, w);
   }
 }
 
@@ -599,17 +702,19 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
   LaunchShape s{};
   const int nint = nx - 2;
   const int es = fp64 ? 8 : 4;
+  const int nxp = pitch_of(nx);
   int P = next_pow2((nint + 19) / 20);
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0 || P > 64) return s;  // unsupported length
-  const int S = (nx % 2) ? nx : nx + 1;
+  const int S = nxp + 1;
   int L = 256 / P;
   auto lds = [&](int Lc) {
     size_t off = (sizeof(long long) + sizeof(int)) * (size_t)Lc;
     off = (off + 15) & ~size_t(15);
     off += (size_t)es * Lc * 2 * P * 4;
     off += (size_t)es * Lc * S * (aos ? 2 : 1);
-    if (!uniform) off += (size_t)Lc * S;
+    off = (off + 15) & ~size_t(15);
+    if (!uniform) off += (size_t)Lc * nxp;
     return off;
   };
   while (L > 1 && lds(L) > 60 * 1024 && L * P > 64) L >>= 1;
@@ -623,28 +728,46 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
   return s;
 }
 
-LaunchShape plan_yz(int n_along, int n_lines, bool fp64) {
+LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64) {
   LaunchShape s{};
+  const int es = fp64 ? 8 : 4;
   const int nint = n_along - 2;
-  int P = (nint + 19) / 20;
-  if (P > 16) P = 16;
+  const int mt = fp64 ? 16 : 20;  // FP64 chunks shorter: lane state in registers
+  int P = (nint + mt - 1) / mt;
+  if (P > 32) return s;  // unsupported length
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0) return s;
   P = (nint + M - 1) / M;
-  int LW = (P <= 8) ? 64 : 32;
+  auto lds = [&](int tw) {
+    return (size_t)es * tw * 2 * P * 4 + (size_t)es * n_along * (tw + 1) + (size_t)n_along * tw;
+  };
+  // Tile width: FP32 arithmetic takes the widest tile (longest contiguous
+  // node-row pieces, 256 B at 64 x) that fits 512 threads and 80 KB of LDS;
+  // FP64 arithmetic is bound by its arithmetic and runs best on narrow
+  // tiles (more, smaller blocks).
+  int TW = 16;
+  if (!fp64) {
+    for (int tw : {64, 32})
+      if (tw * P <= 512 && lds(tw) <= 80 * 1024) {
+        TW = tw;
+        break;
+      }
+  }
+  if (lds(TW) > 160 * 1024) return s;
+  const int ntx = (nx - 2) / TW + 1;
   s.M = M;
   s.P = P;
-  s.LW = LW;
-  s.threads = LW * P;
-  s.blocks = (n_lines + LW - 1) / LW;
-  s.lds = (size_t)LW * 2 * P * 4 * (fp64 ? 8 : 4);
+  s.LW = TW;
+  s.threads = TW * P;
+  s.blocks = ntx * (n_other - 2);
+  s.lds = lds(TW);
   return s;
 }
 
 // Elimination constants of uniform chunks of M rows with face coefficient
 // re (computed in double, stored in A).
 template <typename A>
-static void fill_tab(ChunkTab<A>& tb, int t, double re, int M) {
+static void fill_tab_row(ChunkTab<A>& tb, int t, double re, int M) {
   const double av = -re, bv = 1.0 + 2.0 * re, cv = -re;
   double inv[kMaxChunk] = {0}, ga[kMaxChunk] = {0}, al[kMaxChunk] = {0};
   inv[1] = 1.0 / bv;
@@ -674,39 +797,41 @@ static void fill_tab(ChunkTab<A>& tb, int t, double re, int M) {
   tb.re[t] = (A)re;
 }
 
-template <typename T, typename A>
-static ChunkTab<A> make_tab(const SweepArgs<T>& a, int M) {
-  ChunkTab<A> tb{};
-  if (a.mask == nullptr) {
-    fill_tab(tb, 0, a.re_uniform, M);
-    fill_tab(tb, 1, a.re_uniform, M);
-  } else {
-    fill_tab(tb, 0, a.re[0], M);
-    fill_tab(tb, 1, a.re[2], M);
+template <typename A>
+void fill_chunk_tab(ChunkTab<A>& tb, double re_solvent, double re_solute, int M) {
+  tb = ChunkTab<A>{};
+  fill_tab_row(tb, 0, re_solvent, M);
+  fill_tab_row(tb, 1, re_solute, M);
+}
+template void fill_chunk_tab<float>(ChunkTab<float>&, double, double, int);
+template void fill_chunk_tab<double>(ChunkTab<double>&, double, double, int);
+
+template <typename T>
+static SweepBatch<T> shaped(const SweepBatch<T>& b0, int nf, const LaunchShape& s, int S) {
+  SweepBatch<T> b = b0;
+  for (int f = 0; f < nf; ++f) {
+    b.f[f].M = s.M;
+    b.f[f].P = s.P;
+    b.f[f].LW = s.LW;
+    b.f[f].S = S;
   }
-  return tb;
+  return b;
 }
 
 template <typename T, typename A>
-hipError_t launch_sweep_x(const SweepArgs<T>& a0, const LaunchShape& s, hipStream_t st) {
-  SweepArgs<T> a = a0;
-  const ChunkTab<A> tb = make_tab<T, A>(a, s.M);
-  a.M = s.M;
-  a.P = s.P;
-  a.LW = s.LW;
-  a.S = (a.nx % 2) ? a.nx : a.nx + 1;
-  dim3 g(s.blocks), b(s.threads);
+hipError_t launch_sweep_x(const SweepBatch<T>& b0, int nf, const LaunchShape& s, hipStream_t st) {
+  if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
+  const SweepBatch<T> b = shaped(b0, nf, s, b0.f[0].nxp + 1);
+  dim3 g(s.blocks, nf), blk(s.threads);
   switch (s.M) {
 #define NPB_X_CASE(MM) \
   case MM:             \
-    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM>), g, b, s.lds, st, a, tb); break;
+    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM>), g, blk, s.lds, st, b); break;
     NPB_X_CASE(4)
     NPB_X_CASE(8)
     NPB_X_CASE(12)
     NPB_X_CASE(16)
     NPB_X_CASE(20)
-    NPB_X_CASE(24)
-    NPB_X_CASE(32)
 #undef NPB_X_CASE
     default:
       return hipErrorInvalidValue;
@@ -715,45 +840,53 @@ hipError_t launch_sweep_x(const SweepArgs<T>& a0, const LaunchShape& s, hipStrea
 }
 
 template <typename T, typename A, int VAR>
-static hipError_t launch_yz_var(const SweepArgs<T>& a, int dir, const LaunchShape& s,
+static hipError_t launch_yz_var(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
                                 hipStream_t st) {
-  dim3 g(s.blocks), b(s.threads);
-  const ChunkTab<A> tb = make_tab<T, A>(a, s.M);
+  dim3 g(s.blocks, nf), blk(s.threads);
   switch (s.M) {
 #define NPB_YZ_CASE(MM) \
   case MM:              \
-    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR>), g, b, s.lds, st, a, tb, dir); break;
+    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR>), g, blk, s.lds, st, b, dir); break;
     NPB_YZ_CASE(4)
     NPB_YZ_CASE(8)
     NPB_YZ_CASE(12)
     NPB_YZ_CASE(16)
-    NPB_YZ_CASE(20)
-    NPB_YZ_CASE(24)
-    NPB_YZ_CASE(32)
 #undef NPB_YZ_CASE
+    case 20:
+      // planned only for FP32 arithmetic (FP64 chunks stop at 16 rows)
+      if constexpr (sizeof(A) == 4) {
+        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR>), g, blk, s.lds, st, b, dir);
+        break;
+      }
+      return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+// The fused-work variant covers every field of the batch; the flow and
+// source branches are uniform per block.
 template <typename T, typename A>
-hipError_t launch_sweep_yz(const SweepArgs<T>& a0, int dir, const LaunchShape& s, hipStream_t st) {
-  SweepArgs<T> a = a0;
-  a.M = s.M;
-  a.P = s.P;
-  a.LW = s.LW;
-  const bool general = a.src_stage != 0 || a.mode != MODE_INPLACE;
-  if (general) return launch_yz_var<T, A, kYzGeneral>(a, dir, s, st);
-  if (a.post_nl && a.mask) return launch_yz_var<T, A, kYzFlow>(a, dir, s, st);
-  return launch_yz_var<T, A, kYzPlain>(a, dir, s, st);
+hipError_t launch_sweep_yz(const SweepBatch<T>& b0, int nf, int dir, const LaunchShape& s,
+                           hipStream_t st) {
+  if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
+  const SweepBatch<T> b = shaped(b0, nf, s, s.LW + 1);
+  bool general = false, flow = false;
+  for (int f = 0; f < nf; ++f) {
+    general = general || b.f[f].src_stage != 0 || b.f[f].mode != MODE_INPLACE;
+    flow = flow || (b.f[f].post_nl && b.f[f].mask);
+  }
+  if (general) return launch_yz_var<T, A, kYzGeneral>(b, nf, dir, s, st);
+  if (flow) return launch_yz_var<T, A, kYzFlow>(b, nf, dir, s, st);
+  return launch_yz_var<T, A, kYzPlain>(b, nf, dir, s, st);
 }
 
-template hipError_t launch_sweep_x<float, float>(const SweepArgs<float>&, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_x<float, double>(const SweepArgs<float>&, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_x<double, double>(const SweepArgs<double>&, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_yz<float, float>(const SweepArgs<float>&, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_yz<float, double>(const SweepArgs<float>&, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_yz<double, double>(const SweepArgs<double>&, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_sweep_x<float, float>(const SweepBatch<float>&, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_sweep_x<float, double>(const SweepBatch<float>&, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_sweep_x<double, double>(const SweepBatch<double>&, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_sweep_yz<float, float>(const SweepBatch<float>&, int, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_sweep_yz<float, double>(const SweepBatch<float>&, int, int, const LaunchShape&, hipStream_t);
+template hipError_t launch_sweep_yz<double, double>(const SweepBatch<double>&, int, int, const LaunchShape&, hipStream_t);
 
 }  // namespace npb
