@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--scheme", default="LODIE2", choices=["LODIE2", "LODIE1", "AOSIE2", "AOSIE1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
-                    help="skip the per-kernel event timing in the timed region")
+                    help="skip the per-kernel event timing pass")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -106,9 +106,9 @@ def main():
         solver.run()
     torch.cuda.synchronize()
 
+    # timed region: solves as a caller runs them (graph replay of the
+    # device work, inputs already resident)
     stream = torch.cuda.current_stream()
-    if not args.no_timing:
-        npb.npb_ctx_set_timing(solver.ctx, True)
     lat = []
     results = []
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -123,8 +123,19 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
-    ktimes = npb.npb_ctx_get_kernel_times(solver.ctx) if not args.no_timing else None
-    npb.npb_ctx_set_timing(solver.ctx, False)
+
+    # per-kernel durations: the same solves once more with every launch
+    # bracketed by HIP events on the solve's stream (direct launches; a
+    # kernel's duration does not depend on how it was enqueued)
+    ktimes = None
+    if not args.no_timing:
+        print("[bench] per-kernel timing pass", file=sys.stderr, flush=True)
+        npb.npb_ctx_set_timing(solver.ctx, True)
+        for _ in range(min(args.steps, 5)):
+            solver.run()
+        torch.cuda.synchronize()
+        ktimes = npb.npb_ctx_get_kernel_times(solver.ctx)
+        npb.npb_ctx_set_timing(solver.ctx, False)
 
     # accuracy gate: the FP64 oracle's energies for this workload
     tol = max(1e-3, 1e-5 * abs(ref["dG"]))

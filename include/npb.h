@@ -167,9 +167,18 @@ npb_status npb_ctx_create(int device, npb_ctx** out);
 void npb_ctx_destroy(npb_ctx* ctx);
 
 /* Enable (1) or disable (0) per-kernel event timing; enabling clears the
- * accumulated times. */
+ * accumulated times.  While timing is on, solves launch every kernel
+ * directly (no graph replay) so that each launch can be bracketed. */
 npb_status npb_ctx_set_timing(npb_ctx* ctx, int enable);
 npb_status npb_ctx_get_kernel_times(npb_ctx* ctx, npb_kernel_times* out);
+
+/* Enable (1, the default) or disable (0) graph replay.  With replay on, the
+ * device work of a solve (everything after the host-to-device copy of the
+ * atoms) is captured once into a HIP graph and replayed by later solves
+ * with the same workspace pointer, field pointer, grid, parameters and atom
+ * count; any difference captures a new graph.  Results are bit-identical
+ * to direct launches.  The context keeps one graph. */
+npb_status npb_ctx_set_graph(npb_ctx* ctx, int enable);
 
 /* Host-only checks of a problem: the same argument and stencil checks that
  * npb_solve performs before touching the device.  Returns NPB_OK,

@@ -143,7 +143,11 @@ hipError_t launch_axis_keys(const int* q_idx, const int* nq_dev, int cap, int nx
 hipError_t launch_gather_entries(const int* id, const int* nq_dev, int cap, const int* q_idx,
                                  const double* q_rho, int* lin_out, double* rho_out,
                                  hipStream_t st);
-hipError_t launch_boundary(const SetupArgs& a, double eps, double kappa, double lB, double* bc,
+// Dirichlet values of the solvated (eps_s, kappa) and, if bc_v is not null,
+// the vacuum (eps_v, no screening) medium on the outer shell, in shell
+// order.  fp32_terms: per-pair terms in FP32 (sums stay FP64).
+hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, double eps_v,
+                           double lB, double* bc_s, double* bc_v, bool fp32_terms,
                            hipStream_t st);
 // chunk classes of direction dir (0 = x, 1 = y, 2 = z) for chunks of M rows,
 // P per line; out[p * class_lines + line]

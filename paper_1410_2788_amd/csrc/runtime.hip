@@ -177,9 +177,23 @@ template hipError_t launch_field_init<double>(double*, const double*, int, int, 
 // ---------------------------------------------------------------------------
 // context
 
+// Everything a captured solve graph depends on besides the staged bytes.
+struct GraphKey {
+  void* ws;
+  double* field_out;
+  void* pinned;
+  npb_grid grid;
+  npb_params params;
+  int n_atoms;
+};
+
 struct npb_ctx {
   int device = 0;
   bool timing = false;
+  bool graphs = true;
+  hipStream_t capture = nullptr;  // stream the solve graph is captured on
+  hipGraphExec_t exec = nullptr;
+  GraphKey key{};
   npb_kernel_times times{};
   struct Pending {
     int cls;
@@ -525,9 +539,8 @@ struct Solver {
         if (e != hipSuccess) return e;
       }
       const double kappa = std::sqrt(p->kappa_bar_sq / p->eps_out);
-      e = launch_boundary(sa, p->eps_out, kappa, lB, at<double>(L.bc_s), st);
-      if (e != hipSuccess) return e;
-      if (p->vacuum) e = launch_boundary(sa, p->eps_in, 0.0, lB, at<double>(L.bc_v), st);
+      e = launch_boundary(sa, p->eps_out, kappa, p->eps_in, lB, at<double>(L.bc_s),
+                          p->vacuum ? at<double>(L.bc_v) : nullptr, sizeof(A) == 4, st);
       if (e != hipSuccess) return e;
       for (int d = 0; d < 3 && e == hipSuccess; ++d)
         e = launch_chunk_classes(at<uint8_t>(L.mask), nx, nxp, ny, nz, d, L.shape[d].M,
@@ -663,6 +676,43 @@ struct Solver {
                               at<int>(L.ints), L.cap, at<double>(L.slots) + slot, st);
     });
   }
+
+  // The device work of a solve after staging, all on `st` (captured into a
+  // graph when replay is on): setup, time loops, energies, optional field,
+  // combinations.  Launches only: no allocation, copy or synchronisation.
+  npb_status device_work(const npb_molecule* mol, double* d_field_out) {
+    npb_status s = setup(mol);
+    if (s != NPB_OK) return s;
+    // zero the energy slots
+    s = timed(NPB_K_OTHER, 0, [&] {
+      return launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.slots), 64, 0u, st);
+    });
+    if (s != NPB_OK) return s;
+    s = time_loop();
+    if (s != NPB_OK) return s;
+    for (int r = 0; r < L.n_runs; ++r) {
+      s = energy(r);
+      if (s != NPB_OK) return s;
+    }
+    if (d_field_out) {
+      // selected medium: kT u (plain) or kT (2 u(dt/2) - u(dt)) (Richardson)
+      for (int l = 0; l < (p->richardson ? 2 : 1); ++l) {
+        int r = 0;
+        while (!(L.runs[r].medium == p->field_select && L.runs[r].level == l)) ++r;
+        const double beta = (l == 0) ? 0.0 : 1.0;
+        const double gamma = p->richardson ? (l == 0 ? -kT : 2.0 * kT) : kT;
+        s = timed(NPB_K_OTHER, 0, [&] {
+          return launch_field_out<T>(d_field_out, at<T>(L.field[r]), g->nx, pitch_of(g->nx),
+                                     g->ny, g->nz, beta, gamma, st);
+        });
+        if (s != NPB_OK) return s;
+      }
+    }
+    return timed(NPB_K_OTHER, 0, [&] {
+      return launch_combine(at<double>(L.slots), kT, p->richardson, p->vacuum,
+                            at<double>(L.slots) + 8, st);
+    });
+  }
 };
 
 template <typename T, typename A>
@@ -675,15 +725,42 @@ npb_status solve_t(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* g,
   npb_status s = S.stage(mol);
   if (s != NPB_OK) return s;
   NPB_HIP(hipEventRecord(ctx->t0, st));
-  s = S.setup(mol);
-  if (s != NPB_OK) return s;
-  // zero the energy slots
-  s = S.timed(NPB_K_OTHER, 0, [&] {
-    return launch_fill_u32(reinterpret_cast<uint32_t*>(S.ws + L.slots), 64, 0u, st);
-  });
-  if (s != NPB_OK) return s;
-  s = S.time_loop();
-  if (s != NPB_OK) return s;
+  if (ctx->graphs && !ctx->timing) {
+    GraphKey k;
+    std::memset(&k, 0, sizeof(k));
+    k.ws = d_ws;
+    k.field_out = d_field_out;
+    k.pinned = ctx->pinned;
+    k.grid = *g;
+    k.params = *p;
+    k.n_atoms = mol->n_atoms;
+    if (!ctx->exec || std::memcmp(&k, &ctx->key, sizeof(k)) != 0) {
+      if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+      ctx->exec = nullptr;
+      S.st = ctx->capture;
+      NPB_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+      s = S.device_work(mol, d_field_out);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+      S.st = st;
+      if (s != NPB_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (e != hipSuccess) return fail(NPB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&ctx->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        ctx->exec = nullptr;
+        return fail(NPB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+      ctx->key = k;
+    }
+    NPB_HIP(hipGraphLaunch(ctx->exec, st));
+  } else {
+    s = S.device_work(mol, d_field_out);
+    if (s != NPB_OK) return s;
+  }
   int steps_done = 0;
   double gpu_updates = 0.0;
   const double pts = (double)(g->nx - 2) * (g->ny - 2) * (g->nz - 2);
@@ -691,28 +768,7 @@ npb_status solve_t(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* g,
     const int ns = p->n_steps << L.runs[r].level;
     steps_done += ns;
     gpu_updates += pts * ns;
-    s = S.energy(r);
-    if (s != NPB_OK) return s;
   }
-  if (d_field_out) {
-    // selected medium: kT u (plain) or kT (2 u(dt/2) - u(dt)) (Richardson)
-    for (int l = 0; l < (p->richardson ? 2 : 1); ++l) {
-      int r = 0;
-      while (!(L.runs[r].medium == p->field_select && L.runs[r].level == l)) ++r;
-      const double beta = (l == 0) ? 0.0 : 1.0;
-      const double gamma = p->richardson ? (l == 0 ? -S.kT : 2.0 * S.kT) : S.kT;
-      s = S.timed(NPB_K_OTHER, 0, [&] {
-        return launch_field_out<T>(d_field_out, S.template at<T>(L.field[r]), g->nx,
-                                   pitch_of(g->nx), g->ny, g->nz, beta, gamma, st);
-      });
-      if (s != NPB_OK) return s;
-    }
-  }
-  s = S.timed(NPB_K_OTHER, 0, [&] {
-    return launch_combine(S.template at<double>(L.slots), S.kT, p->richardson, p->vacuum,
-                          S.template at<double>(L.slots) + 8, st);
-  });
-  if (s != NPB_OK) return s;
   NPB_HIP(hipEventRecord(ctx->t1, st));
   // results to the host (first 256 bytes of the staging buffer)
   double* hres = reinterpret_cast<double*>(ctx->pinned);
@@ -766,9 +822,12 @@ npb_status npb_ctx_create(int device, npb_ctx** out) {
   npb_ctx* c = new (std::nothrow) npb_ctx();
   if (!c) return fail(NPB_ENOMEM, "context allocation failed");
   c->device = device;
-  if (hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess) {
+  if (hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+    if (c->t0) (void)hipEventDestroy(c->t0);
+    if (c->t1) (void)hipEventDestroy(c->t1);
     delete c;
-    return fail(NPB_EDEVICE, "event creation failed");
+    return fail(NPB_EDEVICE, "event or stream creation failed");
   }
   *out = c;
   return NPB_OK;
@@ -784,6 +843,8 @@ void npb_ctx_destroy(npb_ctx* c) {
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->t0) (void)hipEventDestroy(c->t0);
   if (c->t1) (void)hipEventDestroy(c->t1);
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }
@@ -792,6 +853,12 @@ npb_status npb_ctx_set_timing(npb_ctx* c, int enable) {
   if (!c) return fail(NPB_EINVAL, "null context");
   c->timing = enable != 0;
   if (c->timing) std::memset(&c->times, 0, sizeof(c->times));
+  return NPB_OK;
+}
+
+npb_status npb_ctx_set_graph(npb_ctx* c, int enable) {
+  if (!c) return fail(NPB_EINVAL, "null context");
+  c->graphs = enable != 0;
   return NPB_OK;
 }
 

@@ -332,6 +332,7 @@ hipError_t launch_gather_entries(const int* id, const int* nq_dev, int cap, cons
 // ---------------------------------------------------------------------------
 // Dirichlet data on the outer shell (Eq. (BoundaryCond)):
 //   u = l_B sum_i q_i exp(-kappa d) / (eps d),  kappa = kbar / sqrt(eps)
+// and its vacuum counterpart (eps_in, kappa = 0).
 // Shell enumeration: face z = 0 (ny*nx), face z = nz-1 (ny*nx), then per
 // interior z the ring y = 0 (nx), y = ny-1 (nx), and x = 0, nx-1 for each
 // interior y.
@@ -367,57 +368,84 @@ __device__ __forceinline__ void shell_node(long long s, int nx, int ny, int nz, 
   }
 }
 
-__global__ __launch_bounds__(256) void boundary_kernel(SetupArgs a, double eps, double kappa,
-                                                       double lB, double* bc, long long nshell) {
+// Both media in one pass: the solvated value with eps_s and kappa, the
+// vacuum value (kappa = 0) with eps_v, sharing the distance of every
+// (shell node, atom) pair.  R is the arithmetic type of one pair's term;
+// the sums over atoms are FP64 in both cases, and the constant factor
+// l_B / eps is applied once at the end.
+template <typename R>
+__device__ __forceinline__ void pair_terms(R dx, R dy, R dz, R q, R kappa, R& ts, R& tv);
+template <>
+__device__ __forceinline__ void pair_terms<double>(double dx, double dy, double dz, double q,
+                                                   double kappa, double& ts, double& tv) {
+  const double d = sqrt(dx * dx + dy * dy + dz * dz);
+  tv = q / d;
+  ts = tv * exp(-kappa * d);
+}
+template <>
+__device__ __forceinline__ void pair_terms<float>(float dx, float dy, float dz, float q,
+                                                  float kappa, float& ts, float& tv) {
+  const float d2 = dx * dx + dy * dy + dz * dz;
+  const float ri = rsqrtf(d2);
+  tv = q * ri;
+  ts = tv * __expf(-kappa * (d2 * ri));
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void boundary_kernel(SetupArgs a, double scale_s, double kappa,
+                                                       double scale_v, double* bc_s, double* bc_v,
+                                                       long long nshell) {
 #pragma clang fp contract(off)
-  __shared__ double sx[256], sy[256], sz[256], sq[256];
+  __shared__ R sx[256], sy[256], sz[256], sq[256];
   const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
   const bool valid = s < nshell;
-  double X = 0, Y = 0, Z = 0;
+  R X = 0, Y = 0, Z = 0;
   if (valid) {
     int i, j, k;
     shell_node(s, a.nx, a.ny, a.nz, i, j, k);
-    X = a.ox + (double)i * a.h;
-    Y = a.oy + (double)j * a.h;
-    Z = a.oz + (double)k * a.h;
+    X = (R)(a.ox + (double)i * a.h);
+    Y = (R)(a.oy + (double)j * a.h);
+    Z = (R)(a.oz + (double)k * a.h);
   }
   const int na = a.n_atoms;
-  double acc = 0.0;
+  const R kap = (R)kappa;
+  double acc_s = 0.0, acc_v = 0.0;
   for (int t0 = 0; t0 < na; t0 += 256) {
     int t = t0 + threadIdx.x;
     if (t < na) {
-      sx[threadIdx.x] = a.atoms[t];
-      sy[threadIdx.x] = a.atoms[na + t];
-      sz[threadIdx.x] = a.atoms[2 * na + t];
-      sq[threadIdx.x] = a.atoms[3 * na + t];
+      sx[threadIdx.x] = (R)a.atoms[t];
+      sy[threadIdx.x] = (R)a.atoms[na + t];
+      sz[threadIdx.x] = (R)a.atoms[2 * na + t];
+      sq[threadIdx.x] = (R)a.atoms[3 * na + t];
     }
     __syncthreads();
     const int cnt = min(256, na - t0);
     if (valid) {
-      if (kappa == 0.0) {
-        for (int jj = 0; jj < cnt; ++jj) {
-          double dx = X - sx[jj], dy = Y - sy[jj], dz = Z - sz[jj];
-          double d = sqrt(dx * dx + dy * dy + dz * dz);
-          acc += sq[jj] / (eps * d);
-        }
-      } else {
-        for (int jj = 0; jj < cnt; ++jj) {
-          double dx = X - sx[jj], dy = Y - sy[jj], dz = Z - sz[jj];
-          double d = sqrt(dx * dx + dy * dy + dz * dz);
-          acc += sq[jj] * exp(-kappa * d) / (eps * d);
-        }
+      for (int jj = 0; jj < cnt; ++jj) {
+        R ts, tv;
+        pair_terms<R>(X - sx[jj], Y - sy[jj], Z - sz[jj], sq[jj], kap, ts, tv);
+        acc_s += (double)ts;
+        acc_v += (double)tv;
       }
     }
     __syncthreads();
   }
-  if (valid) bc[s] = lB * acc;
+  if (valid) {
+    bc_s[s] = scale_s * acc_s;
+    if (bc_v) bc_v[s] = scale_v * acc_v;
+  }
 }
 
-hipError_t launch_boundary(const SetupArgs& a, double eps, double kappa, double lB, double* bc,
+hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, double eps_v,
+                           double lB, double* bc_s, double* bc_v, bool fp32_terms,
                            hipStream_t st) {
   const long long ns = shell_count(a.nx, a.ny, a.nz);
-  hipLaunchKernelGGL(boundary_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, a,
-                     eps, kappa, lB, bc, ns);
+  const dim3 g((unsigned)((ns + 255) / 256)), b(256);
+  const double ss = lB / eps_s, sv = lB / eps_v;
+  if (fp32_terms)
+    hipLaunchKernelGGL(boundary_kernel<float>, g, b, 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
+  else
+    hipLaunchKernelGGL(boundary_kernel<double>, g, b, 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
   return hipGetLastError();
 }
 

@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH):
         lib.npb_ctx_destroy.argtypes = [C.c_void_p]
         lib.npb_ctx_set_timing.restype = C.c_int
         lib.npb_ctx_set_timing.argtypes = [C.c_void_p, C.c_int]
+        lib.npb_ctx_set_graph.restype = C.c_int
+        lib.npb_ctx_set_graph.argtypes = [C.c_void_p, C.c_int]
         lib.npb_ctx_get_kernel_times.restype = C.c_int
         lib.npb_ctx_get_kernel_times.argtypes = [C.c_void_p, P(npb_kernel_times)]
         lib.npb_validate.restype = C.c_int
@@ -141,6 +143,10 @@ def npb_ctx_destroy(ctx) -> None:
 
 def npb_ctx_set_timing(ctx, enable: bool) -> None:
     _check(load_library().npb_ctx_set_timing(ctx, 1 if enable else 0))
+
+
+def npb_ctx_set_graph(ctx, enable: bool) -> None:
+    _check(load_library().npb_ctx_set_graph(ctx, 1 if enable else 0))
 
 
 def npb_ctx_get_kernel_times(ctx) -> dict:

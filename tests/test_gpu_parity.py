@@ -153,6 +153,35 @@ def test_repeat_solves_are_bit_identical():
     assert bool((f1 == s.field).all())
 
 
+@pytest.mark.parametrize("precision,scheme", [("f32", "LODIE2"), ("f64", "AOSIE2")])
+def test_graph_replays_match_direct_launches(precision, scheme):
+    """Graph replays (captured solve) against direct launches of the same
+    solve, several replays with direct work and synchronisation between
+    them; every replay must reproduce the direct result bit for bit."""
+    npb = _npb()
+    import torch
+    w = inputs.small_globular(n=45, n_atoms=150, n_steps=3, precision=precision, scheme=scheme)
+    s = npb.Solver(w.molecule, w.grid, w.params, want_field=True)
+    npb.npb_ctx_set_graph(s.ctx, False)
+    try:
+        ref = s.run()
+        fref = s.field.clone()
+        for i in range(3):
+            npb.npb_ctx_set_graph(s.ctx, True)
+            r = s.run()
+            f = s.field.clone()
+            _say(f"replay {i}: dG {r['dG']!r} direct {ref['dG']!r}")
+            assert (r["dG"], r["G_m"], r["G_0"]) == (ref["dG"], ref["G_m"], ref["G_0"])
+            assert bool((f == fref).all())
+            npb.npb_ctx_set_graph(s.ctx, False)
+            torch.cuda.synchronize()
+            r2 = s.run()
+            assert r2["dG"] == ref["dG"]
+            torch.cuda.synchronize()
+    finally:
+        npb.npb_ctx_set_graph(s.ctx, True)
+
+
 def test_invalid_inputs_raise_before_device_work():
     npb = _npb()
     w = inputs.small_globular(n=21, n_atoms=4, n_steps=2)
