@@ -43,7 +43,7 @@ struct SweepArgs {
   int M;                  // rows per chunk (compile-time in the kernel)
   int P;                  // chunks per line
   int LW;                 // lines per block (x: rows, y/z: consecutive x)
-  int S;                  // LDS stride (x: per row, y/z: per node row)
+  int S;                  // x: LDS elements per row; y/z: LDS tile rows
 };
 
 enum SweepMode { MODE_INPLACE = 0, MODE_AOS_FIRST = 1, MODE_AOS_ADD = 2, MODE_AOS_FINISH = 3 };
@@ -66,10 +66,17 @@ struct LaunchShape {
   size_t lds;
 };
 
-// Row pitch of every field-shaped array: rows start on 16-byte boundaries,
-// so the sweeps move rows in 16-byte pieces.  Padding columns nx..nxp-1
-// hold zeros (field) or 0 (mask) and are never solved.
-inline int pitch_of(int nx) { return (nx + 3) & ~3; }
+// Row pitch of every field-shaped array (the mask shares it): rows start
+// on 128-byte boundaries of the field (one cache line), so the pieces of
+// consecutive x that a y/z tile moves per node row cover whole lines.  The
+// sweeps move the first row4(nx) elements of a row in 16-byte pieces;
+// padding columns nx..nxp-1 hold zeros (field) or 0 (mask) and are never
+// solved.  es = bytes per field element.
+__host__ __device__ inline int row4(int nx) { return (nx + 3) & ~3; }
+inline int pitch_of(int nx, int es) {
+  const int q = 128 / es;
+  return (nx + q - 1) / q * q;
+}
 
 // Elimination constants of a chunk whose M+1 faces all carry the same
 // coefficient re (rows a = c = -re, b = 1 + 2 re): pivot reciprocals,

@@ -269,8 +269,8 @@ bool needs_yz_sources(int scheme) { return scheme == NPB_LODIE1 || scheme == NPB
 
 Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params* p) {
   Layout L{};
-  const size_t n = (size_t)pitch_of(g->nx) * g->ny * g->nz;  // pitched node count
   const size_t es = p->precision == NPB_FP64 ? 8 : 4;
+  const size_t n = (size_t)pitch_of(g->nx, (int)es) * g->ny * g->nz;  // pitched node count
   const int na = mol->n_atoms;
   const int cap = 8 * na;
   const int nb = (cap + 255) / 256;
@@ -488,7 +488,7 @@ struct Solver {
   npb_status setup(const npb_molecule* mol) {
     const int na = mol->n_atoms;
     const int nx = g->nx, ny = g->ny, nz = g->nz;
-    const int nxp = pitch_of(nx);
+    const int nxp = pitch_of(nx, (int)sizeof(T));
     const size_t n = (size_t)nxp * ny * nz;
     sa = SetupArgs{nx, ny, nz, nxp, g->h, g->origin[0], g->origin[1], g->origin[2], na,
                    at<double>(L.atoms)};
@@ -560,7 +560,7 @@ struct Solver {
     a.nx = g->nx;
     a.ny = g->ny;
     a.nz = g->nz;
-    a.nxp = pitch_of(g->nx);
+    a.nxp = pitch_of(g->nx, (int)sizeof(T));
     for (int k = 0; k < 3; ++k) a.re[k] = c.re[k];
     a.re_uniform = c.re_uniform;
     a.ccls = c.vacuum ? nullptr : at<uint8_t>(L.ccls[d]);
@@ -619,7 +619,7 @@ struct Solver {
   // (a prefix of the run list) are swept by one launch per direction.
   npb_status time_loop() {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
-    const int nxp = pitch_of(nx);
+    const int nxp = pitch_of(nx, (int)sizeof(T));
     const size_t n = (size_t)nxp * ny * nz;
     for (int r = 0; r < L.n_runs; ++r) {
       const bool vac = L.runs[r].medium == 1;
@@ -702,8 +702,9 @@ struct Solver {
         const double beta = (l == 0) ? 0.0 : 1.0;
         const double gamma = p->richardson ? (l == 0 ? -kT : 2.0 * kT) : kT;
         s = timed(NPB_K_OTHER, 0, [&] {
-          return launch_field_out<T>(d_field_out, at<T>(L.field[r]), g->nx, pitch_of(g->nx),
-                                     g->ny, g->nz, beta, gamma, st);
+          return launch_field_out<T>(d_field_out, at<T>(L.field[r]), g->nx,
+                                     pitch_of(g->nx, (int)sizeof(T)), g->ny, g->nz, beta, gamma,
+                                     st);
         });
         if (s != NPB_OK) return s;
       }

@@ -29,6 +29,8 @@
 // registers or LDS, so they add no HBM traffic beyond the accumulator.
 //
 // T is the storage type of the field, A the arithmetic type of the solve.
+#include <algorithm>
+
 #include "npb_internal.h"
 
 namespace npb {
@@ -189,17 +191,25 @@ __device__ __forceinline__ void fast_finish(A (&d)[M], const A* ga, const A* al,
 // Reduced systems in LDS: entry (line l, row r, coefficient c) at
 // R[(4 r + c) * nl + l], so that the lanes of one wave (different lines)
 // touch consecutive words.  Thomas on the 2P rows of one line; the solution
-// overwrites the d coefficients.
+// overwrites the d coefficients.  The next row's coefficients are read
+// before the current row's results are stored, so that LDS latency overlaps
+// the arithmetic instead of adding up row after row.
 template <typename A>
 __device__ __forceinline__ void reduced_solve(A* R, int n2, int nl) {
   const A i0 = rcp_pivot(R[1 * nl]);
   A cp = R[2 * nl] * i0;
   A dp = R[3 * nl] * i0;
+  A an = R[4 * nl], bn = R[5 * nl], cn = R[6 * nl], dn = R[7 * nl];
   R[2 * nl] = cp;
   R[3 * nl] = dp;
   for (int r = 1; r < n2; ++r) {
-    const A ar = R[(4 * r + 0) * nl], br = R[(4 * r + 1) * nl];
-    const A cr = R[(4 * r + 2) * nl], dr = R[(4 * r + 3) * nl];
+    const A ar = an, br = bn, cr = cn, dr = dn;
+    if (r + 1 < n2) {
+      an = R[(4 * r + 4) * nl];
+      bn = R[(4 * r + 5) * nl];
+      cn = R[(4 * r + 6) * nl];
+      dn = R[(4 * r + 7) * nl];
+    }
     const A inv = rcp_pivot(fma(-ar, cp, br));
     cp = cr * inv;
     dp = fma(-ar, dp, dr) * inv;
@@ -207,8 +217,14 @@ __device__ __forceinline__ void reduced_solve(A* R, int n2, int nl) {
     R[(4 * r + 3) * nl] = dp;
   }
   A xn = dp;
+  A cq = R[(4 * (n2 - 2) + 2) * nl], dq = R[(4 * (n2 - 2) + 3) * nl];
   for (int r = n2 - 2; r >= 0; --r) {
-    xn = fma(-R[(4 * r + 2) * nl], xn, R[(4 * r + 3) * nl]);
+    const A cr = cq, dr = dq;
+    if (r > 0) {
+      cq = R[(4 * r - 2) * nl];
+      dq = R[(4 * r - 1) * nl];
+    }
+    xn = fma(-cr, xn, dr);
     R[(4 * r + 3) * nl] = xn;
   }
 }
@@ -258,10 +274,9 @@ __device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
 
 // ---------------------------------------------------------------------------
 // x sweep.  Block: L lines x P chunk slots (P a power of two), L*P threads;
-// lane t takes line t % L and chunk t / L.  Rows (pitch nxp, a multiple of
-// four) are moved between HBM and an odd-stride LDS tile with 16-byte
-// vector accesses; the row's boundary and padding columns are written back
-// unchanged.
+// lane t takes line t % L and chunk t / L.  The first row4(nx) elements of
+// each row move between HBM and an odd-stride LDS tile with 16-byte vector
+// accesses; the row's boundary columns are written back unchanged.
 template <typename T, typename A, int M>
 __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
@@ -287,15 +302,18 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   off = (off + 15) & ~size_t(15);
   A* red = reinterpret_cast<A*>(smem + off);
   off += sizeof(A) * (size_t)L * 2 * P * 4;
+  // the tile and the mask rows carry P*M+2 spare elements at their end:
+  // a chunk's reads may run past the last row (values selected away)
   A* tile = reinterpret_cast<A*>(smem + off);
-  off += sizeof(A) * (size_t)L * S;
+  off += sizeof(A) * ((size_t)L * S + P * M + 2);
   A* wtile = nullptr;
   if (aos) {
     wtile = reinterpret_cast<A*>(smem + off);
     off += sizeof(A) * (size_t)L * S;
   }
   off = (off + 15) & ~size_t(15);
-  uint8_t* mt = smem + off;  // L rows of nxp bytes
+  uint8_t* mt = smem + off;  // L rows of nx4 bytes
+  const int nx4 = row4(nx);
 
   if (tid < L) {
     long long l = l0 + tid;
@@ -312,11 +330,14 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   }
   __syncthreads();
 
-  // row loads: all vector loads of a thread in flight before its LDS stores
-  const int vpr = nxp / VX;  // vectors per row
+  // row loads: all vector loads of a thread in flight before its LDS
+  // stores; element e = (row q, vector c) advances by nthreads per step
+  const int vpr = nx4 / VX;  // vectors per row
   const int nvec = L * vpr;
+  const int dq = nthreads / vpr, dc = nthreads - dq * vpr;
   {
     constexpr int kU = 8;
+    int q0 = tid / vpr, c0 = tid - (tid / vpr) * vpr;
     for (int e0 = tid; e0 < nvec; e0 += kU * nthreads) {
       T v[kU][VX];
       uint32_t m[kU];
@@ -326,14 +347,19 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
         const int e = e0 + j * nthreads;
         q[j] = -1;
         if (e < nvec) {
-          const int qq = e / vpr;
-          const long long rb = rowbase[qq];
+          const long long rb = rowbase[q0];
           if (rb >= 0) {
-            q[j] = qq;
-            c[j] = (e - qq * vpr) * VX;
+            q[j] = q0;
+            c[j] = c0 * VX;
             VecIO<T, VX>::ld(a.u + rb + c[j], v[j]);
             if (!uniform) m[j] = ld_mask<VX>(a.mask + rb + c[j]);
           }
+        }
+        q0 += dq;
+        c0 += dc;
+        if (c0 >= vpr) {
+          c0 -= vpr;
+          ++q0;
         }
       }
 #pragma unroll
@@ -343,9 +369,9 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
           for (int i = 0; i < VX; ++i) tile[q[j] * S + c[j] + i] = (A)v[j][i];
           if (!uniform) {
             if constexpr (VX == 4)
-              *reinterpret_cast<uint32_t*>(mt + q[j] * nxp + c[j]) = m[j];
+              *reinterpret_cast<uint32_t*>(mt + q[j] * nx4 + c[j]) = m[j];
             else
-              *reinterpret_cast<uint16_t*>(mt + q[j] * nxp + c[j]) = (uint16_t)m[j];
+              *reinterpret_cast<uint16_t*>(mt + q[j] * nx4 + c[j]) = (uint16_t)m[j];
           }
         }
       }
@@ -358,13 +384,20 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   const int total = L * nx;
   if (aos || a.pre_nl) {
     const A pka = (A)a.pre_ka, pkb = (A)a.pre_kb, wka = (A)a.aos_ka, wkb = (A)a.aos_kb;
+    const int dq2 = nthreads / nx, dx2 = nthreads - dq2 * nx;
+    int q = tid / nx, x = tid - (tid / nx) * nx;
     for (int e = tid; e < total; e += nthreads) {
-      const int q = e / nx, x = e - q * nx;
       if (rowbase[q] >= 0 && x >= 1 && x <= nx - 2) {
         A v = tile[q * S + x];
-        bool solvent = !uniform && mt[q * nxp + x] == 0;
+        bool solvent = !uniform && mt[q * nx4 + x] == 0;
         if (aos) wtile[q * S + x] = (solvent && a.aos_w) ? sinh_flow(v, wka, wkb) : v;
         if (a.pre_nl && solvent) tile[q * S + x] = sinh_flow(v, pka, pkb);
+      }
+      q += dq2;
+      x += dx2;
+      if (x >= nx) {
+        x -= nx;
+        ++q;
       }
     }
     __syncthreads();
@@ -385,14 +418,15 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   const int ql = tid % L;
   const int p = tid / L;
   const bool lvalid = rowbase[ql] >= 0;
-  const A* trow = tile + ql * S;
-  const uint8_t* mrow = mt + ql * nxp;
   const int g0 = p * M;
+  A* trow = tile + ql * S;
+  A* col = trow + 1 + g0;  // row element of interior node g0 + k at col[k]
+  const uint8_t* mrow = mt + ql * nx4;
   A d[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    int g = g0 + k;
-    d[k] = (lvalid && g < nint) ? trow[1 + g] : A(0);
+    const A v = col[k];
+    d[k] = (lvalid && g0 + k < nint) ? v : A(0);
   }
   const A gL = trow[0];
   const A gR = trow[nx - 1];
@@ -418,11 +452,14 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
     const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
     const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
     A reF[M + 1];
+    int prev = uniform ? 1 : (int)mrow[g0];
 #pragma unroll
     for (int k = 0; k <= M; ++k) {
-      int xa = g0 + k;  // face between nodes xa and xa + 1
-      int c = (uniform || xa + 1 > nx - 1) ? 2 : (mrow[xa] + mrow[xa + 1]);
+      // face between nodes g0 + k and g0 + k + 1
+      const int cur = uniform ? 1 : (int)mrow[g0 + k + 1];
+      const int c = (g0 + k + 1 > nx - 1) ? 2 : prev + cur;
       reF[k] = pick3(c, re0, re1, re2);
+      prev = cur;
     }
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
@@ -438,29 +475,38 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
     fast_finish<A, M>(d, tb.ga[t], tb.al[t], xf, xl);
   else
     chunk_finish<A, M>(d, al, ga, xf, xl);
-  A* wrow = tile + ql * S;
+  // results back into the row; a full chunk stores without per-row checks
+  if (lvalid) {
+    if (g0 + M <= nint) {
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    int g = g0 + k;
-    if (lvalid && g < nint) {
-      A v = d[k];
-      if (aos) v = A(0.25) * (wtile[ql * S + 1 + g] + v);
-      wrow[1 + g] = v;
+      for (int k = 0; k < M; ++k) col[k] = aos ? A(0.25) * (wtile[ql * S + 1 + g0 + k] + d[k]) : d[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+        if (g0 + k < nint) col[k] = aos ? A(0.25) * (wtile[ql * S + 1 + g0 + k] + d[k]) : d[k];
     }
   }
   __syncthreads();
 
-  // row stores (boundary and padding columns carry their loaded values)
+  // row stores (boundary columns carry their loaded values)
   T* out = aos ? a.acc : a.u;
-  for (int e = tid; e < nvec; e += nthreads) {
-    const int q = e / vpr;
-    const long long rb = rowbase[q];
-    if (rb < 0) continue;
-    const int c = (e - q * vpr) * VX;
-    T v[VX];
+  {
+    int q = tid / vpr, c = tid - (tid / vpr) * vpr;
+    for (int e = tid; e < nvec; e += nthreads) {
+      const long long rb = rowbase[q];
+      if (rb >= 0) {
+        T v[VX];
 #pragma unroll
-    for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c + i];
-    VecIO<T, VX>::st(out + rb + c, v);
+        for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c * VX + i];
+        VecIO<T, VX>::st(out + rb + c * VX, v);
+      }
+      q += dq;
+      c += dc;
+      if (c >= vpr) {
+        c -= vpr;
+        ++q;
+      }
+    }
   }
 }
 
@@ -468,24 +514,29 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
 // y / z sweep.  Block: one tile of TW consecutive x (x = xb .. xb+TW-1) of
 // one plane of the other transverse index o, across the whole line length
 // n; TW*P threads.  The n node rows of the tile (TW*sizeof(T) contiguous
-// bytes each) move between HBM and an LDS tile [n][TS] with 16-byte vector
-// accesses; lane t then takes line xb + t % TW and chunk t / TW, as in the
-// x sweep.  Columns outside 1..nx-2 are loaded but never solved; they are
-// stored back with the values they came with (the AOS accumulator keeps
-// its own).  VAR selects the fused work at compile time:
+// bytes each, one or two cache lines) move between HBM and an LDS tile
+// [rows][TW+1] with 16-byte vector accesses; lane t then takes line
+// xb + t % TW and chunk t / TW, as in the x sweep.  The LDS tile has
+// a.S >= max(n, P*M+2) rows so that every chunk row and face a lane touches
+// lies inside it (rows past the line hold don't-care values that are
+// selected away).  Columns outside 1..nx-2 are loaded but never solved;
+// they are stored back with the values they came with (the AOS accumulator
+// keeps its own).  VAR selects the fused work at compile time:
 //   kYzPlain   : solve only, in place
 //   kYzFlow    : solve, then the exact sinh flow on solvent nodes, in place
 //   kYzGeneral : sources before/after, flow, AOS accumulation (run-time flags)
 enum { kYzPlain = 0, kYzFlow = 1, kYzGeneral = 2 };
 
-template <typename T, typename A, int M, int VAR>
+template <typename T, typename A, int M, int VAR, int TW>
 __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int dir) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
+  constexpr int TS = TW + 1;                // LDS elements per tile row
+  constexpr int VPR = TW / VX;              // vectors per full tile row
   extern __shared__ __align__(16) unsigned char smem[];
   const SweepArgs<T>& a = batch.f[blockIdx.y];
   const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
   const int nx = a.nx, ny = a.ny, nxp = a.nxp;
-  const int TW = a.LW, P = a.P, TS = a.S;
+  const int P = a.P, nrow = a.S;
   const int nthreads = TW * P;
   const int tid = threadIdx.x;
   const int n = (dir == 1) ? ny : a.nz;
@@ -503,45 +554,43 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
 
   A* red = reinterpret_cast<A*>(smem);
   A* tile = red + (size_t)TW * 2 * P * 4;
-  uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)n * TS);  // [n][TW]
+  uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)nrow * TS);  // [nrow][TW]
 
-  // node-row loads, every vector load of a thread in flight before its LDS
-  // stores; vectors past the row pitch are skipped
-  const int wrow = min(TW, nxp - xb);  // a multiple of 4
-  const int vpr = wrow / VX;
-  const int nvec = n * vpr;
-  {
+  // Node-row traffic: thread = (vector column cv, first row jr); rows step
+  // by RS = nthreads / VPR.  Columns past row4(nx) stay untouched.
+  const int cv = tid % VPR;
+  const int jr = tid / VPR;
+  const int RS = nthreads / VPR;
+  const bool cok = cv * VX < row4(nx) - xb;
+  const uint32_t rstep = (uint32_t)RS * stride;
+  if (cok) {
     constexpr int kU = 8;
-    for (int e0 = tid; e0 < nvec; e0 += kU * nthreads) {
+    uint32_t pt = base + (uint32_t)jr * stride + (uint32_t)(cv * VX);
+    for (int j0 = jr; j0 < n; j0 += kU * RS) {
       T v[kU][VX];
       uint32_t m[kU];
-      int j_[kU], c_[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int e = e0 + u * nthreads;
-        j_[u] = -1;
-        if (e < nvec) {
-          const int j = e / vpr;
-          j_[u] = j;
-          c_[u] = (e - j * vpr) * VX;
-          const uint32_t pt = base + (uint32_t)j * stride + (uint32_t)c_[u];
-          VecIO<T, VX>::ld(a.u + pt, v[u]);
-          if (!uniform) m[u] = ld_mask<VX>(a.mask + pt);
+        if (j0 + u * RS < n) {
+          VecIO<T, VX>::ld(a.u + pt + (uint32_t)u * rstep, v[u]);
+          if (!uniform) m[u] = ld_mask<VX>(a.mask + pt + (uint32_t)u * rstep);
         }
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        if (j_[u] >= 0) {
+        const int j = j0 + u * RS;
+        if (j < n) {
 #pragma unroll
-          for (int i = 0; i < VX; ++i) tile[j_[u] * TS + c_[u] + i] = (A)v[u][i];
+          for (int i = 0; i < VX; ++i) tile[j * TS + cv * VX + i] = (A)v[u][i];
           if (!uniform) {
             if constexpr (VX == 4)
-              *reinterpret_cast<uint32_t*>(mt + j_[u] * TW + c_[u]) = m[u];
+              *reinterpret_cast<uint32_t*>(mt + j * TW + cv * VX) = m[u];
             else
-              *reinterpret_cast<uint16_t*>(mt + j_[u] * TW + c_[u]) = (uint16_t)m[u];
+              *reinterpret_cast<uint16_t*>(mt + j * TW + cv * VX) = (uint16_t)m[u];
           }
         }
       }
+      pt += (uint32_t)kU * rstep;
     }
   }
   __syncthreads();
@@ -569,13 +618,15 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
     __syncthreads();
   }
 
-  // chunk elimination
+  // chunk elimination: the lane's column of the tile from row 1 + g0
   const int g0 = p * M;
+  A* col = tile + (1 + g0) * TS + ql;
+  const uint8_t* mcol = mt + g0 * TW + ql;  // flag of along node g0 + k at mcol[k * TW]
   A d[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    int g = g0 + k;
-    d[k] = (lvalid && g < nint) ? tile[(1 + g) * TS + ql] : A(0);
+    const A v = col[k * TS];
+    d[k] = (g0 + k < nint) ? v : A(0);
   }
   const A gL = tile[ql];
   const A gR = tile[(n - 1) * TS + ql];
@@ -606,11 +657,14 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
     const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
     const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
     A reF[M + 1];
+    int prev = uniform ? 1 : (int)mcol[0];
 #pragma unroll
     for (int k = 0; k <= M; ++k) {
-      const int ja = g0 + k;  // face between along nodes ja and ja + 1
-      const int c = (uniform || ja + 1 > n - 1) ? 2 : (mt[ja * TW + ql] + mt[(ja + 1) * TW + ql]);
+      // face between along nodes g0 + k and g0 + k + 1
+      const int cur = uniform ? 1 : (int)mcol[(k + 1) * TW];
+      const int c = (g0 + k + 1 > n - 1) ? 2 : prev + cur;
       reF[k] = pick3(c, re0, re1, re2);
+      prev = cur;
     }
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
@@ -636,16 +690,15 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const int g = g0 + k;
-        if (g < nint && mt[(1 + g) * TW + ql] == 0) d[k] = sinh_flow(d[k], ka, kb);
-      }
+      for (int k = 0; k < M; ++k)
+        if (mcol[(k + 1) * TW] == 0) d[k] = sinh_flow(d[k], ka, kb);
     }
   }
+  // rows past the line end land in rows n-1.. of the tile, which are
+  // neither stored nor read again
+  if (lvalid) {
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const int g = g0 + k;
-    if (lvalid && g < nint) tile[(1 + g) * TS + ql] = d[k];
+    for (int k = 0; k < M; ++k) col[k * TS] = d[k];
   }
   __syncthreads();
   if (VAR == kYzGeneral && a.src_stage == 2) {
@@ -656,30 +709,29 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
   // interior node rows back to HBM
   const int mode = (VAR == kYzGeneral) ? a.mode : MODE_INPLACE;
   T* out = (mode == MODE_AOS_ADD) ? a.acc : a.u;
-  const int nvi = nint * vpr;
-  for (int e = tid; e < nvi; e += nthreads) {
-    const int j = 1 + e / vpr;
-    const int c = (e - (j - 1) * vpr) * VX;
-    const uint32_t pt = base + (uint32_t)j * stride + (uint32_t)c;
-    T w[VX];
-    if (mode == MODE_AOS_ADD || mode == MODE_AOS_FINISH) {
-      T acc[VX];
-      VecIO<T, VX>::ld(a.acc + pt, acc);
+  if (cok) {
+    uint32_t pt = base + (uint32_t)(1 + jr) * stride + (uint32_t)(cv * VX);
+    for (int j = 1 + jr; j <= nint; j += RS, pt += rstep) {
+      T w[VX];
+      if (mode == MODE_AOS_ADD || mode == MODE_AOS_FINISH) {
+        T acc[VX];
+        VecIO<T, VX>::ld(a.acc + pt, acc);
 #pragma unroll
-      for (int i = 0; i < VX; ++i) {
-        const int xi = xb + c + i;
-        const A tv = tile[j * TS + c + i];
-        const bool live = xi >= 1 && xi <= nx - 2;
-        if (live)
-          w[i] = (T)((A)acc[i] + A(0.25) * tv);
-        else
-          w[i] = (mode == MODE_AOS_ADD) ? acc[i] : (T)tv;
+        for (int i = 0; i < VX; ++i) {
+          const int xi = xb + cv * VX + i;
+          const A tv = tile[j * TS + cv * VX + i];
+          const bool live = xi >= 1 && xi <= nx - 2;
+          if (live)
+            w[i] = (T)((A)acc[i] + A(0.25) * tv);
+          else
+            w[i] = (mode == MODE_AOS_ADD) ? acc[i] : (T)tv;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < VX; ++i) w[i] = (T)tile[j * TS + cv * VX + i];
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < VX; ++i) w[i] = (T)tile[j * TS + c + i];
+      VecIO<T, VX>::st(out + pt, w);
     }
-    VecIO<T, VX>::st(out + pt, w);
   }
 }
 
@@ -702,19 +754,20 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
   LaunchShape s{};
   const int nint = nx - 2;
   const int es = fp64 ? 8 : 4;
-  const int nxp = pitch_of(nx);
+  const int nx4 = row4(nx);
   int P = next_pow2((nint + 19) / 20);
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0 || P > 64) return s;  // unsupported length
-  const int S = nxp + 1;
+  const int S = nx4 + 1;
   int L = 256 / P;
   auto lds = [&](int Lc) {
     size_t off = (sizeof(long long) + sizeof(int)) * (size_t)Lc;
     off = (off + 15) & ~size_t(15);
     off += (size_t)es * Lc * 2 * P * 4;
-    off += (size_t)es * Lc * S * (aos ? 2 : 1);
+    off += (size_t)es * ((size_t)Lc * S + P * M + 2);
+    if (aos) off += (size_t)es * Lc * S;
     off = (off + 15) & ~size_t(15);
-    if (!uniform) off += (size_t)Lc * nxp;
+    if (!uniform) off += (size_t)Lc * nx4 + P * M + 2;
     return off;
   };
   while (L > 1 && lds(L) > 60 * 1024 && L * P > 64) L >>= 1;
@@ -738,21 +791,16 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64) {
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0) return s;
   P = (nint + M - 1) / M;
+  const int nrow = std::max(n_along, P * M + 2);  // LDS tile rows
   auto lds = [&](int tw) {
-    return (size_t)es * tw * 2 * P * 4 + (size_t)es * n_along * (tw + 1) + (size_t)n_along * tw;
+    return (size_t)es * tw * 2 * P * 4 + (size_t)es * nrow * (tw + 1) + (size_t)nrow * tw;
   };
-  // Tile width: FP32 arithmetic takes the widest tile (longest contiguous
-  // node-row pieces, 256 B at 64 x) that fits 512 threads and 80 KB of LDS;
-  // FP64 arithmetic is bound by its arithmetic and runs best on narrow
-  // tiles (more, smaller blocks).
+  // Tile width (measured on 161^3 batches): FP32 arithmetic runs best with
+  // 32 x per tile (one 128-byte line per node row) when that fits 512
+  // threads and 80 KB of LDS; FP64 arithmetic is bound by its arithmetic
+  // and runs best on 16-wide tiles (more, smaller blocks).
   int TW = 16;
-  if (!fp64) {
-    for (int tw : {64, 32})
-      if (tw * P <= 512 && lds(tw) <= 80 * 1024) {
-        TW = tw;
-        break;
-      }
-  }
+  if (!fp64 && 32 * P <= 512 && lds(32) <= 80 * 1024) TW = 32;
   if (lds(TW) > 160 * 1024) return s;
   const int ntx = (nx - 2) / TW + 1;
   s.M = M;
@@ -821,7 +869,7 @@ static SweepBatch<T> shaped(const SweepBatch<T>& b0, int nf, const LaunchShape& 
 template <typename T, typename A>
 hipError_t launch_sweep_x(const SweepBatch<T>& b0, int nf, const LaunchShape& s, hipStream_t st) {
   if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
-  const SweepBatch<T> b = shaped(b0, nf, s, b0.f[0].nxp + 1);
+  const SweepBatch<T> b = shaped(b0, nf, s, row4(b0.f[0].nx) + 1);
   dim3 g(s.blocks, nf), blk(s.threads);
   switch (s.M) {
 #define NPB_X_CASE(MM) \
@@ -839,14 +887,14 @@ hipError_t launch_sweep_x(const SweepBatch<T>& b0, int nf, const LaunchShape& s,
   return hipGetLastError();
 }
 
-template <typename T, typename A, int VAR>
-static hipError_t launch_yz_var(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
-                                hipStream_t st) {
+template <typename T, typename A, int VAR, int TW>
+static hipError_t launch_yz_tw(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
+                               hipStream_t st) {
   dim3 g(s.blocks, nf), blk(s.threads);
   switch (s.M) {
 #define NPB_YZ_CASE(MM) \
   case MM:              \
-    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR>), g, blk, s.lds, st, b, dir); break;
+    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, b, dir); break;
     NPB_YZ_CASE(4)
     NPB_YZ_CASE(8)
     NPB_YZ_CASE(12)
@@ -855,7 +903,7 @@ static hipError_t launch_yz_var(const SweepBatch<T>& b, int nf, int dir, const L
     case 20:
       // planned only for FP32 arithmetic (FP64 chunks stop at 16 rows)
       if constexpr (sizeof(A) == 4) {
-        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR>), g, blk, s.lds, st, b, dir);
+        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, b, dir);
         break;
       }
       return hipErrorInvalidValue;
@@ -865,13 +913,25 @@ static hipError_t launch_yz_var(const SweepBatch<T>& b, int nf, int dir, const L
   return hipGetLastError();
 }
 
+// tile widths compiled: 16 and 32 for FP32 arithmetic, 16 for FP64
+template <typename T, typename A, int VAR>
+static hipError_t launch_yz_var(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
+                                hipStream_t st) {
+  if (s.LW == 16) return launch_yz_tw<T, A, VAR, 16>(b, nf, dir, s, st);
+  if constexpr (sizeof(A) == 4) {
+    if (s.LW == 32) return launch_yz_tw<T, A, VAR, 32>(b, nf, dir, s, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 // The fused-work variant covers every field of the batch; the flow and
 // source branches are uniform per block.
 template <typename T, typename A>
 hipError_t launch_sweep_yz(const SweepBatch<T>& b0, int nf, int dir, const LaunchShape& s,
                            hipStream_t st) {
   if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
-  const SweepBatch<T> b = shaped(b0, nf, s, s.LW + 1);
+  const int n_along = dir == 1 ? b0.f[0].ny : b0.f[0].nz;
+  const SweepBatch<T> b = shaped(b0, nf, s, std::max(n_along, s.P * s.M + 2));
   bool general = false, flow = false;
   for (int f = 0; f < nf; ++f) {
     general = general || b.f[f].src_stage != 0 || b.f[f].mode != MODE_INPLACE;
