@@ -265,7 +265,11 @@ constexpr size_t kTabBytes = sizeof(ChunkTab<double>);
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-bool needs_yz_sources(int scheme) { return scheme == NPB_LODIE1 || scheme == NPB_AOSIE2; }
+// Per-line source lists each scheme's y and z sweeps use: AOSIE2 adds
+// sources in both, LODIE1 after the z solve (LODIE2 and AOSIE1 add theirs
+// in the x sweep).
+bool needs_y_sources(int scheme) { return scheme == NPB_AOSIE2; }
+bool needs_z_sources(int scheme) { return scheme == NPB_AOSIE2 || scheme == NPB_LODIE1; }
 
 Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params* p) {
   Layout L{};
@@ -276,7 +280,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   const int nb = (cap + 255) / 256;
   const size_t ns = (size_t)shell_count(g->nx, g->ny, g->nz);
   const bool aos = p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2;
-  const bool yz = needs_yz_sources(p->scheme);
+  const bool ys = needs_y_sources(p->scheme), zs = needs_z_sources(p->scheme);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -304,12 +308,12 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   L.q_val = take((size_t)cap * 8);
   L.q_rho = take((size_t)cap * 8);
   L.xptr = take(((size_t)g->ny * g->nz + 1) * 4);
-  L.yptr = take(yz ? ((size_t)g->nz * g->nx + 1) * 4 : 0);
-  L.ylin = take(yz ? (size_t)cap * 4 : 0);
-  L.yrho = take(yz ? (size_t)cap * 8 : 0);
-  L.zptr = take(yz ? ((size_t)g->ny * g->nx + 1) * 4 : 0);
-  L.zlin = take(yz ? (size_t)cap * 4 : 0);
-  L.zrho = take(yz ? (size_t)cap * 8 : 0);
+  L.yptr = take(ys ? ((size_t)g->nz * g->nx + 1) * 4 : 0);
+  L.ylin = take(ys ? (size_t)cap * 4 : 0);
+  L.yrho = take(ys ? (size_t)cap * 8 : 0);
+  L.zptr = take(zs ? ((size_t)g->ny * g->nx + 1) * 4 : 0);
+  L.zlin = take(zs ? (size_t)cap * 4 : 0);
+  L.zrho = take(zs ? (size_t)cap * 8 : 0);
   {
     const bool f64a = p->precision != NPB_FP32;
     L.shape[0] = plan_x(g->nx, g->ny, g->nz, f64a, aos, false);
@@ -512,8 +516,8 @@ struct Solver {
       if (e != hipSuccess) return e;
       e = launch_line_ptr(at<int>(L.q_idx), ints, L.cap, ny * nz, nxp, at<int>(L.xptr), st);
       if (e != hipSuccess) return e;
-      if (needs_yz_sources(p->scheme) && L.cap > 0) {
-        for (int axis = 1; axis <= 2; ++axis) {
+      if (needs_z_sources(p->scheme) && L.cap > 0) {
+        for (int axis = needs_y_sources(p->scheme) ? 1 : 2; axis <= 2; ++axis) {
           e = launch_axis_keys(at<int>(L.q_idx), ints, L.cap, nx, nxp, ny, nz, axis,
                                at<int>(L.key_a), at<int>(L.id_a), st);
           if (e != hipSuccess) return e;
@@ -532,8 +536,10 @@ struct Solver {
             e = launch_line_ptr(at<int>(L.key_a), ints, L.cap, ny * nx, nz, at<int>(L.zptr), st);
           if (e != hipSuccess) return e;
         }
-      } else if (needs_yz_sources(p->scheme)) {
-        e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.yptr), (size_t)nz * nx + 1, 0u, st);
+      } else if (needs_z_sources(p->scheme)) {
+        if (needs_y_sources(p->scheme))
+          e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.yptr), (size_t)nz * nx + 1, 0u,
+                              st);
         if (e != hipSuccess) return e;
         e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.zptr), (size_t)ny * nx + 1, 0u, st);
         if (e != hipSuccess) return e;

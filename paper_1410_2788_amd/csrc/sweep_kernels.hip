@@ -277,7 +277,7 @@ __device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
 // lane t takes line t % L and chunk t / L.  The first row4(nx) elements of
 // each row move between HBM and an odd-stride LDS tile with 16-byte vector
 // accesses; the row's boundary columns are written back unchanged.
-template <typename T, typename A, int M>
+template <typename T, typename A, int M, int L>
 __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   extern __shared__ __align__(16) unsigned char smem[];
@@ -285,21 +285,26 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
   const int nx = a.nx, ny = a.ny, nz = a.nz, nxp = a.nxp;
   const int nint = nx - 2;
-  const int P = a.P, L = a.LW, S = a.S;
+  const int P = a.P, S = a.S;
   const int nthreads = L * P;
   const int nyi = ny - 2;
-  const long long nlines = (long long)nyi * (nz - 2);
-  const long long l0 = (long long)blockIdx.x * L;
+  const int nlines = nyi * (nz - 2);
+  const int l0 = blockIdx.x * L;
   const bool uniform = (a.mask == nullptr);
   const bool aos = (a.mode == MODE_AOS_FIRST);
   const int tid = threadIdx.x;
+  // element offset of node 0 of block row q (line l0 + q), -1 past the last
+  // line; offsets fit in 32 bits (n <= 514)
+  auto row_base = [&](int q) -> int {
+    const int l = l0 + q;
+    if (q >= L || l >= nlines) return -1;
+    const int zi = l / nyi;
+    return ((1 + zi) * ny + 1 + (l - zi * nyi)) * nxp;
+  };
 
   size_t off = 0;
-  long long* rowbase = reinterpret_cast<long long*>(smem + off);
-  off += sizeof(long long) * L;
-  int* line2d = reinterpret_cast<int*>(smem + off);
-  off += sizeof(int) * L;
-  off = (off + 15) & ~size_t(15);
+  int* srng = reinterpret_cast<int*>(smem + off);  // source entry range of the block
+  off += 16;
   A* red = reinterpret_cast<A*>(smem + off);
   off += sizeof(A) * (size_t)L * 2 * P * 4;
   // the tile and the mask rows carry P*M+2 spare elements at their end:
@@ -315,63 +320,60 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   uint8_t* mt = smem + off;  // L rows of nx4 bytes
   const int nx4 = row4(nx);
 
-  if (tid < L) {
-    long long l = l0 + tid;
-    long long rb = -1;
-    int l2 = 0;
-    if (l < nlines) {
-      int y = 1 + (int)(l % nyi);
-      int z = 1 + (int)(l / nyi);
-      rb = ((long long)z * ny + y) * nxp;
-      l2 = z * ny + y;
-    }
-    rowbase[tid] = rb;
-    line2d[tid] = l2;
+  // The block's lines are consecutive rows of the per-row source lists:
+  // one contiguous entry range, whose bounds are requested before the rows.
+  const bool src = a.src_stage == 1;
+  if (src && tid == 0) {
+    srng[0] = a.src_ptr[row_base(0) / nxp];
+    srng[1] = a.src_ptr[row_base(min(L, nlines - l0) - 1) / nxp + 1];
   }
-  __syncthreads();
 
-  // row loads: all vector loads of a thread in flight before its LDS
-  // stores; element e = (row q, vector c) advances by nthreads per step
-  const int vpr = nx4 / VX;  // vectors per row
-  const int nvec = L * vpr;
-  const int dq = nthreads / vpr, dc = nthreads - dq * vpr;
+  // Row loads.  Lane t of the block takes vector column cv = t % 16 of rows
+  // t / 16, t / 16 + RQ, ... and column groups cv, cv + 16, ...: a wave
+  // moves 4 rows x 16 vectors per instruction, and with the odd LDS row
+  // stride S those four rows' element writes fall in distinct banks.  All
+  // vector loads of a batch are in flight before its LDS stores.
+  const int vpr = nx4 / VX;          // vectors per row
+  const int ncg = (vpr + 15) >> 4;   // 16-vector column groups per row
+  const int cv = tid & 15;
+  const int RQ = nthreads >> 4;      // rows per pass
+  const int rq = tid >> 4;
+  const int nsteps = rq < L ? ((L - rq + RQ - 1) / RQ) * ncg : 0;
   {
     constexpr int kU = 8;
-    int q0 = tid / vpr, c0 = tid - (tid / vpr) * vpr;
-    for (int e0 = tid; e0 < nvec; e0 += kU * nthreads) {
+    int q = rq, g = 0, rb = row_base(rq);
+    for (int s0 = 0; s0 < nsteps; s0 += kU) {
       T v[kU][VX];
       uint32_t m[kU];
-      int q[kU], c[kU];
+      int lo[kU], mo[kU];
 #pragma unroll
       for (int j = 0; j < kU; ++j) {
-        const int e = e0 + j * nthreads;
-        q[j] = -1;
-        if (e < nvec) {
-          const long long rb = rowbase[q0];
-          if (rb >= 0) {
-            q[j] = q0;
-            c[j] = c0 * VX;
-            VecIO<T, VX>::ld(a.u + rb + c[j], v[j]);
-            if (!uniform) m[j] = ld_mask<VX>(a.mask + rb + c[j]);
+        lo[j] = -1;
+        if (s0 + j < nsteps) {
+          const int c = (cv + 16 * g) * VX;
+          if (c < nx4 && rb >= 0) {
+            lo[j] = q * S + c;
+            mo[j] = q * nx4 + c;
+            VecIO<T, VX>::ld(a.u + rb + c, v[j]);
+            if (!uniform) m[j] = ld_mask<VX>(a.mask + rb + c);
           }
         }
-        q0 += dq;
-        c0 += dc;
-        if (c0 >= vpr) {
-          c0 -= vpr;
-          ++q0;
+        if (++g == ncg) {
+          g = 0;
+          q += RQ;
+          rb = row_base(q);
         }
       }
 #pragma unroll
       for (int j = 0; j < kU; ++j) {
-        if (q[j] >= 0) {
+        if (lo[j] >= 0) {
 #pragma unroll
-          for (int i = 0; i < VX; ++i) tile[q[j] * S + c[j] + i] = (A)v[j][i];
+          for (int i = 0; i < VX; ++i) tile[lo[j] + i] = (A)v[j][i];
           if (!uniform) {
             if constexpr (VX == 4)
-              *reinterpret_cast<uint32_t*>(mt + q[j] * nx4 + c[j]) = m[j];
+              *reinterpret_cast<uint32_t*>(mt + mo[j]) = m[j];
             else
-              *reinterpret_cast<uint16_t*>(mt + q[j] * nx4 + c[j]) = (uint16_t)m[j];
+              *reinterpret_cast<uint16_t*>(mt + mo[j]) = (uint16_t)m[j];
           }
         }
       }
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
     const int dq2 = nthreads / nx, dx2 = nthreads - dq2 * nx;
     int q = tid / nx, x = tid - (tid / nx) * nx;
     for (int e = tid; e < total; e += nthreads) {
-      if (rowbase[q] >= 0 && x >= 1 && x <= nx - 2) {
+      if (l0 + q < nlines && x >= 1 && x <= nx - 2) {
         A v = tile[q * S + x];
         bool solvent = !uniform && mt[q * nx4 + x] == 0;
         if (aos) wtile[q * S + x] = (solvent && a.aos_w) ? sinh_flow(v, wka, wkb) : v;
@@ -402,22 +404,21 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
     }
     __syncthreads();
   }
-  if (a.src_stage == 1) {
-    for (int q = tid; q < L; q += nthreads) {
-      if (rowbase[q] < 0) continue;
-      int b = a.src_ptr[line2d[q]], e = a.src_ptr[line2d[q] + 1];
-      for (int k = b; k < e; ++k) {
-        int xi = (int)(a.src_lin[k] - rowbase[q]);
-        tile[q * S + xi] += (A)(a.src_coef * a.src_rho[k]);
-      }
-    }
+  if (src) {
+    // one entry per thread; entries are distinct nodes
+    auto add_entry = [&](int lin, double rho) {
+      const int row = lin / nxp;
+      const int q = (row / ny - 1) * nyi + (row % ny - 1) - l0;
+      tile[q * S + (lin - row * nxp)] += (A)(a.src_coef * rho);
+    };
+    for (int e = srng[0] + tid; e < srng[1]; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
     __syncthreads();
   }
 
   // chunk elimination
   const int ql = tid % L;
   const int p = tid / L;
-  const bool lvalid = rowbase[ql] >= 0;
+  const bool lvalid = l0 + ql < nlines;
   const int g0 = p * M;
   A* trow = tile + ql * S;
   A* col = trow + 1 + g0;  // row element of interior node g0 + k at col[k]
@@ -488,23 +489,18 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   }
   __syncthreads();
 
-  // row stores (boundary columns carry their loaded values)
+  // row stores (boundary columns carry their loaded values), same lane map
   T* out = aos ? a.acc : a.u;
-  {
-    int q = tid / vpr, c = tid - (tid / vpr) * vpr;
-    for (int e = tid; e < nvec; e += nthreads) {
-      const long long rb = rowbase[q];
-      if (rb >= 0) {
+  for (int q = rq; q < L; q += RQ) {
+    const int rb = row_base(q);
+    if (rb < 0) break;
+    for (int g = 0; g < ncg; ++g) {
+      const int c = (cv + 16 * g) * VX;
+      if (c < nx4) {
         T v[VX];
 #pragma unroll
-        for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c * VX + i];
-        VecIO<T, VX>::st(out + rb + c * VX, v);
-      }
-      q += dq;
-      c += dc;
-      if (c >= vpr) {
-        c -= vpr;
-        ++q;
+        for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c + i];
+        VecIO<T, VX>::st(out + rb + c, v);
       }
     }
   }
@@ -555,6 +551,16 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
   A* red = reinterpret_cast<A*>(smem);
   A* tile = red + (size_t)TW * 2 * P * 4;
   uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)nrow * TS);  // [nrow][TW]
+  int* srng = reinterpret_cast<int*>(mt + (size_t)nrow * TW);          // source entry range
+
+  // Trilinear sources of the tile's lines form one contiguous range of the
+  // per-line lists; its bounds are requested before the node rows.
+  const bool src = VAR == kYzGeneral && a.src_stage != 0;
+  if (src && tid == 0) {
+    const int xlo = max(xb, 1), xhi = min(xb + TW - 1, nx - 2);
+    srng[0] = a.src_ptr[o * nx + xlo];
+    srng[1] = a.src_ptr[o * nx + xhi + 1];
+  }
 
   // Node-row traffic: thread = (vector column cv, first row jr); rows step
   // by RS = nthreads / VPR.  Columns past row4(nx) stay untouched.
@@ -600,18 +606,28 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
   const int x = xb + ql;
   const bool lvalid = x >= 1 && x <= nx - 2;
 
-  // trilinear source entries of this tile's lines (one thread per line)
-  auto add_sources = [&]() {
-    for (int q = tid; q < TW; q += nthreads) {
-      const int xq = xb + q;
-      if (xq < 1 || xq > nx - 2) continue;
-      const int l2 = o * nx + xq;
-      const int sb = a.src_ptr[l2], se = a.src_ptr[l2 + 1];
-      for (int e = sb; e < se; ++e) {
-        const int jj = (int)(((uint32_t)a.src_lin[e] - plane - (uint32_t)xq) / stride);
-        tile[jj * TS + q] += (A)(a.src_coef * a.src_rho[e]);
-      }
+  // source entries: one per thread, requested now and added when needed
+  // (before the solve for stage 1, after it for stage 2); entries are
+  // distinct nodes, so the adds do not collide
+  int sb = 0, se = 0, e_lin = -1;
+  double e_rho = 0.0;
+  if (src) {
+    sb = srng[0];
+    se = srng[1];
+    if (sb + tid < se) {
+      e_lin = a.src_lin[sb + tid];
+      e_rho = a.src_rho[sb + tid];
     }
+  }
+  auto add_entry = [&](int lin, double rho) {
+    const uint32_t off = (uint32_t)lin - plane;
+    const uint32_t jj = off / stride;
+    const int q = (int)(off - jj * stride) - xb;
+    tile[jj * TS + q] += (A)(a.src_coef * rho);
+  };
+  auto add_sources = [&]() {
+    if (e_lin >= 0) add_entry(e_lin, e_rho);
+    for (int e = sb + tid + nthreads; e < se; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
   };
   if (VAR == kYzGeneral && a.src_stage == 1) {
     add_sources();
@@ -757,12 +773,11 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
   const int nx4 = row4(nx);
   int P = next_pow2((nint + 19) / 20);
   int M = pick_chunk((nint + P - 1) / P);
-  if (M < 0 || P > 64) return s;  // unsupported length
+  if (M < 0 || P > 32) return s;  // unsupported length
   const int S = nx4 + 1;
-  int L = 256 / P;
+  int L = std::min(32, 256 / P);  // compiled: 32, 16, 8
   auto lds = [&](int Lc) {
-    size_t off = (sizeof(long long) + sizeof(int)) * (size_t)Lc;
-    off = (off + 15) & ~size_t(15);
+    size_t off = 16;
     off += (size_t)es * Lc * 2 * P * 4;
     off += (size_t)es * ((size_t)Lc * S + P * M + 2);
     if (aos) off += (size_t)es * Lc * S;
@@ -770,7 +785,8 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
     if (!uniform) off += (size_t)Lc * nx4 + P * M + 2;
     return off;
   };
-  while (L > 1 && lds(L) > 60 * 1024 && L * P > 64) L >>= 1;
+  while (L > 8 && lds(L) > 60 * 1024 && L * P > 64) L >>= 1;
+  if (lds(L) > 160 * 1024) return LaunchShape{};
   s.M = M;
   s.P = P;
   s.LW = L;
@@ -793,7 +809,7 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64) {
   P = (nint + M - 1) / M;
   const int nrow = std::max(n_along, P * M + 2);  // LDS tile rows
   auto lds = [&](int tw) {
-    return (size_t)es * tw * 2 * P * 4 + (size_t)es * nrow * (tw + 1) + (size_t)nrow * tw;
+    return (size_t)es * tw * 2 * P * 4 + (size_t)es * nrow * (tw + 1) + (size_t)nrow * tw + 16;
   };
   // Tile width (measured on 161^3 batches): FP32 arithmetic runs best with
   // 32 x per tile (one 128-byte line per node row) when that fits 512
@@ -866,15 +882,13 @@ static SweepBatch<T> shaped(const SweepBatch<T>& b0, int nf, const LaunchShape& 
   return b;
 }
 
-template <typename T, typename A>
-hipError_t launch_sweep_x(const SweepBatch<T>& b0, int nf, const LaunchShape& s, hipStream_t st) {
-  if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
-  const SweepBatch<T> b = shaped(b0, nf, s, row4(b0.f[0].nx) + 1);
+template <typename T, typename A, int L>
+static hipError_t launch_x_l(const SweepBatch<T>& b, int nf, const LaunchShape& s, hipStream_t st) {
   dim3 g(s.blocks, nf), blk(s.threads);
   switch (s.M) {
 #define NPB_X_CASE(MM) \
   case MM:             \
-    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM>), g, blk, s.lds, st, b); break;
+    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, b); break;
     NPB_X_CASE(4)
     NPB_X_CASE(8)
     NPB_X_CASE(12)
@@ -885,6 +899,16 @@ hipError_t launch_sweep_x(const SweepBatch<T>& b0, int nf, const LaunchShape& s,
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, typename A>
+hipError_t launch_sweep_x(const SweepBatch<T>& b0, int nf, const LaunchShape& s, hipStream_t st) {
+  if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
+  const SweepBatch<T> b = shaped(b0, nf, s, row4(b0.f[0].nx) + 1);
+  if (s.LW == 32) return launch_x_l<T, A, 32>(b, nf, s, st);
+  if (s.LW == 16) return launch_x_l<T, A, 16>(b, nf, s, st);
+  if (s.LW == 8) return launch_x_l<T, A, 8>(b, nf, s, st);
+  return hipErrorInvalidValue;
 }
 
 template <typename T, typename A, int VAR, int TW>
