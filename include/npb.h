@@ -204,6 +204,23 @@ npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid
                      const npb_params* params, void* d_ws, size_t ws_bytes,
                      double* d_field_out, void* stream, npb_result* out);
 
+/* Solve n independent problems together (molecules, grids and parameters
+ * may all differ; one precision per batch).  Same semantics per problem as
+ * npb_solve: problem i uses workspace d_ws[i] (ws_bytes[i] bytes, at least
+ * npb_workspace_bytes of that problem, 256-byte aligned, no two problems
+ * sharing one) and writes its field to d_field_out[i] when d_field_out is
+ * not NULL and that entry is not NULL.  Every run of every problem advances
+ * in the same launches: one per sweep direction and launch shape per step,
+ * so uneven grids share launches; the device work is captured as one graph
+ * (see npb_ctx_set_graph).  Results for all n problems go to out[0..n-1].
+ * Errors: EINVAL or ERANGE name the first offending problem ("problem i:
+ * ...") before any device work; EDEVICE; EDIVERGED or ERANGE after the
+ * solves name the first problem concerned (every out[i] is still written). */
+npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols,
+                           const npb_grid* grids, const npb_params* params,
+                           void* const* d_ws, const size_t* ws_bytes,
+                           double* const* d_field_out, void* stream, npb_result* out);
+
 #ifdef __cplusplus
 }
 #endif

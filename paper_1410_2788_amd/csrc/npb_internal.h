@@ -48,14 +48,14 @@ struct SweepArgs {
 
 enum SweepMode { MODE_INPLACE = 0, MODE_AOS_FIRST = 1, MODE_AOS_ADD = 2, MODE_AOS_FINISH = 3 };
 
-// Independent fields of one grid shape swept by one launch (block row
-// blockIdx.y = field): the solvated and vacuum runs at both step sizes of a
-// solve advance together.
+// Runs (fields) of one problem: solvated and vacuum at dt and dt/2.
 constexpr int kMaxFields = 4;
-template <typename T>
-struct SweepBatch {
-  SweepArgs<T> f[kMaxFields];
-};
+
+// y/z sweep variants (fused pointwise work compiled in):
+//   kYzPlain   : solve only, in place
+//   kYzFlow    : solve, then the exact sinh flow on solvent nodes
+//   kYzGeneral : sources before/after, flow, AOS accumulation (run-time flags)
+enum { kYzPlain = 0, kYzFlow = 1, kYzGeneral = 2 };
 
 // Chunk lengths compiled into the sweep kernels (the planners keep the
 // chunk within 20 rows, where a lane's chunk still fits its registers).
@@ -110,13 +110,21 @@ inline long long class_lines(int nx, int ny, int nz, int dir) {
 template <typename A>
 void fill_chunk_tab(ChunkTab<A>& tb, double re_solvent, double re_solute, int M);
 
-// T = storage type of the field, A = arithmetic type of the line solves;
-// fields 0..nf-1 of the batch share the grid shape and the launch shape
+// A sweep launch covers any set of fields (of any grids) that share a
+// launch shape: args is a device array of per-field arguments, already
+// shaped (shape_args), and work[b] = (field, block of that field) for each
+// of the nblocks blocks.  T = storage type of the field, A = arithmetic
+// type of the line solves.
+template <typename T>
+void shape_args(SweepArgs<T>& a, int dir, const LaunchShape& s);
+template <typename T>
+int sweep_variant(const SweepArgs<T>* a, int n);  // kYz* covering every field
 template <typename T, typename A>
-hipError_t launch_sweep_x(const SweepBatch<T>& b, int nf, const LaunchShape& s, hipStream_t st);
+hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nblocks,
+                          const LaunchShape& s, hipStream_t st);
 template <typename T, typename A>
-hipError_t launch_sweep_yz(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
-                           hipStream_t st);
+hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
+                           int var, const LaunchShape& s, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // setup

@@ -2,6 +2,7 @@
 // the sequence of device launches of one solve.  Also the small field and
 // energy kernels (field initialisation, FP64 energy gathers, the
 // solvated-minus-vacuum and Richardson combinations).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -177,11 +178,11 @@ template hipError_t launch_field_init<double>(double*, const double*, int, int, 
 // ---------------------------------------------------------------------------
 // context
 
-// Everything a captured solve graph depends on besides the staged bytes.
+// Everything a captured solve graph depends on besides the staged bytes,
+// per problem of the batch.
 struct GraphKey {
   void* ws;
   double* field_out;
-  void* pinned;
   npb_grid grid;
   npb_params params;
   int n_atoms;
@@ -193,7 +194,11 @@ struct npb_ctx {
   bool graphs = true;
   hipStream_t capture = nullptr;  // stream the solve graph is captured on
   hipGraphExec_t exec = nullptr;
-  GraphKey key{};
+  std::vector<unsigned char> key;  // GraphKey per problem + the launch-table buffer
+  // device buffer of the launch tables (per-field sweep arguments, work
+  // lists), owned by the context and grown on demand
+  void* meta = nullptr;
+  size_t meta_bytes = 0;
   npb_kernel_times times{};
   struct Pending {
     int cls;
@@ -383,21 +388,79 @@ void flow_params(double theta, double& ka, double& kb) {
   kb = -std::expm1(-2.0 * theta);
 }
 
-template <typename T, typename A>
-struct Solver {
-  npb_ctx* ctx;
+// One problem of a batch: its arguments, workspace and layout.
+struct Problem {
+  const npb_molecule* mol;
   const npb_grid* g;
   const npb_params* p;
-  hipStream_t st;
   unsigned char* ws;
+  double* fout;
   Layout L;
   SetupArgs sa;
   double kT, lB;
+  size_t tabs_pinned, atoms_pinned;  // offsets of its staged bytes in the pinned buffer
 
   template <typename Ptr>
-  Ptr* at(size_t off) {
+  Ptr* at(size_t off) const {
     return reinterpret_cast<Ptr*>(ws + off);
   }
+  bool aos() const { return p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2; }
+};
+
+// coefficients of one run (Sec. 3: tau = dt / alpha; AOS sub-steps take
+// 4 tau; faces carry harmonic means of the nodal permittivities)
+struct Coefs {
+  double tau, re[3], re_uniform, t, omt, t4, omt4;
+  bool nl, vacuum;
+};
+
+Coefs run_coefs(const Problem& P, const Run& r) {
+  const npb_params* p = P.p;
+  Coefs c{};
+  const double dt = p->dt / double(1 << r.level);
+  c.vacuum = r.medium == 1;
+  c.tau = dt / p->alpha;
+  const double rc = (P.aos() ? 4.0 * c.tau : c.tau) / (P.g->h * P.g->h);
+  const double ein = p->eps_in, eout = p->eps_out;
+  const double emix = 2.0 * ein * eout / (ein + eout);
+  const double eout_f = 2.0 * eout * eout / (eout + eout);
+  const double ein_f = 2.0 * ein * ein / (ein + ein);
+  c.re[0] = rc * eout_f;
+  c.re[1] = rc * emix;
+  c.re[2] = rc * ein_f;
+  c.re_uniform = rc * ein_f;
+  const double kb2 = c.vacuum ? 0.0 : p->kappa_bar_sq;
+  flow_params(kb2 * dt / (2.0 * p->alpha), c.t, c.omt);
+  flow_params(4.0 * kb2 * dt / (2.0 * p->alpha), c.t4, c.omt4);
+  c.nl = kb2 > 0.0 && !c.vacuum;
+  return c;
+}
+
+// All problems of a batch advance together.  Every run (field) of every
+// problem is swept by one launch per direction and launch shape per step;
+// fields are ordered by step count (longest first) so that the fields
+// still stepping at any step form a prefix of every launch group.
+template <typename T, typename A>
+struct Engine {
+  npb_ctx* ctx;
+  hipStream_t st;
+  std::vector<Problem>& pr;
+
+  struct Field {
+    int prob, run, steps;
+    double bytes[3];  // algorithmic bytes of one sweep per direction
+  };
+  std::vector<Field> fields;
+  struct Group {
+    LaunchShape s;                 // shared shape, lds = max over members
+    int var = kYzPlain;
+    std::vector<int> members;      // field indices, in field order
+    size_t args_off = 0;           // SweepArgs<T>[members] in the launch-table buffer
+    std::vector<int> nblk;         // blocks of the first k members, k = 1..size
+    std::vector<size_t> work_off;  // int2[nblk[k-1]] per k
+  };
+  std::vector<Group> groups[3];
+  std::vector<unsigned char> meta;  // host image of the launch tables
 
   template <typename F>
   npb_status timed(int cls, double bytes, F&& f) {
@@ -417,168 +480,32 @@ struct Solver {
     return NPB_OK;
   }
 
-  bool aos() const { return p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2; }
-
-  // coefficients of one run (Sec. 3: tau = dt / alpha; AOS sub-steps take
-  // 4 tau; faces carry harmonic means of the nodal permittivities)
-  struct Coefs {
-    double tau, re[3], re_uniform, t, omt, t4, omt4;
-    bool nl, vacuum;
-  };
-  Coefs coefs(const Run& r) const {
-    Coefs c{};
-    const double dt = p->dt / double(1 << r.level);
-    c.vacuum = r.medium == 1;
-    c.tau = dt / p->alpha;
-    const double rc = (aos() ? 4.0 * c.tau : c.tau) / (g->h * g->h);
-    const double ein = p->eps_in, eout = p->eps_out;
-    const double emix = 2.0 * ein * eout / (ein + eout);
-    const double eout_f = 2.0 * eout * eout / (eout + eout);
-    const double ein_f = 2.0 * ein * ein / (ein + ein);
-    c.re[0] = rc * eout_f;
-    c.re[1] = rc * emix;
-    c.re[2] = rc * ein_f;
-    c.re_uniform = rc * ein_f;
-    const double kb2 = c.vacuum ? 0.0 : p->kappa_bar_sq;
-    flow_params(kb2 * dt / (2.0 * p->alpha), c.t, c.omt);
-    flow_params(4.0 * kb2 * dt / (2.0 * p->alpha), c.t4, c.omt4);
-    c.nl = kb2 > 0.0 && !c.vacuum;
-    return c;
-  }
-
-  static size_t pinned_need(int na) { return 256 + kTabBytes * 3 * kMaxFields + (size_t)5 * na * 8; }
-
-  // atoms and chunk tables to the device through the context's pinned
-  // staging buffer
-  npb_status stage(const npb_molecule* mol) {
-    const int na = mol->n_atoms;
-    const size_t need = pinned_need(na);
-    // the staging buffer is reused: wait for earlier copies out of it
-    NPB_HIP(hipStreamSynchronize(st));
-    if (ctx->pinned_bytes < need) {
-      if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-      ctx->pinned = nullptr;
-      ctx->pinned_bytes = 0;
-      NPB_HIP(hipHostMalloc(&ctx->pinned, need, hipHostMallocDefault));
-      ctx->pinned_bytes = need;
-    }
-    unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
-    for (int r = 0; r < L.n_runs; ++r) {
-      const Coefs c = coefs(L.runs[r]);
-      for (int d = 0; d < 3; ++d) {
-        ChunkTab<A>& tb = *reinterpret_cast<ChunkTab<A>*>(hb + 256 + kTabBytes * (3 * r + d));
-        if (c.vacuum)
-          fill_chunk_tab(tb, c.re_uniform, c.re_uniform, L.shape[d].M);
-        else
-          fill_chunk_tab(tb, c.re[0], c.re[2], L.shape[d].M);
-      }
-    }
-    NPB_HIP(hipMemcpyAsync(ws + L.tabs, hb + 256, kTabBytes * 3 * L.n_runs, hipMemcpyHostToDevice,
-                           st));
-    if (na > 0) {
-      double* h = reinterpret_cast<double*>(hb + 256 + kTabBytes * 3 * kMaxFields);
-      for (int a = 0; a < na; ++a) {
-        h[a] = mol->xyz[3 * a];
-        h[na + a] = mol->xyz[3 * a + 1];
-        h[2 * na + a] = mol->xyz[3 * a + 2];
-        h[3 * na + a] = mol->q[a];
-        h[4 * na + a] = mol->radius[a];
-      }
-      NPB_HIP(hipMemcpyAsync(ws + L.atoms, h, (size_t)5 * na * 8, hipMemcpyHostToDevice, st));
-    }
-    return NPB_OK;
-  }
-
-  npb_status setup(const npb_molecule* mol) {
-    const int na = mol->n_atoms;
-    const int nx = g->nx, ny = g->ny, nz = g->nz;
-    const int nxp = pitch_of(nx, (int)sizeof(T));
-    const size_t n = (size_t)nxp * ny * nz;
-    sa = SetupArgs{nx, ny, nz, nxp, g->h, g->origin[0], g->origin[1], g->origin[2], na,
-                   at<double>(L.atoms)};
-    int* ints = at<int>(L.ints);  // [0] nq, [1] stencil error
-    return timed(NPB_K_SETUP, 0, [&] {
-      hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ints), 16, 0u, st);
-      if (e != hipSuccess) return e;
-      e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.mask), (n + 3) / 4, 0u, st);
-      if (e != hipSuccess) return e;
-      e = launch_mask_raster(sa, at<uint8_t>(L.mask), st);
-      if (e != hipSuccess) return e;
-      e = launch_stencil(sa, at<int>(L.key_a), at<int>(L.id_a), at<double>(L.sval), ints + 1, st);
-      if (e != hipSuccess) return e;
-      e = radix_sort_pairs(at<int>(L.key_a), at<int>(L.id_a), at<int>(L.key_b), at<int>(L.id_b),
-                           at<int>(L.hist), L.cap, (long long)n, st);
-      if (e != hipSuccess) return e;
-      const double pref = 4.0 * M_PI * lB / (g->h * g->h * g->h);
-      e = launch_merge_charges(at<int>(L.key_a), at<int>(L.id_a), at<double>(L.sval),
-                               at<int>(L.heads), L.cap, ints, at<int>(L.q_idx),
-                               at<double>(L.q_val), at<double>(L.q_rho), pref, st);
-      if (e != hipSuccess) return e;
-      e = launch_line_ptr(at<int>(L.q_idx), ints, L.cap, ny * nz, nxp, at<int>(L.xptr), st);
-      if (e != hipSuccess) return e;
-      if (needs_z_sources(p->scheme) && L.cap > 0) {
-        for (int axis = needs_y_sources(p->scheme) ? 1 : 2; axis <= 2; ++axis) {
-          e = launch_axis_keys(at<int>(L.q_idx), ints, L.cap, nx, nxp, ny, nz, axis,
-                               at<int>(L.key_a), at<int>(L.id_a), st);
-          if (e != hipSuccess) return e;
-          e = radix_sort_pairs(at<int>(L.key_a), at<int>(L.id_a), at<int>(L.key_b),
-                               at<int>(L.id_b), at<int>(L.hist), L.cap,
-                               (long long)nx * ny * nz + 1, st);
-          if (e != hipSuccess) return e;
-          int* lin = at<int>(axis == 1 ? L.ylin : L.zlin);
-          double* rho = at<double>(axis == 1 ? L.yrho : L.zrho);
-          e = launch_gather_entries(at<int>(L.id_a), ints, L.cap, at<int>(L.q_idx),
-                                    at<double>(L.q_rho), lin, rho, st);
-          if (e != hipSuccess) return e;
-          if (axis == 1)
-            e = launch_line_ptr(at<int>(L.key_a), ints, L.cap, nz * nx, ny, at<int>(L.yptr), st);
-          else
-            e = launch_line_ptr(at<int>(L.key_a), ints, L.cap, ny * nx, nz, at<int>(L.zptr), st);
-          if (e != hipSuccess) return e;
-        }
-      } else if (needs_z_sources(p->scheme)) {
-        if (needs_y_sources(p->scheme))
-          e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.yptr), (size_t)nz * nx + 1, 0u,
-                              st);
-        if (e != hipSuccess) return e;
-        e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.zptr), (size_t)ny * nx + 1, 0u, st);
-        if (e != hipSuccess) return e;
-      }
-      const double kappa = std::sqrt(p->kappa_bar_sq / p->eps_out);
-      e = launch_boundary(sa, p->eps_out, kappa, p->eps_in, lB, at<double>(L.bc_s),
-                          p->vacuum ? at<double>(L.bc_v) : nullptr, sizeof(A) == 4, st);
-      if (e != hipSuccess) return e;
-      for (int d = 0; d < 3 && e == hipSuccess; ++d)
-        e = launch_chunk_classes(at<uint8_t>(L.mask), nx, nxp, ny, nz, d, L.shape[d].M,
-                                 L.shape[d].P, at<uint8_t>(L.ccls[d]), st);
-      return e;
-    });
-  }
-
-  // sweep arguments of run r in direction d (scheme-specific fused work:
-  // Sec. 3.1 LODIE2 / LODIE1 orders, Sec. 3.2 AOS accumulation)
-  SweepArgs<T> sweep_args(int r, int d) {
-    const Coefs c = coefs(L.runs[r]);
+  // sweep arguments of run r of problem P in direction d (scheme-specific
+  // fused work: Sec. 3.1 LODIE2 / LODIE1 orders, Sec. 3.2 AOS accumulation)
+  SweepArgs<T> sweep_args(const Problem& P, int r, int d) const {
+    const Coefs c = run_coefs(P, P.L.runs[r]);
+    const npb_params* p = P.p;
+    const Layout& L = P.L;
     SweepArgs<T> a{};
-    a.u = at<T>(L.field[r]);
-    a.acc = aos() ? at<T>(L.acc[r]) : nullptr;
-    a.mask = c.vacuum ? nullptr : at<uint8_t>(L.mask);
-    a.nx = g->nx;
-    a.ny = g->ny;
-    a.nz = g->nz;
-    a.nxp = pitch_of(g->nx, (int)sizeof(T));
+    a.u = P.at<T>(L.field[r]);
+    a.acc = P.aos() ? P.at<T>(L.acc[r]) : nullptr;
+    a.mask = c.vacuum ? nullptr : P.at<uint8_t>(L.mask);
+    a.nx = P.g->nx;
+    a.ny = P.g->ny;
+    a.nz = P.g->nz;
+    a.nxp = pitch_of(P.g->nx, (int)sizeof(T));
     for (int k = 0; k < 3; ++k) a.re[k] = c.re[k];
     a.re_uniform = c.re_uniform;
-    a.ccls = c.vacuum ? nullptr : at<uint8_t>(L.ccls[d]);
-    a.tab = ws + L.tabs + kTabBytes * (3 * r + d);
+    a.ccls = c.vacuum ? nullptr : P.at<uint8_t>(L.ccls[d]);
+    a.tab = P.ws + L.tabs + kTabBytes * (3 * r + d);
     if (d == 0) {
-      a.src_ptr = at<int>(L.xptr);
-      a.src_lin = at<int>(L.q_idx);
-      a.src_rho = at<double>(L.q_rho);
+      a.src_ptr = P.at<int>(L.xptr);
+      a.src_lin = P.at<int>(L.q_idx);
+      a.src_rho = P.at<double>(L.q_rho);
     } else {
-      a.src_ptr = at<int>(d == 1 ? L.yptr : L.zptr);
-      a.src_lin = at<int>(d == 1 ? L.ylin : L.zlin);
-      a.src_rho = at<double>(d == 1 ? L.yrho : L.zrho);
+      a.src_ptr = P.at<int>(d == 1 ? L.yptr : L.zptr);
+      a.src_lin = P.at<int>(d == 1 ? L.ylin : L.zlin);
+      a.src_rho = P.at<double>(d == 1 ? L.yrho : L.zrho);
     }
     if (p->scheme == NPB_LODIE2) {
       if (d == 0) {
@@ -618,190 +545,426 @@ struct Solver {
         }
       }
     }
+    shape_args(a, d, L.shape[d]);
     return a;
   }
 
-  // All runs advance together: at step s the runs with more than s steps
-  // (a prefix of the run list) are swept by one launch per direction.
-  npb_status time_loop() {
-    const int nx = g->nx, ny = g->ny, nz = g->nz;
+  // fields, launch groups and the host image of the launch tables
+  npb_status plan() {
+    for (int i = 0; i < (int)pr.size(); ++i) {
+      const Problem& P = pr[i];
+      const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
+      for (int r = 0; r < P.L.n_runs; ++r) {
+        Field f{};
+        f.prob = i;
+        f.run = r;
+        f.steps = P.p->n_steps << P.L.runs[r].level;
+        // field read + write (+ mask) (+ accumulator)
+        const double mb = P.L.runs[r].medium == 1 ? 0.0 : 1.0;
+        const double ab = P.aos() ? sizeof(T) : 0.0;
+        f.bytes[0] = pts * (2.0 * sizeof(T) + mb + ab);
+        f.bytes[1] = pts * (2.0 * sizeof(T) + mb + 2.0 * ab);
+        f.bytes[2] = pts * (2.0 * sizeof(T) + mb + ab);
+        fields.push_back(f);
+      }
+      for (int d = 0; d < 3; ++d)
+        if (P.L.shape[d].M == 0) return fail(NPB_EINVAL, "unsupported grid shape");
+    }
+    std::stable_sort(fields.begin(), fields.end(),
+                     [](const Field& a, const Field& b) { return a.steps > b.steps; });
+    auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+    size_t off = 0;
+    std::vector<std::vector<SweepArgs<T>>> gargs[3];
+    for (int d = 0; d < 3; ++d) {
+      for (int fi = 0; fi < (int)fields.size(); ++fi) {
+        const LaunchShape& sh = pr[fields[fi].prob].L.shape[d];
+        int g = 0;
+        while (g < (int)groups[d].size() &&
+               !(groups[d][g].s.M == sh.M && groups[d][g].s.P == sh.P &&
+                 groups[d][g].s.LW == sh.LW && groups[d][g].s.threads == sh.threads))
+          ++g;
+        if (g == (int)groups[d].size()) {
+          groups[d].push_back(Group{});
+          groups[d].back().s = sh;
+          gargs[d].emplace_back();
+        }
+        Group& G = groups[d][g];
+        G.s.lds = std::max(G.s.lds, sh.lds);
+        G.members.push_back(fi);
+        gargs[d][g].push_back(sweep_args(pr[fields[fi].prob], fields[fi].run, d));
+      }
+      for (int g = 0; g < (int)groups[d].size(); ++g) {
+        Group& G = groups[d][g];
+        G.var = sweep_variant(gargs[d][g].data(), (int)gargs[d][g].size());
+        G.args_off = off;
+        off = align(off + sizeof(SweepArgs<T>) * G.members.size());
+        int nb = 0;
+        for (int k = 0; k < (int)G.members.size(); ++k) {
+          nb += pr[fields[G.members[k]].prob].L.shape[d].blocks;
+          G.nblk.push_back(nb);
+          G.work_off.push_back(off);
+          off = align(off + sizeof(int2) * (size_t)nb);
+        }
+      }
+    }
+    meta.assign(off, 0);
+    for (int d = 0; d < 3; ++d)
+      for (int g = 0; g < (int)groups[d].size(); ++g) {
+        const Group& G = groups[d][g];
+        std::memcpy(meta.data() + G.args_off, gargs[d][g].data(),
+                    sizeof(SweepArgs<T>) * G.members.size());
+        for (int k = 0; k < (int)G.members.size(); ++k) {
+          int2* w = reinterpret_cast<int2*>(meta.data() + G.work_off[k]);
+          int n = 0;
+          for (int m = 0; m <= k; ++m) {
+            const int nbm = pr[fields[G.members[m]].prob].L.shape[d].blocks;
+            for (int b = 0; b < nbm; ++b) w[n++] = make_int2(m, b);
+          }
+        }
+      }
+    return NPB_OK;
+  }
+
+  // Pinned staging: [results: 128 B per problem][launch tables][per problem:
+  // chunk tables, atom planes].  The host fills it (after the stream has
+  // drained earlier copies out of it), then one copy per region moves it to
+  // the device.  with_meta = false keeps the launch tables already in the
+  // context's device buffer (a graph replay of the same batch).
+  npb_status stage(bool with_meta) {
+    NPB_HIP(hipStreamSynchronize(st));
+    const size_t res_bytes = 128 * pr.size();
+    size_t need = res_bytes + (with_meta ? meta.size() : 0);
+    for (Problem& P : pr) {
+      P.tabs_pinned = need;
+      need += kTabBytes * 3 * kMaxFields;
+      P.atoms_pinned = need;
+      need += (size_t)5 * P.mol->n_atoms * 8;
+    }
+    if (ctx->pinned_bytes < need) {
+      if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+      ctx->pinned = nullptr;
+      ctx->pinned_bytes = 0;
+      NPB_HIP(hipHostMalloc(&ctx->pinned, need, hipHostMallocDefault));
+      ctx->pinned_bytes = need;
+    }
+    unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
+    if (with_meta) {
+      // the captured graph reads the launch tables being replaced: drop it
+      if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+      ctx->exec = nullptr;
+      ctx->key.clear();
+      if (ctx->meta_bytes < meta.size()) {
+        if (ctx->meta) (void)hipFree(ctx->meta);
+        ctx->meta = nullptr;
+        ctx->meta_bytes = 0;
+        NPB_HIP(hipMalloc(&ctx->meta, meta.size()));
+        ctx->meta_bytes = meta.size();
+      }
+      std::memcpy(hb + res_bytes, meta.data(), meta.size());
+      NPB_HIP(hipMemcpyAsync(ctx->meta, hb + res_bytes, meta.size(), hipMemcpyHostToDevice, st));
+    }
+    for (Problem& P : pr) {
+      for (int r = 0; r < P.L.n_runs; ++r) {
+        const Coefs c = run_coefs(P, P.L.runs[r]);
+        for (int d = 0; d < 3; ++d) {
+          ChunkTab<A>& tb =
+              *reinterpret_cast<ChunkTab<A>*>(hb + P.tabs_pinned + kTabBytes * (3 * r + d));
+          if (c.vacuum)
+            fill_chunk_tab(tb, c.re_uniform, c.re_uniform, P.L.shape[d].M);
+          else
+            fill_chunk_tab(tb, c.re[0], c.re[2], P.L.shape[d].M);
+        }
+      }
+      NPB_HIP(hipMemcpyAsync(P.ws + P.L.tabs, hb + P.tabs_pinned, kTabBytes * 3 * P.L.n_runs,
+                             hipMemcpyHostToDevice, st));
+      const int na = P.mol->n_atoms;
+      if (na > 0) {
+        double* h = reinterpret_cast<double*>(hb + P.atoms_pinned);
+        for (int a = 0; a < na; ++a) {
+          h[a] = P.mol->xyz[3 * a];
+          h[na + a] = P.mol->xyz[3 * a + 1];
+          h[2 * na + a] = P.mol->xyz[3 * a + 2];
+          h[3 * na + a] = P.mol->q[a];
+          h[4 * na + a] = P.mol->radius[a];
+        }
+        NPB_HIP(hipMemcpyAsync(P.ws + P.L.atoms, h, (size_t)5 * na * 8, hipMemcpyHostToDevice,
+                               st));
+      }
+    }
+    return NPB_OK;
+  }
+
+  npb_status setup(Problem& P) {
+    const Layout& L = P.L;
+    const npb_params* p = P.p;
+    const int na = P.mol->n_atoms;
+    const int nx = P.g->nx, ny = P.g->ny, nz = P.g->nz;
     const int nxp = pitch_of(nx, (int)sizeof(T));
     const size_t n = (size_t)nxp * ny * nz;
-    for (int r = 0; r < L.n_runs; ++r) {
-      const bool vac = L.runs[r].medium == 1;
-      npb_status s = timed(NPB_K_INIT, (double)n * sizeof(T), [&] {
-        return launch_field_init<T>(at<T>(L.field[r]), at<double>(vac ? L.bc_v : L.bc_s), nx, nxp,
-                                    ny, nz, st);
+    P.sa = SetupArgs{nx, ny, nz, nxp, P.g->h, P.g->origin[0], P.g->origin[1], P.g->origin[2], na,
+                     P.at<double>(L.atoms)};
+    const SetupArgs& sa = P.sa;
+    unsigned char* ws = P.ws;
+    int* ints = P.at<int>(L.ints);  // [0] nq, [1] stencil error
+    return timed(NPB_K_SETUP, 0, [&] {
+      hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ints), 16, 0u, st);
+      if (e != hipSuccess) return e;
+      e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.mask), (n + 3) / 4, 0u, st);
+      if (e != hipSuccess) return e;
+      e = launch_mask_raster(sa, P.at<uint8_t>(L.mask), st);
+      if (e != hipSuccess) return e;
+      e = launch_stencil(sa, P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<double>(L.sval),
+                         ints + 1, st);
+      if (e != hipSuccess) return e;
+      e = radix_sort_pairs(P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<int>(L.key_b),
+                           P.at<int>(L.id_b), P.at<int>(L.hist), L.cap, (long long)n, st);
+      if (e != hipSuccess) return e;
+      const double pref = 4.0 * M_PI * P.lB / (P.g->h * P.g->h * P.g->h);
+      e = launch_merge_charges(P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<double>(L.sval),
+                               P.at<int>(L.heads), L.cap, ints, P.at<int>(L.q_idx),
+                               P.at<double>(L.q_val), P.at<double>(L.q_rho), pref, st);
+      if (e != hipSuccess) return e;
+      e = launch_line_ptr(P.at<int>(L.q_idx), ints, L.cap, ny * nz, nxp, P.at<int>(L.xptr), st);
+      if (e != hipSuccess) return e;
+      if (needs_z_sources(p->scheme) && L.cap > 0) {
+        for (int axis = needs_y_sources(p->scheme) ? 1 : 2; axis <= 2; ++axis) {
+          e = launch_axis_keys(P.at<int>(L.q_idx), ints, L.cap, nx, nxp, ny, nz, axis,
+                               P.at<int>(L.key_a), P.at<int>(L.id_a), st);
+          if (e != hipSuccess) return e;
+          e = radix_sort_pairs(P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<int>(L.key_b),
+                               P.at<int>(L.id_b), P.at<int>(L.hist), L.cap,
+                               (long long)nx * ny * nz + 1, st);
+          if (e != hipSuccess) return e;
+          int* lin = P.at<int>(axis == 1 ? L.ylin : L.zlin);
+          double* rho = P.at<double>(axis == 1 ? L.yrho : L.zrho);
+          e = launch_gather_entries(P.at<int>(L.id_a), ints, L.cap, P.at<int>(L.q_idx),
+                                    P.at<double>(L.q_rho), lin, rho, st);
+          if (e != hipSuccess) return e;
+          if (axis == 1)
+            e = launch_line_ptr(P.at<int>(L.key_a), ints, L.cap, nz * nx, ny, P.at<int>(L.yptr),
+                                st);
+          else
+            e = launch_line_ptr(P.at<int>(L.key_a), ints, L.cap, ny * nx, nz, P.at<int>(L.zptr),
+                                st);
+          if (e != hipSuccess) return e;
+        }
+      } else if (needs_z_sources(p->scheme)) {
+        if (needs_y_sources(p->scheme))
+          e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.yptr), (size_t)nz * nx + 1, 0u,
+                              st);
+        if (e != hipSuccess) return e;
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.zptr), (size_t)ny * nx + 1, 0u, st);
+        if (e != hipSuccess) return e;
+      }
+      const double kappa = std::sqrt(p->kappa_bar_sq / p->eps_out);
+      e = launch_boundary(sa, p->eps_out, kappa, p->eps_in, P.lB, P.at<double>(L.bc_s),
+                          p->vacuum ? P.at<double>(L.bc_v) : nullptr, sizeof(A) == 4, st);
+      if (e != hipSuccess) return e;
+      for (int d = 0; d < 3 && e == hipSuccess; ++d)
+        e = launch_chunk_classes(P.at<uint8_t>(L.mask), nx, nxp, ny, nz, d, L.shape[d].M,
+                                 L.shape[d].P, P.at<uint8_t>(L.ccls[d]), st);
+      return e;
+    });
+  }
+
+  npb_status time_loop() {
+    for (const Field& f : fields) {
+      const Problem& P = pr[f.prob];
+      const bool vac = P.L.runs[f.run].medium == 1;
+      const int nx = P.g->nx, ny = P.g->ny, nz = P.g->nz;
+      const int nxp = pitch_of(nx, (int)sizeof(T));
+      npb_status s = timed(NPB_K_INIT, (double)nxp * ny * nz * sizeof(T), [&] {
+        return launch_field_init<T>(P.at<T>(P.L.field[f.run]),
+                                    P.at<double>(vac ? P.L.bc_v : P.L.bc_s), nx, nxp, ny, nz, st);
       });
       if (s != NPB_OK) return s;
     }
-    if (L.shape[0].M == 0 || L.shape[1].M == 0 || L.shape[2].M == 0)
-      return fail(NPB_EINVAL, "unsupported grid shape");
-    SweepBatch<T> bx{}, by{}, bz{};
-    int steps[kMaxFields];
-    int max_steps = 0;
-    double pbytes[3][kMaxFields];
-    const double pts = (double)(nx - 2) * (ny - 2) * (nz - 2);
-    for (int r = 0; r < L.n_runs; ++r) {
-      bx.f[r] = sweep_args(r, 0);
-      by.f[r] = sweep_args(r, 1);
-      bz.f[r] = sweep_args(r, 2);
-      steps[r] = p->n_steps << L.runs[r].level;
-      if (steps[r] > max_steps) max_steps = steps[r];
-      // algorithmic bytes per sweep: field read + write (+ mask) (+ accumulator)
-      const double mb = L.runs[r].medium == 1 ? 0.0 : 1.0;
-      const double ab = aos() ? sizeof(T) : 0.0;
-      pbytes[0][r] = pts * (2.0 * sizeof(T) + mb + ab);
-      pbytes[1][r] = pts * (2.0 * sizeof(T) + mb + 2.0 * ab);
-      pbytes[2][r] = pts * (2.0 * sizeof(T) + mb + ab);
-    }
+    const int max_steps = fields.empty() ? 0 : fields[0].steps;
+    unsigned char* dm = reinterpret_cast<unsigned char*>(ctx->meta);
     for (int step = 0; step < max_steps; ++step) {
-      int nf = 0;
-      double b3[3] = {0, 0, 0};
-      while (nf < L.n_runs && steps[nf] > step) {
-        for (int d = 0; d < 3; ++d) b3[d] += pbytes[d][nf];
-        ++nf;
+      for (int d = 0; d < 3; ++d) {
+        for (const Group& G : groups[d]) {
+          int k = 0;
+          double bytes = 0.0;
+          while (k < (int)G.members.size() && fields[G.members[k]].steps > step)
+            bytes += fields[G.members[k++]].bytes[d];
+          if (k == 0) continue;
+          const auto* args = reinterpret_cast<const SweepArgs<T>*>(dm + G.args_off);
+          const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[k - 1]);
+          const int nb = G.nblk[k - 1];
+          npb_status s = timed(NPB_K_SWEEP_X + d, bytes, [&] {
+            return d == 0 ? launch_sweep_x<T, A>(args, work, nb, G.s, st)
+                          : launch_sweep_yz<T, A>(args, work, nb, d, G.var, G.s, st);
+          });
+          if (s != NPB_OK) return s;
+        }
       }
-      npb_status s;
-      s = timed(NPB_K_SWEEP_X, b3[0], [&] { return launch_sweep_x<T, A>(bx, nf, L.shape[0], st); });
+    }
+    return NPB_OK;
+  }
+
+  // The device work after staging, all on `st` (captured into a graph when
+  // replay is on): setup, time loops, energies, optional fields,
+  // combinations.  Launches only: no allocation, copy or synchronisation.
+  npb_status device_work() {
+    for (Problem& P : pr) {
+      npb_status s = setup(P);
       if (s != NPB_OK) return s;
-      s = timed(NPB_K_SWEEP_Y, b3[1],
-                [&] { return launch_sweep_yz<T, A>(by, nf, 1, L.shape[1], st); });
+      // zero the energy slots
+      s = timed(NPB_K_OTHER, 0, [&] {
+        return launch_fill_u32(reinterpret_cast<uint32_t*>(P.ws + P.L.slots), 64, 0u, st);
+      });
       if (s != NPB_OK) return s;
-      s = timed(NPB_K_SWEEP_Z, b3[2],
-                [&] { return launch_sweep_yz<T, A>(bz, nf, 2, L.shape[2], st); });
+    }
+    npb_status s = time_loop();
+    if (s != NPB_OK) return s;
+    for (Problem& P : pr) {
+      const Layout& L = P.L;
+      for (int r = 0; r < L.n_runs; ++r) {
+        const int slot = 2 * L.runs[r].medium + L.runs[r].level;
+        s = timed(NPB_K_ENERGY, 0, [&] {
+          return launch_energy<T>(P.at<T>(L.field[r]), P.at<int>(L.q_idx), P.at<double>(L.q_val),
+                                  P.at<int>(L.ints), L.cap, P.at<double>(L.slots) + slot, st);
+        });
+        if (s != NPB_OK) return s;
+      }
+      if (P.fout) {
+        // selected medium: kT u (plain) or kT (2 u(dt/2) - u(dt)) (Richardson)
+        const npb_params* p = P.p;
+        for (int l = 0; l < (p->richardson ? 2 : 1); ++l) {
+          int r = 0;
+          while (!(L.runs[r].medium == p->field_select && L.runs[r].level == l)) ++r;
+          const double beta = (l == 0) ? 0.0 : 1.0;
+          const double gamma = p->richardson ? (l == 0 ? -P.kT : 2.0 * P.kT) : P.kT;
+          s = timed(NPB_K_OTHER, 0, [&] {
+            return launch_field_out<T>(P.fout, P.at<T>(L.field[r]), P.g->nx,
+                                       pitch_of(P.g->nx, (int)sizeof(T)), P.g->ny, P.g->nz, beta,
+                                       gamma, st);
+          });
+          if (s != NPB_OK) return s;
+        }
+      }
+      s = timed(NPB_K_OTHER, 0, [&] {
+        return launch_combine(P.at<double>(L.slots), P.kT, P.p->richardson, P.p->vacuum,
+                              P.at<double>(L.slots) + 8, st);
+      });
       if (s != NPB_OK) return s;
     }
     return NPB_OK;
   }
 
-  npb_status energy(int r) {
-    const int slot = 2 * L.runs[r].medium + L.runs[r].level;
-    return timed(NPB_K_ENERGY, 0, [&] {
-      return launch_energy<T>(at<T>(L.field[r]), at<int>(L.q_idx), at<double>(L.q_val),
-                              at<int>(L.ints), L.cap, at<double>(L.slots) + slot, st);
-    });
+  std::vector<unsigned char> graph_key() const {
+    std::vector<unsigned char> k(sizeof(int) + sizeof(GraphKey) * pr.size(), 0);
+    const int prec = (int)sizeof(T) * 16 + (int)sizeof(A);
+    std::memcpy(k.data(), &prec, sizeof(int));
+    for (size_t i = 0; i < pr.size(); ++i) {
+      GraphKey g;
+      std::memset(&g, 0, sizeof(g));
+      g.ws = pr[i].ws;
+      g.field_out = pr[i].fout;
+      g.grid = *pr[i].g;
+      g.params = *pr[i].p;
+      g.n_atoms = pr[i].mol->n_atoms;
+      std::memcpy(k.data() + sizeof(int) + i * sizeof(GraphKey), &g, sizeof(g));
+    }
+    return k;
   }
 
-  // The device work of a solve after staging, all on `st` (captured into a
-  // graph when replay is on): setup, time loops, energies, optional field,
-  // combinations.  Launches only: no allocation, copy or synchronisation.
-  npb_status device_work(const npb_molecule* mol, double* d_field_out) {
-    npb_status s = setup(mol);
-    if (s != NPB_OK) return s;
-    // zero the energy slots
-    s = timed(NPB_K_OTHER, 0, [&] {
-      return launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.slots), 64, 0u, st);
-    });
-    if (s != NPB_OK) return s;
-    s = time_loop();
-    if (s != NPB_OK) return s;
-    for (int r = 0; r < L.n_runs; ++r) {
-      s = energy(r);
+  npb_status run(npb_result* out) {
+    // A replay of the graph of the same batch needs only the atoms and the
+    // chunk tables staged again; the launch tables in the context's buffer
+    // are the ones the graph was captured with.
+    const bool graph = ctx->graphs && !ctx->timing;
+    std::vector<unsigned char> key = graph_key();
+    const bool replay = graph && ctx->exec && key == ctx->key;
+    npb_status s = NPB_OK;
+    if (!replay) {
+      s = plan();
       if (s != NPB_OK) return s;
     }
-    if (d_field_out) {
-      // selected medium: kT u (plain) or kT (2 u(dt/2) - u(dt)) (Richardson)
-      for (int l = 0; l < (p->richardson ? 2 : 1); ++l) {
-        int r = 0;
-        while (!(L.runs[r].medium == p->field_select && L.runs[r].level == l)) ++r;
-        const double beta = (l == 0) ? 0.0 : 1.0;
-        const double gamma = p->richardson ? (l == 0 ? -kT : 2.0 * kT) : kT;
-        s = timed(NPB_K_OTHER, 0, [&] {
-          return launch_field_out<T>(d_field_out, at<T>(L.field[r]), g->nx,
-                                     pitch_of(g->nx, (int)sizeof(T)), g->ny, g->nz, beta, gamma,
-                                     st);
-        });
-        if (s != NPB_OK) return s;
+    s = stage(!replay);
+    if (s != NPB_OK) return s;
+    NPB_HIP(hipEventRecord(ctx->t0, st));
+    if (graph) {
+      if (!replay) {
+        if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+        ctx->exec = nullptr;
+        ctx->key.clear();
+        const hipStream_t user = st;
+        st = ctx->capture;
+        NPB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        s = device_work();
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        st = user;
+        if (s != NPB_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return s;
+        }
+        if (e != hipSuccess)
+          return fail(NPB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&ctx->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+          ctx->exec = nullptr;
+          return fail(NPB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        ctx->key = key;
       }
+      NPB_HIP(hipGraphLaunch(ctx->exec, st));
+    } else {
+      s = device_work();
+      if (s != NPB_OK) return s;
     }
-    return timed(NPB_K_OTHER, 0, [&] {
-      return launch_combine(at<double>(L.slots), kT, p->richardson, p->vacuum,
-                            at<double>(L.slots) + 8, st);
-    });
+    NPB_HIP(hipEventRecord(ctx->t1, st));
+    // results to the host (first 128 bytes per problem of the staging buffer)
+    unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
+    for (size_t i = 0; i < pr.size(); ++i) {
+      NPB_HIP(hipMemcpyAsync(hb + 128 * i, pr[i].ws + pr[i].L.slots + 8 * 8, 8 * 8,
+                             hipMemcpyDeviceToHost, st));
+      NPB_HIP(hipMemcpyAsync(hb + 128 * i + 64, pr[i].ws + pr[i].L.ints, 8, hipMemcpyDeviceToHost,
+                             st));
+    }
+    NPB_HIP(hipStreamSynchronize(st));
+    float ms = 0.f;
+    NPB_HIP(hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
+    if (ctx->timing) harvest(ctx);
+    npb_status worst = NPB_OK;
+    for (size_t i = 0; i < pr.size(); ++i) {
+      const Problem& P = pr[i];
+      const double* hres = reinterpret_cast<const double*>(hb + 128 * i);
+      const int* hints = reinterpret_cast<const int*>(hb + 128 * i + 64);
+      npb_result& o = out[i];
+      std::memset(&o, 0, sizeof(o));
+      o.dG = hres[0];
+      o.dG_plain = hres[1];
+      o.G_m[0] = hres[2];
+      o.G_m[1] = hres[3];
+      o.G_0[0] = hres[4];
+      o.G_0[1] = hres[5];
+      o.finite = hres[6] != 0.0 ? 1 : 0;
+      const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
+      for (int r = 0; r < P.L.n_runs; ++r) {
+        const int ns = P.p->n_steps << P.L.runs[r].level;
+        o.steps_done += ns;
+        o.grid_point_updates += pts * ns;
+      }
+      o.device_ms = ms;
+      o.n_charge_nodes = hints[0];
+      if (hints[1] != 0 && worst == NPB_OK)
+        worst = fail(NPB_ERANGE, "problem " + std::to_string(i) +
+                                     ": a trilinear stencil touches the boundary");
+      if (!o.finite && worst == NPB_OK)
+        worst = fail(NPB_EDIVERGED, "problem " + std::to_string(i) + ": non-finite energy");
+    }
+    return worst;
   }
 };
 
 template <typename T, typename A>
-npb_status solve_t(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* g,
-                   const npb_params* p, void* d_ws, double* d_field_out, hipStream_t st,
-                   npb_result* out, const Layout& L) {
-  Solver<T, A> S{ctx, g, p, st, reinterpret_cast<unsigned char*>(d_ws), L, {}, 0.0, 0.0};
-  S.kT = thermal_energy(p->temperature_K);
-  S.lB = bjerrum(p->temperature_K);
-  npb_status s = S.stage(mol);
-  if (s != NPB_OK) return s;
-  NPB_HIP(hipEventRecord(ctx->t0, st));
-  if (ctx->graphs && !ctx->timing) {
-    GraphKey k;
-    std::memset(&k, 0, sizeof(k));
-    k.ws = d_ws;
-    k.field_out = d_field_out;
-    k.pinned = ctx->pinned;
-    k.grid = *g;
-    k.params = *p;
-    k.n_atoms = mol->n_atoms;
-    if (!ctx->exec || std::memcmp(&k, &ctx->key, sizeof(k)) != 0) {
-      if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
-      ctx->exec = nullptr;
-      S.st = ctx->capture;
-      NPB_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-      s = S.device_work(mol, d_field_out);
-      hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
-      S.st = st;
-      if (s != NPB_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return s;
-      }
-      if (e != hipSuccess) return fail(NPB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-      e = hipGraphInstantiate(&ctx->exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) {
-        ctx->exec = nullptr;
-        return fail(NPB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-      }
-      ctx->key = k;
-    }
-    NPB_HIP(hipGraphLaunch(ctx->exec, st));
-  } else {
-    s = S.device_work(mol, d_field_out);
-    if (s != NPB_OK) return s;
-  }
-  int steps_done = 0;
-  double gpu_updates = 0.0;
-  const double pts = (double)(g->nx - 2) * (g->ny - 2) * (g->nz - 2);
-  for (int r = 0; r < L.n_runs; ++r) {
-    const int ns = p->n_steps << L.runs[r].level;
-    steps_done += ns;
-    gpu_updates += pts * ns;
-  }
-  NPB_HIP(hipEventRecord(ctx->t1, st));
-  // results to the host (first 256 bytes of the staging buffer)
-  double* hres = reinterpret_cast<double*>(ctx->pinned);
-  NPB_HIP(hipMemcpyAsync(hres, S.ws + L.slots + 8 * 8, 8 * 8, hipMemcpyDeviceToHost, st));
-  NPB_HIP(hipMemcpyAsync(reinterpret_cast<unsigned char*>(hres) + 64, S.ws + L.ints, 8,
-                         hipMemcpyDeviceToHost, st));
-  NPB_HIP(hipStreamSynchronize(st));
-  float ms = 0.f;
-  NPB_HIP(hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
-  if (ctx->timing) harvest(ctx);
-  const int* hints = reinterpret_cast<const int*>(reinterpret_cast<unsigned char*>(hres) + 64);
-  std::memset(out, 0, sizeof(*out));
-  out->dG = hres[0];
-  out->dG_plain = hres[1];
-  out->G_m[0] = hres[2];
-  out->G_m[1] = hres[3];
-  out->G_0[0] = hres[4];
-  out->G_0[1] = hres[5];
-  out->finite = hres[6] != 0.0 ? 1 : 0;
-  out->grid_point_updates = gpu_updates;
-  out->device_ms = ms;
-  out->steps_done = steps_done;
-  out->n_charge_nodes = hints[0];
-  if (hints[1] != 0) return fail(NPB_ERANGE, "a trilinear stencil touches the boundary");
-  if (!out->finite) return fail(NPB_EDIVERGED, "non-finite energy");
-  return NPB_OK;
+npb_status solve_batch_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st, npb_result* out) {
+  Engine<T, A> E{ctx, st, pr, {}, {}, {}};
+  return E.run(out);
 }
 
 }  // namespace
@@ -852,6 +1015,7 @@ void npb_ctx_destroy(npb_ctx* c) {
   if (c->t1) (void)hipEventDestroy(c->t1);
   if (c->exec) (void)hipGraphExecDestroy(c->exec);
   if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->meta) (void)hipFree(c->meta);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }
@@ -888,30 +1052,62 @@ npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
   return NPB_OK;
 }
 
-npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
-                     const npb_params* params, void* d_ws, size_t ws_bytes, double* d_field_out,
-                     void* stream, npb_result* out) {
+npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols, const npb_grid* grids,
+                           const npb_params* params, void* const* d_ws, const size_t* ws_bytes,
+                           double* const* d_field_out, void* stream, npb_result* out) {
   if (!ctx || !out) return fail(NPB_EINVAL, "null context or result");
-  npb_status s = validate(mol, grid, params);
-  if (s != NPB_OK) return s;
-  const Layout L = make_layout(mol, grid, params);
-  if (!d_ws || ws_bytes < L.total)
-    return fail(NPB_EINVAL, "workspace missing or smaller than npb_workspace_bytes");
-  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0)
-    return fail(NPB_EINVAL, "workspace must be 256-byte aligned");
+  if (n < 1 || !mols || !grids || !params || !d_ws || !ws_bytes)
+    return fail(NPB_EINVAL, "empty batch or null array");
+  std::vector<Problem> pr(n);
+  for (int i = 0; i < n; ++i) {
+    npb_status s = validate(&mols[i], &grids[i], &params[i]);
+    if (s != NPB_OK) return fail(s, "problem " + std::to_string(i) + ": " + g_err);
+    if (params[i].precision != params[0].precision)
+      return fail(NPB_EINVAL, "problem " + std::to_string(i) + ": a batch runs one precision");
+    Problem& P = pr[i];
+    P.mol = &mols[i];
+    P.g = &grids[i];
+    P.p = &params[i];
+    P.ws = reinterpret_cast<unsigned char*>(d_ws[i]);
+    P.fout = d_field_out ? d_field_out[i] : nullptr;
+    P.L = make_layout(P.mol, P.g, P.p);
+    P.kT = thermal_energy(P.p->temperature_K);
+    P.lB = bjerrum(P.p->temperature_K);
+    if (!P.ws || ws_bytes[i] < P.L.total)
+      return fail(NPB_EINVAL, "problem " + std::to_string(i) +
+                                  ": workspace missing or smaller than npb_workspace_bytes");
+    if (reinterpret_cast<uintptr_t>(P.ws) % 256 != 0)
+      return fail(NPB_EINVAL, "problem " + std::to_string(i) +
+                                  ": workspace must be 256-byte aligned");
+    for (int j = 0; j < i; ++j)
+      if (pr[j].ws == P.ws)
+        return fail(NPB_EINVAL, "problem " + std::to_string(i) + ": workspace shared with problem " +
+                                    std::to_string(j));
+  }
   NPB_HIP(hipSetDevice(ctx->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   try {
-    if (params->precision == NPB_FP64)
-      return solve_t<double, double>(ctx, mol, grid, params, d_ws, d_field_out, st, out, L);
-    if (params->precision == NPB_FP32X)
-      return solve_t<float, double>(ctx, mol, grid, params, d_ws, d_field_out, st, out, L);
-    return solve_t<float, float>(ctx, mol, grid, params, d_ws, d_field_out, st, out, L);
+    if (params[0].precision == NPB_FP64) return solve_batch_t<double, double>(ctx, pr, st, out);
+    if (params[0].precision == NPB_FP32X) return solve_batch_t<float, double>(ctx, pr, st, out);
+    return solve_batch_t<float, float>(ctx, pr, st, out);
   } catch (const std::exception& e) {
     return fail(NPB_ENOMEM, e.what());
   } catch (...) {
     return fail(NPB_EDEVICE, "unexpected failure");
   }
+}
+
+npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                     const npb_params* params, void* d_ws, size_t ws_bytes, double* d_field_out,
+                     void* stream, npb_result* out) {
+  if (!ctx || !out) return fail(NPB_EINVAL, "null context or result");
+  if (!mol || !grid || !params) return fail(NPB_EINVAL, "null argument");
+  void* ws[1] = {d_ws};
+  const size_t wb[1] = {ws_bytes};
+  double* fo[1] = {d_field_out};
+  const npb_status s = npb_solve_batch(ctx, 1, mol, grid, params, ws, wb, fo, stream, out);
+  if (s != NPB_OK && g_err.rfind("problem 0: ", 0) == 0) g_err = g_err.substr(11);
+  return s;
 }
 
 }  // extern "C"

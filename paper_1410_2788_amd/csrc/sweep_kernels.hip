@@ -278,10 +278,12 @@ __device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
 // each row move between HBM and an odd-stride LDS tile with 16-byte vector
 // accesses; the row's boundary columns are written back unchanged.
 template <typename T, typename A, int M, int L>
-__global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
+__global__ __launch_bounds__(256) void sweep_x_kernel(const SweepArgs<T>* __restrict__ args,
+                                                      const int2* __restrict__ work) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   extern __shared__ __align__(16) unsigned char smem[];
-  const SweepArgs<T>& a = batch.f[blockIdx.y];
+  const int2 w = work[blockIdx.x];  // (field, block of that field)
+  const SweepArgs<T>& a = args[w.x];
   const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
   const int nx = a.nx, ny = a.ny, nz = a.nz, nxp = a.nxp;
   const int nint = nx - 2;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
   const int nthreads = L * P;
   const int nyi = ny - 2;
   const int nlines = nyi * (nz - 2);
-  const int l0 = blockIdx.x * L;
+  const int l0 = w.y * L;
   const bool uniform = (a.mask == nullptr);
   const bool aos = (a.mode == MODE_AOS_FIRST);
   const int tid = threadIdx.x;
@@ -521,15 +523,16 @@ __global__ __launch_bounds__(256) void sweep_x_kernel(SweepBatch<T> batch) {
 //   kYzPlain   : solve only, in place
 //   kYzFlow    : solve, then the exact sinh flow on solvent nodes, in place
 //   kYzGeneral : sources before/after, flow, AOS accumulation (run-time flags)
-enum { kYzPlain = 0, kYzFlow = 1, kYzGeneral = 2 };
 
 template <typename T, typename A, int M, int VAR, int TW>
-__global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int dir) {
+__global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __restrict__ args,
+                                                       const int2* __restrict__ work, int dir) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   constexpr int TS = TW + 1;                // LDS elements per tile row
   constexpr int VPR = TW / VX;              // vectors per full tile row
   extern __shared__ __align__(16) unsigned char smem[];
-  const SweepArgs<T>& a = batch.f[blockIdx.y];
+  const int2 w = work[blockIdx.x];  // (field, block of that field)
+  const SweepArgs<T>& a = args[w.x];
   const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
   const int nx = a.nx, ny = a.ny, nxp = a.nxp;
   const int P = a.P, nrow = a.S;
@@ -538,8 +541,8 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(SweepBatch<T> batch, int 
   const int n = (dir == 1) ? ny : a.nz;
   const int nint = n - 2;
   const int ntx = (nx - 2) / TW + 1;  // tiles holding interior x
-  const int xt = blockIdx.x % ntx;
-  const int o = 1 + (int)(blockIdx.x / ntx);
+  const int xt = w.y % ntx;
+  const int o = 1 + w.y / ntx;
   const int xb = xt * TW;
   // element offsets fit in 32 bits (n <= 514)
   const uint32_t stride = (dir == 1) ? (uint32_t)nxp : (uint32_t)nxp * (uint32_t)ny;
@@ -871,24 +874,40 @@ template void fill_chunk_tab<float>(ChunkTab<float>&, double, double, int);
 template void fill_chunk_tab<double>(ChunkTab<double>&, double, double, int);
 
 template <typename T>
-static SweepBatch<T> shaped(const SweepBatch<T>& b0, int nf, const LaunchShape& s, int S) {
-  SweepBatch<T> b = b0;
-  for (int f = 0; f < nf; ++f) {
-    b.f[f].M = s.M;
-    b.f[f].P = s.P;
-    b.f[f].LW = s.LW;
-    b.f[f].S = S;
+void shape_args(SweepArgs<T>& a, int dir, const LaunchShape& s) {
+  a.M = s.M;
+  a.P = s.P;
+  a.LW = s.LW;
+  if (dir == 0) {
+    a.S = row4(a.nx) + 1;
+  } else {
+    const int n_along = dir == 1 ? a.ny : a.nz;
+    a.S = std::max(n_along, s.P * s.M + 2);
   }
-  return b;
 }
+template void shape_args<float>(SweepArgs<float>&, int, const LaunchShape&);
+template void shape_args<double>(SweepArgs<double>&, int, const LaunchShape&);
+
+template <typename T>
+int sweep_variant(const SweepArgs<T>* a, int n) {
+  bool general = false, flow = false;
+  for (int f = 0; f < n; ++f) {
+    general = general || a[f].src_stage != 0 || a[f].mode != MODE_INPLACE;
+    flow = flow || (a[f].post_nl && a[f].mask);
+  }
+  return general ? kYzGeneral : (flow ? kYzFlow : kYzPlain);
+}
+template int sweep_variant<float>(const SweepArgs<float>*, int);
+template int sweep_variant<double>(const SweepArgs<double>*, int);
 
 template <typename T, typename A, int L>
-static hipError_t launch_x_l(const SweepBatch<T>& b, int nf, const LaunchShape& s, hipStream_t st) {
-  dim3 g(s.blocks, nf), blk(s.threads);
+static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nblocks,
+                             const LaunchShape& s, hipStream_t st) {
+  dim3 g(nblocks), blk(s.threads);
   switch (s.M) {
 #define NPB_X_CASE(MM) \
   case MM:             \
-    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, b); break;
+    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, args, work); break;
     NPB_X_CASE(4)
     NPB_X_CASE(8)
     NPB_X_CASE(12)
@@ -902,23 +921,23 @@ static hipError_t launch_x_l(const SweepBatch<T>& b, int nf, const LaunchShape& 
 }
 
 template <typename T, typename A>
-hipError_t launch_sweep_x(const SweepBatch<T>& b0, int nf, const LaunchShape& s, hipStream_t st) {
-  if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
-  const SweepBatch<T> b = shaped(b0, nf, s, row4(b0.f[0].nx) + 1);
-  if (s.LW == 32) return launch_x_l<T, A, 32>(b, nf, s, st);
-  if (s.LW == 16) return launch_x_l<T, A, 16>(b, nf, s, st);
-  if (s.LW == 8) return launch_x_l<T, A, 8>(b, nf, s, st);
+hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nblocks,
+                          const LaunchShape& s, hipStream_t st) {
+  if (nblocks < 1) return hipErrorInvalidValue;
+  if (s.LW == 32) return launch_x_l<T, A, 32>(args, work, nblocks, s, st);
+  if (s.LW == 16) return launch_x_l<T, A, 16>(args, work, nblocks, s, st);
+  if (s.LW == 8) return launch_x_l<T, A, 8>(args, work, nblocks, s, st);
   return hipErrorInvalidValue;
 }
 
 template <typename T, typename A, int VAR, int TW>
-static hipError_t launch_yz_tw(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
-                               hipStream_t st) {
-  dim3 g(s.blocks, nf), blk(s.threads);
+static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
+                               const LaunchShape& s, hipStream_t st) {
+  dim3 g(nblocks), blk(s.threads);
   switch (s.M) {
 #define NPB_YZ_CASE(MM) \
   case MM:              \
-    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, b, dir); break;
+    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, args, work, dir); break;
     NPB_YZ_CASE(4)
     NPB_YZ_CASE(8)
     NPB_YZ_CASE(12)
@@ -927,7 +946,7 @@ static hipError_t launch_yz_tw(const SweepBatch<T>& b, int nf, int dir, const La
     case 20:
       // planned only for FP32 arithmetic (FP64 chunks stop at 16 rows)
       if constexpr (sizeof(A) == 4) {
-        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, b, dir);
+        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, args, work, dir);
         break;
       }
       return hipErrorInvalidValue;
@@ -939,38 +958,32 @@ static hipError_t launch_yz_tw(const SweepBatch<T>& b, int nf, int dir, const La
 
 // tile widths compiled: 16 and 32 for FP32 arithmetic, 16 for FP64
 template <typename T, typename A, int VAR>
-static hipError_t launch_yz_var(const SweepBatch<T>& b, int nf, int dir, const LaunchShape& s,
-                                hipStream_t st) {
-  if (s.LW == 16) return launch_yz_tw<T, A, VAR, 16>(b, nf, dir, s, st);
+static hipError_t launch_yz_var(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
+                                const LaunchShape& s, hipStream_t st) {
+  if (s.LW == 16) return launch_yz_tw<T, A, VAR, 16>(args, work, nblocks, dir, s, st);
   if constexpr (sizeof(A) == 4) {
-    if (s.LW == 32) return launch_yz_tw<T, A, VAR, 32>(b, nf, dir, s, st);
+    if (s.LW == 32) return launch_yz_tw<T, A, VAR, 32>(args, work, nblocks, dir, s, st);
   }
   return hipErrorInvalidValue;
 }
 
-// The fused-work variant covers every field of the batch; the flow and
-// source branches are uniform per block.
 template <typename T, typename A>
-hipError_t launch_sweep_yz(const SweepBatch<T>& b0, int nf, int dir, const LaunchShape& s,
-                           hipStream_t st) {
-  if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
-  const int n_along = dir == 1 ? b0.f[0].ny : b0.f[0].nz;
-  const SweepBatch<T> b = shaped(b0, nf, s, std::max(n_along, s.P * s.M + 2));
-  bool general = false, flow = false;
-  for (int f = 0; f < nf; ++f) {
-    general = general || b.f[f].src_stage != 0 || b.f[f].mode != MODE_INPLACE;
-    flow = flow || (b.f[f].post_nl && b.f[f].mask);
-  }
-  if (general) return launch_yz_var<T, A, kYzGeneral>(b, nf, dir, s, st);
-  if (flow) return launch_yz_var<T, A, kYzFlow>(b, nf, dir, s, st);
-  return launch_yz_var<T, A, kYzPlain>(b, nf, dir, s, st);
+hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
+                           int var, const LaunchShape& s, hipStream_t st) {
+  if (nblocks < 1) return hipErrorInvalidValue;
+  if (var == kYzGeneral) return launch_yz_var<T, A, kYzGeneral>(args, work, nblocks, dir, s, st);
+  if (var == kYzFlow) return launch_yz_var<T, A, kYzFlow>(args, work, nblocks, dir, s, st);
+  return launch_yz_var<T, A, kYzPlain>(args, work, nblocks, dir, s, st);
 }
 
-template hipError_t launch_sweep_x<float, float>(const SweepBatch<float>&, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_x<float, double>(const SweepBatch<float>&, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_x<double, double>(const SweepBatch<double>&, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_yz<float, float>(const SweepBatch<float>&, int, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_yz<float, double>(const SweepBatch<float>&, int, int, const LaunchShape&, hipStream_t);
-template hipError_t launch_sweep_yz<double, double>(const SweepBatch<double>&, int, int, const LaunchShape&, hipStream_t);
+#define NPB_INST(T, A)                                                                          \
+  template hipError_t launch_sweep_x<T, A>(const SweepArgs<T>*, const int2*, int,              \
+                                           const LaunchShape&, hipStream_t);                    \
+  template hipError_t launch_sweep_yz<T, A>(const SweepArgs<T>*, const int2*, int, int, int,   \
+                                            const LaunchShape&, hipStream_t);
+NPB_INST(float, float)
+NPB_INST(float, double)
+NPB_INST(double, double)
+#undef NPB_INST
 
 }  // namespace npb

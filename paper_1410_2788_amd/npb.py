@@ -98,6 +98,10 @@ def load_library(path: str = LIB_PATH):
         lib.npb_workspace_bytes.restype = C.c_int
         lib.npb_workspace_bytes.argtypes = [P(npb_molecule), P(npb_grid), P(npb_params),
                                             P(C.c_size_t)]
+        lib.npb_solve_batch.restype = C.c_int
+        lib.npb_solve_batch.argtypes = [C.c_void_p, C.c_int, P(npb_molecule), P(npb_grid),
+                                        P(npb_params), P(C.c_void_p), P(C.c_size_t),
+                                        P(C.c_void_p), C.c_void_p, P(npb_result)]
         lib.npb_solve.restype = C.c_int
         lib.npb_solve.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, P(npb_result)]
@@ -182,6 +186,26 @@ def npb_solve(ctx, mol: npb_molecule, grid: npb_grid, params: npb_params, d_ws: 
     return res
 
 
+def npb_solve_batch(ctx, mols, grids, params, d_ws, ws_bytes, d_field_out, stream) -> list:
+    """Arrays of C structs / pointers in, a list of npb_result out."""
+    n = len(mols)
+    M = (npb_molecule * n)(*mols)
+    G = (npb_grid * n)(*grids)
+    Pp = (npb_params * n)(*params)
+    W = (C.c_void_p * n)(*[C.c_void_p(p) for p in d_ws])
+    B = (C.c_size_t * n)(*ws_bytes)
+    F = None
+    if d_field_out is not None:
+        F = (C.c_void_p * n)(*[C.c_void_p(p) if p else None for p in d_field_out])
+    R = (npb_result * n)()
+    st = load_library().npb_solve_batch(ctx, n, M, G, Pp, W, B, F, C.c_void_p(stream), R)
+    if st != NPB_OK:
+        err = NPBError(st, npb_last_error())
+        err.results = list(R)
+        raise err
+    return list(R)
+
+
 # ---------------------------------------------------------------------------
 # marshalling helpers
 
@@ -247,6 +271,38 @@ class Solver:
                         self.ws_bytes, self.field.data_ptr() if self.field is not None else None,
                         stream)
         return result_dict(res)
+
+
+class BatchSolver:
+    """Device state for a batch of problems (any mix of sizes): one
+    workspace per problem, allocated once; `run` solves them all together
+    with npb_solve_batch on the current torch stream."""
+
+    def __init__(self, problems, device: int = 0, want_field: bool = False):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.mols = [Molecule(m.xyz, m.q, m.radius) for m, _, _ in problems]
+        self.grids = [make_grid(g) for _, g, _ in problems]
+        self.params = [make_params(p) for _, _, p in problems]
+        self.ctx = context(device)
+        dev = torch.device("cuda", device)
+        self.ws_bytes = [npb_workspace_bytes(m.c, g, p)
+                         for m, g, p in zip(self.mols, self.grids, self.params)]
+        self.ws = [torch.empty(b, dtype=torch.uint8, device=dev) for b in self.ws_bytes]
+        self.fields = None
+        if want_field:
+            self.fields = [torch.empty((g.nz, g.ny, g.nx), dtype=torch.float64, device=dev)
+                           for _, g, _ in problems]
+
+    def run(self) -> list:
+        torch = self.torch
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        res = npb_solve_batch(self.ctx, [m.c for m in self.mols], self.grids, self.params,
+                              [w.data_ptr() for w in self.ws], self.ws_bytes,
+                              [f.data_ptr() for f in self.fields] if self.fields else None,
+                              stream)
+        return [result_dict(r) for r in res]
 
 
 def result_dict(res: npb_result) -> dict:

@@ -98,3 +98,26 @@ def test_solve_without_context_is_rejected(npb):
     st = lib.npb_solve(None, ctypes.byref(m.c), ctypes.byref(g), ctypes.byref(p), None, 0, None,
                        None, ctypes.byref(res))
     assert st == npb.NPB_EINVAL
+
+
+def test_batch_rejects_bad_arguments_before_device_work(npb):
+    w = inputs.small_globular(n=21, n_atoms=4)
+    w2 = inputs.small_globular(n=25, n_atoms=6, precision="f32")
+    m1, g1, p1 = _c(npb, w)
+    m2, g2, p2 = _c(npb, w2)
+    fake = [256 * 1024, 512 * 1024]  # never dereferenced: validation fails first
+    big = [1 << 30, 1 << 30]
+    with pytest.raises(npb.NPBError) as ei:
+        npb.npb_solve_batch(None, [m1.c, m2.c], [g1, g2], [p1, p2], fake, big, None, 0)
+    assert ei.value.status == npb.NPB_EINVAL
+    ctx_like = ctypes.c_void_p(1)  # validation precedes any use of the context
+    with pytest.raises(npb.NPBError) as ei:
+        npb.npb_solve_batch(ctx_like, [m1.c, m2.c], [g1, g2], [p1, p2], fake, big, None, 0)
+    assert ei.value.status == npb.NPB_EINVAL and "one precision" in npb.npb_last_error()
+    with pytest.raises(npb.NPBError) as ei:
+        npb.npb_solve_batch(ctx_like, [m1.c, m1.c], [g1, g1], [p1, p1], [fake[0], fake[0]], big,
+                            None, 0)
+    assert ei.value.status == npb.NPB_EINVAL and "shared" in npb.npb_last_error()
+    with pytest.raises(npb.NPBError) as ei:
+        npb.npb_solve_batch(ctx_like, [m1.c, m1.c], [g1, g1], [p1, p1], fake, [1, 1], None, 0)
+    assert ei.value.status == npb.NPB_EINVAL and "problem 0" in npb.npb_last_error()
