@@ -221,6 +221,47 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols,
                            void* const* d_ws, const size_t* ws_bytes,
                            double* const* d_field_out, void* stream, npb_result* out);
 
+/* ---- request loop (serving) ----------------------------------------------
+ * A server solves molecules as they arrive.  It owns a device arena of
+ * hbm_budget bytes and one worker thread with its own context and stream.
+ * Requests are admitted in arrival order while their workspaces
+ * (npb_workspace_bytes) fit the arena, at most max_batch at a time, and
+ * each admitted set is solved by npb_solve_batch; when it finishes the next
+ * set is formed from whatever is waiting (continuous batching).  No field is
+ * returned, only npb_result.  Callers for whom the step-by-step path of one
+ * molecule matters use npb_solve. */
+typedef struct npb_server npb_server;
+
+typedef struct npb_server_stats {
+  int64_t submitted, completed, failed, refused, batches, queued;
+  double busy_ms;          /* wall time of the worker inside npb_solve_batch */
+  double p50_ms, p99_ms;   /* submit -> result latency of finished requests */
+} npb_server_stats;
+
+/* Create a server on ctx's device (ctx is only read; the server keeps its
+ * own).  max_queue bounds the requests waiting for admission.  Errors:
+ * EINVAL, ENOMEM (arena), EDEVICE. */
+npb_status npb_server_create(npb_ctx* ctx, size_t hbm_budget, int max_batch, int max_queue,
+                             npb_server** out);
+
+/* Queue one request; the molecule arrays are copied before returning.
+ * *ticket identifies it for npb_poll.  Errors: EINVAL / ERANGE (the checks
+ * of npb_validate), EBUSY (its workspace exceeds the arena, or the queue is
+ * full: admission refused). */
+npb_status npb_submit(npb_server* server, const npb_molecule* mol, const npb_grid* grid,
+                      const npb_params* params, uint64_t* ticket);
+
+/* *done = 0 while the request is queued or running.  Once done: *done = 1,
+ * *out holds its result, the ticket is released, and the return value is
+ * the request's own status (NPB_OK, EDIVERGED, or the batch's device
+ * error).  Unknown or released ticket: EINVAL. */
+npb_status npb_poll(npb_server* server, uint64_t ticket, npb_result* out, int* done);
+
+npb_status npb_server_get_stats(npb_server* server, npb_server_stats* out);
+
+/* Finishes every queued request, then frees the arena and the worker. */
+void npb_server_destroy(npb_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,12 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "npb.h"
+
 namespace npb {
+
+// device of a context (the server's worker uses the same device)
+int ctx_device(const npb_ctx* ctx);
 
 // ---------------------------------------------------------------------------
 // Arguments of one implicit line sweep (one of the 1-D sub-steps of the

@@ -212,6 +212,8 @@ struct npb_ctx {
   hipEvent_t t0 = nullptr, t1 = nullptr;
 };
 
+int npb::ctx_device(const npb_ctx* ctx) { return ctx->device; }
+
 namespace {
 
 hipEvent_t ev_get(npb_ctx* c) {

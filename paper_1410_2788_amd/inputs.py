@@ -216,6 +216,14 @@ def batch_mix(n_mol: int = 64, seed: int = 3, precision: str = "f32",
     return out
 
 
+def serve_requests(n_req: int, seed: int = 4, precision: str = "f32") -> List[Workload]:
+    """Serving requests: atom counts log-uniform in [500, 20000] (seeds
+    (seed, i)), grids 103..257 nodes at h = 0.5 from the cluster size,
+    LODIE2 RE+V with 20 / 40 steps."""
+    return batch_mix(n_mol=n_req, seed=seed, precision=precision, n_min=103, n_max=257,
+                     a_lo=500.0, a_hi=20000.0, n_steps=20)
+
+
 def poisson_arrivals(rate_per_s: float, n_req: int, seed: int = 4) -> np.ndarray:
     """Arrival times (s) of a Poisson stream."""
     rng = np.random.default_rng(seed)

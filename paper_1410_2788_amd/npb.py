@@ -55,6 +55,12 @@ class npb_kernel_times(C.Structure):
     _fields_ = [("count", C.c_int64 * 8), ("ms", C.c_double * 8), ("bytes", C.c_double * 8)]
 
 
+class npb_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("refused", C.c_int64), ("batches", C.c_int64), ("queued", C.c_int64),
+                ("busy_ms", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double)]
+
+
 class NPBError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -102,6 +108,18 @@ def load_library(path: str = LIB_PATH):
         lib.npb_solve_batch.argtypes = [C.c_void_p, C.c_int, P(npb_molecule), P(npb_grid),
                                         P(npb_params), P(C.c_void_p), P(C.c_size_t),
                                         P(C.c_void_p), C.c_void_p, P(npb_result)]
+        lib.npb_server_create.restype = C.c_int
+        lib.npb_server_create.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_int,
+                                          P(C.c_void_p)]
+        lib.npb_submit.restype = C.c_int
+        lib.npb_submit.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
+                                   P(C.c_uint64)]
+        lib.npb_poll.restype = C.c_int
+        lib.npb_poll.argtypes = [C.c_void_p, C.c_uint64, P(npb_result), P(C.c_int)]
+        lib.npb_server_get_stats.restype = C.c_int
+        lib.npb_server_get_stats.argtypes = [C.c_void_p, P(npb_server_stats)]
+        lib.npb_server_destroy.restype = None
+        lib.npb_server_destroy.argtypes = [C.c_void_p]
         lib.npb_solve.restype = C.c_int
         lib.npb_solve.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, P(npb_result)]
@@ -206,6 +224,41 @@ def npb_solve_batch(ctx, mols, grids, params, d_ws, ws_bytes, d_field_out, strea
     return list(R)
 
 
+def npb_server_create(ctx, hbm_budget: int, max_batch: int = 16, max_queue: int = 256):
+    sv = C.c_void_p()
+    _check(load_library().npb_server_create(ctx, hbm_budget, max_batch, max_queue,
+                                            C.byref(sv)))
+    return sv
+
+
+def npb_submit(server, mol: npb_molecule, grid: npb_grid, params: npb_params) -> int:
+    t = C.c_uint64()
+    _check(load_library().npb_submit(server, C.byref(mol), C.byref(grid), C.byref(params),
+                                     C.byref(t)))
+    return int(t.value)
+
+
+def npb_poll(server, ticket: int):
+    """(done, status, npb_result or None); raises NPBError for an unknown ticket."""
+    res = npb_result()
+    done = C.c_int()
+    st = load_library().npb_poll(server, ticket, C.byref(res), C.byref(done))
+    if not done.value:
+        _check(st)
+        return False, NPB_OK, None
+    return True, st, res
+
+
+def npb_server_get_stats(server) -> dict:
+    s = npb_server_stats()
+    _check(load_library().npb_server_get_stats(server, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in npb_server_stats._fields_}
+
+
+def npb_server_destroy(server) -> None:
+    load_library().npb_server_destroy(server)
+
+
 # ---------------------------------------------------------------------------
 # marshalling helpers
 
@@ -303,6 +356,33 @@ class BatchSolver:
                               [f.data_ptr() for f in self.fields] if self.fields else None,
                               stream)
         return [result_dict(r) for r in res]
+
+
+class Server:
+    """The request loop of include/npb.h: submit molecules as they arrive,
+    poll for results.  hbm_budget bytes of device memory are held until
+    close()."""
+
+    def __init__(self, hbm_budget: int, max_batch: int = 16, max_queue: int = 256,
+                 device: int = 0):
+        self.handle = npb_server_create(context(device), hbm_budget, max_batch, max_queue)
+
+    def submit(self, mol, grid, params) -> int:
+        m = Molecule(mol.xyz, mol.q, mol.radius)  # copied by the library before returning
+        return npb_submit(self.handle, m.c, make_grid(grid), make_params(params))
+
+    def poll(self, ticket: int):
+        """None while pending, else (status, result dict)."""
+        done, st, res = npb_poll(self.handle, ticket)
+        return None if not done else (st, result_dict(res))
+
+    def stats(self) -> dict:
+        return npb_server_get_stats(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            npb_server_destroy(self.handle)
+            self.handle = None
 
 
 def result_dict(res: npb_result) -> dict:
