@@ -76,6 +76,112 @@ def cpu_baseline(workload, n_steps_meas: int = 2):
             "seconds_measured": t_setup + n_steps_meas * t_step}
 
 
+def bench_batch(args):
+    """64 uneven grids (atom counts log-uniform 200..5000, 79..193 nodes at
+    h = 0.5), LODIE2 RE+V, solved together by npb_solve_batch."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2788_amd import inputs, npb
+    probs = inputs.batch_mix(n_mol=64, seed=3, precision=args.precision)
+    bs = npb.BatchSolver([(w.molecule, w.grid, w.params) for w in probs])
+    print(f"[bench] batch of {len(probs)} grids, {sum(w.grid.nx ** 3 for w in probs) / 1e6:.1f} M nodes",
+          file=sys.stderr, flush=True)
+    for _ in range(max(1, args.warmup)):
+        res = bs.run()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        res = bs.run()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    pts = sum(r["grid_point_updates"] for r in res)
+    finite = sum(1 for r in res if r["finite"])
+    return {"metric": "LOD grid-point-updates/s, batch of uneven grids", "value": pts * finite / len(res) / (ms * 1e-3),
+            "unit": "grid-point-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": args.precision, "data": "synthetic",
+            "config": {"workload": "batch_mix_64_seed3", "grids": [w.grid.nx for w in probs],
+                       "scheme": "LODIE2", "richardson": True, "vacuum": True,
+                       "grid_point_updates_per_batch": pts, "finite": finite}}
+
+
+def bench_serve(args):
+    """Serving: requests with atom counts log-uniform 500..20000 (grids
+    103..257 at h = 0.5), LODIE2 RE+V 20/40 steps, Poisson arrivals (seed 4)
+    at 70 % of the capacity measured with a saturated queue first."""
+    import numpy as np
+
+    from paper_1410_2788_amd import inputs, npb
+    reqs = inputs.serve_requests(args.requests, seed=4, precision=args.precision)
+    budget = int(args.arena_gb * (1 << 30))
+    sv = npb.Server(budget, max_batch=args.max_batch, max_queue=4 * len(reqs))
+
+    def drain(tickets):
+        lat, done, t_end = {}, set(), None
+        while len(done) < len(tickets):
+            for t in tickets:
+                if t not in done:
+                    r = sv.poll(t)
+                    if r is not None:
+                        done.add(t)
+                        lat[t] = (time.perf_counter(), r[0], r[1])
+            time.sleep(0.0005)
+        return lat
+
+    try:
+        # warm-up and capacity: everything submitted at once
+        drain([sv.submit(w.molecule, w.grid, w.params) for w in reqs[:4]])
+        t0 = time.perf_counter()
+        tk = [sv.submit(w.molecule, w.grid, w.params) for w in reqs]
+        drain(tk)
+        cap = len(reqs) / (time.perf_counter() - t0)
+        rate = 0.7 * cap
+        arr = inputs.poisson_arrivals(rate, len(reqs), seed=4)
+        print(f"[bench] serve: capacity {cap:.2f} req/s, arrivals at {rate:.2f} req/s",
+              file=sys.stderr, flush=True)
+        before = sv.stats()
+        t0 = time.perf_counter()
+        sub = {}
+        i = 0
+        pending = []
+        lat = {}
+        while len(lat) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and arr[i] <= now:
+                t = sv.submit(reqs[i].molecule, reqs[i].grid, reqs[i].params)
+                sub[t] = time.perf_counter()
+                pending.append(t)
+                i += 1
+            for t in list(pending):
+                r = sv.poll(t)
+                if r is not None:
+                    lat[t] = (time.perf_counter() - sub[t], r[0], r[1])
+                    pending.remove(t)
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        after = sv.stats()
+    finally:
+        sv.close()
+    ls = np.array([v[0] for v in lat.values()]) * 1e3
+    pts = sum(v[2]["grid_point_updates"] for v in lat.values() if v[1] == npb.NPB_OK)
+    return {"metric": "serving: LOD grid-point-updates/s and p50/p99 request latency",
+            "value": pts / wall, "unit": "grid-point-updates/s", "n_gpus": 1,
+            "steps": len(reqs), "warmup": 4, "ms_per_step": wall * 1e3 / len(reqs),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": args.precision, "data": "synthetic",
+            "config": {"workload": f"serve_requests_{len(reqs)}_seed4", "arrival_rate_per_s": rate,
+                       "capacity_per_s": cap, "arena_bytes": budget, "max_batch": args.max_batch,
+                       "grids": [w.grid.nx for w in reqs]},
+            "latency_ms": {"p50": float(np.percentile(ls, 50)), "p99": float(np.percentile(ls, 99)),
+                           "max": float(ls.max())},
+            "server": {k: after[k] - before.get(k, 0) if k in ("submitted", "completed", "failed", "batches") else after[k]
+                       for k in after}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +192,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-kernel event timing pass")
+    ap.add_argument("--batch", action="store_true",
+                    help="time a batch of 64 uneven grids instead (own JSON line)")
+    ap.add_argument("--serve", action="store_true",
+                    help="time the request loop under Poisson arrivals instead (own JSON line)")
+    ap.add_argument("--requests", type=int, default=48)
+    ap.add_argument("--arena-gb", type=float, default=24.0)
+    ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with plain device copies of 256 MiB (FP32) that calibrate "
                          "the HBM byte counters of a profiler run")
@@ -94,6 +207,13 @@ def main():
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+
+    if args.batch:
+        print(json.dumps(bench_batch(args)))
+        return
+    if args.serve:
+        print(json.dumps(bench_serve(args)))
+        return
 
     import numpy as np
     import torch
