@@ -221,6 +221,26 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols,
                            void* const* d_ws, const size_t* ws_bytes,
                            double* const* d_field_out, void* stream, npb_result* out);
 
+/* Choose the line-solver launch shapes for this grid size, precision and
+ * splitting family (LOD / AOS) by timing: the problem is set up in d_ws
+ * (as npb_solve would), then for each sweep direction every candidate shape
+ * (target chunk length 12, 16 or 20 rows; x: 32, 16 or 8 lines per block;
+ * y, z: tile width 32 or 16) sweeps all of the problem's runs a few times
+ * on `stream`, and the fastest is recorded in ctx.  Later npb_solve,
+ * npb_solve_batch and servers created from ctx use the recorded shapes for
+ * grids of that size (results change only by rounding: a different chunk
+ * partition).  ms_out (nullable, 3 entries): mean launch time of the chosen
+ * shape per direction.  The workspace's fields are left undefined. */
+npb_status npb_autotune(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                        const npb_params* params, void* d_ws, size_t ws_bytes, void* stream,
+                        double* ms_out);
+
+/* Launch shapes a solve on ctx (NULL: the built-in defaults) would use:
+ * out[4 d + 0..3] = rows per chunk, chunks per line, lines per block (x) or
+ * tile width (y, z), threads per block, for d = x, y, z.  Pure host. */
+npb_status npb_launch_shapes(const npb_ctx* ctx, const npb_grid* grid, const npb_params* params,
+                             int32_t* out);
+
 /* ---- request loop (serving) ----------------------------------------------
  * A server solves molecules as they arrive.  It owns a device arena of
  * hbm_budget bytes and one worker thread with its own context and stream.

@@ -10,8 +10,10 @@
 
 namespace npb {
 
-// device of a context (the server's worker uses the same device)
+// device of a context (the server's worker uses the same device), and the
+// tuned line-solver shapes it hands to a server's own context
 int ctx_device(const npb_ctx* ctx);
+void copy_tuning(const npb_ctx* from, npb_ctx* to);
 
 // ---------------------------------------------------------------------------
 // Arguments of one implicit line sweep (one of the 1-D sub-steps of the
@@ -99,8 +101,25 @@ struct ChunkTab {
 // Pick chunk length / chunk count and the block shape for a line length.
 // plan_x: fp64 = arithmetic type is double.  plan_yz: lines along an axis of
 // n_along nodes, n_other nodes on the other transverse axis.
-LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform);
-LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64_arith);
+// mt: target chunk length (0 = default), lw / tw: preferred lines per block
+// (x: 32, 16, 8) or tile width (y/z: 16, 32); 0 = default heuristic.  An
+// unsupported combination returns a shape with M == 0.
+LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, int mt = 0,
+                   int lw = 0);
+LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt = 0, int tw = 0);
+
+// Largest chunk count per line any planner choice can produce (chunk-class
+// tables are sized for it, so the workspace does not depend on the choice).
+inline int max_chunks(int n_along, bool x_dir) {
+  const int nint = n_along - 2;
+  int P = (nint + 11) / 12;  // shortest target chunk a tuner tries: 12 rows
+  if (x_dir) {
+    int q = 1;
+    while (q < P) q <<= 1;
+    P = q;
+  }
+  return P;
+}
 
 // number of interior lines of a direction (entries per chunk of its class
 // table): x lines (y, z) -> (z-1)(ny-2) + y-1; y lines (z, x) -> (z-1)(nx-2)

@@ -3,7 +3,9 @@
 // energy kernels (field initialisation, FP64 energy gathers, the
 // solvated-minus-vacuum and Richardson combinations).
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -195,6 +197,11 @@ struct npb_ctx {
   hipStream_t capture = nullptr;  // stream the solve graph is captured on
   hipGraphExec_t exec = nullptr;
   std::vector<unsigned char> key;  // GraphKey per problem + the launch-table buffer
+  // line-solver shapes chosen by npb_autotune, per (nx, ny, nz, precision,
+  // aos): for x (target chunk, lines per block), y and z (target chunk,
+  // tile width); tune_gen changes whenever the table does
+  std::map<std::array<int, 5>, std::array<int, 6>> tune;
+  int tune_gen = 0;
   // device buffer of the launch tables (per-field sweep arguments, work
   // lists), owned by the context and grown on demand
   void* meta = nullptr;
@@ -213,6 +220,10 @@ struct npb_ctx {
 };
 
 int npb::ctx_device(const npb_ctx* ctx) { return ctx->device; }
+void npb::copy_tuning(const npb_ctx* from, npb_ctx* to) {
+  to->tune = from->tune;
+  to->tune_gen += 1;
+}
 
 namespace {
 
@@ -326,9 +337,10 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
     L.shape[0] = plan_x(g->nx, g->ny, g->nz, f64a, aos, false);
     L.shape[1] = plan_yz(g->nx, g->ny, g->nz, f64a);
     L.shape[2] = plan_yz(g->nx, g->nz, g->ny, f64a);
+    const int na_d[3] = {g->nx, g->ny, g->nz};
     for (int d = 0; d < 3; ++d) {
       const long long nl = class_lines(g->nx, g->ny, g->nz, d);
-      L.ccls[d] = take((size_t)nl * (size_t)(L.shape[d].P > 0 ? L.shape[d].P : 1));
+      L.ccls[d] = take((size_t)nl * (size_t)max_chunks(na_d[d], d == 0));
     }
   }
   L.slots = take(32 * 8);
@@ -337,6 +349,31 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   L.cap = cap;
   L.nblocks = nb;
   return L;
+}
+
+std::array<int, 5> tune_key(const npb_grid* g, const npb_params* p) {
+  const int aos = (p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2) ? 1 : 0;
+  return {g->nx, g->ny, g->nz, p->precision, aos};
+}
+
+// shapes of a tuned choice c = {x: mt, lw; y: mt, tw; z: mt, tw}
+void tuned_shapes(const npb_grid* g, const npb_params* p, const std::array<int, 6>& c,
+                  LaunchShape out[3]) {
+  const bool f64a = p->precision != NPB_FP32;
+  const bool aos = p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2;
+  out[0] = plan_x(g->nx, g->ny, g->nz, f64a, aos, false, c[0], c[1]);
+  out[1] = plan_yz(g->nx, g->ny, g->nz, f64a, c[2], c[3]);
+  out[2] = plan_yz(g->nx, g->nz, g->ny, f64a, c[4], c[5]);
+}
+
+// the context's tuned shapes, where it has them, replace the defaults
+void apply_tuning(const npb_ctx* ctx, const npb_grid* g, const npb_params* p, Layout& L) {
+  auto it = ctx->tune.find(tune_key(g, p));
+  if (it == ctx->tune.end()) return;
+  LaunchShape sh[3];
+  tuned_shapes(g, p, it->second, sh);
+  for (int d = 0; d < 3; ++d)
+    if (sh[d].M != 0) L.shape[d] = sh[d];
 }
 
 constexpr int kMaxN = 514;
@@ -856,9 +893,10 @@ struct Engine {
   }
 
   std::vector<unsigned char> graph_key() const {
-    std::vector<unsigned char> k(sizeof(int) + sizeof(GraphKey) * pr.size(), 0);
+    std::vector<unsigned char> k(2 * sizeof(int) + sizeof(GraphKey) * pr.size(), 0);
     const int prec = (int)sizeof(T) * 16 + (int)sizeof(A);
     std::memcpy(k.data(), &prec, sizeof(int));
+    std::memcpy(k.data() + sizeof(int), &ctx->tune_gen, sizeof(int));
     for (size_t i = 0; i < pr.size(); ++i) {
       GraphKey g;
       std::memset(&g, 0, sizeof(g));
@@ -867,7 +905,7 @@ struct Engine {
       g.grid = *pr[i].g;
       g.params = *pr[i].p;
       g.n_atoms = pr[i].mol->n_atoms;
-      std::memcpy(k.data() + sizeof(int) + i * sizeof(GraphKey), &g, sizeof(g));
+      std::memcpy(k.data() + 2 * sizeof(int) + i * sizeof(GraphKey), &g, sizeof(g));
     }
     return k;
   }
@@ -962,6 +1000,137 @@ struct Engine {
     return worst;
   }
 };
+
+// Line-solver shape tuning on one problem: its setup, then for each sweep
+// direction every candidate (target chunk length x lines per block or tile
+// width) is timed over all of the problem's runs, as the solve sweeps them;
+// the fastest is kept.  The fields end in an arbitrary state (the next solve
+// initialises them again).
+template <typename T, typename A>
+npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
+                      std::array<int, 6>& choice, double ms[3]) {
+  Engine<T, A> E{ctx, st, pr, {}, {}, {}};
+  Problem& P = pr[0];
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  struct Restore {
+    npb_ctx* c;
+    bool t;
+    ~Restore() { c->timing = t; }
+  } restore{ctx, timing};
+  npb_status s = E.plan();
+  if (s != NPB_OK) return s;
+  s = E.stage(true);
+  if (s != NPB_OK) return s;
+  s = E.setup(P);
+  if (s != NPB_OK) return s;
+  const int nx = P.g->nx, ny = P.g->ny, nz = P.g->nz;
+  const int nxp = pitch_of(nx, (int)sizeof(T));
+  for (int r = 0; r < P.L.n_runs; ++r) {
+    const bool vac = P.L.runs[r].medium == 1;
+    NPB_HIP(launch_field_init<T>(P.at<T>(P.L.field[r]), P.at<double>(vac ? P.L.bc_v : P.L.bc_s),
+                                 nx, nxp, ny, nz, st));
+  }
+  const bool f64a = P.p->precision != NPB_FP32;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  NPB_HIP(hipEventCreate(&e0));
+  NPB_HIP(hipEventCreate(&e1));
+  void* dbuf = nullptr;
+  size_t dbytes = 0;
+  struct Free {
+    hipEvent_t a, b;
+    void** buf;
+    ~Free() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      if (*buf) (void)hipFree(*buf);
+    }
+  } cleanup{e0, e1, &dbuf};
+  const int nr = P.L.n_runs;
+  for (int d = 0; d < 3; ++d) {
+    double best = 1e300;
+    LaunchShape best_shape = P.L.shape[d];
+    int bc0 = 0, bc1 = 0;
+    std::vector<std::array<int, 3>> tried;
+    for (int mt : {12, 16, 20}) {
+      for (int pref : {32, 16, 8}) {
+        if (d > 0 && pref == 8) continue;
+        const LaunchShape sh = d == 0 ? plan_x(nx, ny, nz, f64a, P.aos(), false, mt, pref)
+                                      : plan_yz(nx, d == 1 ? ny : nz, d == 1 ? nz : ny, f64a, mt,
+                                                pref);
+        if (sh.M == 0) continue;
+        const std::array<int, 3> id{sh.M, sh.P, sh.LW};
+        if (std::find(tried.begin(), tried.end(), id) != tried.end()) continue;
+        tried.push_back(id);
+        P.L.shape[d] = sh;
+        NPB_HIP(launch_chunk_classes(P.at<uint8_t>(P.L.mask), nx, nxp, ny, nz, d, sh.M, sh.P,
+                                     P.at<uint8_t>(P.L.ccls[d]), st));
+        // chunk tables of this chunk length for every run
+        NPB_HIP(hipStreamSynchronize(st));
+        unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
+        for (int r = 0; r < nr; ++r) {
+          const Coefs c = run_coefs(P, P.L.runs[r]);
+          ChunkTab<A>& tb =
+              *reinterpret_cast<ChunkTab<A>*>(hb + P.tabs_pinned + kTabBytes * (3 * r + d));
+          if (c.vacuum)
+            fill_chunk_tab(tb, c.re_uniform, c.re_uniform, sh.M);
+          else
+            fill_chunk_tab(tb, c.re[0], c.re[2], sh.M);
+          NPB_HIP(hipMemcpyAsync(P.ws + P.L.tabs + kTabBytes * (3 * r + d),
+                                 hb + P.tabs_pinned + kTabBytes * (3 * r + d), kTabBytes,
+                                 hipMemcpyHostToDevice, st));
+        }
+        // launch tables: every run, all blocks
+        std::vector<SweepArgs<T>> args(nr);
+        for (int r = 0; r < nr; ++r) args[r] = E.sweep_args(P, r, d);
+        const int nb = sh.blocks * nr;
+        std::vector<int2> work(nb);
+        for (int r = 0, k = 0; r < nr; ++r)
+          for (int b = 0; b < sh.blocks; ++b) work[k++] = make_int2(r, b);
+        const size_t ab = (sizeof(SweepArgs<T>) * nr + 255) & ~size_t(255);
+        const size_t need = ab + sizeof(int2) * nb;
+        if (need > dbytes) {
+          NPB_HIP(hipStreamSynchronize(st));
+          if (dbuf) (void)hipFree(dbuf);
+          dbuf = nullptr;
+          NPB_HIP(hipMalloc(&dbuf, need));
+          dbytes = need;
+        }
+        NPB_HIP(hipStreamSynchronize(st));
+        NPB_HIP(hipMemcpy(dbuf, args.data(), sizeof(SweepArgs<T>) * nr, hipMemcpyHostToDevice));
+        NPB_HIP(hipMemcpy(static_cast<unsigned char*>(dbuf) + ab, work.data(),
+                          sizeof(int2) * nb, hipMemcpyHostToDevice));
+        const auto* dargs = static_cast<const SweepArgs<T>*>(dbuf);
+        const auto* dwork = reinterpret_cast<const int2*>(static_cast<unsigned char*>(dbuf) + ab);
+        const int var = sweep_variant(args.data(), nr);
+        auto launch = [&] {
+          return d == 0 ? launch_sweep_x<T, A>(dargs, dwork, nb, sh, st)
+                        : launch_sweep_yz<T, A>(dargs, dwork, nb, d, var, sh, st);
+        };
+        constexpr int kWarm = 2, kReps = 5;
+        for (int i = 0; i < kWarm; ++i) NPB_HIP(launch());
+        NPB_HIP(hipEventRecord(e0, st));
+        for (int i = 0; i < kReps; ++i) NPB_HIP(launch());
+        NPB_HIP(hipEventRecord(e1, st));
+        NPB_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        NPB_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (t / kReps < best) {
+          best = t / kReps;
+          best_shape = sh;
+          bc0 = mt;
+          bc1 = pref;
+        }
+      }
+    }
+    P.L.shape[d] = best_shape;
+    choice[2 * d] = bc0;
+    choice[2 * d + 1] = bc1;
+    ms[d] = best;
+  }
+  NPB_HIP(hipStreamSynchronize(st));
+  return NPB_OK;
+}
 
 template <typename T, typename A>
 npb_status solve_batch_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st, npb_result* out) {
@@ -1086,6 +1255,8 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols, const 
         return fail(NPB_EINVAL, "problem " + std::to_string(i) + ": workspace shared with problem " +
                                     std::to_string(j));
   }
+  // every argument checked: only now is the context read
+  for (Problem& P : pr) apply_tuning(ctx, P.g, P.p, P.L);
   NPB_HIP(hipSetDevice(ctx->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   try {
@@ -1097,6 +1268,65 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols, const 
   } catch (...) {
     return fail(NPB_EDEVICE, "unexpected failure");
   }
+}
+
+npb_status npb_autotune(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                        const npb_params* params, void* d_ws, size_t ws_bytes, void* stream,
+                        double* ms_out) {
+  if (!ctx || !mol || !grid || !params) return fail(NPB_EINVAL, "null argument");
+  npb_status s = validate(mol, grid, params);
+  if (s != NPB_OK) return s;
+  std::vector<Problem> pr(1);
+  Problem& P = pr[0];
+  P.mol = mol;
+  P.g = grid;
+  P.p = params;
+  P.ws = reinterpret_cast<unsigned char*>(d_ws);
+  P.fout = nullptr;
+  P.L = make_layout(mol, grid, params);
+  P.kT = thermal_energy(params->temperature_K);
+  P.lB = bjerrum(params->temperature_K);
+  if (!P.ws || ws_bytes < P.L.total)
+    return fail(NPB_EINVAL, "workspace missing or smaller than npb_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(P.ws) % 256 != 0)
+    return fail(NPB_EINVAL, "workspace must be 256-byte aligned");
+  NPB_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::array<int, 6> choice{};
+  double ms[3] = {0, 0, 0};
+  try {
+    if (params->precision == NPB_FP64)
+      s = autotune_t<double, double>(ctx, pr, st, choice, ms);
+    else if (params->precision == NPB_FP32X)
+      s = autotune_t<float, double>(ctx, pr, st, choice, ms);
+    else
+      s = autotune_t<float, float>(ctx, pr, st, choice, ms);
+  } catch (const std::exception& e) {
+    return fail(NPB_ENOMEM, e.what());
+  }
+  if (s != NPB_OK) return s;
+  ctx->tune[tune_key(grid, params)] = choice;
+  ctx->tune_gen += 1;
+  if (ms_out)
+    for (int d = 0; d < 3; ++d) ms_out[d] = ms[d];
+  return NPB_OK;
+}
+
+npb_status npb_launch_shapes(const npb_ctx* ctx, const npb_grid* grid, const npb_params* params,
+                             int32_t* out) {
+  if (!grid || !params || !out) return fail(NPB_EINVAL, "null argument");
+  npb_molecule none{0, nullptr, nullptr, nullptr};
+  npb_status s = validate(&none, grid, params);
+  if (s != NPB_OK) return s;
+  Layout L = make_layout(&none, grid, params);
+  if (ctx) apply_tuning(ctx, grid, params, L);
+  for (int d = 0; d < 3; ++d) {
+    out[4 * d] = L.shape[d].M;
+    out[4 * d + 1] = L.shape[d].P;
+    out[4 * d + 2] = L.shape[d].LW;
+    out[4 * d + 3] = L.shape[d].threads;
+  }
+  return NPB_OK;
 }
 
 npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,

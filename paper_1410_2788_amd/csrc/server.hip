@@ -159,6 +159,7 @@ npb_status npb_server_create(npb_ctx* ctx, size_t hbm_budget, int max_batch, int
   }
   // batches differ from one to the next: direct launches, no graph capture
   (void)npb_ctx_set_graph(sv->ctx, 0);
+  npb::copy_tuning(ctx, sv->ctx);
   if (hipSetDevice(device) != hipSuccess ||
       hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess) {
     npb_ctx_destroy(sv->ctx);

@@ -769,16 +769,19 @@ static int next_pow2(int v) {
   return p;
 }
 
-LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
+LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, int mt, int lw) {
   LaunchShape s{};
   const int nint = nx - 2;
   const int es = fp64 ? 8 : 4;
   const int nx4 = row4(nx);
-  int P = next_pow2((nint + 19) / 20);
+  if (mt <= 0) mt = 20;
+  if (lw <= 0) lw = 32;
+  int P = next_pow2((nint + mt - 1) / mt);
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0 || P > 32) return s;  // unsupported length
   const int S = nx4 + 1;
-  int L = std::min(32, 256 / P);  // compiled: 32, 16, 8
+  int L = std::min(lw, 256 / P);  // compiled: 32, 16, 8
+  if (L < 8) return s;
   auto lds = [&](int Lc) {
     size_t off = 16;
     off += (size_t)es * Lc * 2 * P * 4;
@@ -789,7 +792,8 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
     return off;
   };
   while (L > 8 && lds(L) > 60 * 1024 && L * P > 64) L >>= 1;
-  if (lds(L) > 160 * 1024) return LaunchShape{};
+  // the row traffic maps lanes as 16 vector columns x rows: whole groups of 16
+  if (lds(L) > 160 * 1024 || (L * P) % 16 != 0) return LaunchShape{};
   s.M = M;
   s.P = P;
   s.LW = L;
@@ -800,11 +804,13 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform) {
   return s;
 }
 
-LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64) {
+LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw) {
   LaunchShape s{};
   const int es = fp64 ? 8 : 4;
   const int nint = n_along - 2;
-  const int mt = fp64 ? 16 : 20;  // FP64 chunks shorter: lane state in registers
+  // FP64 chunks stop at 16 rows (lane state in registers)
+  if (mt <= 0) mt = fp64 ? 16 : 20;
+  if (fp64) mt = std::min(mt, 16);
   int P = (nint + mt - 1) / mt;
   if (P > 32) return s;  // unsupported length
   int M = pick_chunk((nint + P - 1) / P);
@@ -819,8 +825,11 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64) {
   // threads and 80 KB of LDS; FP64 arithmetic is bound by its arithmetic
   // and runs best on 16-wide tiles (more, smaller blocks).
   int TW = 16;
-  if (!fp64 && 32 * P <= 512 && lds(32) <= 80 * 1024) TW = 32;
-  if (lds(TW) > 160 * 1024) return s;
+  if (tw == 32 || tw <= 0) {
+    if (!fp64 && 32 * P <= 512 && lds(32) <= 80 * 1024) TW = 32;
+  }
+  if (tw == 32 && TW != 32) return s;  // asked for a width that does not fit
+  if (TW * P > 512 || lds(TW) > 160 * 1024) return s;
   const int ntx = (nx - 2) / TW + 1;
   s.M = M;
   s.P = P;

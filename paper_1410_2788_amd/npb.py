@@ -120,6 +120,11 @@ def load_library(path: str = LIB_PATH):
         lib.npb_server_get_stats.argtypes = [C.c_void_p, P(npb_server_stats)]
         lib.npb_server_destroy.restype = None
         lib.npb_server_destroy.argtypes = [C.c_void_p]
+        lib.npb_autotune.restype = C.c_int
+        lib.npb_autotune.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
+                                     C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_double)]
+        lib.npb_launch_shapes.restype = C.c_int
+        lib.npb_launch_shapes.argtypes = [C.c_void_p, P(npb_grid), P(npb_params), P(C.c_int32)]
         lib.npb_solve.restype = C.c_int
         lib.npb_solve.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, P(npb_result)]
@@ -224,6 +229,21 @@ def npb_solve_batch(ctx, mols, grids, params, d_ws, ws_bytes, d_field_out, strea
     return list(R)
 
 
+def npb_autotune(ctx, mol: npb_molecule, grid: npb_grid, params: npb_params, d_ws: int,
+                 ws_bytes: int, stream: int) -> list:
+    ms = (C.c_double * 3)()
+    _check(load_library().npb_autotune(ctx, C.byref(mol), C.byref(grid), C.byref(params),
+                                       C.c_void_p(d_ws), ws_bytes, C.c_void_p(stream), ms))
+    return list(ms)
+
+
+def npb_launch_shapes(ctx, grid: npb_grid, params: npb_params) -> list:
+    """[(M, P, lines or tile width, threads) for x, y, z]."""
+    out = (C.c_int32 * 12)()
+    _check(load_library().npb_launch_shapes(ctx, C.byref(grid), C.byref(params), out))
+    return [tuple(out[4 * d:4 * d + 4]) for d in range(3)]
+
+
 def npb_server_create(ctx, hbm_budget: int, max_batch: int = 16, max_queue: int = 256):
     sv = C.c_void_p()
     _check(load_library().npb_server_create(ctx, hbm_budget, max_batch, max_queue,
@@ -316,6 +336,12 @@ class Solver:
         self.field = None
         if want_field:
             self.field = torch.empty((grid.nz, grid.ny, grid.nx), dtype=torch.float64, device=dev)
+
+    def autotune(self) -> list:
+        """Tune this problem's launch shapes on its own workspace (ctx-wide)."""
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        return npb_autotune(self.ctx, self.mol.c, self.grid, self.params, self.ws.data_ptr(),
+                            self.ws_bytes, stream)
 
     def run(self) -> dict:
         torch = self.torch

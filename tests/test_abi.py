@@ -121,3 +121,17 @@ def test_batch_rejects_bad_arguments_before_device_work(npb):
     with pytest.raises(npb.NPBError) as ei:
         npb.npb_solve_batch(ctx_like, [m1.c, m1.c], [g1, g1], [p1, p1], fake, [1, 1], None, 0)
     assert ei.value.status == npb.NPB_EINVAL and "problem 0" in npb.npb_last_error()
+
+
+def test_default_launch_shapes_are_consistent(npb):
+    # shapes the planner gives without tuning: chunks cover every interior row
+    for n, prec in ((161, "f32"), (161, "f64"), (43, "f32"), (257, "f32"), (514, "f64")):
+        w = inputs.small_globular(n=n, n_atoms=10, precision=prec)
+        g = npb.make_grid(w.grid)
+        p = npb.make_params(w.params)
+        shapes = npb.npb_launch_shapes(None, g, p)
+        for M, P, lw, thr in shapes:
+            assert M in (4, 8, 12, 16, 20) and M * P >= n - 2 and M * (P - 1) < n - 2 + M
+            assert thr == lw * P and thr % 16 == 0 and thr <= 512
+        if prec == "f64":
+            assert shapes[1][0] <= 16 and shapes[1][2] == 16
