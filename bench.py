@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-kernel event timing pass")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes instead of tuning them first")
     ap.add_argument("--batch", action="store_true",
                     help="time a batch of 64 uneven grids instead (own JSON line)")
     ap.add_argument("--serve", action="store_true",
@@ -225,6 +227,9 @@ def main():
     solver = npb.Solver(w.molecule, w.grid, w.params, device=0)
     print(f"[bench] {w.name} precision={args.precision} scheme={args.scheme} "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    # launch shapes: tuned for this grid size once, before any timing
+    tune_ms = None if args.no_autotune else solver.autotune()
+    shapes = npb.npb_launch_shapes(solver.ctx, solver.grid, solver.params)
     for _ in range(args.warmup):
         solver.run()
     torch.cuda.synchronize()
@@ -295,6 +300,8 @@ def main():
                    "atoms": w.molecule.n_atoms, "scheme": args.scheme, "richardson": True,
                    "vacuum": True, "dt": [w.params.dt, w.params.dt / 2],
                    "steps_per_solve": results[0]["steps_done"],
+                   "launch_shapes": {"x": shapes[0], "y": shapes[1], "z": shapes[2],
+                                     "autotuned": tune_ms is not None},
                    "grid_point_updates_per_solve": per_solve},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "device_ms_median": float(np.median([r["device_ms"] for r in results]))},

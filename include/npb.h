@@ -224,7 +224,7 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols,
 /* Choose the line-solver launch shapes for this grid size, precision and
  * splitting family (LOD / AOS) by timing: the problem is set up in d_ws
  * (as npb_solve would), then for each sweep direction every candidate shape
- * (target chunk length 12, 16 or 20 rows; x: 32, 16 or 8 lines per block;
+ * (target chunk length 12, 16 or 20 rows; x: 64, 32, 16 or 8 lines per block;
  * y, z: tile width 32 or 16) sweeps all of the problem's runs a few times
  * on `stream`, and the fastest is recorded in ctx.  Later npb_solve,
  * npb_solve_batch and servers created from ctx use the recorded shapes for

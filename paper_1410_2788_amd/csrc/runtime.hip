@@ -1053,8 +1053,8 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
     int bc0 = 0, bc1 = 0;
     std::vector<std::array<int, 3>> tried;
     for (int mt : {12, 16, 20}) {
-      for (int pref : {32, 16, 8}) {
-        if (d > 0 && pref == 8) continue;
+      for (int pref : {64, 32, 16, 8}) {
+        if (d > 0 && (pref == 8 || pref == 64)) continue;
         const LaunchShape sh = d == 0 ? plan_x(nx, ny, nz, f64a, P.aos(), false, mt, pref)
                                       : plan_yz(nx, d == 1 ? ny : nz, d == 1 ? nz : ny, f64a, mt,
                                                 pref);

@@ -278,7 +278,8 @@ __device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
 // each row move between HBM and an odd-stride LDS tile with 16-byte vector
 // accesses; the row's boundary columns are written back unchanged.
 template <typename T, typename A, int M, int L>
-__global__ __launch_bounds__(256) void sweep_x_kernel(const SweepArgs<T>* __restrict__ args,
+__global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) void sweep_x_kernel(
+    const SweepArgs<T>* __restrict__ args,
                                                       const int2* __restrict__ work) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   extern __shared__ __align__(16) unsigned char smem[];
@@ -780,7 +781,9 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, in
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0 || P > 32) return s;  // unsupported length
   const int S = nx4 + 1;
-  int L = std::min(lw, 256 / P);  // compiled: 32, 16, 8
+  // compiled: 64, 32, 16, 8 lines; 64 only as an explicit (tuned) choice
+  // (64 lines: up to 512 threads; otherwise at most 256)
+  int L = (lw == 64 && 64 * P <= 512) ? 64 : std::min(lw == 64 ? 32 : lw, 256 / P);
   if (L < 8) return s;
   auto lds = [&](int Lc) {
     size_t off = 16;
@@ -791,7 +794,8 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, in
     if (!uniform) off += (size_t)Lc * nx4 + P * M + 2;
     return off;
   };
-  while (L > 8 && lds(L) > 60 * 1024 && L * P > 64) L >>= 1;
+  const size_t cap = L == 64 ? 100 * 1024 : 60 * 1024;  // 64 lines: one block per CU half
+  while (L > 8 && lds(L) > cap && L * P > 64) L >>= 1;
   // the row traffic maps lanes as 16 vector columns x rows: whole groups of 16
   if (lds(L) > 160 * 1024 || (L * P) % 16 != 0) return LaunchShape{};
   s.M = M;
@@ -909,14 +913,28 @@ int sweep_variant(const SweepArgs<T>* a, int n) {
 template int sweep_variant<float>(const SweepArgs<float>*, int);
 template int sweep_variant<double>(const SweepArgs<double>*, int);
 
+// Dynamic LDS above 64 KB (up to the 160 KB of a CU) must be allowed per
+// kernel before the launch.
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <typename T, typename A, int L>
 static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nblocks,
                              const LaunchShape& s, hipStream_t st) {
+  // the block size must stay within the instantiation's launch bound
+  if (s.threads > (L == 64 ? 512 : 256) || s.threads != L * s.P) return hipErrorInvalidValue;
   dim3 g(nblocks), blk(s.threads);
   switch (s.M) {
-#define NPB_X_CASE(MM) \
-  case MM:             \
-    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, args, work); break;
+#define NPB_X_CASE(MM)                                                                 \
+  case MM: {                                                                           \
+    hipError_t e = allow_lds(sweep_x_kernel<T, A, MM, L>, s.lds);                      \
+    if (e != hipSuccess) return e;                                                     \
+    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, args, work);  \
+  } break;
     NPB_X_CASE(4)
     NPB_X_CASE(8)
     NPB_X_CASE(12)
@@ -933,6 +951,7 @@ template <typename T, typename A>
 hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nblocks,
                           const LaunchShape& s, hipStream_t st) {
   if (nblocks < 1) return hipErrorInvalidValue;
+  if (s.LW == 64) return launch_x_l<T, A, 64>(args, work, nblocks, s, st);
   if (s.LW == 32) return launch_x_l<T, A, 32>(args, work, nblocks, s, st);
   if (s.LW == 16) return launch_x_l<T, A, 16>(args, work, nblocks, s, st);
   if (s.LW == 8) return launch_x_l<T, A, 8>(args, work, nblocks, s, st);
@@ -942,11 +961,16 @@ hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nblock
 template <typename T, typename A, int VAR, int TW>
 static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
                                const LaunchShape& s, hipStream_t st) {
+  if (s.threads > 512 || s.threads != TW * s.P) return hipErrorInvalidValue;
   dim3 g(nblocks), blk(s.threads);
   switch (s.M) {
-#define NPB_YZ_CASE(MM) \
-  case MM:              \
-    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, args, work, dir); break;
+#define NPB_YZ_CASE(MM)                                                                      \
+  case MM: {                                                                                \
+    hipError_t e = allow_lds(sweep_yz_kernel<T, A, MM, VAR, TW>, s.lds);                    \
+    if (e != hipSuccess) return e;                                                          \
+    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, args, work, \
+                       dir);                                                                \
+  } break;
     NPB_YZ_CASE(4)
     NPB_YZ_CASE(8)
     NPB_YZ_CASE(12)
@@ -955,7 +979,10 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
     case 20:
       // planned only for FP32 arithmetic (FP64 chunks stop at 16 rows)
       if constexpr (sizeof(A) == 4) {
-        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, args, work, dir);
+        hipError_t e = allow_lds(sweep_yz_kernel<T, A, 20, VAR, TW>, s.lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, args, work,
+                           dir);
         break;
       }
       return hipErrorInvalidValue;
