@@ -83,6 +83,91 @@ __global__ void field_init_kernel(T* u, const double* bc, int nx, int nxp, int n
   }
 }
 
+// the runs of one problem at once: block row blockIdx.y = run
+template <typename T>
+struct InitSet {
+  T* u[kMaxFields];
+  const double* bc[kMaxFields];
+};
+template <typename T>
+__global__ void field_init_multi_kernel(InitSet<T> set, int nx, int nxp, int ny, int nz) {
+  const int r = blockIdx.y;
+  T* u = set.u[r];
+  const double* bc = set.bc[r];
+  const long long n = (long long)nxp * ny * nz;
+  const long long nxy = (long long)nx * ny;
+  const long long ring = 2LL * nx + 2LL * (ny - 2);
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(p % nxp);
+    long long t = p / nxp;
+    int j = (int)(t % ny);
+    int k = (int)(t / ny);
+    T v = T(0);
+    if (i >= nx) {
+      v = T(0);
+    } else if (k == 0) {
+      v = (T)bc[(long long)j * nx + i];
+    } else if (k == nz - 1) {
+      v = (T)bc[nxy + (long long)j * nx + i];
+    } else {
+      long long base = 2 * nxy + (long long)(k - 1) * ring;
+      if (j == 0)
+        v = (T)bc[base + i];
+      else if (j == ny - 1)
+        v = (T)bc[base + nx + i];
+      else if (i == 0)
+        v = (T)bc[base + 2LL * nx + 2LL * (j - 1)];
+      else if (i == nx - 1)
+        v = (T)bc[base + 2LL * nx + 2LL * (j - 1) + 1];
+    }
+    u[p] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_field_init_multi(const InitSet<T>& set, int nruns, int nx, int nxp, int ny,
+                                   int nz, hipStream_t st) {
+  long long n = (long long)nxp * ny * nz;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((field_init_multi_kernel<T>), dim3((unsigned)blocks, nruns), dim3(256), 0, st,
+                     set, nx, nxp, ny, nz);
+  return hipGetLastError();
+}
+
+// energy slots of the runs of one problem at once: block r sums run r
+template <typename T>
+struct EnergySet {
+  const T* u[kMaxFields];
+  double* slot[kMaxFields];
+};
+template <typename T>
+__global__ __launch_bounds__(1024) void energy_multi_kernel(EnergySet<T> set, const int* q_idx,
+                                                            const double* q_val,
+                                                            const int* nq_dev) {
+  __shared__ double part[1024];
+  const T* u = set.u[blockIdx.x];
+  const int nq = *nq_dev;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nq; k += 1024) s += q_val[k] * (double)u[q_idx[k]];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *set.slot[blockIdx.x] = part[0];
+}
+
+template <typename T>
+hipError_t launch_energy_multi(const EnergySet<T>& set, int nruns, const int* q_idx,
+                               const double* q_val, const int* nq_dev, hipStream_t st) {
+  hipLaunchKernelGGL((energy_multi_kernel<T>), dim3(nruns), dim3(1024), 0, st, set, q_idx, q_val,
+                     nq_dev);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_field_init(T* u, const double* bc, int nx, int nxp, int ny, int nz,
                              hipStream_t st) {
@@ -807,14 +892,16 @@ struct Engine {
   }
 
   npb_status time_loop() {
-    for (const Field& f : fields) {
-      const Problem& P = pr[f.prob];
-      const bool vac = P.L.runs[f.run].medium == 1;
+    for (const Problem& P : pr) {
       const int nx = P.g->nx, ny = P.g->ny, nz = P.g->nz;
       const int nxp = pitch_of(nx, (int)sizeof(T));
-      npb_status s = timed(NPB_K_INIT, (double)nxp * ny * nz * sizeof(T), [&] {
-        return launch_field_init<T>(P.at<T>(P.L.field[f.run]),
-                                    P.at<double>(vac ? P.L.bc_v : P.L.bc_s), nx, nxp, ny, nz, st);
+      InitSet<T> set{};
+      for (int r = 0; r < P.L.n_runs; ++r) {
+        set.u[r] = P.at<T>(P.L.field[r]);
+        set.bc[r] = P.at<double>(P.L.runs[r].medium == 1 ? P.L.bc_v : P.L.bc_s);
+      }
+      npb_status s = timed(NPB_K_INIT, (double)nxp * ny * nz * sizeof(T) * P.L.n_runs, [&] {
+        return launch_field_init_multi<T>(set, P.L.n_runs, nx, nxp, ny, nz, st);
       });
       if (s != NPB_OK) return s;
     }
@@ -859,14 +946,16 @@ struct Engine {
     if (s != NPB_OK) return s;
     for (Problem& P : pr) {
       const Layout& L = P.L;
+      EnergySet<T> set{};
       for (int r = 0; r < L.n_runs; ++r) {
-        const int slot = 2 * L.runs[r].medium + L.runs[r].level;
-        s = timed(NPB_K_ENERGY, 0, [&] {
-          return launch_energy<T>(P.at<T>(L.field[r]), P.at<int>(L.q_idx), P.at<double>(L.q_val),
-                                  P.at<int>(L.ints), L.cap, P.at<double>(L.slots) + slot, st);
-        });
-        if (s != NPB_OK) return s;
+        set.u[r] = P.at<T>(L.field[r]);
+        set.slot[r] = P.at<double>(L.slots) + 2 * L.runs[r].medium + L.runs[r].level;
       }
+      s = timed(NPB_K_ENERGY, 0, [&] {
+        return launch_energy_multi<T>(set, L.n_runs, P.at<int>(L.q_idx), P.at<double>(L.q_val),
+                                      P.at<int>(L.ints), st);
+      });
+      if (s != NPB_OK) return s;
       if (P.fout) {
         // selected medium: kT u (plain) or kT (2 u(dt/2) - u(dt)) (Richardson)
         const npb_params* p = P.p;

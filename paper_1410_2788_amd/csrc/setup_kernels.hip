@@ -189,8 +189,45 @@ __global__ __launch_bounds__(1024) void scan_kernel(int* data, int n, int* total
   if (tid == 1023 && total) *total = part[1023];
 }
 
+// the same scan with the array staged through LDS by coalesced loads and
+// stores (n <= kScanLds): the per-thread chunk walk reads LDS, not HBM
+constexpr int kScanLds = 16384;
+__global__ __launch_bounds__(1024) void scan_lds_kernel(int* data, int n, int* total) {
+  extern __shared__ int buf[];
+  __shared__ int part[1024];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += 1024) buf[i] = data[i];
+  __syncthreads();
+  const int per = (n + 1023) / 1024;
+  const int b = tid * per;
+  const int e = min(b + per, n);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += buf[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - s;
+  for (int i = b; i < e; ++i) {
+    int v = buf[i];
+    buf[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 1024) data[i] = buf[i];
+  if (tid == 1023 && total) *total = part[1023];
+}
+
 hipError_t launch_exclusive_scan(int* data, int n, int* total, hipStream_t st) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, data, n, total);
+  if (n <= kScanLds)
+    hipLaunchKernelGGL(scan_lds_kernel, dim3(1), dim3(1024), (size_t)n * sizeof(int), st, data, n,
+                       total);
+  else
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, data, n, total);
   return hipGetLastError();
 }
 
