@@ -143,12 +143,14 @@ template <typename T>
 void shape_args(SweepArgs<T>& a, int dir, const LaunchShape& s);
 template <typename T>
 int sweep_variant(const SweepArgs<T>* a, int n);  // kYz* covering every field
+// nbu > 0: every field has nbu blocks and block b is (b / nbu, b % nbu);
+// work may then be null.
 template <typename T, typename A>
-hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nblocks,
+hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                           const LaunchShape& s, hipStream_t st);
 template <typename T, typename A>
-hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
-                           int var, const LaunchShape& s, hipStream_t st);
+hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
+                           int dir, int var, const LaunchShape& s, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // setup

@@ -582,6 +582,7 @@ struct Engine {
     size_t args_off = 0;           // SweepArgs<T>[members] in the launch-table buffer
     std::vector<int> nblk;         // blocks of the first k members, k = 1..size
     std::vector<size_t> work_off;  // int2[nblk[k-1]] per k
+    int nbu = 0;                   // blocks per member when all members have the same count
   };
   std::vector<Group> groups[3];
   std::vector<unsigned char> meta;  // host image of the launch tables
@@ -720,6 +721,9 @@ struct Engine {
       for (int g = 0; g < (int)groups[d].size(); ++g) {
         Group& G = groups[d][g];
         G.var = sweep_variant(gargs[d][g].data(), (int)gargs[d][g].size());
+        G.nbu = pr[fields[G.members[0]].prob].L.shape[d].blocks;
+        for (int m : G.members)
+          if (pr[fields[m].prob].L.shape[d].blocks != G.nbu) G.nbu = 0;
         G.args_off = off;
         off = align(off + sizeof(SweepArgs<T>) * G.members.size());
         int nb = 0;
@@ -919,8 +923,8 @@ struct Engine {
           const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[k - 1]);
           const int nb = G.nblk[k - 1];
           npb_status s = timed(NPB_K_SWEEP_X + d, bytes, [&] {
-            return d == 0 ? launch_sweep_x<T, A>(args, work, nb, G.s, st)
-                          : launch_sweep_yz<T, A>(args, work, nb, d, G.var, G.s, st);
+            return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.s, st)
+                          : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, st);
           });
           if (s != NPB_OK) return s;
         }
@@ -1193,8 +1197,8 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
         const auto* dwork = reinterpret_cast<const int2*>(static_cast<unsigned char*>(dbuf) + ab);
         const int var = sweep_variant(args.data(), nr);
         auto launch = [&] {
-          return d == 0 ? launch_sweep_x<T, A>(dargs, dwork, nb, sh, st)
-                        : launch_sweep_yz<T, A>(dargs, dwork, nb, d, var, sh, st);
+          return d == 0 ? launch_sweep_x<T, A>(dargs, dwork, sh.blocks, nb, sh, st)
+                        : launch_sweep_yz<T, A>(dargs, dwork, sh.blocks, nb, d, var, sh, st);
         };
         constexpr int kWarm = 2, kReps = 5;
         for (int i = 0; i < kWarm; ++i) NPB_HIP(launch());

@@ -279,11 +279,13 @@ __device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
 // accesses; the row's boundary columns are written back unchanged.
 template <typename T, typename A, int M, int L>
 __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) void sweep_x_kernel(
-    const SweepArgs<T>* __restrict__ args,
-                                                      const int2* __restrict__ work) {
+    const SweepArgs<T>* __restrict__ args, const int2* __restrict__ work, int nbu) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   extern __shared__ __align__(16) unsigned char smem[];
-  const int2 w = work[blockIdx.x];  // (field, block of that field)
+  // (field, block of that field): arithmetic when every field of the
+  // launch has nbu blocks, else from the work list
+  const int2 w = nbu > 0 ? make_int2((int)blockIdx.x / nbu, (int)blockIdx.x % nbu)
+                         : work[blockIdx.x];
   const SweepArgs<T>& a = args[w.x];
   const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
   const int nx = a.nx, ny = a.ny, nz = a.nz, nxp = a.nxp;
@@ -527,12 +529,16 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
 
 template <typename T, typename A, int M, int VAR, int TW>
 __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __restrict__ args,
-                                                       const int2* __restrict__ work, int dir) {
+                                                       const int2* __restrict__ work, int nbu,
+                                                       int dir) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   constexpr int TS = TW + 1;                // LDS elements per tile row
   constexpr int VPR = TW / VX;              // vectors per full tile row
   extern __shared__ __align__(16) unsigned char smem[];
-  const int2 w = work[blockIdx.x];  // (field, block of that field)
+  // (field, block of that field): arithmetic when every field of the
+  // launch has nbu blocks, else from the work list
+  const int2 w = nbu > 0 ? make_int2((int)blockIdx.x / nbu, (int)blockIdx.x % nbu)
+                         : work[blockIdx.x];
   const SweepArgs<T>& a = args[w.x];
   const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
   const int nx = a.nx, ny = a.ny, nxp = a.nxp;
@@ -923,7 +929,7 @@ static hipError_t allow_lds(K kernel, size_t lds) {
 }
 
 template <typename T, typename A, int L>
-static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nblocks,
+static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                              const LaunchShape& s, hipStream_t st) {
   // the block size must stay within the instantiation's launch bound
   if (s.threads > (L == 64 ? 512 : 256) || s.threads != L * s.P) return hipErrorInvalidValue;
@@ -933,7 +939,7 @@ static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nbl
   case MM: {                                                                           \
     hipError_t e = allow_lds(sweep_x_kernel<T, A, MM, L>, s.lds);                      \
     if (e != hipSuccess) return e;                                                     \
-    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, args, work);  \
+    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, args, work, nbu); \
   } break;
     NPB_X_CASE(4)
     NPB_X_CASE(8)
@@ -948,19 +954,19 @@ static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nbl
 }
 
 template <typename T, typename A>
-hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nblocks,
+hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                           const LaunchShape& s, hipStream_t st) {
-  if (nblocks < 1) return hipErrorInvalidValue;
-  if (s.LW == 64) return launch_x_l<T, A, 64>(args, work, nblocks, s, st);
-  if (s.LW == 32) return launch_x_l<T, A, 32>(args, work, nblocks, s, st);
-  if (s.LW == 16) return launch_x_l<T, A, 16>(args, work, nblocks, s, st);
-  if (s.LW == 8) return launch_x_l<T, A, 8>(args, work, nblocks, s, st);
+  if (nblocks < 1 || (nbu <= 0 && !work)) return hipErrorInvalidValue;
+  if (s.LW == 64) return launch_x_l<T, A, 64>(args, work, nbu, nblocks, s, st);
+  if (s.LW == 32) return launch_x_l<T, A, 32>(args, work, nbu, nblocks, s, st);
+  if (s.LW == 16) return launch_x_l<T, A, 16>(args, work, nbu, nblocks, s, st);
+  if (s.LW == 8) return launch_x_l<T, A, 8>(args, work, nbu, nblocks, s, st);
   return hipErrorInvalidValue;
 }
 
 template <typename T, typename A, int VAR, int TW>
-static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
-                               const LaunchShape& s, hipStream_t st) {
+static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
+                               int dir, const LaunchShape& s, hipStream_t st) {
   if (s.threads > 512 || s.threads != TW * s.P) return hipErrorInvalidValue;
   dim3 g(nblocks), blk(s.threads);
   switch (s.M) {
@@ -969,7 +975,7 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
     hipError_t e = allow_lds(sweep_yz_kernel<T, A, MM, VAR, TW>, s.lds);                    \
     if (e != hipSuccess) return e;                                                          \
     hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, args, work, \
-                       dir);                                                                \
+                       nbu, dir);                                                           \
   } break;
     NPB_YZ_CASE(4)
     NPB_YZ_CASE(8)
@@ -982,7 +988,7 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
         hipError_t e = allow_lds(sweep_yz_kernel<T, A, 20, VAR, TW>, s.lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, args, work,
-                           dir);
+                           nbu, dir);
         break;
       }
       return hipErrorInvalidValue;
@@ -994,29 +1000,30 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
 
 // tile widths compiled: 16 and 32 for FP32 arithmetic, 16 for FP64
 template <typename T, typename A, int VAR>
-static hipError_t launch_yz_var(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
-                                const LaunchShape& s, hipStream_t st) {
-  if (s.LW == 16) return launch_yz_tw<T, A, VAR, 16>(args, work, nblocks, dir, s, st);
+static hipError_t launch_yz_var(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
+                                int dir, const LaunchShape& s, hipStream_t st) {
+  if (s.LW == 16) return launch_yz_tw<T, A, VAR, 16>(args, work, nbu, nblocks, dir, s, st);
   if constexpr (sizeof(A) == 4) {
-    if (s.LW == 32) return launch_yz_tw<T, A, VAR, 32>(args, work, nblocks, dir, s, st);
+    if (s.LW == 32) return launch_yz_tw<T, A, VAR, 32>(args, work, nbu, nblocks, dir, s, st);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T, typename A>
-hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nblocks, int dir,
-                           int var, const LaunchShape& s, hipStream_t st) {
-  if (nblocks < 1) return hipErrorInvalidValue;
-  if (var == kYzGeneral) return launch_yz_var<T, A, kYzGeneral>(args, work, nblocks, dir, s, st);
-  if (var == kYzFlow) return launch_yz_var<T, A, kYzFlow>(args, work, nblocks, dir, s, st);
-  return launch_yz_var<T, A, kYzPlain>(args, work, nblocks, dir, s, st);
+hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
+                           int dir, int var, const LaunchShape& s, hipStream_t st) {
+  if (nblocks < 1 || (nbu <= 0 && !work)) return hipErrorInvalidValue;
+  if (var == kYzGeneral)
+    return launch_yz_var<T, A, kYzGeneral>(args, work, nbu, nblocks, dir, s, st);
+  if (var == kYzFlow) return launch_yz_var<T, A, kYzFlow>(args, work, nbu, nblocks, dir, s, st);
+  return launch_yz_var<T, A, kYzPlain>(args, work, nbu, nblocks, dir, s, st);
 }
 
 #define NPB_INST(T, A)                                                                          \
-  template hipError_t launch_sweep_x<T, A>(const SweepArgs<T>*, const int2*, int,              \
+  template hipError_t launch_sweep_x<T, A>(const SweepArgs<T>*, const int2*, int, int,         \
                                            const LaunchShape&, hipStream_t);                    \
   template hipError_t launch_sweep_yz<T, A>(const SweepArgs<T>*, const int2*, int, int, int,   \
-                                            const LaunchShape&, hipStream_t);
+                                            int, const LaunchShape&, hipStream_t);
 NPB_INST(float, float)
 NPB_INST(float, double)
 NPB_INST(double, double)
