@@ -71,6 +71,7 @@ constexpr int kChunkChoices[] = {4, 8, 12, 16, 20};
 struct LaunchShape {
   int M, P, LW, threads, blocks;
   size_t lds;
+  int S;  // x: LDS elements per tile row; y/z: LDS tile rows
 };
 
 // Row pitch of every field-shaped array (the mask shares it): rows start
@@ -80,6 +81,14 @@ struct LaunchShape {
 // padding columns nx..nxp-1 hold zeros (field) or 0 (mask) and are never
 // solved.  es = bytes per field element.
 __host__ __device__ inline int row4(int nx) { return (nx + 3) & ~3; }
+// LDS elements per row of an x-sweep tile.  FP32: one more than a multiple
+// of 32, so that the four rows x eight 16-byte pieces a half-wave moves,
+// and the 32 lines' chunk rows it reads, fall in distinct banks.  FP64
+// (two banks per element): one more than row4(nx).
+inline int x_tile_stride(int nx, bool fp64) {
+  const int nx4 = row4(nx);
+  return fp64 ? nx4 + 1 : ((nx4 + 31) & ~31) + 1;
+}
 inline int pitch_of(int nx, int es) {
   const int q = 128 / es;
   return (nx + q - 1) / q * q;
@@ -113,7 +122,7 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt = 0, int
 inline int max_chunks(int n_along, bool x_dir) {
   const int nint = n_along - 2;
   int P = (nint + 11) / 12;  // shortest target chunk a tuner tries: 12 rows
-  if (x_dir) {
+  if (x_dir) {               // x chunk counts are powers of two
     int q = 1;
     while (q < P) q <<= 1;
     P = q;

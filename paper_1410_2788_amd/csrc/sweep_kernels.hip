@@ -189,9 +189,94 @@ __device__ __forceinline__ void fast_finish(A (&d)[M], const A* ga, const A* al,
 }
 
 // Reduced systems in LDS: entry (line l, row r, coefficient c) at
-// R[(4 r + c) * nl + l], so that the lanes of one wave (different lines)
-// touch consecutive words.  Thomas on the 2P rows of one line; the solution
-// overwrites the d coefficients.  The next row's coefficients are read
+// R[(4 r + c) * rs + l], rs = lines + 1, so that the lanes of one wave
+// writing them (different lines, same row) touch distinct banks.  Row 2p
+// is the first row of chunk p, row 2p+1 its last; the 2P rows of a line
+// form a tridiagonal system (A x_{r-1} + B x_r + C x_{r+1} = D) whose first
+// A and last C are zero.
+//
+// x sweeps solve it by parallel cyclic reduction with the P lanes of a line
+// side by side in one wave (lane t: line t / P, rows 2p and 2p+1 of
+// p = t % P, P a power of two): each step eliminates a row's couplings to
+// the rows at distance d using those rows (fetched from the neighbour
+// lanes), after which the row couples to the rows at distance 2d; after
+// steps d = 1, 2, ..., P every row stands alone and x_r = D_r / B_r.  Rows
+// outside the system act as identity rows (their coupling is already zero).
+template <typename A>
+struct RRow {
+  A a, b, c, d;
+};
+
+template <typename A>
+__device__ __forceinline__ RRow<A> rrow_identity() {
+  return RRow<A>{A(0), A(1), A(0), A(0)};
+}
+
+// row r combined with its neighbours at distance d: couples to r +- 2d
+template <typename A>
+__device__ __forceinline__ RRow<A> pcr_combine(const RRow<A>& r, const RRow<A>& up,
+                                               const RRow<A>& dn) {
+  const A k1 = r.a * rcp_pivot(up.b);
+  const A k2 = r.c * rcp_pivot(dn.b);
+  RRow<A> o;
+  o.a = -up.a * k1;
+  o.b = r.b - up.c * k1 - dn.a * k2;
+  o.c = -dn.c * k2;
+  o.d = r.d - up.d * k1 - dn.d * k2;
+  return o;
+}
+
+template <typename A>
+__device__ __forceinline__ RRow<A> shfl_row_up(const RRow<A>& r, int delta, int width) {
+  return RRow<A>{__shfl_up(r.a, delta, width), __shfl_up(r.b, delta, width),
+                 __shfl_up(r.c, delta, width), __shfl_up(r.d, delta, width)};
+}
+template <typename A>
+__device__ __forceinline__ RRow<A> shfl_row_down(const RRow<A>& r, int delta, int width) {
+  return RRow<A>{__shfl_down(r.a, delta, width), __shfl_down(r.b, delta, width),
+                 __shfl_down(r.c, delta, width), __shfl_down(r.d, delta, width)};
+}
+
+// Solve the reduced systems of all lines of the block (every thread takes
+// part); the solution overwrites the D coefficients.
+template <typename A>
+__device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
+  const int p = tid & (P - 1);
+  A* R = red + tid / P;
+  auto get = [&](int r) {
+    return RRow<A>{R[(4 * r) * rs], R[(4 * r + 1) * rs], R[(4 * r + 2) * rs],
+                   R[(4 * r + 3) * rs]};
+  };
+  RRow<A> r0 = get(2 * p), r1 = get(2 * p + 1);
+  {
+    // d = 1: row 2p pairs with row 2p-1 (lane p-1) and 2p+1 (this lane)
+    RRow<A> up = shfl_row_up(r1, 1, P);
+    RRow<A> dn = shfl_row_down(r0, 1, P);
+    if (p == 0) up = rrow_identity<A>();
+    if (p == P - 1) dn = rrow_identity<A>();
+    const RRow<A> n0 = pcr_combine(r0, up, r1);
+    const RRow<A> n1 = pcr_combine(r1, r0, dn);
+    r0 = n0;
+    r1 = n1;
+  }
+  // d = 2e: the rows at distance d sit e lanes away, in the same slot
+  for (int e = 1; e < P; e <<= 1) {
+    RRow<A> u0 = shfl_row_up(r0, e, P), u1 = shfl_row_up(r1, e, P);
+    RRow<A> d0 = shfl_row_down(r0, e, P), d1 = shfl_row_down(r1, e, P);
+    if (p < e) u0 = u1 = rrow_identity<A>();
+    if (p + e >= P) d0 = d1 = rrow_identity<A>();
+    const RRow<A> n0 = pcr_combine(r0, u0, d0);
+    const RRow<A> n1 = pcr_combine(r1, u1, d1);
+    r0 = n0;
+    r1 = n1;
+  }
+  R[(4 * (2 * p) + 3) * rs] = r0.d * rcp_pivot(r0.b);
+  R[(4 * (2 * p + 1) + 3) * rs] = r1.d * rcp_pivot(r1.b);
+}
+
+// Serial Thomas on the 2P reduced rows of one line, by one lane (y/z
+// sweeps, whose chunk counts need not be powers of two); the solution
+// overwrites the D coefficients.  The next row's coefficients are read
 // before the current row's results are stored, so that LDS latency overlaps
 // the arithmetic instead of adding up row after row.
 template <typename A>
@@ -311,7 +396,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   int* srng = reinterpret_cast<int*>(smem + off);  // source entry range of the block
   off += 16;
   A* red = reinterpret_cast<A*>(smem + off);
-  off += sizeof(A) * (size_t)L * 2 * P * 4;
+  off += sizeof(A) * (size_t)(L + 1) * 2 * P * 4;
   // the tile and the mask rows carry P*M+2 spare elements at their end:
   // a chunk's reads may run past the last row (values selected away)
   A* tile = reinterpret_cast<A*>(smem + off);
@@ -333,16 +418,17 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     srng[1] = a.src_ptr[row_base(min(L, nlines - l0) - 1) / nxp + 1];
   }
 
-  // Row loads.  Lane t of the block takes vector column cv = t % 16 of rows
-  // t / 16, t / 16 + RQ, ... and column groups cv, cv + 16, ...: a wave
-  // moves 4 rows x 16 vectors per instruction, and with the odd LDS row
-  // stride S those four rows' element writes fall in distinct banks.  All
-  // vector loads of a batch are in flight before its LDS stores.
-  const int vpr = nx4 / VX;          // vectors per row
-  const int ncg = (vpr + 15) >> 4;   // 16-vector column groups per row
-  const int cv = tid & 15;
-  const int RQ = nthreads >> 4;      // rows per pass
-  const int rq = tid >> 4;
+  // Row loads.  Lane t of the block takes vector column cv = t % 8 of rows
+  // t / 8, t / 8 + RQ, ... and column groups cv, cv + 8, ...: a wave moves
+  // 8 rows x 8 vectors (128 contiguous bytes of each row) per instruction,
+  // and with the LDS row stride S (x_tile_stride) the element writes of a
+  // half-wave's four rows fall in distinct banks.  All vector loads of a
+  // batch are in flight before its LDS stores.
+  const int vpr = nx4 / VX;         // vectors per row
+  const int ncg = (vpr + 7) >> 3;   // 8-vector column groups per row
+  const int cv = tid & 7;
+  const int RQ = nthreads >> 3;     // rows per pass
+  const int rq = tid >> 3;
   const int nsteps = rq < L ? ((L - rq + RQ - 1) / RQ) * ncg : 0;
   {
     constexpr int kU = 8;
@@ -355,7 +441,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
       for (int j = 0; j < kU; ++j) {
         lo[j] = -1;
         if (s0 + j < nsteps) {
-          const int c = (cv + 16 * g) * VX;
+          const int c = (cv + 8 * g) * VX;
           if (c < nx4 && rb >= 0) {
             lo[j] = q * S + c;
             mo[j] = q * nx4 + c;
@@ -471,12 +557,12 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
   }
   A* R = red + ql;
-  put_reduced(R, L, p, rf, rl);
+  put_reduced(R, L + 1, p, rf, rl);
   __syncthreads();
-  if (p == 0 && lvalid) reduced_solve(R, 2 * P, L);
+  pcr_reduced(red, L + 1, P, tid);
   __syncthreads();
-  const A xf = R[(4 * (2 * p) + 3) * L];
-  const A xl = R[(4 * (2 * p + 1) + 3) * L];
+  const A xf = R[(4 * (2 * p) + 3) * (L + 1)];
+  const A xl = R[(4 * (2 * p + 1) + 3) * (L + 1)];
   if (fast)
     fast_finish<A, M>(d, tb.ga[t], tb.al[t], xf, xl);
   else
@@ -500,7 +586,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     const int rb = row_base(q);
     if (rb < 0) break;
     for (int g = 0; g < ncg; ++g) {
-      const int c = (cv + 16 * g) * VX;
+      const int c = (cv + 8 * g) * VX;
       if (c < nx4) {
         T v[VX];
 #pragma unroll
@@ -559,7 +645,7 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   const bool uniform = (a.mask == nullptr);
 
   A* red = reinterpret_cast<A*>(smem);
-  A* tile = red + (size_t)TW * 2 * P * 4;
+  A* tile = red + (size_t)(TW + 1) * 2 * P * 4;
   uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)nrow * TS);  // [nrow][TW]
   int* srng = reinterpret_cast<int*>(mt + (size_t)nrow * TW);          // source entry range
 
@@ -696,12 +782,12 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
   }
   A* R = red + ql;
-  put_reduced(R, TW, p, rf, rl);
+  put_reduced(R, TS, p, rf, rl);
   __syncthreads();
-  if (p == 0 && lvalid) reduced_solve(R, 2 * P, TW);
+  if (p == 0 && lvalid) reduced_solve(R, 2 * P, TS);
   __syncthreads();
-  const A xf = R[(4 * (2 * p) + 3) * TW];
-  const A xl = R[(4 * (2 * p + 1) + 3) * TW];
+  const A xf = R[(4 * (2 * p) + 3) * TS];
+  const A xl = R[(4 * (2 * p + 1) + 3) * TS];
   if (fast)
     fast_finish<A, M>(d, tb.ga[t], tb.al[t], xf, xl);
   else
@@ -786,14 +872,14 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, in
   int P = next_pow2((nint + mt - 1) / mt);
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0 || P > 32) return s;  // unsupported length
-  const int S = nx4 + 1;
+  const int S = x_tile_stride(nx, fp64);
   // compiled: 64, 32, 16, 8 lines; 64 only as an explicit (tuned) choice
   // (64 lines: up to 512 threads; otherwise at most 256)
   int L = (lw == 64 && 64 * P <= 512) ? 64 : std::min(lw == 64 ? 32 : lw, 256 / P);
   if (L < 8) return s;
   auto lds = [&](int Lc) {
     size_t off = 16;
-    off += (size_t)es * Lc * 2 * P * 4;
+    off += (size_t)es * (Lc + 1) * 2 * P * 4;
     off += (size_t)es * ((size_t)Lc * S + P * M + 2);
     if (aos) off += (size_t)es * Lc * S;
     off = (off + 15) & ~size_t(15);
@@ -811,6 +897,7 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, in
   long long nlines = (long long)(ny - 2) * (nz - 2);
   s.blocks = (int)((nlines + L - 1) / L);
   s.lds = lds(L);
+  s.S = S;
   return s;
 }
 
@@ -823,12 +910,13 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw)
   if (fp64) mt = std::min(mt, 16);
   int P = (nint + mt - 1) / mt;
   if (P > 32) return s;  // unsupported length
-  int M = pick_chunk((nint + P - 1) / P);
+  const int M = pick_chunk((nint + P - 1) / P);
   if (M < 0) return s;
   P = (nint + M - 1) / M;
   const int nrow = std::max(n_along, P * M + 2);  // LDS tile rows
   auto lds = [&](int tw) {
-    return (size_t)es * tw * 2 * P * 4 + (size_t)es * nrow * (tw + 1) + (size_t)nrow * tw + 16;
+    return (size_t)es * (tw + 1) * 2 * P * 4 + (size_t)es * nrow * (tw + 1) + (size_t)nrow * tw +
+           16;
   };
   // Tile width (measured on 161^3 batches): FP32 arithmetic runs best with
   // 32 x per tile (one 128-byte line per node row) when that fits 512
@@ -847,6 +935,7 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw)
   s.threads = TW * P;
   s.blocks = ntx * (n_other - 2);
   s.lds = lds(TW);
+  s.S = nrow;
   return s;
 }
 
@@ -897,12 +986,7 @@ void shape_args(SweepArgs<T>& a, int dir, const LaunchShape& s) {
   a.M = s.M;
   a.P = s.P;
   a.LW = s.LW;
-  if (dir == 0) {
-    a.S = row4(a.nx) + 1;
-  } else {
-    const int n_along = dir == 1 ? a.ny : a.nz;
-    a.S = std::max(n_along, s.P * s.M + 2);
-  }
+  a.S = s.S;
 }
 template void shape_args<float>(SweepArgs<float>&, int, const LaunchShape&);
 template void shape_args<double>(SweepArgs<double>&, int, const LaunchShape&);

@@ -131,7 +131,14 @@ def test_default_launch_shapes_are_consistent(npb):
         p = npb.make_params(w.params)
         shapes = npb.npb_launch_shapes(None, g, p)
         for M, P, lw, thr in shapes:
-            assert M in (4, 8, 12, 16, 20) and M * P >= n - 2 and M * (P - 1) < n - 2 + M
+            assert M in (4, 8, 12, 16, 20) and M * P >= n - 2
+        # x: chunk counts are powers of two (reduced systems solved across
+        # lanes), and half as many chunks would not cover the line; y/z: no
+        # chunk lies wholly past the line
+        M, P = shapes[0][0], shapes[0][1]
+        assert P & (P - 1) == 0 and M * (P // 2) < n - 2
+        for M, P, _, _ in shapes[1:]:
+            assert M * (P - 1) < n - 2
             assert thr == lw * P and thr % 16 == 0 and thr <= 512
         if prec == "f64":
             assert shapes[1][0] <= 16 and shapes[1][2] == 16
