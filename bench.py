@@ -9,10 +9,14 @@ before the timed region (atoms are copied in by the solve itself, 80 kB).
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f32x|f64]
                     [--no-cpu-baseline]
+    python bench.py --batch [--scheme AOSIE2]   64 uneven grids in one batch
+    python bench.py --serve                     request loop, p50/p99 latency
+    python bench.py --large                     30000 atoms on 321^3 nodes
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -76,17 +80,49 @@ def cpu_baseline(workload, n_steps_meas: int = 2):
             "seconds_measured": t_setup + n_steps_meas * t_step}
 
 
+def _energy_tol(ref):
+    return max(1e-3, 1e-5 * abs(ref))
+
+
+def _golden(name):
+    p = os.path.join(ROOT, "tests", "golden", name)
+    return json.load(open(p)) if os.path.exists(p) else None
+
+
+def _single_f64(probs, npb):
+    """Plain single-solve FP64 GPU path, one problem after another: device
+    time per problem (graph replay after a warm-up solve) and the energies."""
+    import torch
+    out = []
+    for w in probs:
+        p = dataclasses.replace(w.params, precision="f64")
+        s = npb.Solver(w.molecule, w.grid, p, device=0)
+        s.run()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        r = s.run()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        out.append((ev0.elapsed_time(ev1), r))
+        del s
+    return out
+
+
 def bench_batch(args):
     """64 uneven grids (atom counts log-uniform 200..5000, 79..193 nodes at
-    h = 0.5), LODIE2 RE+V, solved together by npb_solve_batch."""
-    import numpy as np
+    h = 0.5), RE+V, solved together by npb_solve_batch.  Every member's
+    energy is checked against the FP64 single-solve GPU path (itself held
+    to the FP64 oracle); sampled members also against stored oracle values."""
     import torch
 
     from paper_1410_2788_amd import inputs, npb
-    probs = inputs.batch_mix(n_mol=64, seed=3, precision=args.precision)
+    scheme = args.scheme
+    probs = inputs.batch_mix(n_mol=64, seed=3, precision=args.precision, scheme=scheme)
     bs = npb.BatchSolver([(w.molecule, w.grid, w.params) for w in probs])
-    print(f"[bench] batch of {len(probs)} grids, {sum(w.grid.nx ** 3 for w in probs) / 1e6:.1f} M nodes",
-          file=sys.stderr, flush=True)
+    print(f"[bench] batch of {len(probs)} grids, {sum(w.grid.nx ** 3 for w in probs) / 1e6:.1f} M nodes, "
+          f"{scheme} {args.precision}", file=sys.stderr, flush=True)
     for _ in range(max(1, args.warmup)):
         res = bs.run()
     stream = torch.cuda.current_stream()
@@ -98,15 +134,87 @@ def bench_batch(args):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    pts = sum(r["grid_point_updates"] for r in res)
-    finite = sum(1 for r in res if r["finite"])
-    return {"metric": "LOD grid-point-updates/s, batch of uneven grids", "value": pts * finite / len(res) / (ms * 1e-3),
+    del bs
+    print("[bench] FP64 single solves of the same problems", file=sys.stderr, flush=True)
+    single = _single_f64(probs, npb)
+    single_ms = sum(t for t, _ in single)
+    errs = [abs(res[i]["dG"] - single[i][1]["dG"]) for i in range(len(probs))]
+    ok = [res[i]["finite"] and errs[i] <= _energy_tol(single[i][1]["dG"]) for i in range(len(probs))]
+    pts_all = [r["grid_point_updates"] for r in res]
+    pts = sum(pts_all)
+    pts_ok = sum(p for p, k in zip(pts_all, ok) if k)
+    sampled = {}
+    g = _golden("batch_mix_64_samples.json")
+    if g:
+        for key, ref in g["members"].items():
+            sch, i = key.split(":")
+            if sch == scheme:
+                i = int(i)
+                sampled[i] = {"grid": probs[i].grid.nx, "dG": res[i]["dG"], "oracle_dG": ref["dG"],
+                              "abs_err": abs(res[i]["dG"] - ref["dG"]), "tolerance": _energy_tol(ref["dG"]),
+                              "fp64_gpu_abs_err": abs(single[i][1]["dG"] - ref["dG"])}
+    return {"metric": "LOD grid-point-updates/s, batch of uneven grids", "value": pts_ok / (ms * 1e-3),
             "unit": "grid-point-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": args.precision, "data": "synthetic",
             "config": {"workload": "batch_mix_64_seed3", "grids": [w.grid.nx for w in probs],
-                       "scheme": "LODIE2", "richardson": True, "vacuum": True,
-                       "grid_point_updates_per_batch": pts, "finite": finite}}
+                       "scheme": scheme, "richardson": True, "vacuum": True,
+                       "grid_point_updates_per_batch": pts},
+            "accuracy": {"reference": "FP64 single-solve GPU path, same inputs",
+                         "within_tolerance": int(sum(ok)), "members": len(probs),
+                         "max_abs_err": max(errs), "oracle_samples": sampled},
+            "single_f64": {"ms_total": single_ms, "grid_point_updates_per_s": pts / (single_ms * 1e-3),
+                           "speedup_of_batch": single_ms / ms}}
+
+
+def bench_large(args):
+    """The 30000-atom complex on 321^3 nodes (h = 0.35): FP32 LODIE2, FP32
+    AOSIE2 and FP64 LODIE2 at dt 0.4 (20 / 40 steps, RE+V), and FP32 LODIE2
+    at dt 0.2 (40 / 80 steps); energies against stored oracle values."""
+    import torch
+
+    from paper_1410_2788_amd import inputs, npb
+    runs = [("f32", "LODIE2", 0.4, 20, "large_complex_321_lodie2_dt04.json"),
+            ("f32", "AOSIE2", 0.4, 20, "large_complex_321_aosie2_dt04.json"),
+            ("f64", "LODIE2", 0.4, 20, "large_complex_321_lodie2_dt04.json"),
+            ("f32", "LODIE2", 0.2, 40, "large_complex_321_lodie2_dt02.json")]
+    out_runs = []
+    for prec, scheme, dt, n, gname in runs:
+        w = inputs.large_complex(precision=prec, scheme=scheme, dt=dt, n_steps=n)
+        print(f"[bench] {w.name} {prec} {scheme} dt={dt} n={n}", file=sys.stderr, flush=True)
+        s = npb.Solver(w.molecule, w.grid, w.params, device=0)
+        if not args.no_autotune:
+            s.autotune()
+        for _ in range(max(1, args.warmup)):
+            s.run()
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        rs = [s.run() for _ in range(args.steps)]
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        ref = _golden(gname)
+        rec = {"precision": prec, "scheme": scheme, "dt": [dt, dt / 2], "steps": [n, 2 * n],
+               "ms_per_solve": ms, "grid_point_updates_per_solve": rs[0]["grid_point_updates"],
+               "dG": rs[0]["dG"], "dG_plain": rs[0]["dG_plain"]}
+        good = len(rs)
+        if ref:
+            errs = [abs(r["dG"] - ref["dG"]) for r in rs]
+            good = sum(e <= _energy_tol(ref["dG"]) for e in errs)
+            rec.update(oracle_dG=ref["dG"], abs_err=errs[0], tolerance=_energy_tol(ref["dG"]))
+        rec["grid_point_updates_per_s"] = rs[0]["grid_point_updates"] * good / (ms * 1e-3)
+        out_runs.append(rec)
+        del s
+    head = out_runs[0]
+    return {"metric": "LOD grid-point-updates/s, 321^3 complex", "value": head["grid_point_updates_per_s"],
+            "unit": "grid-point-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": head["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "large_complex_321", "grid": [321, 321, 321], "h": 0.35,
+                       "atoms": 30000},
+            "runs": out_runs}
 
 
 def bench_serve(args):
@@ -196,6 +304,8 @@ def main():
                     help="keep the built-in launch shapes instead of tuning them first")
     ap.add_argument("--batch", action="store_true",
                     help="time a batch of 64 uneven grids instead (own JSON line)")
+    ap.add_argument("--large", action="store_true",
+                    help="time the 30000-atom 321^3 complex in FP32 LOD, FP32 AOS and FP64 LOD (own JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="time the request loop under Poisson arrivals instead (own JSON line)")
     ap.add_argument("--requests", type=int, default=48)
@@ -215,6 +325,9 @@ def main():
         return
     if args.serve:
         print(json.dumps(bench_serve(args)))
+        return
+    if args.large:
+        print(json.dumps(bench_large(args)))
         return
 
     import numpy as np

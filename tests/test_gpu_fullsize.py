@@ -1,0 +1,164 @@
+"""GPU parity at the full workload sizes, in the launch configurations
+bench.py times, against oracle values stored by tests/golden/make_golden.py:
+
+  * the 30000-atom complex on 321^3 nodes (h 0.35): FP32 LODIE2 and AOSIE2,
+    FP64 LODIE2 and AOSIE2 at dt 0.4, FP32 LODIE2 at dt 0.2 -- energies and
+    the field at sampled nodes (random interior and boundary-shell nodes and
+    the largest |phi|);
+  * the 64-grid uneven batch (79..193^3), LODIE2 and AOSIE2 in FP32, solved
+    together: sampled members against the oracle (energies and field),
+    every member's energies equal to its single solve bit for bit;
+  * 48 serving requests (111..257^3) through the request loop: sampled
+    requests against the oracle, every result equal to its single solve.
+
+Tolerances: energies max(1e-3 kcal/mol, 1e-5 |E|) in FP32, 1e-9 relative in
+FP64; sampled field values 1e-10 max|phi| in FP64 and 1e-4 max|phi| in FP32
+(the FP32 field error grows with the number of steps and the line length;
+the measured error is printed with each case).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1410_2788_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+F32_FIELD = 1e-4
+F64_FIELD = 1e-10
+
+
+def _npb():
+    from paper_1410_2788_amd import npb
+    return npb
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _golden(name):
+    p = os.path.join(GOLDEN, name)
+    assert os.path.exists(p), f"stored oracle values missing: {p}"
+    return json.load(open(p))
+
+
+def _energy_tol(prec, ref):
+    return max(1e-3, 1e-5 * abs(ref)) if prec != "f64" else max(1e-7, 1e-9 * abs(ref))
+
+
+def _check_energies(prec, got, ref, tag):
+    bad = []
+    for k in ("dG", "dG_plain"):
+        if abs(got[k] - ref[k]) > _energy_tol(prec, ref[k]):
+            bad.append((k, got[k], ref[k]))
+    for k in ("G_m", "G_0"):
+        for lv in range(2):
+            if abs(got[k][lv] - ref[k][lv]) > _energy_tol(prec, ref[k][lv]):
+                bad.append((k, lv, got[k][lv], ref[k][lv]))
+    _say(f"  {tag}: dG {got['dG']!r} oracle {ref['dG']!r} err {got['dG'] - ref['dG']:.3e}")
+    assert got["n_charge_nodes"] == ref["n_charge_nodes"], tag
+    return bad
+
+
+def _check_field(prec, phi, ref, which, tag):
+    nodes = np.asarray(ref["field_nodes"], dtype=np.int64)
+    want = np.asarray(ref[which])
+    got = phi.ravel()[nodes]
+    rel = float(np.max(np.abs(got - want)) / ref[which + "_absmax"])
+    tol = F64_FIELD if prec == "f64" else F32_FIELD
+    _say(f"  {tag}: {which} at {len(nodes)} nodes, max err / max|phi| = {rel:.3e} (tol {tol:g})")
+    return [] if rel <= tol else [(which, rel)]
+
+
+LARGE = [("f32", "LODIE2", 0.4, 20, "lodie2_dt04"),
+         ("f32", "AOSIE2", 0.4, 20, "aosie2_dt04"),
+         ("f64", "LODIE2", 0.4, 20, "lodie2_dt04"),
+         ("f64", "AOSIE2", 0.4, 20, "aosie2_dt04"),
+         ("f32", "LODIE2", 0.2, 40, "lodie2_dt02")]
+
+
+@pytest.mark.parametrize("prec,scheme,dt,n,tag", LARGE, ids=[f"{p}-{s}-dt{d}" for p, s, d, _, _ in LARGE])
+def test_large_complex_321(prec, scheme, dt, n, tag):
+    npb = _npb()
+    ref = _golden(f"large_complex_321_{tag}.json")
+    w = inputs.large_complex(precision=prec, scheme=scheme, dt=dt, n_steps=n)
+    _say(f"case large_complex_321 {prec} {scheme} dt={dt} n={n}")
+    bad = []
+    for sel, which in ((0, "phi_m"), (1, "phi_0")):
+        s = npb.Solver(w.molecule, w.grid, w.params, want_field=True, field_select=sel)
+        r = s.run()
+        phi = s.field.cpu().numpy()
+        del s
+        if sel == 0:
+            bad += _check_energies(prec, r, ref, "energies")
+        bad += _check_field(prec, phi, ref, which, which)
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("scheme", ["LODIE2", "AOSIE2"])
+def test_batch_mix_64_full(scheme):
+    npb = _npb()
+    ref = _golden("batch_mix_64_samples.json")["members"]
+    probs = inputs.batch_mix(64, precision="f32", scheme=scheme)
+    _say(f"case batch_mix_64 f32 {scheme}: {sum(w.grid.nx ** 3 for w in probs) / 1e6:.1f} M nodes")
+    bs = npb.BatchSolver([(w.molecule, w.grid, w.params) for w in probs], want_field=True)
+    res = bs.run()
+    bad = []
+    for key, rv in ref.items():
+        sch, i = key.split(":")
+        if sch != scheme:
+            continue
+        i = int(i)
+        tag = f"member {i} ({probs[i].grid.nx}^3)"
+        bad += _check_energies("f32", res[i], rv, tag)
+        bad += _check_field("f32", bs.fields[i].cpu().numpy(), rv, "phi_m", tag)
+    del bs
+    for i, w in enumerate(probs):
+        one = npb.solve(w.molecule, w.grid, w.params)
+        for k in ("dG", "dG_plain", "G_m", "G_0", "n_charge_nodes", "steps_done"):
+            if res[i][k] != one[k]:
+                bad.append((i, k, res[i][k], one[k]))
+    assert not bad, bad
+
+
+def test_serve_48_full():
+    npb = _npb()
+    ref = _golden("serve_48_samples.json")["members"]
+    reqs = inputs.serve_requests(48, precision="f32")
+    _say("case serve_requests_48 f32 through the request loop (24 GiB arena, batches of 8)")
+    sv = npb.Server(24 << 30, max_batch=8, max_queue=64)
+    try:
+        tickets = [sv.submit(w.molecule, w.grid, w.params) for w in reqs]
+        out = {}
+        t0 = time.time()
+        while len(out) < len(tickets):
+            for t in tickets:
+                if t not in out:
+                    r = sv.poll(t)
+                    if r is not None:
+                        out[t] = r
+            assert time.time() - t0 < 90.0, "server did not finish in time"
+            time.sleep(0.002)
+        st = sv.stats()
+    finally:
+        sv.close()
+    _say("  server stats:", st)
+    bad = []
+    for i, (t, w) in enumerate(zip(tickets, reqs)):
+        status, r = out[t]
+        if status != npb.NPB_OK:
+            bad.append((i, "status", status))
+            continue
+        if str(i) in ref:
+            bad += _check_energies("f32", r, ref[str(i)], f"request {i} ({w.grid.nx}^3)")
+        one = npb.solve(w.molecule, w.grid, w.params)
+        if (r["dG"], r["G_m"], r["G_0"]) != (one["dG"], one["G_m"], one["G_0"]):
+            bad.append((i, r["dG"], one["dG"]))
+    assert not bad, bad
