@@ -94,17 +94,22 @@ inline int pitch_of(int nx, int es) {
   return (nx + q - 1) / q * q;
 }
 
+constexpr int kMaxChunk = 20;  // longest chunk compiled into the sweeps
 // Elimination constants of a chunk whose M+1 faces all carry the same
-// coefficient re (rows a = c = -re, b = 1 + 2 re): pivot reciprocals,
-// normalised couplings and the coefficients of the chunk's reduced rows.
-// Index t = 0: solvent chunks (or the uniform medium), t = 1: solute chunks.
-constexpr int kMaxChunk = 20;
+// coefficient re (rows with alpha = gamma = re and leak 1), index t = 0:
+// solvent chunks (or the uniform medium), t = 1: solute chunks.  inv, ga,
+// al: pivot reciprocals and the negated couplings of the eliminated rows
+// (ga = -gam_k, al = -lam_k); rf_c, rf_l: gamma and leak of the reduced row
+// of x_0 (its alpha is re, or 0 with re added to the leak on a line's
+// first chunk); rl_a, rl_c, rl_l: alpha, gamma and leak of the reduced row
+// of x_{M-1}.  Computed in double by the leak recurrences of the sweeps.
 template <typename A>
 struct ChunkTab {
   A inv[2][kMaxChunk];
   A ga[2][kMaxChunk];
   A al[2][kMaxChunk];
-  A ap[2], gp[2], re[2];
+  A re[2];
+  A rf_c[2], rf_l[2], rl_a[2], rl_c[2], rl_l[2];
 };
 
 // Pick chunk length / chunk count and the block shape for a line length.

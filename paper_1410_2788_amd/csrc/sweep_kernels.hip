@@ -73,74 +73,115 @@ __device__ __forceinline__ double rcp_pivot(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// Chunk elimination shared by both kernels.
+// Line systems and their precision.
 //
-// Rows k = 0..M-1 of one chunk are global interior rows g = g0 + k.  Row k
-// couples to row k-1 through -reF[k] and to row k+1 through -reF[k+1]
-// (reF = r * eps at the faces around the row).  The first interior row
-// (g = 0) has taken its left Dirichlet value into d; the last one (local
-// index kR = nint-1-g0) takes gR here.  Rows past it are identity rows with
-// zero right-hand side (d is 0 there on entry).  On return:
-//   al, ga, d hold the forward-eliminated rows 1..M-1 in the form
-//     x_k + al[k] x_0 + ga[k] x_{k+1} = d[k]
-//   rf[4] = reduced row of x_0 : (A x_prev_last + B x_0 + C x_{M-1} = D)
-//   rl[4] = reduced row of x_{M-1}: (A x_0 + B x_{M-1} + C x_next_first = D)
+// Every row of a line system (I - tau delta^2) v = s reads
+//   -alpha v_{k-1} + (ell + alpha + gamma) v_k - gamma v_{k+1} = d_k,
+// alpha, gamma = r * eps at the row's two faces and ell >= 1 the row-sum
+// defect ("leak"): 1 from the identity, plus the coupling to a Dirichlet
+// neighbour moved to the right-hand side.  The diagonal is up to a few
+// thousand while the solution depends on its unit part: formed as one FP32
+// number, every pivot of a line carries the same rounding at every step, a
+// fixed bias of the discrete operator (~1e-5 of the energy at production
+// sizes) rather than noise.  So the eliminations below never form a
+// diagonal: they carry the leak of each (partially eliminated) row as its
+// own non-negative quantity, the complement technique of the GTH algorithm
+// for M-matrices, and every pivot is a sum of non-negative terms.  Rounding
+// then stays relative to each quantity, and FP32 arithmetic gives the
+// accuracy of FP64 pivots.
+//
+// Chunk elimination.  Rows k = 0..M-1 of one chunk are global interior rows
+// g = g0 + k; reF[k] is r * eps at the face between rows k-1 and k.  The
+// first interior row (g = 0) has taken its left Dirichlet value into d; the
+// last one (local index kR = nint-1-g0) takes gR here.  Rows past it are
+// identity rows with zero right-hand side (d is 0 there on entry).  Rows
+// 1..M-1 are eliminated forward into
+//   x_k = d[k] + lam_k x_0 + gam_k x_{k+1},   al[k] = -lam_k, ga[k] = -gam_k,
+// with leak tau_k = 1 - lam_k - gam_k >= 0:
+//   den_k = ell_k + gamma_k + alpha_k (tau_{k-1} + lam_{k-1}),
+//   lam_k = alpha_k lam_{k-1} / den_k,  gam_k = gamma_k / den_k,
+//   tau_k = (ell_k + alpha_k tau_{k-1}) / den_k   (lam_0 = 1, tau_0 = 0).
+// Back substitution gives x_1 = D + P x_0 + G x_{M-1} with G = prod gam_k
+// and leak s = 1 - P - G = sum_j tau_j prod_{i<j} gam_i (j, i = 1..M-2),
+// accumulated forward.  Reduced rows (alpha, gamma, ell, d):
+//   rf, row of x_0:     (alpha_0, gamma_0 G, ell_0 + gamma_0 s, d_0 + gamma_0 D)
+//   rl, row of x_{M-1}: (lam_{M-1}, gam_{M-1}, tau_{M-1}, d[M-1])
+template <typename A>
+struct RRow {
+  A a, c, l, d;  // alpha, gamma, leak, right-hand side
+};
+
 template <typename A, int M>
-__device__ __forceinline__ void chunk_eliminate(A (&d)[M], A (&al)[M], A (&ga)[M], A (&rf)[4],
-                                                A (&rl)[4], const A (&reF)[M + 1], bool first,
+__device__ __forceinline__ void chunk_eliminate(A (&d)[M], A (&al)[M], A (&ga)[M], RRow<A>& rf,
+                                                RRow<A>& rl, const A (&reF)[M + 1], bool first,
                                                 int kR, A gR) {
-  static_assert(M >= 2, "chunks need at least two rows");
-  auto row = [&](int k, A& ak, A& bk, A& ck) {
+  static_assert(M >= 4, "chunks of at least four rows");
+  // the coefficients of row k
+  auto row = [&](int k, A& ak, A& ck, A& lk) {
     const bool real = k <= kR;
-    ak = (real && !(k == 0 && first)) ? -reF[k] : A(0);
-    ck = (k < kR) ? -reF[k + 1] : A(0);
-    bk = real ? A(1) + (reF[k] + reF[k + 1]) : A(1);
-    if (k == kR) d[k] = fma(reF[k + 1], gR, d[k]);
+    ak = (real && !(k == 0 && first)) ? reF[k] : A(0);
+    ck = (k < kR) ? reF[k + 1] : A(0);
+    lk = A(1);
+    if (real && k == 0 && first) lk += reF[0];
+    if (k == kR) {
+      lk += reF[k + 1];
+      d[k] = fma(reF[k + 1], gR, d[k]);
+    }
   };
-  A a0, b0, c0;
-  row(0, a0, b0, c0);
-  {
-    A a1, b1, c1;
-    row(1, a1, b1, c1);
-    A inv = rcp_pivot(b1);
-    al[1] = a1 * inv;
-    ga[1] = c1 * inv;
-    d[1] = d[1] * inv;
-  }
+  A a0, c0, l0;
+  row(0, a0, c0, l0);
+  if constexpr (sizeof(A) == 8) {
+    // FP64 arithmetic resolves the unit part of a diagonal directly: the
+    // textbook recurrences (fewer live registers), with the reduced rows'
+    // leaks taken as B + A + C at the end
 #pragma unroll
-  for (int k = 2; k < M; ++k) {
-    A ak, bk, ck;
-    row(k, ak, bk, ck);
-    A inv = rcp_pivot(fma(-ak, ga[k - 1], bk));
-    al[k] = -ak * al[k - 1] * inv;
-    ga[k] = ck * inv;
-    d[k] = fma(-ak, d[k - 1], d[k]) * inv;
-  }
-  rl[0] = al[M - 1];
-  rl[1] = A(1);
-  rl[2] = ga[M - 1];
-  rl[3] = d[M - 1];
-  // express x_1 through x_0 and x_{M-1}: x_1 = dp - ap x_0 - gp x_{M-1}
-  A ap, gp, dp;
-  if constexpr (M == 2) {
-    ap = A(0);
-    gp = A(-1);
-    dp = A(0);
-  } else {
-    ap = al[M - 2];
-    gp = ga[M - 2];
-    dp = d[M - 2];
+    for (int k = 1; k < M; ++k) {
+      A ak, ck, lk;
+      row(k, ak, ck, lk);
+      const A bk = lk + (ak + ck);
+      const A inv = rcp_pivot(k == 1 ? bk : fma(ak, ga[k - 1], bk));
+      al[k] = k == 1 ? -ak * inv : ak * al[k - 1] * inv;
+      ga[k] = -ck * inv;
+      d[k] = (k == 1 ? d[k] : fma(ak, d[k - 1], d[k])) * inv;
+    }
+    rl = RRow<A>{-al[M - 1], -ga[M - 1], A(1) + al[M - 1] + ga[M - 1], d[M - 1]};
+    // x_1 = dp - ap x_0 - gp x_{M-1}
+    A ap = al[M - 2], gp = ga[M - 2], dp = d[M - 2];
 #pragma unroll
     for (int k = M - 3; k >= 1; --k) {
       ap = fma(-ga[k], ap, al[k]);
       gp = -ga[k] * gp;
       dp = fma(-ga[k], dp, d[k]);
     }
+    // row 0: -a0 x_prev + (l0 + a0 + c0) x_0 - c0 x_1 = d_0
+    const A bf = fma(c0, ap, l0 + (a0 + c0));
+    const A cf = c0 * gp;  // = -C of the reduced row
+    rf = RRow<A>{a0, -cf, bf - a0 + cf, fma(c0, dp, d[0])};
+    return;
   }
-  rf[0] = a0;
-  rf[1] = fma(-c0, ap, b0);
-  rf[2] = -c0 * gp;
-  rf[3] = fma(-c0, dp, d[0]);
+  A lam = A(1), tau = A(0);
+  A s = A(0), G = A(1);  // leak and far coupling of x_1
+#pragma unroll
+  for (int k = 1; k < M; ++k) {
+    A ak, ck, lk;
+    row(k, ak, ck, lk);
+    const A inv = rcp_pivot(fma(ak, tau + lam, lk + ck));
+    lam = ak * lam * inv;
+    const A gam = ck * inv;
+    tau = fma(ak, tau, lk) * inv;
+    d[k] = (k == 1 ? d[k] : fma(ak, d[k - 1], d[k])) * inv;
+    al[k] = -lam;
+    ga[k] = -gam;
+    if (k <= M - 2) {
+      s = fma(tau, G, s);
+      G *= gam;
+    }
+    if (k == M - 1) rl = RRow<A>{lam, gam, tau, d[M - 1]};
+  }
+  A dp = d[M - 2];
+#pragma unroll
+  for (int k = M - 3; k >= 1; --k) dp = fma(-ga[k], dp, d[k]);
+  rf = RRow<A>{a0, c0 * G, fma(c0, s, l0), fma(c0, dp, d[0])};
 }
 
 // back substitution once x_0 (xf) and x_{M-1} (xl) are known; d becomes x
@@ -153,31 +194,25 @@ __device__ __forceinline__ void chunk_finish(A (&d)[M], const A (&al)[M], const 
   d[0] = xf;
 }
 
-// Uniform chunks (every face coefficient equal to re): the pivots and
-// couplings are the tabulated constants of ChunkTab, so only the right-hand
-// side is eliminated.  Same results as chunk_eliminate / chunk_finish with
-// reF[k] = re for all k (up to rounding of the tabulated values).
-template <typename A, int M>
-__device__ __forceinline__ void fast_eliminate(A (&d)[M], const A* inv, const A* ga, const A* al,
-                                               A re, A ap, A gp, bool first, A (&rf)[4],
-                                               A (&rl)[4]) {
-  d[1] = d[1] * inv[1];
+// Uniform chunks (every face coefficient equal to re, leak 1): the pivots,
+// couplings and reduced-row coefficients are the tabulated constants of
+// ChunkTab (computed by the same recurrences in FP64), so only the
+// right-hand side is eliminated.  tb: the table, t: its row (solvent /
+// solute).  The first chunk of a line has its left Dirichlet coupling in
+// the leak of row 0.
+template <typename A, int M, typename TB>
+__device__ __forceinline__ void fast_eliminate(A (&d)[M], const TB& tb, int t, bool first,
+                                               RRow<A>& rf, RRow<A>& rl) {
+  const A re = tb.re[t];
+  d[1] = d[1] * tb.inv[t][1];
 #pragma unroll
-  for (int k = 2; k < M; ++k) d[k] = fma(re, d[k - 1], d[k]) * inv[k];
-  rl[0] = al[M - 1];
-  rl[1] = A(1);
-  rl[2] = ga[M - 1];
-  rl[3] = d[M - 1];
-  A dp = A(0);
-  if constexpr (M > 2) {
-    dp = d[M - 2];
+  for (int k = 2; k < M; ++k) d[k] = fma(re, d[k - 1], d[k]) * tb.inv[t][k];
+  rl = RRow<A>{tb.rl_a[t], tb.rl_c[t], tb.rl_l[t], d[M - 1]};
+  A dp = d[M - 2];
 #pragma unroll
-    for (int k = M - 3; k >= 1; --k) dp = fma(-ga[k], dp, d[k]);
-  }
-  rf[0] = first ? A(0) : -re;
-  rf[1] = fma(re, ap, fma(A(2), re, A(1)));
-  rf[2] = re * gp;
-  rf[3] = fma(re, dp, d[0]);
+  for (int k = M - 3; k >= 1; --k) dp = fma(-tb.ga[t][k], dp, d[k]);
+  rf = RRow<A>{first ? A(0) : re, tb.rf_c[t], first ? tb.rf_l[t] + re : tb.rf_l[t],
+               fma(re, dp, d[0])};
 }
 
 template <typename A, int M>
@@ -189,56 +224,54 @@ __device__ __forceinline__ void fast_finish(A (&d)[M], const A* ga, const A* al,
 }
 
 // Reduced systems in LDS: entry (line l, row r, coefficient c) at
-// R[(4 r + c) * rs + l], rs = lines + 1, so that the lanes of one wave
-// writing them (different lines, same row) touch distinct banks.  Row 2p
-// is the first row of chunk p, row 2p+1 its last; the 2P rows of a line
-// form a tridiagonal system (A x_{r-1} + B x_r + C x_{r+1} = D) whose first
-// A and last C are zero.
+// R[(4 r + c) * rs + l], c = alpha, gamma, leak, d; rs = lines + 1, so
+// that the lanes of one wave writing them (different lines, same row) touch
+// distinct banks.  Row 2p is the first row of chunk p, row 2p+1 its last;
+// the 2P rows of a line form a tridiagonal system in the form above, whose
+// first alpha and last gamma are zero.  Both solvers keep it in that form.
 //
-// x sweeps solve it by parallel cyclic reduction with the P lanes of a line
-// side by side in one wave (lane t: line t / P, rows 2p and 2p+1 of
-// p = t % P, P a power of two): each step eliminates a row's couplings to
-// the rows at distance d using those rows (fetched from the neighbour
-// lanes), after which the row couples to the rows at distance 2d; after
-// steps d = 1, 2, ..., P every row stands alone and x_r = D_r / B_r.  Rows
-// outside the system act as identity rows (their coupling is already zero).
-template <typename A>
-struct RRow {
-  A a, b, c, d;
-};
-
+// x sweeps: parallel cyclic reduction with the P lanes of a line side by
+// side in one wave (lane t: line t / P, rows 2p and 2p+1 of p = t % P, P a
+// power of two).  Each step eliminates a row's couplings to the rows at
+// distance d using those rows (from the neighbour lanes): with
+// B = leak + alpha + gamma of each row, k1 = alpha_r / B_up, k2 = gamma_r / B_dn,
+//   alpha' = alpha_up k1,  gamma' = gamma_dn k2,
+//   leak'  = leak_r + leak_up k1 + leak_dn k2,  d' = d_r + d_up k1 + d_dn k2,
+// after which the row couples to the rows at distance 2d; after steps
+// d = 1, 2, ..., P every row stands alone and x_r = d_r / B_r.  Rows outside
+// the system act as identity rows (their coupling is already zero).
 template <typename A>
 __device__ __forceinline__ RRow<A> rrow_identity() {
-  return RRow<A>{A(0), A(1), A(0), A(0)};
+  return RRow<A>{A(0), A(0), A(1), A(0)};
 }
 
-// row r combined with its neighbours at distance d: couples to r +- 2d
+template <typename A>
+__device__ __forceinline__ A rrow_b(const RRow<A>& r) {
+  return r.l + (r.a + r.c);
+}
+
 template <typename A>
 __device__ __forceinline__ RRow<A> pcr_combine(const RRow<A>& r, const RRow<A>& up,
                                                const RRow<A>& dn) {
-  const A k1 = r.a * rcp_pivot(up.b);
-  const A k2 = r.c * rcp_pivot(dn.b);
-  RRow<A> o;
-  o.a = -up.a * k1;
-  o.b = r.b - up.c * k1 - dn.a * k2;
-  o.c = -dn.c * k2;
-  o.d = r.d - up.d * k1 - dn.d * k2;
-  return o;
+  const A k1 = r.a * rcp_pivot(rrow_b(up));
+  const A k2 = r.c * rcp_pivot(rrow_b(dn));
+  return RRow<A>{up.a * k1, dn.c * k2, fma(up.l, k1, fma(dn.l, k2, r.l)),
+                 fma(up.d, k1, fma(dn.d, k2, r.d))};
 }
 
 template <typename A>
 __device__ __forceinline__ RRow<A> shfl_row_up(const RRow<A>& r, int delta, int width) {
-  return RRow<A>{__shfl_up(r.a, delta, width), __shfl_up(r.b, delta, width),
-                 __shfl_up(r.c, delta, width), __shfl_up(r.d, delta, width)};
+  return RRow<A>{__shfl_up(r.a, delta, width), __shfl_up(r.c, delta, width),
+                 __shfl_up(r.l, delta, width), __shfl_up(r.d, delta, width)};
 }
 template <typename A>
 __device__ __forceinline__ RRow<A> shfl_row_down(const RRow<A>& r, int delta, int width) {
-  return RRow<A>{__shfl_down(r.a, delta, width), __shfl_down(r.b, delta, width),
-                 __shfl_down(r.c, delta, width), __shfl_down(r.d, delta, width)};
+  return RRow<A>{__shfl_down(r.a, delta, width), __shfl_down(r.c, delta, width),
+                 __shfl_down(r.l, delta, width), __shfl_down(r.d, delta, width)};
 }
 
 // Solve the reduced systems of all lines of the block (every thread takes
-// part); the solution overwrites the D coefficients.
+// part); the solution overwrites the d coefficients.
 template <typename A>
 __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
   const int p = tid & (P - 1);
@@ -270,58 +303,61 @@ __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
     r0 = n0;
     r1 = n1;
   }
-  R[(4 * (2 * p) + 3) * rs] = r0.d * rcp_pivot(r0.b);
-  R[(4 * (2 * p + 1) + 3) * rs] = r1.d * rcp_pivot(r1.b);
+  R[(4 * (2 * p) + 3) * rs] = r0.d * rcp_pivot(rrow_b(r0));
+  R[(4 * (2 * p + 1) + 3) * rs] = r1.d * rcp_pivot(rrow_b(r1));
 }
 
-// Serial Thomas on the 2P reduced rows of one line, by one lane (y/z
-// sweeps, whose chunk counts need not be powers of two); the solution
-// overwrites the D coefficients.  The next row's coefficients are read
-// before the current row's results are stored, so that LDS latency overlaps
-// the arithmetic instead of adding up row after row.
+// y/z sweeps (chunk counts need not be powers of two): Thomas on the 2P
+// reduced rows of one line by one lane, with u = 1 - (upper coupling of the
+// eliminated previous row) carried as a non-negative quantity:
+//   den = leak + gamma + alpha u,  cp = gamma / den,
+//   dp = (d + alpha dp_prev) / den,  u' = (leak + alpha u) / den;
+// back substitution x_r = dp_r + cp_r x_{r+1}.  cp and dp overwrite gamma
+// and d; the next row's coefficients are read before the current row's
+// results are stored, so that LDS latency overlaps the arithmetic.
 template <typename A>
 __device__ __forceinline__ void reduced_solve(A* R, int n2, int nl) {
-  const A i0 = rcp_pivot(R[1 * nl]);
-  A cp = R[2 * nl] * i0;
-  A dp = R[3 * nl] * i0;
-  A an = R[4 * nl], bn = R[5 * nl], cn = R[6 * nl], dn = R[7 * nl];
-  R[2 * nl] = cp;
-  R[3 * nl] = dp;
-  for (int r = 1; r < n2; ++r) {
-    const A ar = an, br = bn, cr = cn, dr = dn;
+  A u = A(0), dp = A(0);
+  A an = R[0], cn = R[1 * nl], ln = R[2 * nl], dn = R[3 * nl];
+  for (int r = 0; r < n2; ++r) {
+    const A ar = an, cr = cn, lr = ln, dr = dn;
     if (r + 1 < n2) {
       an = R[(4 * r + 4) * nl];
-      bn = R[(4 * r + 5) * nl];
-      cn = R[(4 * r + 6) * nl];
+      cn = R[(4 * r + 5) * nl];
+      ln = R[(4 * r + 6) * nl];
       dn = R[(4 * r + 7) * nl];
     }
-    const A inv = rcp_pivot(fma(-ar, cp, br));
-    cp = cr * inv;
-    dp = fma(-ar, dp, dr) * inv;
-    R[(4 * r + 2) * nl] = cp;
+    const A inv = rcp_pivot(fma(ar, u, lr + cr));
+    dp = fma(ar, dp, dr) * inv;
+    u = fma(ar, u, lr) * inv;
+    R[(4 * r + 1) * nl] = cr * inv;
     R[(4 * r + 3) * nl] = dp;
   }
   A xn = dp;
-  A cq = R[(4 * (n2 - 2) + 2) * nl], dq = R[(4 * (n2 - 2) + 3) * nl];
+  A cq = R[(4 * (n2 - 2) + 1) * nl], dq = R[(4 * (n2 - 2) + 3) * nl];
   for (int r = n2 - 2; r >= 0; --r) {
     const A cr = cq, dr = dq;
     if (r > 0) {
-      cq = R[(4 * r - 2) * nl];
+      cq = R[(4 * r - 3) * nl];
       dq = R[(4 * r - 1) * nl];
     }
-    xn = fma(-cr, xn, dr);
+    xn = fma(cr, xn, dr);
     R[(4 * r + 3) * nl] = xn;
   }
 }
 
 template <typename A>
-__device__ __forceinline__ void put_reduced(A* R, int nl, int p, const A (&rf)[4],
-                                            const A (&rl)[4]) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    R[(4 * (2 * p) + c) * nl] = rf[c];
-    R[(4 * (2 * p + 1) + c) * nl] = rl[c];
-  }
+__device__ __forceinline__ void put_reduced(A* R, int nl, int p, const RRow<A>& rf,
+                                            const RRow<A>& rl) {
+  const int f = 4 * (2 * p), l = 4 * (2 * p + 1);
+  R[(f + 0) * nl] = rf.a;
+  R[(f + 1) * nl] = rf.c;
+  R[(f + 2) * nl] = rf.l;
+  R[(f + 3) * nl] = rf.d;
+  R[(l + 0) * nl] = rl.a;
+  R[(l + 1) * nl] = rl.c;
+  R[(l + 2) * nl] = rl.l;
+  R[(l + 3) * nl] = rl.d;
 }
 
 // 16-byte vector access of V consecutive elements (V * sizeof(T) == 16);
@@ -395,7 +431,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   size_t off = 0;
   int* srng = reinterpret_cast<int*>(smem + off);  // source entry range of the block
   off += 16;
-  A* red = reinterpret_cast<A*>(smem + off);
+  A* red = reinterpret_cast<A*>(smem + off);  // reduced systems
   off += sizeof(A) * (size_t)(L + 1) * 2 * P * 4;
   // the tile and the mask rows carry P*M+2 spare elements at their end:
   // a chunk's reads may run past the last row (values selected away)
@@ -534,11 +570,10 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
   const int t = (fast && bs != 0) ? 1 : 0;
   A al[M], ga[M];
-  A rf[4], rl[4];
+  RRow<A> rf, rl;
   if (fast) {
-    const A re = tb.re[t];
-    if (first) d[0] = fma(re, gL, d[0]);
-    fast_eliminate<A, M>(d, tb.inv[t], tb.ga[t], tb.al[t], re, tb.ap[t], tb.gp[t], first, rf, rl);
+    if (first) d[0] = fma(tb.re[t], gL, d[0]);
+    fast_eliminate<A, M>(d, tb, t, first, rf, rl);
   } else {
     const A re0 = (A)(uniform ? a.re_uniform : a.re[0]);
     const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
@@ -644,7 +679,7 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   const uint32_t base = plane + (uint32_t)xb;
   const bool uniform = (a.mask == nullptr);
 
-  A* red = reinterpret_cast<A*>(smem);
+  A* red = reinterpret_cast<A*>(smem);  // reduced systems
   A* tile = red + (size_t)(TW + 1) * 2 * P * 4;
   uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)nrow * TS);  // [nrow][TW]
   int* srng = reinterpret_cast<int*>(mt + (size_t)nrow * TW);          // source entry range
@@ -759,11 +794,10 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
   const int t = (fast && bs != 0) ? 1 : 0;
   A al[M], ga[M];
-  A rf[4], rl[4];
+  RRow<A> rf, rl;
   if (fast) {
-    const A re = tb.re[t];
-    if (first) d[0] = fma(re, gL, d[0]);
-    fast_eliminate<A, M>(d, tb.inv[t], tb.ga[t], tb.al[t], re, tb.ap[t], tb.gp[t], first, rf, rl);
+    if (first) d[0] = fma(tb.re[t], gL, d[0]);
+    fast_eliminate<A, M>(d, tb, t, first, rf, rl);
   } else {
     const A re0 = (A)(uniform ? a.re_uniform : a.re[0]);
     const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
@@ -905,8 +939,9 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw)
   LaunchShape s{};
   const int es = fp64 ? 8 : 4;
   const int nint = n_along - 2;
-  // FP64 chunks stop at 16 rows (lane state in registers)
-  if (mt <= 0) mt = fp64 ? 16 : 20;
+  // FP64 chunks stop at 16 rows (lane state in registers); by default 12,
+  // which keeps three waves per SIMD resident
+  if (mt <= 0) mt = fp64 ? 12 : 20;
   if (fp64) mt = std::min(mt, 16);
   int P = (nint + mt - 1) / mt;
   if (P > 32) return s;  // unsupported length
@@ -940,26 +975,27 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw)
 }
 
 // Elimination constants of uniform chunks of M rows with face coefficient
-// re (computed in double, stored in A).
+// re: the leak recurrences of chunk_eliminate in double, stored in A.
 template <typename A>
 static void fill_tab_row(ChunkTab<A>& tb, int t, double re, int M) {
-  const double av = -re, bv = 1.0 + 2.0 * re, cv = -re;
   double inv[kMaxChunk] = {0}, ga[kMaxChunk] = {0}, al[kMaxChunk] = {0};
-  inv[1] = 1.0 / bv;
-  ga[1] = cv * inv[1];
-  al[1] = av * inv[1];
-  for (int k = 2; k < M; ++k) {
-    inv[k] = 1.0 / (bv - av * ga[k - 1]);
-    ga[k] = cv * inv[k];
-    al[k] = -av * al[k - 1] * inv[k];
-  }
-  double ap = 0.0, gp = -1.0;
-  if (M > 2) {
-    ap = al[M - 2];
-    gp = ga[M - 2];
-    for (int k = M - 3; k >= 1; --k) {
-      ap = al[k] - ga[k] * ap;
-      gp = -ga[k] * gp;
+  double lam = 1.0, tau = 0.0, s = 0.0, G = 1.0;
+  for (int k = 1; k < M; ++k) {
+    const double den = 1.0 + re + re * (tau + lam);
+    inv[k] = 1.0 / den;
+    lam = re * lam * inv[k];
+    const double gam = re * inv[k];
+    tau = (1.0 + re * tau) * inv[k];
+    al[k] = -lam;
+    ga[k] = -gam;
+    if (k <= M - 2) {
+      s += tau * G;
+      G *= gam;
+    }
+    if (k == M - 1) {
+      tb.rl_a[t] = (A)lam;
+      tb.rl_c[t] = (A)gam;
+      tb.rl_l[t] = (A)tau;
     }
   }
   for (int k = 0; k < kMaxChunk; ++k) {
@@ -967,9 +1003,9 @@ static void fill_tab_row(ChunkTab<A>& tb, int t, double re, int M) {
     tb.ga[t][k] = (A)ga[k];
     tb.al[t][k] = (A)al[k];
   }
-  tb.ap[t] = (A)ap;
-  tb.gp[t] = (A)gp;
   tb.re[t] = (A)re;
+  tb.rf_c[t] = (A)(re * G);
+  tb.rf_l[t] = (A)(1.0 + re * s);
 }
 
 template <typename A>
