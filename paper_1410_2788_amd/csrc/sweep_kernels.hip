@@ -940,8 +940,9 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw)
   const int es = fp64 ? 8 : 4;
   const int nint = n_along - 2;
   // FP64 chunks stop at 16 rows (lane state in registers); by default 12,
-  // which keeps three waves per SIMD resident
-  if (mt <= 0) mt = fp64 ? 12 : 20;
+  // which keeps three waves per SIMD resident, unless a line would need
+  // more than 32 of them
+  if (mt <= 0) mt = fp64 ? ((nint + 11) / 12 <= 32 ? 12 : 16) : 20;
   if (fp64) mt = std::min(mt, 16);
   int P = (nint + mt - 1) / mt;
   if (P > 32) return s;  // unsupported length
