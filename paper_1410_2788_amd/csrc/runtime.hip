@@ -89,50 +89,56 @@ struct InitSet {
   T* u[kMaxFields];
   const double* bc[kMaxFields];
 };
+// One node row (j, k) per wave, 16-byte stores along it; the row's indices
+// are wave-uniform, so only the boundary columns of interior rows branch.
 template <typename T>
-__global__ void field_init_multi_kernel(InitSet<T> set, int nx, int nxp, int ny, int nz) {
+__global__ __launch_bounds__(256) void field_init_multi_kernel(InitSet<T> set, int nx, int nxp,
+                                                               int ny, int nz) {
+  constexpr int VX = 16 / (int)sizeof(T);
   const int r = blockIdx.y;
-  T* u = set.u[r];
+  const int row = blockIdx.x * 4 + (int)(threadIdx.x >> 6);  // row = k * ny + j
+  if (row >= ny * nz) return;
+  const int k = row / ny, j = row - k * ny;
+  T* u = set.u[r] + (size_t)row * nxp;
   const double* bc = set.bc[r];
-  const long long n = (long long)nxp * ny * nz;
   const long long nxy = (long long)nx * ny;
   const long long ring = 2LL * nx + 2LL * (ny - 2);
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    int i = (int)(p % nxp);
-    long long t = p / nxp;
-    int j = (int)(t % ny);
-    int k = (int)(t / ny);
-    T v = T(0);
-    if (i >= nx) {
-      v = T(0);
-    } else if (k == 0) {
-      v = (T)bc[(long long)j * nx + i];
-    } else if (k == nz - 1) {
-      v = (T)bc[nxy + (long long)j * nx + i];
-    } else {
-      long long base = 2 * nxy + (long long)(k - 1) * ring;
-      if (j == 0)
-        v = (T)bc[base + i];
-      else if (j == ny - 1)
-        v = (T)bc[base + nx + i];
-      else if (i == 0)
-        v = (T)bc[base + 2LL * nx + 2LL * (j - 1)];
-      else if (i == nx - 1)
-        v = (T)bc[base + 2LL * nx + 2LL * (j - 1) + 1];
+  const bool face = (k == 0 || k == nz - 1 || j == 0 || j == ny - 1);
+  const long long base = (k == 0)        ? (long long)j * nx
+                         : (k == nz - 1) ? nxy + (long long)j * nx
+                         : (j == 0)      ? 2 * nxy + (long long)(k - 1) * ring
+                         : (j == ny - 1) ? 2 * nxy + (long long)(k - 1) * ring + nx
+                                         : 2 * nxy + (long long)(k - 1) * ring + 2LL * nx +
+                                               2LL * (j - 1);
+  for (int c = (int)(threadIdx.x & 63) * VX; c < nxp; c += 64 * VX) {
+    T v[VX];
+#pragma unroll
+    for (int q = 0; q < VX; ++q) {
+      const int x = c + q;
+      T val = T(0);
+      if (x < nx) {
+        if (face)
+          val = (T)bc[base + x];
+        else if (x == 0)
+          val = (T)bc[base];
+        else if (x == nx - 1)
+          val = (T)bc[base + 1];
+      }
+      v[q] = val;
     }
-    u[p] = v;
+    if constexpr (VX == 4)
+      *reinterpret_cast<float4*>(u + c) = make_float4(v[0], v[1], v[2], v[3]);
+    else
+      *reinterpret_cast<double2*>(u + c) = make_double2(v[0], v[1]);
   }
 }
 
 template <typename T>
 hipError_t launch_field_init_multi(const InitSet<T>& set, int nruns, int nx, int nxp, int ny,
                                    int nz, hipStream_t st) {
-  long long n = (long long)nxp * ny * nz;
-  long long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((field_init_multi_kernel<T>), dim3((unsigned)blocks, nruns), dim3(256), 0, st,
-                     set, nx, nxp, ny, nz);
+  const int rows = ny * nz;
+  hipLaunchKernelGGL((field_init_multi_kernel<T>), dim3((unsigned)((rows + 3) / 4), nruns),
+                     dim3(256), 0, st, set, nx, nxp, ny, nz);
   return hipGetLastError();
 }
 

@@ -163,71 +163,72 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const int* kin, cons
   }
 }
 
-// single-block exclusive scan of n ints in place; *total = sum
-__global__ __launch_bounds__(1024) void scan_kernel(int* data, int n, int* total) {
-  __shared__ int part[1024];
-  const int tid = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int b = tid * per;
-  const int e = min(b + per, n);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += data[i];
-  part[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int run = part[tid] - s;
-  for (int i = b; i < e; ++i) {
-    int v = data[i];
-    data[i] = run;
-    run += v;
-  }
-  if (tid == 1023 && total) *total = part[1023];
-}
+// Exclusive prefix sum of n ints by one block of 1024 threads, tile by
+// tile (kScanTile entries staged in LDS by coalesced loads and stores, with
+// one padding word per 32 entries so that the per-thread walks over
+// consecutive entries fall in distinct banks), carrying the running total
+// from tile to tile.  The total goes to *total if given.
+constexpr int kScanTile = 32768;
+__host__ __device__ inline int scan_pad(int i) { return i + (i >> 5); }
 
-// the same scan with the array staged through LDS by coalesced loads and
-// stores (n <= kScanLds): the per-thread chunk walk reads LDS, not HBM
-constexpr int kScanLds = 16384;
-__global__ __launch_bounds__(1024) void scan_lds_kernel(int* data, int n, int* total) {
+__global__ __launch_bounds__(1024) void scan_lds_kernel(int* data, int n, int tile, int* total) {
   extern __shared__ int buf[];
-  __shared__ int part[1024];
+  __shared__ int wtot[16];
   const int tid = threadIdx.x;
-  for (int i = tid; i < n; i += 1024) buf[i] = data[i];
-  __syncthreads();
-  const int per = (n + 1023) / 1024;
-  const int b = tid * per;
-  const int e = min(b + per, n);
-  int s = 0;
-  for (int i = b; i < e; ++i) s += buf[i];
-  part[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = tid >= off ? part[tid - off] : 0;
+  const int lane = tid & 63, w = tid >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += tile) {
+    const int m = min(tile, n - base);
+    for (int i = tid; i < m; i += 1024) buf[scan_pad(i)] = data[base + i];
     __syncthreads();
-    part[tid] += v;
+    const int per = (m + 1023) / 1024;
+    const int b = tid * per;
+    const int e = min(b + per, m);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += buf[scan_pad(i)];
+    // inclusive scan of the per-thread sums: within each wave by shuffles,
+    // then over the 16 wave totals
+    int inc = s;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += v;
+    }
+    if (lane == 63) wtot[w] = inc;
     __syncthreads();
+    if (w == 0) {
+      int t = lane < 16 ? wtot[lane] : 0;
+      for (int off = 1; off < 16; off <<= 1) {
+        const int v = __shfl_up(t, off, 64);
+        if (lane >= off) t += v;
+      }
+      if (lane < 16) wtot[lane] = t;
+    }
+    __syncthreads();
+    int run = carry + (w > 0 ? wtot[w - 1] : 0) + inc - s;
+    for (int i = b; i < e; ++i) {
+      const int v = buf[scan_pad(i)];
+      buf[scan_pad(i)] = run;
+      run += v;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += 1024) data[base + i] = buf[scan_pad(i)];
+    carry += wtot[15];
+    __syncthreads();  // buf and wtot are reused by the next tile
   }
-  int run = part[tid] - s;
-  for (int i = b; i < e; ++i) {
-    int v = buf[i];
-    buf[i] = run;
-    run += v;
-  }
-  __syncthreads();
-  for (int i = tid; i < n; i += 1024) data[i] = buf[i];
-  if (tid == 1023 && total) *total = part[1023];
+  if (tid == 0 && total) *total = carry;
 }
 
 hipError_t launch_exclusive_scan(int* data, int n, int* total, hipStream_t st) {
-  if (n <= kScanLds)
-    hipLaunchKernelGGL(scan_lds_kernel, dim3(1), dim3(1024), (size_t)n * sizeof(int), st, data, n,
-                       total);
-  else
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, data, n, total);
+  const int tile = n < kScanTile ? (n > 0 ? n : 1) : kScanTile;
+  const size_t lds = (size_t)scan_pad(tile) * sizeof(int);
+  if (lds > 64 * 1024) {
+    // allowed once for the largest tile
+    static const hipError_t allowed = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(scan_lds_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(scan_pad(kScanTile) * sizeof(int)));
+    if (allowed != hipSuccess) return allowed;
+  }
+  hipLaunchKernelGGL(scan_lds_kernel, dim3(1), dim3(1024), lds, st, data, n, tile, total);
   return hipGetLastError();
 }
 
@@ -407,9 +408,10 @@ __device__ __forceinline__ void shell_node(long long s, int nx, int ny, int nz, 
 
 // Both media in one pass: the solvated value with eps_s and kappa, the
 // vacuum value (kappa = 0) with eps_v, sharing the distance of every
-// (shell node, atom) pair.  R is the arithmetic type of one pair's term;
-// the sums over atoms are FP64 in both cases, and the constant factor
-// l_B / eps is applied once at the end.
+// (shell node, atom) pair.  R is the arithmetic type of one pair's term
+// (FP64 here; FP32 terms use boundary_f32_kernel below); the sums over
+// atoms are FP64, and the constant factor l_B / eps is applied once at the
+// end.
 template <typename R>
 __device__ __forceinline__ void pair_terms(R dx, R dy, R dz, R q, R kappa, R& ts, R& tv);
 template <>
@@ -418,14 +420,6 @@ __device__ __forceinline__ void pair_terms<double>(double dx, double dy, double 
   const double d = sqrt(dx * dx + dy * dy + dz * dz);
   tv = q / d;
   ts = tv * exp(-kappa * d);
-}
-template <>
-__device__ __forceinline__ void pair_terms<float>(float dx, float dy, float dz, float q,
-                                                  float kappa, float& ts, float& tv) {
-  const float d2 = dx * dx + dy * dy + dz * dz;
-  const float ri = rsqrtf(d2);
-  tv = q * ri;
-  ts = tv * __expf(-kappa * (d2 * ri));
 }
 
 template <typename R>
@@ -473,6 +467,73 @@ __global__ __launch_bounds__(256) void boundary_kernel(SetupArgs a, double scale
   }
 }
 
+// FP32 terms: a block takes 64 shell nodes and splits the atoms four ways
+// (thread = node t % 64, slice t / 64), so that a small shell still fills
+// the device; atoms are staged as (x, y, z, q) in LDS (one 16-byte read per
+// pair), the terms of up to 32 atoms are summed in FP32 before they join
+// the FP64 sums (the per-term rounding of FP32 terms is of the same
+// order), and the four slices' FP64 sums are added in LDS at the end.
+constexpr int kBcNodes = 64, kBcSlices = 4;
+__global__ __launch_bounds__(256) void boundary_f32_kernel(SetupArgs a, double scale_s,
+                                                           double kappa, double scale_v,
+                                                           double* bc_s, double* bc_v,
+                                                           long long nshell) {
+  __shared__ float4 sa[256];
+  __shared__ double rs[kBcSlices][kBcNodes], rv[kBcSlices][kBcNodes];
+  const int tn = threadIdx.x % kBcNodes, sl = threadIdx.x / kBcNodes;
+  const long long s = (long long)blockIdx.x * kBcNodes + tn;
+  const bool valid = s < nshell;
+  float X = 0.0f, Y = 0.0f, Z = 0.0f;
+  if (valid) {
+    int i, j, k;
+    shell_node(s, a.nx, a.ny, a.nz, i, j, k);
+    X = (float)(a.ox + (double)i * a.h);
+    Y = (float)(a.oy + (double)j * a.h);
+    Z = (float)(a.oz + (double)k * a.h);
+  }
+  const int na = a.n_atoms;
+  const float nk = -(float)kappa;
+  double acc_s = 0.0, acc_v = 0.0;
+  for (int t0 = 0; t0 < na; t0 += 256) {
+    const int t = t0 + threadIdx.x;
+    if (t < na)
+      sa[threadIdx.x] = make_float4((float)a.atoms[t], (float)a.atoms[na + t],
+                                    (float)a.atoms[2 * na + t], (float)a.atoms[3 * na + t]);
+    __syncthreads();
+    // this slice's atoms of the tile: sl, sl + 4, ...
+    const int cnt = min(256, na - t0);
+    for (int j0 = sl; j0 < cnt; j0 += 32 * kBcSlices) {
+      float ps = 0.0f, pv = 0.0f;
+      const int je = min(j0 + 32 * kBcSlices, cnt);
+      for (int jj = j0; jj < je; jj += kBcSlices) {
+        const float4 at = sa[jj];
+        const float dx = X - at.x, dy = Y - at.y, dz = Z - at.z;
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float ri = rsqrtf(d2);
+        const float tv = at.w * ri;
+        pv += tv;
+        ps = fmaf(tv, __expf(nk * (d2 * ri)), ps);
+      }
+      acc_s += (double)ps;
+      acc_v += (double)pv;
+    }
+    __syncthreads();
+  }
+  rs[sl][tn] = acc_s;
+  rv[sl][tn] = acc_v;
+  __syncthreads();
+  if (sl == 0 && valid) {
+    double ts = 0.0, tv = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBcSlices; ++q) {
+      ts += rs[q][tn];
+      tv += rv[q][tn];
+    }
+    bc_s[s] = scale_s * ts;
+    if (bc_v) bc_v[s] = scale_v * tv;
+  }
+}
+
 hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, double eps_v,
                            double lB, double* bc_s, double* bc_v, bool fp32_terms,
                            hipStream_t st) {
@@ -480,7 +541,8 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
   const dim3 g((unsigned)((ns + 255) / 256)), b(256);
   const double ss = lB / eps_s, sv = lB / eps_v;
   if (fp32_terms)
-    hipLaunchKernelGGL(boundary_kernel<float>, g, b, 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
+    hipLaunchKernelGGL(boundary_f32_kernel, dim3((unsigned)((ns + kBcNodes - 1) / kBcNodes)),
+                       dim3(kBcNodes * kBcSlices), 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
   else
     hipLaunchKernelGGL(boundary_kernel<double>, g, b, 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
   return hipGetLastError();
