@@ -286,6 +286,10 @@ struct npb_ctx {
   bool timing = false;
   bool graphs = true;
   hipStream_t capture = nullptr;  // stream the solve graph is captured on
+  // second lane of the time loops (vacuum runs) and its fork / lag / join
+  // events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, lag = nullptr, join = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<unsigned char> key;  // GraphKey per problem + the launch-table buffer
   // line-solver shapes chosen by npb_autotune, per (nx, ny, nz, precision,
@@ -578,6 +582,7 @@ struct Engine {
 
   struct Field {
     int prob, run, steps;
+    int lane;         // 0: solvated runs, 1: vacuum runs (their own stream)
     double bytes[3];  // algorithmic bytes of one sweep per direction
   };
   std::vector<Field> fields;
@@ -589,23 +594,28 @@ struct Engine {
     std::vector<int> nblk;         // blocks of the first k members, k = 1..size
     std::vector<size_t> work_off;  // int2[nblk[k-1]] per k
     int nbu = 0;                   // blocks per member when all members have the same count
+    int lane = 0;
   };
   std::vector<Group> groups[3];
   std::vector<unsigned char> meta;  // host image of the launch tables
 
   template <typename F>
   npb_status timed(int cls, double bytes, F&& f) {
+    return timed_on(st, cls, bytes, f);
+  }
+  template <typename F>
+  npb_status timed_on(hipStream_t s, int cls, double bytes, F&& f) {
     hipEvent_t a = nullptr, b = nullptr;
     if (ctx->timing) {
       a = ev_get(ctx);
       b = ev_get(ctx);
       if (!a || !b) return fail(NPB_EDEVICE, "event creation failed");
-      NPB_HIP(hipEventRecord(a, st));
+      NPB_HIP(hipEventRecord(a, s));
     }
     hipError_t e = f();
     if (e != hipSuccess) return fail(NPB_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
     if (ctx->timing) {
-      NPB_HIP(hipEventRecord(b, st));
+      NPB_HIP(hipEventRecord(b, s));
       ctx->pending.push_back({cls, a, b, bytes});
     }
     return NPB_OK;
@@ -696,6 +706,7 @@ struct Engine {
         f.bytes[0] = pts * (2.0 * sizeof(T) + mb + ab);
         f.bytes[1] = pts * (2.0 * sizeof(T) + mb + 2.0 * ab);
         f.bytes[2] = pts * (2.0 * sizeof(T) + mb + ab);
+        f.lane = P.L.runs[r].medium == 1 ? 1 : 0;
         fields.push_back(f);
       }
       for (int d = 0; d < 3; ++d)
@@ -710,13 +721,16 @@ struct Engine {
       for (int fi = 0; fi < (int)fields.size(); ++fi) {
         const LaunchShape& sh = pr[fields[fi].prob].L.shape[d];
         int g = 0;
+        const int lane = fields[fi].lane;
         while (g < (int)groups[d].size() &&
                !(groups[d][g].s.M == sh.M && groups[d][g].s.P == sh.P &&
-                 groups[d][g].s.LW == sh.LW && groups[d][g].s.threads == sh.threads))
+                 groups[d][g].s.LW == sh.LW && groups[d][g].s.threads == sh.threads &&
+                 groups[d][g].lane == lane))
           ++g;
         if (g == (int)groups[d].size()) {
           groups[d].push_back(Group{});
           groups[d].back().s = sh;
+          groups[d].back().lane = lane;
           gargs[d].emplace_back();
         }
         Group& G = groups[d][g];
@@ -915,26 +929,58 @@ struct Engine {
       });
       if (s != NPB_OK) return s;
     }
+    // Two lanes: the solvated runs on `st`, the vacuum runs (independent
+    // problems) on the context's side stream, one sweep behind.  Sweeps of
+    // the two lanes then run at the same time in different phases (one
+    // launch's loads while the other's blocks solve), which one launch
+    // alone cannot do: its blocks move between memory and arithmetic
+    // phases in step.  The side stream joins `st` before and after the
+    // loops (in a captured graph these are graph dependencies).
+    bool two = false;
+    for (const Field& f : fields) two = two || f.lane == 1;
+    hipStream_t ls[2] = {st, two ? ctx->side : st};
+    if (two) {
+      NPB_HIP(hipEventRecord(ctx->fork, st));
+      NPB_HIP(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    }
+    bool lag_recorded = false, lag_waited = !two;
     const int max_steps = fields.empty() ? 0 : fields[0].steps;
     unsigned char* dm = reinterpret_cast<unsigned char*>(ctx->meta);
     for (int step = 0; step < max_steps; ++step) {
       for (int d = 0; d < 3; ++d) {
-        for (const Group& G : groups[d]) {
-          int k = 0;
-          double bytes = 0.0;
-          while (k < (int)G.members.size() && fields[G.members[k]].steps > step)
-            bytes += fields[G.members[k++]].bytes[d];
-          if (k == 0) continue;
-          const auto* args = reinterpret_cast<const SweepArgs<T>*>(dm + G.args_off);
-          const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[k - 1]);
-          const int nb = G.nblk[k - 1];
-          npb_status s = timed(NPB_K_SWEEP_X + d, bytes, [&] {
-            return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.s, st)
-                          : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, st);
-          });
-          if (s != NPB_OK) return s;
+        for (int lane = 0; lane < 2; ++lane) {
+          for (const Group& G : groups[d]) {
+            if (G.lane != lane) continue;
+            int k = 0;
+            double bytes = 0.0;
+            while (k < (int)G.members.size() && fields[G.members[k]].steps > step)
+              bytes += fields[G.members[k++]].bytes[d];
+            if (k == 0) continue;
+            if (lane == 1 && !lag_waited) {
+              // the side lane starts once the first solvated sweep is done
+              if (lag_recorded) NPB_HIP(hipStreamWaitEvent(ctx->side, ctx->lag, 0));
+              lag_waited = true;
+            }
+            const hipStream_t s = ls[lane];
+            const auto* args = reinterpret_cast<const SweepArgs<T>*>(dm + G.args_off);
+            const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[k - 1]);
+            const int nb = G.nblk[k - 1];
+            npb_status r = timed_on(s, NPB_K_SWEEP_X + d, bytes, [&] {
+              return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.s, s)
+                            : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, s);
+            });
+            if (r != NPB_OK) return r;
+            if (two && lane == 0 && !lag_recorded) {
+              NPB_HIP(hipEventRecord(ctx->lag, st));
+              lag_recorded = true;
+            }
+          }
         }
       }
+    }
+    if (two) {
+      NPB_HIP(hipEventRecord(ctx->join, ctx->side));
+      NPB_HIP(hipStreamWaitEvent(st, ctx->join, 0));
     }
     return NPB_OK;
   }
@@ -1263,9 +1309,14 @@ npb_status npb_ctx_create(int device, npb_ctx** out) {
   if (!c) return fail(NPB_ENOMEM, "context allocation failed");
   c->device = device;
   if (hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
-    if (c->t0) (void)hipEventDestroy(c->t0);
-    if (c->t1) (void)hipEventDestroy(c->t1);
+      hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->lag, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    for (hipEvent_t e : {c->t0, c->t1, c->fork, c->lag, c->join})
+      if (e) (void)hipEventDestroy(e);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
     delete c;
     return fail(NPB_EDEVICE, "event or stream creation failed");
   }
@@ -1281,10 +1332,11 @@ void npb_ctx_destroy(npb_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
-  if (c->t0) (void)hipEventDestroy(c->t0);
-  if (c->t1) (void)hipEventDestroy(c->t1);
+  for (hipEvent_t e : {c->t0, c->t1, c->fork, c->lag, c->join})
+    if (e) (void)hipEventDestroy(e);
   if (c->exec) (void)hipGraphExecDestroy(c->exec);
   if (c->capture) (void)hipStreamDestroy(c->capture);
+  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->meta) (void)hipFree(c->meta);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
