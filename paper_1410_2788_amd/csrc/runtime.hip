@@ -286,10 +286,14 @@ struct npb_ctx {
   bool timing = false;
   bool graphs = true;
   hipStream_t capture = nullptr;  // stream the solve graph is captured on
-  // second lane of the time loops (vacuum runs) and its fork / lag / join
-  // events
-  hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, lag = nullptr, join = nullptr;
+  // further lanes of the time loops (runs of other media / levels) and
+  // their fork / lag / join events
+  static constexpr int kLanes = 4;
+  hipStream_t side[kLanes - 1] = {};
+  hipEvent_t fork = nullptr, lag[kLanes - 1] = {}, join[kLanes - 1] = {};
+  // lanes used: 2 (by medium) measured fastest; 4 (by medium and level)
+  // runs the short coarse-step runs beside the long ones and was slower
+  int lanes = 2;
   hipGraphExec_t exec = nullptr;
   std::vector<unsigned char> key;  // GraphKey per problem + the launch-table buffer
   // line-solver shapes chosen by npb_autotune, per (nx, ny, nz, precision,
@@ -582,7 +586,7 @@ struct Engine {
 
   struct Field {
     int prob, run, steps;
-    int lane;         // 0: solvated runs, 1: vacuum runs (their own stream)
+    int lane;         // stream of the run: by medium and level, see plan()
     double bytes[3];  // algorithmic bytes of one sweep per direction
   };
   std::vector<Field> fields;
@@ -706,7 +710,10 @@ struct Engine {
         f.bytes[0] = pts * (2.0 * sizeof(T) + mb + ab);
         f.bytes[1] = pts * (2.0 * sizeof(T) + mb + 2.0 * ab);
         f.bytes[2] = pts * (2.0 * sizeof(T) + mb + ab);
-        f.lane = P.L.runs[r].medium == 1 ? 1 : 0;
+        // lanes: 2 -> by medium; 4 -> by medium and level
+        f.lane = ctx->lanes >= 4 ? 2 * P.L.runs[r].medium + P.L.runs[r].level
+                 : ctx->lanes >= 2 ? P.L.runs[r].medium
+                                   : 0;
         fields.push_back(f);
       }
       for (int d = 0; d < 3; ++d)
@@ -929,26 +936,29 @@ struct Engine {
       });
       if (s != NPB_OK) return s;
     }
-    // Two lanes: the solvated runs on `st`, the vacuum runs (independent
-    // problems) on the context's side stream, one sweep behind.  Sweeps of
-    // the two lanes then run at the same time in different phases (one
-    // launch's loads while the other's blocks solve), which one launch
-    // alone cannot do: its blocks move between memory and arithmetic
-    // phases in step.  The side stream joins `st` before and after the
-    // loops (in a captured graph these are graph dependencies).
-    bool two = false;
-    for (const Field& f : fields) two = two || f.lane == 1;
-    hipStream_t ls[2] = {st, two ? ctx->side : st};
-    if (two) {
+    // Lanes: the runs of each medium (and, with four lanes, each level) are
+    // independent problems; lane 0 sweeps on `st`, lane k > 0 on a side
+    // stream of the context, started one sweep after lane k-1.  Sweeps of
+    // different lanes then run at the same time in different phases (one
+    // launch's loads while another's blocks solve), which one launch alone
+    // cannot do: its blocks move between memory and arithmetic phases in
+    // step.  The side streams join `st` before and after the loops (in a
+    // captured graph these are graph dependencies).
+    int nl = 1;
+    for (const Field& f : fields) nl = std::max(nl, f.lane + 1);
+    hipStream_t ls[npb_ctx::kLanes];
+    ls[0] = st;
+    for (int l = 1; l < nl; ++l) ls[l] = ctx->side[l - 1];
+    if (nl > 1) {
       NPB_HIP(hipEventRecord(ctx->fork, st));
-      NPB_HIP(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+      for (int l = 1; l < nl; ++l) NPB_HIP(hipStreamWaitEvent(ls[l], ctx->fork, 0));
     }
-    bool lag_recorded = false, lag_waited = !two;
+    bool started[npb_ctx::kLanes] = {};
     const int max_steps = fields.empty() ? 0 : fields[0].steps;
     unsigned char* dm = reinterpret_cast<unsigned char*>(ctx->meta);
     for (int step = 0; step < max_steps; ++step) {
       for (int d = 0; d < 3; ++d) {
-        for (int lane = 0; lane < 2; ++lane) {
+        for (int lane = 0; lane < nl; ++lane) {
           for (const Group& G : groups[d]) {
             if (G.lane != lane) continue;
             int k = 0;
@@ -956,11 +966,11 @@ struct Engine {
             while (k < (int)G.members.size() && fields[G.members[k]].steps > step)
               bytes += fields[G.members[k++]].bytes[d];
             if (k == 0) continue;
-            if (lane == 1 && !lag_waited) {
-              // the side lane starts once the first solvated sweep is done
-              if (lag_recorded) NPB_HIP(hipStreamWaitEvent(ctx->side, ctx->lag, 0));
-              lag_waited = true;
-            }
+            // a lane starts once the previous lane's first sweep is done
+            if (!started[lane] && lane > 0 && started[lane - 1])
+              NPB_HIP(hipStreamWaitEvent(ls[lane], ctx->lag[lane - 1], 0));
+            const bool first = !started[lane];
+            started[lane] = true;
             const hipStream_t s = ls[lane];
             const auto* args = reinterpret_cast<const SweepArgs<T>*>(dm + G.args_off);
             const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[k - 1]);
@@ -970,17 +980,14 @@ struct Engine {
                             : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, s);
             });
             if (r != NPB_OK) return r;
-            if (two && lane == 0 && !lag_recorded) {
-              NPB_HIP(hipEventRecord(ctx->lag, st));
-              lag_recorded = true;
-            }
+            if (first && lane + 1 < nl) NPB_HIP(hipEventRecord(ctx->lag[lane], s));
           }
         }
       }
     }
-    if (two) {
-      NPB_HIP(hipEventRecord(ctx->join, ctx->side));
-      NPB_HIP(hipStreamWaitEvent(st, ctx->join, 0));
+    for (int l = 1; l < nl; ++l) {
+      NPB_HIP(hipEventRecord(ctx->join[l - 1], ls[l]));
+      NPB_HIP(hipStreamWaitEvent(st, ctx->join[l - 1], 0));
     }
     return NPB_OK;
   }
@@ -1298,6 +1305,19 @@ double npb_kappa_bar_sq(double ionic_molar, double temperature_K) {
   return kKbar2PerMolar298 * (298.0 / temperature_K) * ionic_molar;
 }
 
+// streams and events of a context, then the context itself
+static void ctx_release(npb_ctx* c) {
+  for (hipEvent_t e : {c->t0, c->t1, c->fork})
+    if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < npb_ctx::kLanes - 1; ++i) {
+    if (c->lag[i]) (void)hipEventDestroy(c->lag[i]);
+    if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+    if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
+  }
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  delete c;
+}
+
 npb_status npb_ctx_create(int device, npb_ctx** out) {
   if (!out) return fail(NPB_EINVAL, "null output pointer");
   *out = nullptr;
@@ -1308,16 +1328,15 @@ npb_status npb_ctx_create(int device, npb_ctx** out) {
   npb_ctx* c = new (std::nothrow) npb_ctx();
   if (!c) return fail(NPB_ENOMEM, "context allocation failed");
   c->device = device;
-  if (hipEventCreate(&c->t0) != hipSuccess || hipEventCreate(&c->t1) != hipSuccess ||
-      hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->lag, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
-    for (hipEvent_t e : {c->t0, c->t1, c->fork, c->lag, c->join})
-      if (e) (void)hipEventDestroy(e);
-    if (c->capture) (void)hipStreamDestroy(c->capture);
-    delete c;
+  bool ok = hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess &&
+            hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < npb_ctx::kLanes - 1; ++i)
+    ok = hipEventCreateWithFlags(&c->lag[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming) == hipSuccess &&
+         hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    ctx_release(c);
     return fail(NPB_EDEVICE, "event or stream creation failed");
   }
   *out = c;
@@ -1332,14 +1351,10 @@ void npb_ctx_destroy(npb_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {c->t0, c->t1, c->fork, c->lag, c->join})
-    if (e) (void)hipEventDestroy(e);
   if (c->exec) (void)hipGraphExecDestroy(c->exec);
-  if (c->capture) (void)hipStreamDestroy(c->capture);
-  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->meta) (void)hipFree(c->meta);
   if (c->pinned) (void)hipHostFree(c->pinned);
-  delete c;
+  ctx_release(c);
 }
 
 npb_status npb_ctx_set_timing(npb_ctx* c, int enable) {
