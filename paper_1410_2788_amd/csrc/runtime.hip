@@ -953,36 +953,50 @@ struct Engine {
       NPB_HIP(hipEventRecord(ctx->fork, st));
       for (int l = 1; l < nl; ++l) NPB_HIP(hipStreamWaitEvent(ls[l], ctx->fork, 0));
     }
-    bool started[npb_ctx::kLanes] = {};
+    // the launches of every lane in order, then issued with lane l offset
+    // by l * lag launches of lane 0 (so that at any time the lanes run
+    // different sweeps)
+    struct Launch {
+      const Group* G;
+      int d, k;
+      double bytes;
+    };
+    std::vector<Launch> seq[npb_ctx::kLanes];
     const int max_steps = fields.empty() ? 0 : fields[0].steps;
-    unsigned char* dm = reinterpret_cast<unsigned char*>(ctx->meta);
-    for (int step = 0; step < max_steps; ++step) {
-      for (int d = 0; d < 3; ++d) {
-        for (int lane = 0; lane < nl; ++lane) {
-          for (const Group& G : groups[d]) {
-            if (G.lane != lane) continue;
-            int k = 0;
-            double bytes = 0.0;
-            while (k < (int)G.members.size() && fields[G.members[k]].steps > step)
-              bytes += fields[G.members[k++]].bytes[d];
-            if (k == 0) continue;
-            // a lane starts once the previous lane's first sweep is done
-            if (!started[lane] && lane > 0 && started[lane - 1])
-              NPB_HIP(hipStreamWaitEvent(ls[lane], ctx->lag[lane - 1], 0));
-            const bool first = !started[lane];
-            started[lane] = true;
-            const hipStream_t s = ls[lane];
-            const auto* args = reinterpret_cast<const SweepArgs<T>*>(dm + G.args_off);
-            const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[k - 1]);
-            const int nb = G.nblk[k - 1];
-            npb_status r = timed_on(s, NPB_K_SWEEP_X + d, bytes, [&] {
-              return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.s, s)
-                            : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, s);
-            });
-            if (r != NPB_OK) return r;
-            if (first && lane + 1 < nl) NPB_HIP(hipEventRecord(ctx->lag[lane], s));
-          }
+    for (int step = 0; step < max_steps; ++step)
+      for (int d = 0; d < 3; ++d)
+        for (const Group& G : groups[d]) {
+          int k = 0;
+          double bytes = 0.0;
+          while (k < (int)G.members.size() && fields[G.members[k]].steps > step)
+            bytes += fields[G.members[k++]].bytes[d];
+          if (k > 0) seq[G.lane].push_back(Launch{&G, d, k, bytes});
         }
+    // stagger of one sweep measured best (0, 2 and 3 sweeps: 2-3 % slower)
+    const int lag = 1;
+    unsigned char* dm = reinterpret_cast<unsigned char*>(ctx->meta);
+    size_t total = 0;
+    for (int l = 0; l < nl; ++l) total = std::max(total, seq[l].size() + (size_t)l * lag);
+    for (size_t i = 0; i < total; ++i) {
+      for (int lane = 0; lane < nl; ++lane) {
+        const long long j = (long long)i - (long long)lane * lag;
+        if (j < 0 || j >= (long long)seq[lane].size()) continue;
+        const Launch& L = seq[lane][j];
+        // a lane starts once the previous lane has done `lag` sweeps
+        if (j == 0 && lane > 0 && lag > 0)
+          NPB_HIP(hipStreamWaitEvent(ls[lane], ctx->lag[lane - 1], 0));
+        const hipStream_t s = ls[lane];
+        const Group& G = *L.G;
+        const int d = L.d;
+        const auto* args = reinterpret_cast<const SweepArgs<T>*>(dm + G.args_off);
+        const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[L.k - 1]);
+        const int nb = G.nblk[L.k - 1];
+        npb_status r = timed_on(s, NPB_K_SWEEP_X + d, L.bytes, [&] {
+          return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.s, s)
+                        : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, s);
+        });
+        if (r != NPB_OK) return r;
+        if (lane + 1 < nl && lag > 0 && j + 1 == lag) NPB_HIP(hipEventRecord(ctx->lag[lane], s));
       }
     }
     for (int l = 1; l < nl; ++l) {
