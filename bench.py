@@ -35,15 +35,16 @@ def _sweep_source_sha():
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def _traffic(kernel_class: str, precision: str):
-    """HBM bytes per launch from the committed PMC summary, if it was taken
-    on the current sweep source; else None."""
+def _traffic(kernel: str, precision: str):
+    """HBM bytes per launch of `kernel` (the profiler's name of the template
+    instance) from the committed PMC summary, if it was taken on the current
+    sweep source and the same instance ran there; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
-        e = d.get(f"{kernel_class}:{precision}")
+        e = d.get(kernel)
         if e and e.get("source_sha") == _sweep_source_sha():
             return e.get("bytes_per_launch")
     except (OSError, ValueError):
@@ -368,8 +369,9 @@ def main():
     total_ms = ev0.elapsed_time(ev1)
 
     # per-kernel durations: the same solves once more with every launch
-    # bracketed by HIP events on the solve's stream (direct launches; a
-    # kernel's duration does not depend on how it was enqueued)
+    # bracketed by HIP events (direct launches, the launches of the two
+    # media one after another on the solve's stream, so that each duration
+    # is the kernel's own and not shared with a concurrent launch)
     ktimes = None
     if not args.no_timing:
         print("[bench] per-kernel timing pass", file=sys.stderr, flush=True)
@@ -391,26 +393,40 @@ def main():
 
     roof = None
     if ktimes:
-        cls = max(("sweep_x", "sweep_y", "sweep_z"), key=lambda c: ktimes[c]["ms"])
-        kt = ktimes[cls]
+        # dominant sweep kernel (the one with the largest summed duration),
+        # named as the profiler names the template instance that ran it
+        bk = ktimes["by_kernel"]
+        kname = max(bk, key=lambda k: bk[k]["ms"])
+        kt = bk[kname]
         avg_ms = kt["ms"] / max(kt["count"], 1)
         bpl = kt["bytes"] / max(kt["count"], 1)
         ach = bpl / (avg_ms * 1e-3) / 1e9
+        tname = {"f32": "float, float", "f32x": "float, double", "f64": "double, double"}[args.precision]
+        if kname == "x":
+            full = f"npb::sweep_x_kernel<{tname}, {shapes[0][0]}, {shapes[0][2]}>"
+        else:
+            var = {"yz_plain": 0, "yz_flow": 1, "yz_general": 2}[kname]
+            d = 1 if var != 1 else 2
+            full = f"npb::sweep_yz_kernel<{tname}, {shapes[d][0]}, {var}, {shapes[d][2]}>"
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": _traffic(cls, args.precision),
-                "kernel": f"npb::sweep_{cls[-1]}_kernel", "avg_launch_us": round(avg_ms * 1e3, 2),
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": _traffic(full, args.precision),
+                "kernel": full, "avg_launch_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": bpl,
+                "timing": "HIP events around each launch of the timing pass; the two "
+                          "media's launches issued one after another on one stream",
+                "per_kernel": {k: {"launches": bk[k]["count"],
+                                   "avg_us": round(bk[k]["ms"] / max(bk[k]["count"], 1) * 1e3, 2),
+                                   "GBps": round(bk[k]["bytes"] / max(bk[k]["ms"], 1e-12) / 1e6, 1)}
+                               for k in bk if bk[k]["count"]},
                 "per_class": {c: {"launches": ktimes[c]["count"],
                                   "avg_us": round(ktimes[c]["ms"] / max(ktimes[c]["count"], 1) * 1e3, 2),
                                   "GBps": round(ktimes[c]["bytes"] / max(ktimes[c]["ms"], 1e-12) / 1e6, 1)}
                               for c in ("sweep_x", "sweep_y", "sweep_z", "init", "setup", "energy")}}
 
     if roof is not None:
-        # The solvated and vacuum runs sweep on two concurrent streams, so a
-        # launch shares the device with the other lane's launch and its own
-        # duration understates the rate.  Whole-solve figure: algorithmic
-        # bytes of every sweep of one solve over the solve's device time
-        # (setup and energies included).
+        # Whole-solve figure for the timed solves, whose two media sweep on
+        # concurrent streams: algorithmic bytes of every sweep of one solve
+        # over the solve's device time (setup and energies included).
         sweep_bytes = sum(ktimes[c]["bytes"] for c in ("sweep_x", "sweep_y", "sweep_z"))
         nsolves = max(min(args.steps, 5), 1)
         dev_ms = float(np.median([r["device_ms"] for r in results]))

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NPB_ABI_VERSION 1
+#define NPB_ABI_VERSION 2
 
 typedef enum npb_status {
   NPB_OK = 0,
@@ -137,17 +137,30 @@ typedef struct npb_result {
 typedef struct npb_ctx npb_ctx;
 
 /* Per-kernel timing gathered while timing is enabled (npb_ctx_set_timing):
- * launches and summed device milliseconds for each kernel class, measured
- * with HIP events recorded on the solve's stream around each launch. */
+ * launches, summed device milliseconds and algorithmic bytes, measured with
+ * HIP events recorded around each launch on the stream it runs on.
+ * count/ms/bytes are indexed by npb_kernel_class (the sweeps by direction);
+ * kcount/kms/kbytes split the sweep launches again by the kernel that ran
+ * them, indexed by npb_sweep_kernel. */
 typedef struct npb_kernel_times {
   int64_t count[8];
   double ms[8];
   double bytes[8];   /* algorithmic bytes moved by those launches */
+  int64_t kcount[4];
+  double kms[4];
+  double kbytes[4];
 } npb_kernel_times;
 
 enum npb_kernel_class {
   NPB_K_SWEEP_X = 0, NPB_K_SWEEP_Y = 1, NPB_K_SWEEP_Z = 2,
   NPB_K_SETUP = 3, NPB_K_INIT = 4, NPB_K_ENERGY = 5, NPB_K_OTHER = 6
+};
+
+enum npb_sweep_kernel {
+  NPB_SK_X = 0,          /* x sweep (every scheme)                              */
+  NPB_SK_YZ_PLAIN = 1,   /* y/z sweep, line solves only                         */
+  NPB_SK_YZ_FLOW = 2,    /* y/z sweep fused with the sinh sub-step (LODIE2 z)   */
+  NPB_SK_YZ_GENERAL = 3  /* y/z sweep with sources and AOS accumulation         */
 };
 
 /* Returns NPB_ABI_VERSION.  Pure. */
@@ -168,7 +181,10 @@ void npb_ctx_destroy(npb_ctx* ctx);
 
 /* Enable (1) or disable (0) per-kernel event timing; enabling clears the
  * accumulated times.  While timing is on, solves launch every kernel
- * directly (no graph replay) so that each launch can be bracketed. */
+ * directly (no graph replay) and one at a time on the solve's stream (the
+ * time loops of the two media, which otherwise run on concurrent streams,
+ * are serialized), so that each bracketed launch has the device to itself
+ * and its duration is the kernel's own.  Results do not change. */
 npb_status npb_ctx_set_timing(npb_ctx* ctx, int enable);
 npb_status npb_ctx_get_kernel_times(npb_ctx* ctx, npb_kernel_times* out);
 

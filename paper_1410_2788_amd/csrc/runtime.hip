@@ -308,6 +308,7 @@ struct npb_ctx {
   npb_kernel_times times{};
   struct Pending {
     int cls;
+    int sk;  // npb_sweep_kernel of a sweep launch, else -1
     hipEvent_t a, b;
     double bytes;
   };
@@ -345,6 +346,11 @@ void harvest(npb_ctx* c) {
       c->times.count[p.cls] += 1;
       c->times.ms[p.cls] += ms;
       c->times.bytes[p.cls] += p.bytes;
+      if (p.sk >= 0) {
+        c->times.kcount[p.sk] += 1;
+        c->times.kms[p.sk] += ms;
+        c->times.kbytes[p.sk] += p.bytes;
+      }
     }
     c->pool.push_back(p.a);
     c->pool.push_back(p.b);
@@ -605,10 +611,10 @@ struct Engine {
 
   template <typename F>
   npb_status timed(int cls, double bytes, F&& f) {
-    return timed_on(st, cls, bytes, f);
+    return timed_on(st, cls, -1, bytes, f);
   }
   template <typename F>
-  npb_status timed_on(hipStream_t s, int cls, double bytes, F&& f) {
+  npb_status timed_on(hipStream_t s, int cls, int sk, double bytes, F&& f) {
     hipEvent_t a = nullptr, b = nullptr;
     if (ctx->timing) {
       a = ev_get(ctx);
@@ -620,7 +626,7 @@ struct Engine {
     if (e != hipSuccess) return fail(NPB_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
     if (ctx->timing) {
       NPB_HIP(hipEventRecord(b, s));
-      ctx->pending.push_back({cls, a, b, bytes});
+      ctx->pending.push_back({cls, sk, a, b, bytes});
     }
     return NPB_OK;
   }
@@ -946,10 +952,13 @@ struct Engine {
     // captured graph these are graph dependencies).
     int nl = 1;
     for (const Field& f : fields) nl = std::max(nl, f.lane + 1);
+    // While timing, the lanes keep their launches but all issue on `st`, one
+    // after another, so that each bracketed launch has the device alone.
+    const bool serial = ctx->timing;
     hipStream_t ls[npb_ctx::kLanes];
     ls[0] = st;
-    for (int l = 1; l < nl; ++l) ls[l] = ctx->side[l - 1];
-    if (nl > 1) {
+    for (int l = 1; l < nl; ++l) ls[l] = serial ? st : ctx->side[l - 1];
+    if (nl > 1 && !serial) {
       NPB_HIP(hipEventRecord(ctx->fork, st));
       for (int l = 1; l < nl; ++l) NPB_HIP(hipStreamWaitEvent(ls[l], ctx->fork, 0));
     }
@@ -983,7 +992,7 @@ struct Engine {
         if (j < 0 || j >= (long long)seq[lane].size()) continue;
         const Launch& L = seq[lane][j];
         // a lane starts once the previous lane has done `lag` sweeps
-        if (j == 0 && lane > 0 && lag > 0)
+        if (j == 0 && lane > 0 && lag > 0 && !serial)
           NPB_HIP(hipStreamWaitEvent(ls[lane], ctx->lag[lane - 1], 0));
         const hipStream_t s = ls[lane];
         const Group& G = *L.G;
@@ -991,15 +1000,20 @@ struct Engine {
         const auto* args = reinterpret_cast<const SweepArgs<T>*>(dm + G.args_off);
         const auto* work = reinterpret_cast<const int2*>(dm + G.work_off[L.k - 1]);
         const int nb = G.nblk[L.k - 1];
-        npb_status r = timed_on(s, NPB_K_SWEEP_X + d, L.bytes, [&] {
+        const int sk = d == 0 ? NPB_SK_X
+                       : G.var == kYzPlain ? NPB_SK_YZ_PLAIN
+                       : G.var == kYzFlow ? NPB_SK_YZ_FLOW
+                                          : NPB_SK_YZ_GENERAL;
+        npb_status r = timed_on(s, NPB_K_SWEEP_X + d, sk, L.bytes, [&] {
           return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.s, s)
                         : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, s);
         });
         if (r != NPB_OK) return r;
-        if (lane + 1 < nl && lag > 0 && j + 1 == lag) NPB_HIP(hipEventRecord(ctx->lag[lane], s));
+        if (lane + 1 < nl && lag > 0 && j + 1 == lag && !serial)
+          NPB_HIP(hipEventRecord(ctx->lag[lane], s));
       }
     }
-    for (int l = 1; l < nl; ++l) {
+    for (int l = 1; l < nl && !serial; ++l) {
       NPB_HIP(hipEventRecord(ctx->join[l - 1], ls[l]));
       NPB_HIP(hipStreamWaitEvent(st, ctx->join[l - 1], 0));
     }

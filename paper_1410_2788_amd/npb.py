@@ -24,6 +24,9 @@ STATUS_NAMES = {0: "NPB_OK", 1: "NPB_EINVAL", 2: "NPB_ERANGE", 3: "NPB_ENOMEM",
 SCHEMES = {"LODIE2": 0, "LODIE1": 1, "AOSIE2": 2, "AOSIE1": 3}
 PRECISIONS = {"f64": 0, "f32": 1, "f32x": 2}
 KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other"]
+# sweep launches split again by the kernel that ran them (npb_sweep_kernel)
+SWEEP_KERNELS = ["x", "yz_plain", "yz_flow", "yz_general"]
+ABI_VERSION = 2
 
 
 class npb_molecule(C.Structure):
@@ -52,7 +55,8 @@ class npb_result(C.Structure):
 
 
 class npb_kernel_times(C.Structure):
-    _fields_ = [("count", C.c_int64 * 8), ("ms", C.c_double * 8), ("bytes", C.c_double * 8)]
+    _fields_ = [("count", C.c_int64 * 8), ("ms", C.c_double * 8), ("bytes", C.c_double * 8),
+                ("kcount", C.c_int64 * 4), ("kms", C.c_double * 4), ("kbytes", C.c_double * 4)]
 
 
 class npb_server_stats(C.Structure):
@@ -86,6 +90,9 @@ def load_library(path: str = LIB_PATH):
         lib = C.CDLL(path)
         P = C.POINTER
         lib.npb_abi_version.restype = C.c_int
+        if lib.npb_abi_version() != ABI_VERSION:
+            raise ImportError(f"{path} has ABI version {lib.npb_abi_version()}, this binding "
+                              f"expects {ABI_VERSION}: rebuild it")
         lib.npb_last_error.restype = C.c_char_p
         lib.npb_kappa_bar_sq.restype = C.c_double
         lib.npb_kappa_bar_sq.argtypes = [C.c_double, C.c_double]
@@ -134,7 +141,8 @@ def load_library(path: str = LIB_PATH):
 
 def header_functions(path: str = HEADER_PATH):
     """Names of the functions include/npb.h declares."""
-    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", " ", open(path).read(), flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
     return sorted(set(re.findall(r"\b(npb_[a-z_0-9]+)\s*\(", text)))
 
 
@@ -179,8 +187,12 @@ def npb_ctx_set_graph(ctx, enable: bool) -> None:
 def npb_ctx_get_kernel_times(ctx) -> dict:
     t = npb_kernel_times()
     _check(load_library().npb_ctx_get_kernel_times(ctx, C.byref(t)))
-    return {name: {"count": int(t.count[i]), "ms": float(t.ms[i]), "bytes": float(t.bytes[i])}
-            for i, name in enumerate(KERNEL_CLASSES)}
+    out = {name: {"count": int(t.count[i]), "ms": float(t.ms[i]), "bytes": float(t.bytes[i])}
+           for i, name in enumerate(KERNEL_CLASSES)}
+    out["by_kernel"] = {name: {"count": int(t.kcount[i]), "ms": float(t.kms[i]),
+                               "bytes": float(t.kbytes[i])}
+                        for i, name in enumerate(SWEEP_KERNELS)}
+    return out
 
 
 def npb_validate(mol: npb_molecule, grid: npb_grid, params: npb_params) -> int:
