@@ -194,6 +194,12 @@ __device__ __forceinline__ void chunk_finish(A (&d)[M], const A (&al)[M], const 
   d[0] = xf;
 }
 
+// Chunk tables are read through the constant address space with a
+// wave-uniform row index, so that they come in by scalar loads rather than
+// per-lane flat loads (which wait on both memory counters).
+template <typename A>
+using ConstTab = const __attribute__((address_space(4))) ChunkTab<A>;
+
 // Uniform chunks (every face coefficient equal to re, leak 1): the pivots,
 // couplings and reduced-row coefficients are the tabulated constants of
 // ChunkTab (computed by the same recurrences in FP64), so only the
@@ -215,8 +221,8 @@ __device__ __forceinline__ void fast_eliminate(A (&d)[M], const TB& tb, int t, b
                fma(re, dp, d[0])};
 }
 
-template <typename A, int M>
-__device__ __forceinline__ void fast_finish(A (&d)[M], const A* ga, const A* al, A xf, A xl) {
+template <typename A, int M, typename Ptr>
+__device__ __forceinline__ void fast_finish(A (&d)[M], Ptr ga, Ptr al, A xf, A xl) {
   d[M - 1] = xl;
 #pragma unroll
   for (int k = M - 2; k >= 1; --k) d[k] = fma(-ga[k], d[k + 1], fma(-al[k], xf, d[k]));
@@ -408,7 +414,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   const int2 w = nbu > 0 ? make_int2((int)blockIdx.x / nbu, (int)blockIdx.x % nbu)
                          : work[blockIdx.x];
   const SweepArgs<T>& a = args[w.x];
-  const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
+  ConstTab<A>& tb = *(ConstTab<A>*)(a.tab);
   const int nx = a.nx, ny = a.ny, nz = a.nz, nxp = a.nxp;
   const int nint = nx - 2;
   const int P = a.P, S = a.S;
@@ -568,7 +574,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   const unsigned long long bf = __ballot(lvalid && inner);
   const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
   const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
-  const int t = (fast && bs != 0) ? 1 : 0;
+  const int t = __builtin_amdgcn_readfirstlane((fast && bs != 0) ? 1 : 0);
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
@@ -599,7 +605,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   const A xf = R[(4 * (2 * p) + 3) * (L + 1)];
   const A xl = R[(4 * (2 * p + 1) + 3) * (L + 1)];
   if (fast)
-    fast_finish<A, M>(d, tb.ga[t], tb.al[t], xf, xl);
+    fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl);
   else
     chunk_finish<A, M>(d, al, ga, xf, xl);
   // results back into the row; a full chunk stores without per-row checks
@@ -632,6 +638,117 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   }
 }
 
+// Face class of lane tid's chunk (line x = xb + tid % TW, chunk tid / TW)
+// in a y (dir 1) or z (dir 2) sweep of the lines at transverse index o: 0
+// uniform solvent, 2 uniform solute, 1 mixed (the uniform medium: 0).
+template <typename T, int TW>
+__device__ __forceinline__ int yz_chunk_class(const SweepArgs<T>& a, int dir, int o, int xb,
+                                              int tid) {
+  const int nx = a.nx;
+  const int x = xb + tid % TW;
+  if (x < 1 || x > nx - 2) return 1;
+  if (a.mask == nullptr) return 0;
+  if (!a.ccls) return 1;
+  const long long nl = (long long)(nx - 2) * ((dir == 1 ? a.nz : a.ny) - 2);
+  const auto* cc = (const __attribute__((address_space(1))) uint8_t*)a.ccls;
+  return (int)cc[(size_t)(tid / TW) * nl + (size_t)(o - 1) * (nx - 2) + (x - 1)];
+}
+
+// Line solves of one y/z tile held in LDS: tile[row * ts + q] is node row
+// `row` (0..n-1 along the line) of x = xb + q, mt[row * TW + q] its solute
+// flag; red holds the reduced systems ((TW + 1)-strided).  Lane tid takes
+// line q = tid % TW and chunk p = tid / TW; cls is the chunk's face class
+// (yz_chunk_class).  On return the tile holds the solution (with the fused
+// flow of kYzFlow / post_nl) on the interior rows of the lane's line; other
+// columns are untouched.  Contains the block barriers of the reduced solve.
+template <typename T, typename A, int M, int VAR, int TW>
+__device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, int ts,
+                                               const uint8_t* mt, A* red, int n, int xb, int cls,
+                                               int tid) {
+  ConstTab<A>& tb = *(ConstTab<A>*)(a.tab);
+  const int nx = a.nx, P = a.P;
+  const int nint = n - 2;
+  const bool uniform = (a.mask == nullptr);
+  const int ql = tid % TW;
+  const int p = tid / TW;
+  const int x = xb + ql;
+  const bool lvalid = x >= 1 && x <= nx - 2;
+  // chunk elimination: the lane's column of the tile from row 1 + g0
+  const int g0 = p * M;
+  A* col = tile + (1 + g0) * ts + ql;
+  const uint8_t* mcol = mt + g0 * TW + ql;  // flag of along node g0 + k at mcol[k * TW]
+  A d[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const A v = col[k * ts];
+    d[k] = (g0 + k < nint) ? v : A(0);
+  }
+  const A gL = tile[ql];
+  const A gR = tile[(n - 1) * ts + ql];
+  const bool first = (g0 == 0);
+  const int kR = lvalid ? nint - 1 - g0 : -1;
+  // lanes without a line follow whatever path their wave takes
+  const bool inner = cls != 1 && kR >= M;
+  const unsigned long long bv = __ballot(lvalid);
+  const unsigned long long bf = __ballot(lvalid && inner);
+  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
+  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
+  const int t = __builtin_amdgcn_readfirstlane((fast && bs != 0) ? 1 : 0);
+  A al[M], ga[M];
+  RRow<A> rf, rl;
+  if (fast) {
+    if (first) d[0] = fma(tb.re[t], gL, d[0]);
+    fast_eliminate<A, M>(d, tb, t, first, rf, rl);
+  } else {
+    const A re0 = (A)(uniform ? a.re_uniform : a.re[0]);
+    const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
+    const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
+    A reF[M + 1];
+    int prev = uniform ? 1 : (int)mcol[0];
+#pragma unroll
+    for (int k = 0; k <= M; ++k) {
+      // face between along nodes g0 + k and g0 + k + 1
+      const int cur = uniform ? 1 : (int)mcol[(k + 1) * TW];
+      const int c = (g0 + k + 1 > n - 1) ? 2 : prev + cur;
+      reF[k] = pick3(c, re0, re1, re2);
+      prev = cur;
+    }
+    if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
+    chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
+  }
+  A* R = red + ql;
+  put_reduced(R, TW + 1, p, rf, rl);
+  __syncthreads();
+  if (p == 0 && lvalid) reduced_solve(R, 2 * P, TW + 1);
+  __syncthreads();
+  const A xf = R[(4 * (2 * p) + 3) * (TW + 1)];
+  const A xl = R[(4 * (2 * p + 1) + 3) * (TW + 1)];
+  if (fast)
+    fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl);
+  else
+    chunk_finish<A, M>(d, al, ga, xf, xl);
+
+  if ((VAR == kYzFlow || (VAR == kYzGeneral && a.post_nl)) && !uniform) {
+    const A ka = (A)a.post_ka, kb = (A)a.post_kb;
+    if (fast) {
+      if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) d[k] = sinh_flow(d[k], ka, kb);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+        if (mcol[(k + 1) * TW] == 0) d[k] = sinh_flow(d[k], ka, kb);
+    }
+  }
+  // rows past the line end land in rows n-1.. of the tile, which are
+  // neither stored nor read again
+  if (lvalid) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) col[k * ts] = d[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // y / z sweep.  Block: one tile of TW consecutive x (x = xb .. xb+TW-1) of
 // one plane of the other transverse index o, across the whole line length
@@ -661,7 +778,6 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   const int2 w = nbu > 0 ? make_int2((int)blockIdx.x / nbu, (int)blockIdx.x % nbu)
                          : work[blockIdx.x];
   const SweepArgs<T>& a = args[w.x];
-  const ChunkTab<A>& tb = *static_cast<const ChunkTab<A>*>(a.tab);
   const int nx = a.nx, ny = a.ny, nxp = a.nxp;
   const int P = a.P, nrow = a.S;
   const int nthreads = TW * P;
@@ -732,11 +848,6 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   }
   __syncthreads();
 
-  const int ql = tid % TW;
-  const int p = tid / TW;
-  const int x = xb + ql;
-  const bool lvalid = x >= 1 && x <= nx - 2;
-
   // source entries: one per thread, requested now and added when needed
   // (before the solve for stage 1, after it for stage 2); entries are
   // distinct nodes, so the adds do not collide
@@ -765,87 +876,8 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
     __syncthreads();
   }
 
-  // chunk elimination: the lane's column of the tile from row 1 + g0
-  const int g0 = p * M;
-  A* col = tile + (1 + g0) * TS + ql;
-  const uint8_t* mcol = mt + g0 * TW + ql;  // flag of along node g0 + k at mcol[k * TW]
-  A d[M];
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const A v = col[k * TS];
-    d[k] = (g0 + k < nint) ? v : A(0);
-  }
-  const A gL = tile[ql];
-  const A gR = tile[(n - 1) * TS + ql];
-  const bool first = (g0 == 0);
-  const int kR = lvalid ? nint - 1 - g0 : -1;
-  int cls = 1;
-  if (lvalid) {
-    const long long nl = (long long)(nx - 2) * ((dir == 1 ? a.nz : ny) - 2);
-    cls = uniform ? 0
-                  : (a.ccls ? (int)a.ccls[(size_t)p * nl + (size_t)(o - 1) * (nx - 2) + (x - 1)]
-                            : 1);
-  }
-  // lanes without a line follow whatever path their wave takes
-  const bool inner = cls != 1 && kR >= M;
-  const unsigned long long bv = __ballot(lvalid);
-  const unsigned long long bf = __ballot(lvalid && inner);
-  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
-  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
-  const int t = (fast && bs != 0) ? 1 : 0;
-  A al[M], ga[M];
-  RRow<A> rf, rl;
-  if (fast) {
-    if (first) d[0] = fma(tb.re[t], gL, d[0]);
-    fast_eliminate<A, M>(d, tb, t, first, rf, rl);
-  } else {
-    const A re0 = (A)(uniform ? a.re_uniform : a.re[0]);
-    const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
-    const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
-    A reF[M + 1];
-    int prev = uniform ? 1 : (int)mcol[0];
-#pragma unroll
-    for (int k = 0; k <= M; ++k) {
-      // face between along nodes g0 + k and g0 + k + 1
-      const int cur = uniform ? 1 : (int)mcol[(k + 1) * TW];
-      const int c = (g0 + k + 1 > n - 1) ? 2 : prev + cur;
-      reF[k] = pick3(c, re0, re1, re2);
-      prev = cur;
-    }
-    if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
-    chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
-  }
-  A* R = red + ql;
-  put_reduced(R, TS, p, rf, rl);
-  __syncthreads();
-  if (p == 0 && lvalid) reduced_solve(R, 2 * P, TS);
-  __syncthreads();
-  const A xf = R[(4 * (2 * p) + 3) * TS];
-  const A xl = R[(4 * (2 * p + 1) + 3) * TS];
-  if (fast)
-    fast_finish<A, M>(d, tb.ga[t], tb.al[t], xf, xl);
-  else
-    chunk_finish<A, M>(d, al, ga, xf, xl);
-
-  if ((VAR == kYzFlow || (VAR == kYzGeneral && a.post_nl)) && !uniform) {
-    const A ka = (A)a.post_ka, kb = (A)a.post_kb;
-    if (fast) {
-      if (t == 0) {
-#pragma unroll
-        for (int k = 0; k < M; ++k) d[k] = sinh_flow(d[k], ka, kb);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < M; ++k)
-        if (mcol[(k + 1) * TW] == 0) d[k] = sinh_flow(d[k], ka, kb);
-    }
-  }
-  // rows past the line end land in rows n-1.. of the tile, which are
-  // neither stored nor read again
-  if (lvalid) {
-#pragma unroll
-    for (int k = 0; k < M; ++k) col[k * TS] = d[k];
-  }
+  const int cls = yz_chunk_class<T, TW>(a, dir, o, xb, tid);
+  yz_solve_lines<T, A, M, VAR, TW>(a, tile, TS, mt, red, n, xb, cls, tid);
   __syncthreads();
   if (VAR == kYzGeneral && a.src_stage == 2) {
     add_sources();
