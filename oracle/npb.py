@@ -21,6 +21,10 @@ the electrostatic analysis of solvated biomolecules"):
   * solvation energy ........... Sec. 4.1, Eq. (deltaG); vacuum by the same
                                  scheme, Sec. 4.3, Eq. (deltaG3)
   * Richardson extrapolation ... Sec. 4.3, Eq. (rich)
+  * vacuum potential by a fast   Sec. 4.1 (text after Eq. (deltaG)),
+    Poisson solver, energy and   Sec. 4.3, Eq. (deltaG2); recovered
+    recovered potential ........ potential, Sec. 4.4 (surface potential
+                                 paragraph)
 
 Readings of points the paper leaves open (each listed in the design notes):
   * kT(T) = 0.592183 * T / 298 kcal/mol; Bjerrum length l_B = 332.06371 / kT
@@ -35,7 +39,10 @@ Readings of points the paper leaves open (each listed in the design notes):
     printed leading factor 4 would map u to 4u when kbar = 0);
   * the vacuum problem uses eps_in everywhere, kbar = 0 and Coulomb
     boundary data in eps_in;
-  * a charge stencil (8 trilinear nodes) must lie in the interior.
+  * a charge stencil (8 trilinear nodes) must lie in the interior;
+  * the recovered potential is phi_m - phi_0^LOD + phi_0^FFT (the printed
+    "+ phi_0^LOD - phi_0^FFT" is the only other sign pattern; with it
+    (1/2) sum Q (phi_rec - phi_0^FFT) would not equal the RE+V energy).
 """
 from __future__ import annotations
 
@@ -43,6 +50,7 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
+from scipy.fft import dstn, idstn
 
 # ---------------------------------------------------------------------------
 # constants (Sec. 2.1)
@@ -364,7 +372,43 @@ def richardson(u_dt: np.ndarray, u_half: np.ndarray) -> np.ndarray:
     return 2.0 * u_half - u_dt
 
 
-def solve(mol, grid, params, want_fields: bool = False) -> dict:
+# ---------------------------------------------------------------------------
+# the vacuum potential without pseudo-time (Sec. 4.1, text after Eq. (deltaG))
+
+def poisson_direct(pb: Problem) -> np.ndarray:
+    """phi_0 from the Poisson equation with a constant dielectric, solved
+    directly: -eps delta^2 u = rho on the interior nodes (the operator of
+    Eq. (SpatialOperators) summed over x, y, z, eps constant), u = u0 (the
+    Dirichlet data) on the shell.  The Dirichlet couplings move to the
+    right-hand side; the type-I discrete sine transform along each axis
+    diagonalises what remains (eigenvalue of mode m on an axis with N
+    interior nodes: (eps/h^2) 4 sin^2(pi m / (2 (N + 1)))), which is the
+    fast-transform Poisson solver the paper uses for phi_0."""
+    e = float(pb.eps_node.flat[0])
+    if not np.all(pb.eps_node == e):
+        raise ValueError("the direct Poisson solve needs a uniform dielectric")
+    h = pb.grid.h
+    g = pb.u0
+    c = e / (h * h)
+    f = pb.rho[1:-1, 1:-1, 1:-1].copy()
+    f[0, :, :] += c * g[0, 1:-1, 1:-1]
+    f[-1, :, :] += c * g[-1, 1:-1, 1:-1]
+    f[:, 0, :] += c * g[1:-1, 0, 1:-1]
+    f[:, -1, :] += c * g[1:-1, -1, 1:-1]
+    f[:, :, 0] += c * g[1:-1, 1:-1, 0]
+    f[:, :, -1] += c * g[1:-1, 1:-1, -1]
+
+    def eig(N):
+        return 4.0 * np.sin(np.pi * np.arange(1, N + 1) / (2.0 * (N + 1))) ** 2
+
+    Nz, Ny, Nx = f.shape
+    lam = c * (eig(Nz)[:, None, None] + eig(Ny)[None, :, None] + eig(Nx)[None, None, :])
+    u = g.copy()
+    u[1:-1, 1:-1, 1:-1] = idstn(dstn(f, type=1) / lam, type=1)
+    return u
+
+
+def solve(mol, grid, params, want_fields: bool = False, vacuum_direct: bool = False) -> dict:
     """Full solve as the C library defines it: solvated loop(s) and, if
     requested, the vacuum loop(s) by the same scheme (Eq. (deltaG3)), with
     Richardson extrapolation on each medium when requested (Eq. (rich)).
@@ -373,7 +417,12 @@ def solve(mol, grid, params, want_fields: bool = False) -> dict:
       G_m[1], G_0[1]  : the same at dt/2 (2n steps), only with Richardson
       dG_plain        : (1/2) sum Q (phi_m - phi_0) at dt
       dG              : the same from the Richardson-combined potentials
-                        (equal to dG_plain without Richardson)."""
+                        (equal to dG_plain without Richardson).
+    With vacuum_direct (needs params.vacuum) also:
+      dG_direct       : (1/2) sum Q (phi_m - phi_0^FFT), Eq. (deltaG2), with
+                        phi_m Richardson-combined when Richardson is on and
+                        phi_0^FFT from poisson_direct
+      (fields) phi_0_direct = kT u_0^FFT, phi_rec = phi_m - phi_0 + phi_0^FFT"""
     T = params.temperature_K
     kT = thermal_energy(T)
     out = {"G_m": [0.0, 0.0], "G_0": [0.0, 0.0]}
@@ -403,6 +452,15 @@ def solve(mol, grid, params, want_fields: bool = False) -> dict:
     else:
         out["dG_plain"] = float("nan")
         out["dG"] = float("nan")
+    if vacuum_direct:
+        if not params.vacuum:
+            raise ValueError("vacuum_direct needs the vacuum problem")
+        u_dir = poisson_direct(make_problem(mol, grid, params, "vacuum"))
+        umf = fields["solvated"][1]
+        out["dG_direct"] = 0.5 * float(np.sum(Qc * (kT * umf - kT * u_dir)))
+        if want_fields:
+            out["phi_0_direct"] = kT * u_dir
+            out["phi_rec"] = kT * umf - kT * fields["vacuum"][1] + kT * u_dir
     if want_fields:
         out["phi_m"] = kT * fields["solvated"][1]
         out["u_m_levels"] = fields["solvated"][0]

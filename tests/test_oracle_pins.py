@@ -479,3 +479,74 @@ def test_mirror_symmetry_of_a_centred_ion():
     m = np.max(np.abs(u))
     for ax in range(3):
         assert np.max(np.abs(u - np.flip(u, axis=ax))) < 1e-12 * m
+
+
+# --------------------------------------------------------------------------
+# vacuum potential by the direct (sine-transform) Poisson solve, Sec. 4.1;
+# Eq. (deltaG2) and the recovered potential of Sec. 4.4
+
+def _vacuum_problem(nx=8, ny=9, nz=7, eps_in=2.0):
+    grid = _tiny(nx, 0.5, ny=ny, nz=nz)
+    p = _params(eps_in=eps_in, ionic_molar=0.0)
+    return oracle.make_problem(_two_atoms(), grid, p, "vacuum")
+
+
+def test_direct_poisson_matches_dense_solve_with_arbitrary_boundary_data():
+    # non-cubic grid and random data on every face: a swapped axis, a
+    # dropped face or a wrong eigenvalue fails this
+    import dataclasses
+    pb = _vacuum_problem()
+    rng = np.random.default_rng(21)
+    g = pb.u0.copy()
+    B = oracle.boundary_shell(pb.grid)
+    g[B] = rng.normal(0.0, 50.0, int(B.sum()))
+    pb = dataclasses.replace(pb, u0=g)
+    D = sum(_dense.dense_second_difference(pb.eps_node, pb.grid.h, ax) for ax in range(3))
+    I = _dense.interior_flags(g.shape)
+    # -D u = rho on interior rows, u = g on the shell
+    ex = g.ravel().copy()
+    ex[I] = np.linalg.solve(-D[np.ix_(I, I)], pb.rho.ravel()[I] + D[np.ix_(I, ~I)] @ g.ravel()[~I])
+    u = oracle.poisson_direct(pb)
+    assert np.max(np.abs(u.ravel() - ex)) <= 1e-11 * np.max(np.abs(ex))
+    assert np.array_equal(u[B], g[B])
+
+
+def test_direct_poisson_reproduces_discrete_harmonic_functions():
+    # x^2 - y^2 + 2 x z - 3 z + 1 has a zero 7-point Laplacian: with no
+    # charge and these Dirichlet values the interior must equal it
+    import dataclasses
+    pb = _vacuum_problem(9, 7, 8)
+    grid = pb.grid
+    Z, Y, X = np.meshgrid(*(oracle.axis_coords(grid, d) for d in (2, 1, 0)), indexing="ij")
+    f = X ** 2 - Y ** 2 + 2.0 * X * Z - 3.0 * Z + 1.0
+    g = np.where(oracle.boundary_shell(grid), f, 0.0)
+    pb = dataclasses.replace(pb, u0=g, rho=np.zeros_like(g))
+    u = oracle.poisson_direct(pb)
+    assert np.max(np.abs(u - f)) <= 1e-12 * np.max(np.abs(f))
+
+
+def test_direct_poisson_is_the_small_step_limit_of_the_vacuum_lod_run():
+    pb = _vacuum_problem(9, 9, 9)
+    ex = oracle.poisson_direct(pb)
+    errs, sols = [], []
+    for tau in (0.04, 0.02, 0.01):
+        u = _steady(pb, tau, 1.0, "LODIE2")
+        sols.append(u)
+        errs.append(np.max(np.abs(u - ex)))
+    assert 1.7 < errs[0] / errs[1] < 2.4 and 1.7 < errs[1] / errs[2] < 2.4
+    assert np.max(np.abs(oracle.richardson(sols[1], sols[2]) - ex)) < errs[2] / 3
+
+
+def test_recovered_potential_reproduces_the_re_v_energy():
+    # (1/2) sum Q (phi_rec - phi_0^FFT) = (1/2) sum Q (phi_m - phi_0^LOD):
+    # the reading phi_m - phi_0^LOD + phi_0^FFT of the recovery formula
+    w = inputs.small_globular(seed=5, n_atoms=30, n=25, n_steps=4, richardson=True)
+    r = oracle.solve(w.molecule, w.grid, w.params, want_fields=True, vacuum_direct=True)
+    lhs = 0.5 * float(np.sum(r["Q"] * (r["phi_rec"] - r["phi_0_direct"])))
+    assert lhs == pytest.approx(r["dG"], rel=1e-11)
+    d2 = 0.5 * float(np.sum(r["Q"] * (r["phi_m"] - r["phi_0_direct"])))
+    assert r["dG_direct"] == pytest.approx(d2, rel=1e-12)
+    # on the shell the recovered potential is the solvated Dirichlet data
+    B = oracle.boundary_shell(w.grid)
+    scale = np.max(np.abs(r["phi_0_direct"]))
+    assert np.max(np.abs(r["phi_rec"][B] - r["phi_m"][B])) <= 1e-13 * scale
