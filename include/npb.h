@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NPB_ABI_VERSION 2
+#define NPB_ABI_VERSION 3
 
 typedef enum npb_status {
   NPB_OK = 0,
@@ -94,8 +94,18 @@ typedef struct npb_grid {
  *   vacuum          : 1 = also solve the uniform-eps_in, kbar = 0 problem by
  *                     the same scheme and report the solvation energy
  *                     (Sec. 4.3, Eq. (deltaG3)); 0 = solvated potential only
- *   field_select    : which potential d_field_out receives: 0 = solvated,
- *                     1 = vacuum (needs vacuum = 1)                          */
+ *   vacuum_direct   : 1 = also solve the vacuum Poisson problem directly
+ *                     (no pseudo-time: the constant-eps_in 7-point problem
+ *                     with the vacuum Dirichlet data, by type-I sine
+ *                     transforms in FP64; the paper's "FFT" phi_0, Sec. 4.1)
+ *                     and report dG_direct (Eq. (deltaG2)); needs vacuum = 1
+ *   field_select    : which potential d_field_out receives:
+ *                     0 = solvated, 1 = vacuum by the scheme (needs vacuum),
+ *                     2 = vacuum by the direct solve (needs vacuum_direct),
+ *                     3 = recovered potential phi_m - phi_0 + phi_0^direct
+ *                         (Sec. 4.4; needs vacuum_direct); phi_m and phi_0
+ *                         Richardson-combined when richardson = 1
+ *   reserved        : must be 0                                             */
 typedef struct npb_params {
   double eps_in, eps_out, kappa_bar_sq, temperature_K, alpha, dt;
   int32_t n_steps;
@@ -104,7 +114,8 @@ typedef struct npb_params {
   int32_t richardson;
   int32_t vacuum;
   int32_t field_select;
-  int32_t reserved[2];
+  int32_t vacuum_direct;
+  int32_t reserved;
 } npb_params;
 
 /* Results, all energies in kcal/mol.
@@ -120,7 +131,11 @@ typedef struct npb_params {
  *   device_ms       : device time from the first setup kernel to the
  *                     energies being ready
  *   n_charge_nodes  : distinct nodes carrying trilinear charge
- *   finite          : 1 if every reported energy is finite             */
+ *   finite          : 1 if every reported energy is finite
+ *   dG_direct       : with vacuum_direct, (1/2) sum_p Q_p (phi_m,p - phi_0,p)
+ *                     with phi_0 from the direct Poisson solve and phi_m
+ *                     Richardson-combined when richardson = 1 (Eq. (deltaG2));
+ *                     else NaN                                           */
 typedef struct npb_result {
   double dG;
   double dG_plain;
@@ -132,6 +147,7 @@ typedef struct npb_result {
   int32_t n_charge_nodes;
   int32_t finite;
   int32_t reserved;
+  double dG_direct;
 } npb_result;
 
 typedef struct npb_ctx npb_ctx;
@@ -153,7 +169,8 @@ typedef struct npb_kernel_times {
 
 enum npb_kernel_class {
   NPB_K_SWEEP_X = 0, NPB_K_SWEEP_Y = 1, NPB_K_SWEEP_Z = 2,
-  NPB_K_SETUP = 3, NPB_K_INIT = 4, NPB_K_ENERGY = 5, NPB_K_OTHER = 6
+  NPB_K_SETUP = 3, NPB_K_INIT = 4, NPB_K_ENERGY = 5, NPB_K_OTHER = 6,
+  NPB_K_DIRECT = 7  /* the direct vacuum Poisson solve (vacuum_direct) */
 };
 
 enum npb_sweep_kernel {
@@ -212,8 +229,8 @@ npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
  * combinations on `stream`, then waits for that stream and fills *out.
  *   d_ws, ws_bytes : device workspace, at least npb_workspace_bytes
  *   d_field_out    : NULL, or a device array of nx*ny*nz doubles that
- *                    receives phi = kT u (kcal/mol/e) of the selected medium,
- *                    Richardson-combined when richardson = 1
+ *                    receives the potential chosen by field_select
+ *                    (kcal/mol/e), Richardson-combined when richardson = 1
  * Errors: EINVAL, ERANGE (before any device work), EDEVICE, EDIVERGED (the
  * energies are still written to *out). */
 npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,

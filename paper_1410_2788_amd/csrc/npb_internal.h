@@ -222,12 +222,52 @@ hipError_t launch_energy(const T* u, const int* q_idx, const double* q_val, cons
 template <typename T>
 hipError_t launch_field_out(double* out, const T* u, int nx, int nxp, int ny, int nz, double beta,
                             double gamma, hipStream_t st);
-hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum,
+// res = [dG, dG_plain, G_m0, G_m1, G_00, G_01, finite, dG_direct]; S[4] is the
+// charge-weighted sum of the direct vacuum solve when direct != 0
+hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum, int direct,
                           double* res, hipStream_t st);
 
 // number of nodes on the outer shell of an nx*ny*nz grid
 inline long long shell_count(int nx, int ny, int nz) {
   return (long long)nx * ny * nz - (long long)(nx - 2) * (ny - 2) * (nz - 2);
 }
+
+// Position of shell node (i, j, k) in the shell order of the boundary data:
+// face z = 0 (ny*nx, x fastest), face z = nz-1, then per interior z the row
+// y = 0 (nx), the row y = ny-1 (nx), and x = 0, nx-1 of each interior y.
+__host__ __device__ inline long long shell_slot(int i, int j, int k, int nx, int ny, int nz) {
+  const long long nxy = (long long)nx * ny;
+  if (k == 0) return (long long)j * nx + i;
+  if (k == nz - 1) return nxy + (long long)j * nx + i;
+  const long long base = 2 * nxy + (long long)(k - 1) * (2LL * nx + 2LL * (ny - 2));
+  if (j == 0) return base + i;
+  if (j == ny - 1) return base + nx + i;
+  return base + 2LL * nx + 2LL * (j - 1) + (i == 0 ? 0 : 1);
+}
+
+// ---------------------------------------------------------------------------
+// vacuum potential by a direct Poisson solve (poisson_kernels.hip)
+
+struct DirectPoissonArgs {
+  int nx, ny, nz, nxp;     // grid (nxp: row pitch of the pitched charge indices)
+  double h, eps;
+  const double* bc;        // vacuum Dirichlet data, shell order
+  const int* q_idx;        // charge nodes (pitched linear index)
+  const double* q_rho;     // source density at them
+  const double* q_val;     // trilinear charge at them (e)
+  const int* nq_dev;       // number of charge nodes (device)
+  int cap;                 // capacity of the charge list
+  double* work;            // direct_poisson_bytes(nx, ny, nz) bytes
+  double* slot;            // receives sum over charge nodes of q u
+};
+
+// Workspace of the solve: the interior field and the transform tables.
+size_t direct_poisson_bytes(int nx, int ny, int nz);
+// Solves into work (interior nodes, dense [nz-2][ny-2][nx-2]) and writes
+// the charge-weighted sum to slot.
+hipError_t launch_direct_poisson(const DirectPoissonArgs& a, hipStream_t st);
+// dense out[nz][ny][nx] = beta * out + gamma * (interior u, shell bc)
+hipError_t launch_direct_field_out(double* out, const double* u, const double* bc, int nx, int ny,
+                                   int nz, double beta, double gamma, hipStream_t st);
 
 }  // namespace npb

@@ -233,10 +233,10 @@ hipError_t launch_field_out(double* out, const T* u, int nx, int nxp, int ny, in
   return hipGetLastError();
 }
 
-// S = [solvated dt, solvated dt/2, vacuum dt, vacuum dt/2] sums of q u.
-// res = [dG, dG_plain, G_m0, G_m1, G_00, G_01, finite]
+// S = [solvated dt, solvated dt/2, vacuum dt, vacuum dt/2, direct vacuum]
+// sums of q u.  res = [dG, dG_plain, G_m0, G_m1, G_00, G_01, finite, dG_direct]
 __global__ void combine_kernel(const double* S, double kT, int richardson, int vacuum,
-                               double* res) {
+                               int direct, double* res) {
   const double h = 0.5 * kT;
   double Gm0 = h * S[0], Gm1 = richardson ? h * S[1] : 0.0;
   double G00 = vacuum ? h * S[2] : 0.0, G01 = (vacuum && richardson) ? h * S[3] : 0.0;
@@ -252,12 +252,18 @@ __global__ void combine_kernel(const double* S, double kT, int richardson, int v
   res[5] = G01;
   bool fin = isfinite(Gm0) && isfinite(Gm1) && isfinite(G00) && isfinite(G01) &&
              (!vacuum || (isfinite(dG) && isfinite(dplain)));
+  // Eq. (deltaG2): the solvated potential (Richardson-combined when on)
+  // against the vacuum potential of the direct Poisson solve
+  const double dd = direct ? h * ((richardson ? 2.0 * S[1] - S[0] : S[0]) - S[4]) : nan;
+  res[7] = dd;
+  if (direct) fin = fin && isfinite(dd);
   res[6] = fin ? 1.0 : 0.0;
 }
 
-hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum, double* res,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(1), 0, st, S, kT, richardson, vacuum, res);
+hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum, int direct,
+                          double* res, hipStream_t st) {
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(1), 0, st, S, kT, richardson, vacuum, direct,
+                     res);
   return hipGetLastError();
 }
 
@@ -378,6 +384,7 @@ struct Layout {
   size_t field[kMaxFields], acc[kMaxFields];
   size_t mask, bc_s, bc_v, atoms, tabs, key_a, id_a, key_b, id_b, sval, hist, heads;
   size_t q_idx, q_val, q_rho, xptr, yptr, ylin, yrho, zptr, zlin, zrho, ccls[3], slots, ints, total;
+  size_t direct;  // work of the direct vacuum Poisson solve (vacuum_direct)
   LaunchShape shape[3];
   Run runs[kMaxFields];
   int n_runs, cap, nblocks;
@@ -450,6 +457,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   }
   L.slots = take(32 * 8);
   L.ints = take(16 * 4);
+  L.direct = take(p->vacuum_direct ? direct_poisson_bytes(g->nx, g->ny, g->nz) : 0);
   L.total = off;
   L.cap = cap;
   L.nblocks = nb;
@@ -503,8 +511,15 @@ npb_status validate(const npb_molecule* mol, const npb_grid* g, const npb_params
   if (p->n_steps < 1) return fail(NPB_EINVAL, "n_steps must be >= 1");
   if (p->scheme < 0 || p->scheme > 3) return fail(NPB_EINVAL, "unknown scheme");
   if (p->precision < 0 || p->precision > 2) return fail(NPB_EINVAL, "unknown precision");
-  if (p->field_select < 0 || p->field_select > 1 || (p->field_select == 1 && !p->vacuum))
-    return fail(NPB_EINVAL, "field_select 1 needs vacuum = 1");
+  if (p->vacuum_direct != 0 && p->vacuum_direct != 1)
+    return fail(NPB_EINVAL, "vacuum_direct must be 0 or 1");
+  if (p->vacuum_direct && !p->vacuum) return fail(NPB_EINVAL, "vacuum_direct needs vacuum = 1");
+  if (p->reserved != 0) return fail(NPB_EINVAL, "reserved parameter must be 0");
+  if (p->field_select < 0 || p->field_select > 3)
+    return fail(NPB_EINVAL, "field_select must be 0, 1, 2 or 3");
+  if (p->field_select == 1 && !p->vacuum) return fail(NPB_EINVAL, "field_select 1 needs vacuum = 1");
+  if (p->field_select >= 2 && !p->vacuum_direct)
+    return fail(NPB_EINVAL, "field_select 2 and 3 need vacuum_direct = 1");
   if (mol->n_atoms < 0) return fail(NPB_EINVAL, "negative atom count");
   if (mol->n_atoms > 0 && (!mol->xyz || !mol->q || !mol->radius))
     return fail(NPB_EINVAL, "null atom arrays");
@@ -1047,25 +1062,62 @@ struct Engine {
                                       P.at<int>(L.ints), st);
       });
       if (s != NPB_OK) return s;
+      const npb_params* p = P.p;
+      if (p->vacuum_direct) {
+        // Sec. 4.1: phi_0 from the Poisson equation solved directly
+        DirectPoissonArgs da{};
+        da.nx = P.g->nx;
+        da.ny = P.g->ny;
+        da.nz = P.g->nz;
+        da.nxp = pitch_of(P.g->nx, (int)sizeof(T));
+        da.h = P.g->h;
+        da.eps = p->eps_in;
+        da.bc = P.at<double>(L.bc_v);
+        da.q_idx = P.at<int>(L.q_idx);
+        da.q_rho = P.at<double>(L.q_rho);
+        da.q_val = P.at<double>(L.q_val);
+        da.nq_dev = P.at<int>(L.ints);
+        da.cap = L.cap;
+        da.work = P.at<double>(L.direct);
+        da.slot = P.at<double>(L.slots) + 4;
+        s = timed(NPB_K_DIRECT, 0, [&] { return launch_direct_poisson(da, st); });
+        if (s != NPB_OK) return s;
+      }
       if (P.fout) {
-        // selected medium: kT u (plain) or kT (2 u(dt/2) - u(dt)) (Richardson)
-        const npb_params* p = P.p;
-        for (int l = 0; l < (p->richardson ? 2 : 1); ++l) {
-          int r = 0;
-          while (!(L.runs[r].medium == p->field_select && L.runs[r].level == l)) ++r;
-          const double beta = (l == 0) ? 0.0 : 1.0;
-          const double gamma = p->richardson ? (l == 0 ? -P.kT : 2.0 * P.kT) : P.kT;
+        // field_select 0 / 1: kT u of that medium (plain) or
+        // kT (2 u(dt/2) - u(dt)) (Richardson); 2: kT u of the direct vacuum
+        // solve; 3: solvated - vacuum (as 0 and 1) + direct vacuum (Sec. 4.4)
+        const int fs = p->field_select;
+        bool first = true;
+        for (int medium = 0; medium < 2; ++medium) {
+          const double sign = (fs == 3 && medium == 1) ? -1.0 : 1.0;
+          if (!(fs == medium || fs == 3)) continue;
+          for (int l = 0; l < (p->richardson ? 2 : 1); ++l) {
+            int r = 0;
+            while (!(L.runs[r].medium == medium && L.runs[r].level == l)) ++r;
+            const double beta = first ? 0.0 : 1.0;
+            const double gamma = sign * (p->richardson ? (l == 0 ? -P.kT : 2.0 * P.kT) : P.kT);
+            s = timed(NPB_K_OTHER, 0, [&] {
+              return launch_field_out<T>(P.fout, P.at<T>(L.field[r]), P.g->nx,
+                                         pitch_of(P.g->nx, (int)sizeof(T)), P.g->ny, P.g->nz,
+                                         beta, gamma, st);
+            });
+            if (s != NPB_OK) return s;
+            first = false;
+          }
+        }
+        if (fs >= 2) {
           s = timed(NPB_K_OTHER, 0, [&] {
-            return launch_field_out<T>(P.fout, P.at<T>(L.field[r]), P.g->nx,
-                                       pitch_of(P.g->nx, (int)sizeof(T)), P.g->ny, P.g->nz, beta,
-                                       gamma, st);
+            return launch_direct_field_out(P.fout, P.at<double>(L.direct), P.at<double>(L.bc_v),
+                                           P.g->nx, P.g->ny, P.g->nz, first ? 0.0 : 1.0, P.kT,
+                                           st);
           });
           if (s != NPB_OK) return s;
         }
       }
       s = timed(NPB_K_OTHER, 0, [&] {
-        return launch_combine(P.at<double>(L.slots), P.kT, P.p->richardson, P.p->vacuum,
-                              P.at<double>(L.slots) + 8, st);
+        return launch_combine(P.at<double>(L.slots), P.kT, p->richardson, p->vacuum,
+                              p->vacuum_direct, P.at<double>(L.slots) + 8, st);
       });
       if (s != NPB_OK) return s;
     }
@@ -1163,6 +1215,7 @@ struct Engine {
       o.G_0[0] = hres[4];
       o.G_0[1] = hres[5];
       o.finite = hres[6] != 0.0 ? 1 : 0;
+      o.dG_direct = hres[7];
       const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
       for (int r = 0; r < P.L.n_runs; ++r) {
         const int ns = P.p->n_steps << P.L.runs[r].level;

@@ -23,10 +23,10 @@ STATUS_NAMES = {0: "NPB_OK", 1: "NPB_EINVAL", 2: "NPB_ERANGE", 3: "NPB_ENOMEM",
                 4: "NPB_EDEVICE", 5: "NPB_EDIVERGED", 6: "NPB_EBUSY"}
 SCHEMES = {"LODIE2": 0, "LODIE1": 1, "AOSIE2": 2, "AOSIE1": 3}
 PRECISIONS = {"f64": 0, "f32": 1, "f32x": 2}
-KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other"]
+KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other", "direct"]
 # sweep launches split again by the kernel that ran them (npb_sweep_kernel)
 SWEEP_KERNELS = ["x", "yz_plain", "yz_flow", "yz_general"]
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class npb_molecule(C.Structure):
@@ -44,14 +44,15 @@ class npb_params(C.Structure):
                 ("temperature_K", C.c_double), ("alpha", C.c_double), ("dt", C.c_double),
                 ("n_steps", C.c_int32), ("scheme", C.c_int32), ("precision", C.c_int32),
                 ("richardson", C.c_int32), ("vacuum", C.c_int32), ("field_select", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("vacuum_direct", C.c_int32), ("reserved", C.c_int32)]
 
 
 class npb_result(C.Structure):
     _fields_ = [("dG", C.c_double), ("dG_plain", C.c_double), ("G_m", C.c_double * 2),
                 ("G_0", C.c_double * 2), ("grid_point_updates", C.c_double),
                 ("device_ms", C.c_double), ("steps_done", C.c_int32),
-                ("n_charge_nodes", C.c_int32), ("finite", C.c_int32), ("reserved", C.c_int32)]
+                ("n_charge_nodes", C.c_int32), ("finite", C.c_int32), ("reserved", C.c_int32),
+                ("dG_direct", C.c_double)]
 
 
 class npb_kernel_times(C.Structure):
@@ -311,12 +312,12 @@ def make_grid(g) -> npb_grid:
     return npb_grid(int(g.nx), int(g.ny), int(g.nz), 0, float(g.h), o)
 
 
-def make_params(p, field_select: int = 0) -> npb_params:
+def make_params(p, field_select: int = 0, vacuum_direct: bool = False) -> npb_params:
     kb2 = npb_kappa_bar_sq(p.ionic_molar, p.temperature_K)
     return npb_params(float(p.eps_in), float(p.eps_out), kb2, float(p.temperature_K),
                       float(p.alpha), float(p.dt), int(p.n_steps), SCHEMES[p.scheme],
                       PRECISIONS[p.precision], 1 if p.richardson else 0, 1 if p.vacuum else 0,
-                      int(field_select), (C.c_int32 * 2)(0, 0))
+                      int(field_select), 1 if vacuum_direct else 0, 0)
 
 
 _ctx_cache = {}
@@ -334,13 +335,13 @@ class Solver:
     npb_solve on the current torch stream."""
 
     def __init__(self, mol, grid, params, device: int = 0, want_field: bool = False,
-                 field_select: int = 0):
+                 field_select: int = 0, vacuum_direct: bool = False):
         import torch
         self.torch = torch
         self.device = device
         self.mol = Molecule(mol.xyz, mol.q, mol.radius)
         self.grid = make_grid(grid)
-        self.params = make_params(params, field_select)
+        self.params = make_params(params, field_select, vacuum_direct)
         self.ctx = context(device)
         self.ws_bytes = npb_workspace_bytes(self.mol.c, self.grid, self.params)
         dev = torch.device("cuda", device)
@@ -427,14 +428,15 @@ def result_dict(res: npb_result) -> dict:
     return {"dG": res.dG, "dG_plain": res.dG_plain, "G_m": [res.G_m[0], res.G_m[1]],
             "G_0": [res.G_0[0], res.G_0[1]], "grid_point_updates": res.grid_point_updates,
             "device_ms": res.device_ms, "steps_done": res.steps_done,
-            "n_charge_nodes": res.n_charge_nodes, "finite": bool(res.finite)}
+            "n_charge_nodes": res.n_charge_nodes, "finite": bool(res.finite),
+            "dG_direct": res.dG_direct}
 
 
 def solve(mol, grid, params, device: int = 0, want_field: bool = False,
-          field_select: int = 0) -> dict:
+          field_select: int = 0, vacuum_direct: bool = False) -> dict:
     """One solve; with want_field the result also holds 'phi' (numpy, FP64,
-    [nz][ny][nx], kcal/mol/e)."""
-    s = Solver(mol, grid, params, device, want_field, field_select)
+    [nz][ny][nx], kcal/mol/e) as chosen by field_select."""
+    s = Solver(mol, grid, params, device, want_field, field_select, vacuum_direct)
     out = s.run()
     if want_field:
         out["phi"] = s.field.cpu().numpy()

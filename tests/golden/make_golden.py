@@ -4,8 +4,9 @@ Calls only the FP64 oracle (and the seeded input generators); nothing here
 comes from the HIP library.
 
 Usage:  python tests/golden/make_golden.py [name ...]
-        names: globular_2000, large_complex_lod04, large_complex_lod02,
-               large_complex_aos04, batch_mix_samples, serve_samples
+        names: globular_2000, globular_2000_direct, large_complex_lod04,
+               large_complex_lod02, large_complex_aos04, batch_mix_samples,
+               serve_samples
         (no name: all of them; each writes its own JSON file)
 """
 import json
@@ -86,6 +87,24 @@ def globular_2000():
     _write("globular_2000_161.json", out)
 
 
+def globular_2000_direct():
+    """The benchmark workload with the direct vacuum solve: Eq. (deltaG2)
+    energy and sampled nodes of phi_0^direct and of the recovered potential."""
+    w = inputs.globular_2000(precision="f64")
+    t = time.time()
+    r = oracle.solve(w.molecule, w.grid, w.params, want_fields=True, vacuum_direct=True)
+    nodes = _sample_nodes(w.grid, r["phi_0_direct"], 2)
+    out = {"_source": "oracle.solve(..., vacuum_direct=True) on inputs.globular_2000() (seed 2, "
+                      "161^3, RE+V, dt 0.2/0.1, 20/40 steps)",
+           "dG": r["dG"], "dG_direct": r["dG_direct"], "field_nodes": nodes,
+           "phi_0_direct": [float(r["phi_0_direct"].ravel()[i]) for i in nodes],
+           "phi_rec": [float(r["phi_rec"].ravel()[i]) for i in nodes],
+           "phi_0_direct_absmax": float(np.max(np.abs(r["phi_0_direct"]))),
+           "phi_rec_absmax": float(np.max(np.abs(r["phi_rec"]))),
+           "oracle_seconds": time.time() - t}
+    _write("globular_2000_161_direct.json", out)
+
+
 def _large(scheme, dt, n_steps, tag):
     w = inputs.large_complex(precision="f64", scheme=scheme, dt=dt, n_steps=n_steps)
     out = _record(w, f"oracle.solve on inputs.large_complex(scheme={scheme!r}, dt={dt}, "
@@ -130,7 +149,7 @@ def serve_samples():
     _write("serve_48_samples.json", out)
 
 
-ALL = [globular_2000, large_complex_lod04, large_complex_lod02, large_complex_aos04,
+ALL = [globular_2000, globular_2000_direct, large_complex_lod04, large_complex_lod02, large_complex_aos04,
        batch_mix_samples, serve_samples]
 
 if __name__ == "__main__":

@@ -29,7 +29,7 @@ def test_every_declared_function_is_exported(npb):
 
 
 def test_version_and_kappa_helper(npb):
-    assert npb.npb_abi_version() == npb.ABI_VERSION == 2
+    assert npb.npb_abi_version() == npb.ABI_VERSION == 3
     g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     assert npb.npb_kappa_bar_sq(1.0, 298.0) == pytest.approx(g["kbar2_per_molar_298_inv_A2"], rel=1e-15)
     assert npb.npb_kappa_bar_sq(0.1, 300.0) == pytest.approx(0.84303, rel=1e-5)
@@ -142,3 +142,22 @@ def test_default_launch_shapes_are_consistent(npb):
             assert thr == lw * P and thr % 16 == 0 and thr <= 512
         if prec == "f64":
             assert shapes[1][0] <= 16 and shapes[1][2] == 16
+
+
+def test_direct_vacuum_parameters_are_validated(npb):
+    w = inputs.small_globular(n=21, n_atoms=4, n_steps=2)
+    mol = npb.Molecule(w.molecule.xyz, w.molecule.q, w.molecule.radius)
+    g = npb.make_grid(w.grid)
+    ok = npb.make_params(w.params, field_select=3, vacuum_direct=True)
+    assert npb.npb_validate(mol.c, g, ok) == npb.NPB_OK
+    assert npb.npb_validate(mol.c, g, npb.make_params(w.params, field_select=2)) == npb.NPB_EINVAL
+    assert npb.npb_validate(mol.c, g, npb.make_params(w.params, field_select=4,
+                                                      vacuum_direct=True)) == npb.NPB_EINVAL
+    import dataclasses
+    novac = dataclasses.replace(w.params, vacuum=False)
+    assert npb.npb_validate(mol.c, g, npb.make_params(novac, vacuum_direct=True)) == npb.NPB_EINVAL
+    # the workspace grows by the interior field and the transform tables
+    b0 = npb.npb_workspace_bytes(mol.c, g, npb.make_params(w.params))
+    b1 = npb.npb_workspace_bytes(mol.c, g, ok)
+    n = 19
+    assert b1 - b0 >= 8 * (n ** 3 + 3 * n * n + 3 * n)
