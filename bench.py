@@ -12,6 +12,7 @@ Prints one JSON line.  Usage:
     python bench.py --batch [--scheme AOSIE2]   64 uneven grids in one batch
     python bench.py --serve                     request loop, p50/p99 latency
     python bench.py --large                     30000 atoms on 321^3 nodes
+    python bench.py --direct                    direct vacuum Poisson solve, recovered potential
 """
 from __future__ import annotations
 
@@ -220,6 +221,70 @@ def bench_large(args):
             "runs": out_runs}
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def bench_direct(args):
+    """The 2000-atom workload with the direct vacuum Poisson solve
+    (vacuum_direct): device time of the solve with and without it, the
+    transforms' FP64 rate, Eq. (deltaG2) energy and sampled nodes of the
+    recovered potential against stored oracle values."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2788_amd import inputs, npb
+    w = inputs.globular_2000(precision=args.precision)
+    ref = _golden("globular_2000_161_direct.json")
+    X, Y, Z = w.grid.nx - 2, w.grid.ny - 2, w.grid.nz - 2
+    # forward and inverse: each line of each axis times an N x N matrix
+    flops = 2 * 2 * (Y * Z * X * X + X * Z * Y * Y + X * Y * Z * Z)
+    out = {}
+    for vd in (False, True):
+        s = npb.Solver(w.molecule, w.grid, w.params, device=0, vacuum_direct=vd,
+                       want_field=vd, field_select=3 if vd else 0)
+        if not args.no_autotune:
+            s.autotune()
+        for _ in range(max(1, args.warmup)):
+            s.run()
+        torch.cuda.synchronize()
+        rs = [s.run() for _ in range(args.steps)]
+        out[vd] = (float(np.median([r["device_ms"] for r in rs])), rs)
+        if vd:
+            npb.npb_ctx_set_timing(s.ctx, True)
+            for _ in range(3):
+                s.run()
+            torch.cuda.synchronize()
+            kt = npb.npb_ctx_get_kernel_times(s.ctx)["direct"]
+            npb.npb_ctx_set_timing(s.ctx, False)
+            phi = s.field.cpu().numpy().ravel()
+        del s
+    ms_direct = kt["ms"] / max(kt["count"], 1)
+    tf = flops / (ms_direct * 1e-3) / 1e12
+    r = out[True][1][0]
+    rec = {"metric": "direct vacuum Poisson solve (Sec. 4.1) beside the RE+V solve",
+           "value": ms_direct, "unit": "ms per direct solve", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[True][0],
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 (direct solve); " + args.precision + " (time loops)", "data": "synthetic",
+           "config": {"workload": w.name, "grid": [w.grid.nx, w.grid.ny, w.grid.nz],
+                      "field_select": "recovered potential"},
+           "solve_device_ms": {"without_direct": out[False][0], "with_direct_and_field": out[True][0]},
+           "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                        "traffic": None, "kernel": "npb::dst_lines_kernel (+ rhs, scale, energy)",
+                        "flops_per_direct_solve": flops,
+                        "note": "FP64 FMA on the vector units; the launch group's time includes "
+                                "the right-hand side, scaling and energy kernels"},
+           "energy": {"dG": r["dG"], "dG_direct": r["dG_direct"]}}
+    if ref:
+        tol = _energy_tol(ref["dG_direct"])
+        rec["energy"].update(oracle_dG_direct=ref["dG_direct"],
+                             abs_err=abs(r["dG_direct"] - ref["dG_direct"]), tolerance=tol)
+        d = np.array([phi[i] for i in ref["field_nodes"]]) - np.array(ref["phi_rec"])
+        rec["recovered_field_sampled_rel_err"] = float(np.max(np.abs(d)) / ref["phi_rec_absmax"])
+    return rec
+
+
 def bench_serve(args):
     """Serving: requests with atom counts log-uniform 500..20000 (grids
     103..257 at h = 0.5), LODIE2 RE+V 20/40 steps, Poisson arrivals (seed 4)
@@ -309,6 +374,9 @@ def main():
                     help="time a batch of 64 uneven grids instead (own JSON line)")
     ap.add_argument("--large", action="store_true",
                     help="time the 30000-atom 321^3 complex in FP32 LOD, FP32 AOS and FP64 LOD (own JSON line)")
+    ap.add_argument("--direct", action="store_true",
+                    help="time the direct vacuum Poisson solve and the recovered potential "
+                         "(own JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="time the request loop under Poisson arrivals instead (own JSON line)")
     ap.add_argument("--requests", type=int, default=48)
@@ -328,6 +396,9 @@ def main():
         return
     if args.serve:
         print(json.dumps(bench_serve(args)))
+        return
+    if args.direct:
+        print(json.dumps(bench_direct(args)))
         return
     if args.large:
         print(json.dumps(bench_large(args)))

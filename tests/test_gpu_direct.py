@@ -84,3 +84,35 @@ def test_direct_solve_without_field_and_repeat():
     assert abs(r1["dG_direct"] - o["dG_direct"]) <= max(1e-3, 1e-5 * abs(o["dG_direct"]))
     plain = npb.solve(w.molecule, w.grid, w.params)
     assert np.isnan(plain["dG_direct"]) and plain["dG"] == r1["dG"]
+
+
+def test_globular_2000_direct_full_size_against_stored_oracle():
+    """The benchmark workload (161^3, 2000 atoms, RE+V) with the direct
+    vacuum solve, against oracle values written by
+    tests/golden/make_golden.py (globular_2000_direct): Eq. (deltaG2) energy,
+    sampled nodes of phi_0^direct and of the recovered potential."""
+    import json
+    import os
+    from paper_1410_2788_amd import npb
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "globular_2000_161_direct.json")))
+    nodes = ref["field_nodes"]
+    failures = []
+    for prec, fs in (("f64", 3), ("f32", 3), ("f32", 2)):
+        w = inputs.globular_2000(precision=prec)
+        g = npb.solve(w.molecule, w.grid, w.params, want_field=True, field_select=fs,
+                      vacuum_direct=True)
+        phi = g["phi"].ravel()
+        key = "phi_rec" if fs == 3 else "phi_0_direct"
+        fe = float(np.max(np.abs(np.array([phi[i] for i in nodes]) - np.array(ref[key])))
+                   / ref[key + "_absmax"])
+        de = abs(g["dG_direct"] - ref["dG_direct"])
+        _say(prec, "field_select", fs, "sampled rel err", fe, "dG_direct err", de)
+        ftol = 1e-10 if (prec == "f64" or fs == 2) else 1e-4
+        etol = max(1e-7, 1e-9 * abs(ref["dG_direct"])) if prec == "f64" else \
+            max(1e-3, 1e-5 * abs(ref["dG_direct"]))
+        if fe > ftol:
+            failures.append((prec, fs, "field", fe))
+        if de > etol:
+            failures.append((prec, fs, "dG_direct", de))
+    assert not failures, failures
