@@ -16,6 +16,8 @@ the electrostatic analysis of solvated biomolecules"):
                                  (SpatialOperators); LODIE2 = same five
                                  equations with the source first and the
                                  nonlinear sub-step last
+  * LODCN1 / LODCN2 ............ Sec. 3.1, Eqs. (LODCN1_2)-(LODCN1_4) in
+                                 place of the three implicit sweeps
   * AOSIE1 / AOSIE2 ............ Sec. 3.2, Eqs. (AOSIE1_1)-(AOSIE1_5),
                                  (AOSIE2_2)-(AOSIE2_4)
   * solvation energy ........... Sec. 4.1, Eq. (deltaG); vacuum by the same
@@ -59,7 +61,7 @@ KT_298_KCAL = 0.592183          # kcal/mol per unit dimensionless potential at 2
 KBAR2_PER_MOLAR_298 = 8.486902807  # Angstrom^-2 per mol/L at 298 K
 COULOMB_KCAL_A = 332.06371      # e^2/(4 pi eps0) in kcal Angstrom / mol (CODATA)
 
-SCHEMES = ("LODIE2", "LODIE1", "AOSIE2", "AOSIE1")
+SCHEMES = ("LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2")
 
 
 def thermal_energy(T: float) -> float:
@@ -249,6 +251,32 @@ def implicit_sweep(s: np.ndarray, eps_node: np.ndarray, tau: float, h: float,
     return out
 
 
+def explicit_half(s: np.ndarray, eps_node: np.ndarray, c: float, h: float,
+                  axis: int) -> np.ndarray:
+    """(1 + c delta^2) s along array axis `axis` on the interior nodes (the
+    central difference of Eq. (SpatialOperators), neighbours on the shell
+    included); other nodes are returned unchanged."""
+    S = np.moveaxis(s, axis, 0)
+    E = np.moveaxis(face_eps(eps_node, axis), axis, 0)
+    out = s.copy()
+    O = np.moveaxis(out, axis, 0)
+    mid = S[1:-1, 1:-1, 1:-1]
+    up = S[2:, 1:-1, 1:-1]
+    dn = S[:-2, 1:-1, 1:-1]
+    e_up = E[1:, 1:-1, 1:-1]     # eps at i + 1/2, i = 1..n-2
+    e_dn = E[:-1, 1:-1, 1:-1]    # eps at i - 1/2
+    O[1:-1, 1:-1, 1:-1] = mid + (c / (h * h)) * (e_up * (up - mid) + e_dn * (dn - mid))
+    return out
+
+
+def cn_sweep(s: np.ndarray, eps_node: np.ndarray, tau: float, h: float, axis: int) -> np.ndarray:
+    """One Crank-Nicolson 1-D sub-step (Eqs. (LODCN1_2)-(LODCN1_4)):
+    (1 - tau/2 delta^2) v = (1 + tau/2 delta^2) s on every interior line,
+    Dirichlet values at both ends."""
+    return implicit_sweep(explicit_half(s, eps_node, 0.5 * tau, h, axis), eps_node, 0.5 * tau,
+                          h, axis)
+
+
 def nonlinear_substep(u: np.ndarray, theta: np.ndarray, interior: np.ndarray) -> np.ndarray:
     """Exact flow of alpha w_t = -kbar^2 sinh(w) over one step (Eq. (ana3)):
     w = ln[(cosh t + e^{-u} sinh t) / (e^{-u} cosh t + sinh t)], t = theta
@@ -307,8 +335,9 @@ def make_problem(mol, grid, params, medium: str = "solvated") -> Problem:
 
 
 def lod_step(u, pb: Problem, dt: float, alpha: float, order: str = "LODIE2"):
-    """One LODIE step.  LODIE1: N, X, Y, Z, S (Eqs. (LODIE1_1)-(LODIE1_5));
-    LODIE2: S, X, Y, Z, N (Sec. 3.1, last paragraph)."""
+    """One LOD step.  LODIE1: N, X, Y, Z, S (Eqs. (LODIE1_1)-(LODIE1_5));
+    LODIE2: S, X, Y, Z, N (Sec. 3.1, last paragraph); LODCN1 / LODCN2: the
+    same orders with the Crank-Nicolson sweeps of Eqs. (LODCN1_2)-(LODCN1_4)."""
     tau = dt / alpha
     theta = pb.kbar2_node * dt / (2.0 * alpha)
     h = pb.grid.h
@@ -323,6 +352,18 @@ def lod_step(u, pb: Problem, dt: float, alpha: float, order: str = "LODIE2"):
         v = implicit_sweep(w, pb.eps_node, tau, h, axis=2)
         p = implicit_sweep(v, pb.eps_node, tau, h, axis=1)
         qq = implicit_sweep(p, pb.eps_node, tau, h, axis=0)
+        return qq + tau * pb.rho
+    if order == "LODCN2":
+        s = u + tau * pb.rho
+        v = cn_sweep(s, pb.eps_node, tau, h, axis=2)
+        p = cn_sweep(v, pb.eps_node, tau, h, axis=1)
+        qq = cn_sweep(p, pb.eps_node, tau, h, axis=0)
+        return nonlinear_substep(qq, theta, pb.interior)
+    if order == "LODCN1":
+        w = nonlinear_substep(u, theta, pb.interior)
+        v = cn_sweep(w, pb.eps_node, tau, h, axis=2)
+        p = cn_sweep(v, pb.eps_node, tau, h, axis=1)
+        qq = cn_sweep(p, pb.eps_node, tau, h, axis=0)
         return qq + tau * pb.rho
     raise ValueError(order)
 
@@ -355,7 +396,7 @@ def run(pb: Problem, dt: float, alpha: float, n_steps: int, scheme: str = "LODIE
     """Fixed number of pseudo-time steps from u^0 (zero inside)."""
     u = pb.u0.copy() if u_init is None else u_init.copy()
     for _ in range(n_steps):
-        if scheme in ("LODIE2", "LODIE1"):
+        if scheme in ("LODIE2", "LODIE1", "LODCN1", "LODCN2"):
             u = lod_step(u, pb, dt, alpha, scheme)
         else:
             u = aos_step(u, pb, dt, alpha, scheme)

@@ -316,6 +316,14 @@ def _step_map_dense(pb, dt, alpha, scheme):
         if scheme == "LODIE2":
             return Minv, Minv @ (tau * rho)
         return Minv, tau * rho
+    if scheme in ("LODCN2", "LODCN1"):
+        # (I - tau/2 D_d)^-1 (I + tau/2 D_d) per direction, x then y then z
+        Minv = np.eye(N)
+        for D in Ds:
+            Minv = np.linalg.solve(np.eye(N) - 0.5 * tau * D, (np.eye(N) + 0.5 * tau * D) @ Minv)
+        if scheme == "LODCN2":
+            return Minv, Minv @ (tau * rho)
+        return Minv, tau * rho
     c = {"AOSIE1": (4.0, 0.0, 0.0), "AOSIE2": (4.0 / 3, 4.0 / 3, 4.0 / 3)}[scheme]
     M = np.eye(N) * 0.25
     cv = np.zeros(N)
@@ -326,7 +334,7 @@ def _step_map_dense(pb, dt, alpha, scheme):
     return M, cv
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "AOSIE1"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2"])
 def test_linear_fixed_point_matches_dense_solve(scheme):
     grid = _tiny(9, 0.5)
     mol = _two_atoms()
@@ -338,7 +346,7 @@ def test_linear_fixed_point_matches_dense_solve(scheme):
     assert np.max(np.abs(u.ravel() - ud)) <= 1e-10 * np.max(np.abs(ud))
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "LODCN1", "LODCN2"])
 def test_one_step_matches_dense_map(scheme):
     grid = _tiny(8, 0.5, ny=9, nz=7)
     mol = _two_atoms()
@@ -385,7 +393,7 @@ def test_lod_steady_state_converges_to_poisson_first_order_and_richardson_second
     assert re1 < errs[1] / 3 and 3.0 < re1 / re2 < 5.0
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "LODCN2"])
 def test_nonlinear_steady_state_converges_to_discrete_npb(scheme):
     grid = _tiny(9, 0.5)
     mol = _two_atoms()
@@ -550,3 +558,37 @@ def test_recovered_potential_reproduces_the_re_v_energy():
     B = oracle.boundary_shell(w.grid)
     scale = np.max(np.abs(r["phi_0_direct"]))
     assert np.max(np.abs(r["phi_rec"][B] - r["phi_m"][B])) <= 1e-13 * scale
+
+
+# --------------------------------------------------------------------------
+# Crank-Nicolson sub-steps (Eqs. (LODCN1_2)-(LODCN1_4))
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_explicit_half_matches_dense_operator(axis):
+    grid = _tiny(8, 0.5, ny=9, nz=7)
+    p = _params(eps_in=2.0, eps_out=80.0)
+    pb = oracle.make_problem(_two_atoms(), grid, p, "solvated")
+    rng = np.random.default_rng(7 + axis)
+    s = rng.normal(0.0, 10.0, pb.u0.shape)
+    D = _dense.dense_second_difference(pb.eps_node, grid.h, axis)
+    got = oracle.explicit_half(s, pb.eps_node, 0.3, grid.h, axis)
+    ref = s.ravel() + 0.3 * (D @ s.ravel())
+    assert np.max(np.abs(got.ravel() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_cn_sweep_amplifies_an_eigenmode_by_the_crank_nicolson_factor():
+    # constant eps, zero Dirichlet data: sin(pi m i / (n - 1)) along x is an
+    # eigenvector of delta_x^2 with eigenvalue -(eps/h^2) 4 sin^2(pi m / (2 (n - 1)));
+    # one sub-step multiplies it by (1 - c lam) / (1 + c lam), c = tau / 2
+    n, h, eps, tau, m = 17, 0.5, 3.0, 0.8, 5
+    grid = _tiny(n, h, ny=6, nz=5)
+    eps_node = np.full((5, 6, n), eps)
+    i = np.arange(n)
+    mode = np.sin(np.pi * m * i / (n - 1))
+    s = np.zeros((5, 6, n))
+    s[1:-1, 1:-1, :] = mode
+    lam = (eps / h ** 2) * 4.0 * np.sin(np.pi * m / (2.0 * (n - 1))) ** 2
+    g = (1.0 - 0.5 * tau * lam) / (1.0 + 0.5 * tau * lam)
+    v = oracle.cn_sweep(s, eps_node, tau, h, axis=2)
+    assert np.max(np.abs(v[1:-1, 1:-1, :] - g * s[1:-1, 1:-1, :])) <= 1e-13
+    assert abs(g) < 1.0 and g < 0.0   # a stiff mode: damped with a sign flip
