@@ -5,7 +5,9 @@ oracle (oracle.poisson_direct, scipy's type-I DST) on the same inputs.
 
 Tolerances: the direct solve is FP64 in every precision mode; its field is
 a sum of O(N) terms per transform, rounding ~1e-13 relative, so 1e-10 of
-max|phi_0| and 1e-9 relative on energies.  The recovered potential adds
+max|phi_0| and 1e-9 relative on energies in FP64 mode.  In FP32 mode its
+Dirichlet data come from FP32 pair terms (FP64 sums, ~1e-8 relative): 1e-6
+of max|phi_0| there.  The recovered potential adds
 the pseudo-time fields: FP64 1e-10, FP32 2e-5 of max|phi| (as the plain
 fields); dG_direct in FP32 within the energy contract max(1e-3, 1e-5 |E|).
 """
@@ -108,7 +110,9 @@ def test_globular_2000_direct_full_size_against_stored_oracle():
                    / ref[key + "_absmax"])
         de = abs(g["dG_direct"] - ref["dG_direct"])
         _say(prec, "field_select", fs, "sampled rel err", fe, "dG_direct err", de)
-        ftol = 1e-10 if (prec == "f64" or fs == 2) else 1e-4
+        # FP32 mode: the Dirichlet data come from FP32 pair terms with FP64
+        # sums (~1e-8 relative), which the FP64 direct solve carries
+        ftol = 1e-10 if prec == "f64" else (1e-6 if fs == 2 else 1e-4)
         etol = max(1e-7, 1e-9 * abs(ref["dG_direct"])) if prec == "f64" else \
             max(1e-3, 1e-5 * abs(ref["dG_direct"]))
         if fe > ftol:
