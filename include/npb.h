@@ -51,7 +51,9 @@ typedef enum npb_scheme {
   NPB_LODIE2 = 0,  /* source, x, y, z sweeps, nonlinear (Sec. 3.1, last paragraph) */
   NPB_LODIE1 = 1,  /* nonlinear, x, y, z sweeps, source (Eqs. (LODIE1_1)-(LODIE1_5)) */
   NPB_AOSIE2 = 2,  /* additive, source split 1/3 per direction (Eqs. (AOSIE2_2)-(AOSIE2_4)) */
-  NPB_AOSIE1 = 3   /* additive, source on x only (Eqs. (AOSIE1_1)-(AOSIE1_5)) */
+  NPB_AOSIE1 = 3,  /* additive, source on x only (Eqs. (AOSIE1_1)-(AOSIE1_5)) */
+  NPB_LODCN1 = 4,  /* LODIE1 order with Crank-Nicolson sweeps (Eqs. (LODCN1_2)-(LODCN1_4)) */
+  NPB_LODCN2 = 5   /* LODIE2 order with Crank-Nicolson sweeps (Sec. 3.1, last paragraph) */
 } npb_scheme;
 
 typedef enum npb_precision {

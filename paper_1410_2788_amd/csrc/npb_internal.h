@@ -40,6 +40,8 @@ struct SweepArgs {
   const int* src_lin;     // linear node index of each entry
   const double* src_rho;  // source density at that node
   int mode;               // 0 in place, 1 acc = (W+V)/4, 2 acc += P/4, 3 u = acc + Q/4
+  int cn;                 // 1: Crank-Nicolson, the right-hand side is (1 + r delta^2) s
+                          // with the same face coefficients as the implicit side
   // per (chunk, line) face class of this direction's launch shape: 0 = every
   // face of the chunk solvent-solvent, 2 = every face solute-solute, 1 =
   // mixed; nullptr for the uniform medium (all chunks uniform)
@@ -157,11 +159,14 @@ template <typename T>
 void shape_args(SweepArgs<T>& a, int dir, const LaunchShape& s);
 template <typename T>
 int sweep_variant(const SweepArgs<T>* a, int n);  // kYz* covering every field
+template <typename T>
+int sweep_cn(const SweepArgs<T>* a, int n);       // 1 if any field is Crank-Nicolson
 // nbu > 0: every field has nbu blocks and block b is (b / nbu, b % nbu);
 // work may then be null.
+// cn: compile the Crank-Nicolson right-hand side in (some field has cn set)
 template <typename T, typename A>
 hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
-                          const LaunchShape& s, hipStream_t st);
+                          int cn, const LaunchShape& s, hipStream_t st);
 template <typename T, typename A>
 hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                            int dir, int var, const LaunchShape& s, hipStream_t st);

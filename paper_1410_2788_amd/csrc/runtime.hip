@@ -399,7 +399,12 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // sources in both, LODIE1 after the z solve (LODIE2 and AOSIE1 add theirs
 // in the x sweep).
 bool needs_y_sources(int scheme) { return scheme == NPB_AOSIE2; }
-bool needs_z_sources(int scheme) { return scheme == NPB_AOSIE2 || scheme == NPB_LODIE1; }
+bool needs_z_sources(int scheme) {
+  return scheme == NPB_AOSIE2 || scheme == NPB_LODIE1 || scheme == NPB_LODCN1;
+}
+// Crank-Nicolson LOD schemes: the sweeps of the IE counterpart with half
+// the implicit coefficient and the explicit half on the right-hand side
+bool is_cn(int scheme) { return scheme == NPB_LODCN1 || scheme == NPB_LODCN2; }
 
 Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params* p) {
   Layout L{};
@@ -509,7 +514,7 @@ npb_status validate(const npb_molecule* mol, const npb_grid* g, const npb_params
   if (!(p->alpha > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->alpha) || !std::isfinite(p->dt))
     return fail(NPB_EINVAL, "alpha and dt must be positive");
   if (p->n_steps < 1) return fail(NPB_EINVAL, "n_steps must be >= 1");
-  if (p->scheme < 0 || p->scheme > 3) return fail(NPB_EINVAL, "unknown scheme");
+  if (p->scheme < 0 || p->scheme > 5) return fail(NPB_EINVAL, "unknown scheme");
   if (p->precision < 0 || p->precision > 2) return fail(NPB_EINVAL, "unknown precision");
   if (p->vacuum_direct != 0 && p->vacuum_direct != 1)
     return fail(NPB_EINVAL, "vacuum_direct must be 0 or 1");
@@ -579,7 +584,9 @@ Coefs run_coefs(const Problem& P, const Run& r) {
   const double dt = p->dt / double(1 << r.level);
   c.vacuum = r.medium == 1;
   c.tau = dt / p->alpha;
-  const double rc = (P.aos() ? 4.0 * c.tau : c.tau) / (P.g->h * P.g->h);
+  // implicit coefficient: 4 tau (AOS), tau / 2 (Crank-Nicolson), else tau
+  const double rc =
+      (P.aos() ? 4.0 * c.tau : (is_cn(p->scheme) ? 0.5 * c.tau : c.tau)) / (P.g->h * P.g->h);
   const double ein = p->eps_in, eout = p->eps_out;
   const double emix = 2.0 * ein * eout / (ein + eout);
   const double eout_f = 2.0 * eout * eout / (eout + eout);
@@ -673,7 +680,8 @@ struct Engine {
       a.src_lin = P.at<int>(d == 1 ? L.ylin : L.zlin);
       a.src_rho = P.at<double>(d == 1 ? L.yrho : L.zrho);
     }
-    if (p->scheme == NPB_LODIE2) {
+    a.cn = is_cn(p->scheme) ? 1 : 0;
+    if (p->scheme == NPB_LODIE2 || p->scheme == NPB_LODCN2) {
       if (d == 0) {
         a.src_stage = 1;
         a.src_coef = c.tau;
@@ -683,7 +691,7 @@ struct Engine {
         a.post_ka = c.t;
         a.post_kb = c.omt;
       }
-    } else if (p->scheme == NPB_LODIE1) {
+    } else if (p->scheme == NPB_LODIE1 || p->scheme == NPB_LODCN1) {
       if (d == 0 && c.nl) {
         a.pre_nl = 1;
         a.pre_ka = c.t;
@@ -768,7 +776,9 @@ struct Engine {
       }
       for (int g = 0; g < (int)groups[d].size(); ++g) {
         Group& G = groups[d][g];
-        G.var = sweep_variant(gargs[d][g].data(), (int)gargs[d][g].size());
+        // y / z: the kernel variant; x: whether the Crank-Nicolson code is needed
+        G.var = d == 0 ? sweep_cn(gargs[d][g].data(), (int)gargs[d][g].size())
+                       : sweep_variant(gargs[d][g].data(), (int)gargs[d][g].size());
         G.nbu = pr[fields[G.members[0]].prob].L.shape[d].blocks;
         for (int m : G.members)
           if (pr[fields[m].prob].L.shape[d].blocks != G.nbu) G.nbu = 0;
@@ -1020,7 +1030,7 @@ struct Engine {
                        : G.var == kYzFlow ? NPB_SK_YZ_FLOW
                                           : NPB_SK_YZ_GENERAL;
         npb_status r = timed_on(s, NPB_K_SWEEP_X + d, sk, L.bytes, [&] {
-          return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.s, s)
+          return d == 0 ? launch_sweep_x<T, A>(args, work, G.nbu, nb, G.var, G.s, s)
                         : launch_sweep_yz<T, A>(args, work, G.nbu, nb, d, G.var, G.s, s);
         });
         if (r != NPB_OK) return r;
@@ -1335,9 +1345,9 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
                           sizeof(int2) * nb, hipMemcpyHostToDevice));
         const auto* dargs = static_cast<const SweepArgs<T>*>(dbuf);
         const auto* dwork = reinterpret_cast<const int2*>(static_cast<unsigned char*>(dbuf) + ab);
-        const int var = sweep_variant(args.data(), nr);
+        const int var = d == 0 ? sweep_cn(args.data(), nr) : sweep_variant(args.data(), nr);
         auto launch = [&] {
-          return d == 0 ? launch_sweep_x<T, A>(dargs, dwork, sh.blocks, nb, sh, st)
+          return d == 0 ? launch_sweep_x<T, A>(dargs, dwork, sh.blocks, nb, var, sh, st)
                         : launch_sweep_yz<T, A>(dargs, dwork, sh.blocks, nb, d, var, sh, st);
         };
         constexpr int kWarm = 2, kReps = 5;

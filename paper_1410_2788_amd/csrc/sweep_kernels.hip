@@ -200,6 +200,39 @@ __device__ __forceinline__ void chunk_finish(A (&d)[M], const A (&al)[M], const 
 template <typename A>
 using ConstTab = const __attribute__((address_space(4))) ChunkTab<A>;
 
+// Crank-Nicolson right-hand side (Eqs. (LODCN1_2)-(LODCN1_4)): the chunk's
+// rows d[0..M-1] become (1 + r delta^2) s with the implicit side's face
+// coefficients reF (face k between local rows k-1 and k), left / right the
+// values next to the chunk and gR the Dirichlet value after local row kR
+// (the line's last interior row when it lies in the chunk).  Rows past kR
+// stay zero.  The differences are formed first, so a large coefficient
+// multiplies only the variation of s.
+template <typename A, int M>
+__device__ __forceinline__ void cn_rhs(A (&d)[M], const A (&reF)[M + 1], A left, A right, int kR,
+                                       A gR) {
+  A prev = left;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const A cur = d[k];
+    const A nxt = (k == kR) ? gR : (k + 1 < M ? d[k + 1] : right);
+    d[k] = (k <= kR) ? fma(reF[k], prev - cur, fma(reF[k + 1], nxt - cur, cur)) : A(0);
+    prev = cur;
+  }
+}
+
+// the same for a chunk of uniform faces re with every row interior
+template <typename A, int M>
+__device__ __forceinline__ void cn_rhs_uniform(A (&d)[M], A re, A left, A right) {
+  A prev = left;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const A cur = d[k];
+    const A nxt = k + 1 < M ? d[k + 1] : right;
+    d[k] = fma(re, (prev - cur) + (nxt - cur), cur);
+    prev = cur;
+  }
+}
+
 // Uniform chunks (every face coefficient equal to re, leak 1): the pivots,
 // couplings and reduced-row coefficients are the tabulated constants of
 // ChunkTab (computed by the same recurrences in FP64), so only the
@@ -404,7 +437,7 @@ __device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
 // lane t takes line t % L and chunk t / L.  The first row4(nx) elements of
 // each row move between HBM and an odd-stride LDS tile with 16-byte vector
 // accesses; the row's boundary columns are written back unchanged.
-template <typename T, typename A, int M, int L>
+template <typename T, typename A, int M, int L, bool CN>
 __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) void sweep_x_kernel(
     const SweepArgs<T>* __restrict__ args, const int2* __restrict__ work, int nbu) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
@@ -578,6 +611,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
+    if (CN && a.cn) cn_rhs_uniform<A, M>(d, tb.re[t], col[-1], col[M]);
     if (first) d[0] = fma(tb.re[t], gL, d[0]);
     fast_eliminate<A, M>(d, tb, t, first, rf, rl);
   } else {
@@ -594,6 +628,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
       reF[k] = pick3(c, re0, re1, re2);
       prev = cur;
     }
+    if (CN && a.cn) cn_rhs<A, M>(d, reF, col[-1], col[M], kR, gR);
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
   }
@@ -697,6 +732,7 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
+    if (VAR == kYzGeneral && a.cn) cn_rhs_uniform<A, M>(d, tb.re[t], col[-ts], col[M * ts]);
     if (first) d[0] = fma(tb.re[t], gL, d[0]);
     fast_eliminate<A, M>(d, tb, t, first, rf, rl);
   } else {
@@ -713,6 +749,7 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
       reF[k] = pick3(c, re0, re1, re2);
       prev = cur;
     }
+    if (VAR == kYzGeneral && a.cn) cn_rhs<A, M>(d, reF, col[-ts], col[M * ts], kR, gR);
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
   }
@@ -1060,17 +1097,28 @@ void shape_args(SweepArgs<T>& a, int dir, const LaunchShape& s) {
 template void shape_args<float>(SweepArgs<float>&, int, const LaunchShape&);
 template void shape_args<double>(SweepArgs<double>&, int, const LaunchShape&);
 
+// y/z: the Crank-Nicolson right-hand side is a run-time flag of the general
+// variant only, so the plain and flow kernels carry none of its code
 template <typename T>
 int sweep_variant(const SweepArgs<T>* a, int n) {
   bool general = false, flow = false;
   for (int f = 0; f < n; ++f) {
-    general = general || a[f].src_stage != 0 || a[f].mode != MODE_INPLACE;
+    general = general || a[f].src_stage != 0 || a[f].mode != MODE_INPLACE || a[f].cn;
     flow = flow || (a[f].post_nl && a[f].mask);
   }
   return general ? kYzGeneral : (flow ? kYzFlow : kYzPlain);
 }
 template int sweep_variant<float>(const SweepArgs<float>*, int);
 template int sweep_variant<double>(const SweepArgs<double>*, int);
+
+template <typename T>
+int sweep_cn(const SweepArgs<T>* a, int n) {
+  for (int f = 0; f < n; ++f)
+    if (a[f].cn) return 1;
+  return 0;
+}
+template int sweep_cn<float>(const SweepArgs<float>*, int);
+template int sweep_cn<double>(const SweepArgs<double>*, int);
 
 // Dynamic LDS above 64 KB (up to the 160 KB of a CU) must be allowed per
 // kernel before the launch.
@@ -1081,7 +1129,7 @@ static hipError_t allow_lds(K kernel, size_t lds) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <typename T, typename A, int L>
+template <typename T, typename A, int L, bool CN>
 static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                              const LaunchShape& s, hipStream_t st) {
   // the block size must stay within the instantiation's launch bound
@@ -1090,9 +1138,10 @@ static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nbu
   switch (s.M) {
 #define NPB_X_CASE(MM)                                                                 \
   case MM: {                                                                           \
-    hipError_t e = allow_lds(sweep_x_kernel<T, A, MM, L>, s.lds);                      \
+    hipError_t e = allow_lds(sweep_x_kernel<T, A, MM, L, CN>, s.lds);                  \
     if (e != hipSuccess) return e;                                                     \
-    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L>), g, blk, s.lds, st, args, work, nbu); \
+    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L, CN>), g, blk, s.lds, st, args, work, \
+                       nbu);                                                           \
   } break;
     NPB_X_CASE(4)
     NPB_X_CASE(8)
@@ -1106,15 +1155,22 @@ static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nbu
   return hipGetLastError();
 }
 
+template <typename T, typename A, bool CN>
+static hipError_t launch_x_cn(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
+                              const LaunchShape& s, hipStream_t st) {
+  if (s.LW == 64) return launch_x_l<T, A, 64, CN>(args, work, nbu, nblocks, s, st);
+  if (s.LW == 32) return launch_x_l<T, A, 32, CN>(args, work, nbu, nblocks, s, st);
+  if (s.LW == 16) return launch_x_l<T, A, 16, CN>(args, work, nbu, nblocks, s, st);
+  if (s.LW == 8) return launch_x_l<T, A, 8, CN>(args, work, nbu, nblocks, s, st);
+  return hipErrorInvalidValue;
+}
+
 template <typename T, typename A>
 hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
-                          const LaunchShape& s, hipStream_t st) {
+                          int cn, const LaunchShape& s, hipStream_t st) {
   if (nblocks < 1 || (nbu <= 0 && !work)) return hipErrorInvalidValue;
-  if (s.LW == 64) return launch_x_l<T, A, 64>(args, work, nbu, nblocks, s, st);
-  if (s.LW == 32) return launch_x_l<T, A, 32>(args, work, nbu, nblocks, s, st);
-  if (s.LW == 16) return launch_x_l<T, A, 16>(args, work, nbu, nblocks, s, st);
-  if (s.LW == 8) return launch_x_l<T, A, 8>(args, work, nbu, nblocks, s, st);
-  return hipErrorInvalidValue;
+  return cn ? launch_x_cn<T, A, true>(args, work, nbu, nblocks, s, st)
+            : launch_x_cn<T, A, false>(args, work, nbu, nblocks, s, st);
 }
 
 template <typename T, typename A, int VAR, int TW>
@@ -1173,7 +1229,7 @@ hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nbu, 
 }
 
 #define NPB_INST(T, A)                                                                          \
-  template hipError_t launch_sweep_x<T, A>(const SweepArgs<T>*, const int2*, int, int,         \
+  template hipError_t launch_sweep_x<T, A>(const SweepArgs<T>*, const int2*, int, int, int,    \
                                            const LaunchShape&, hipStream_t);                    \
   template hipError_t launch_sweep_yz<T, A>(const SweepArgs<T>*, const int2*, int, int, int,   \
                                             int, const LaunchShape&, hipStream_t);
