@@ -20,6 +20,11 @@ the electrostatic analysis of solvated biomolecules"):
                                  place of the three implicit sweeps
   * AOSIE1 / AOSIE2 ............ Sec. 3.2, Eqs. (AOSIE1_1)-(AOSIE1_5),
                                  (AOSIE2_2)-(AOSIE2_4)
+  * AOSCN1 / AOSCN2 ............ Sec. 3.2, Eqs. (AOSCN1_2)-(AOSCN1_4),
+                                 (AOSCN2_2)-(AOSCN2_4)
+  * MAOSIE / MAOSCN ............ Sec. 3.3, Eqs. (MAOS1_1)-(MAOS1_5), implicit
+                                 Euler or Crank-Nicolson in the three
+                                 directional sub-systems
   * solvation energy ........... Sec. 4.1, Eq. (deltaG); vacuum by the same
                                  scheme, Sec. 4.3, Eq. (deltaG3)
   * Richardson extrapolation ... Sec. 4.3, Eq. (rich)
@@ -61,7 +66,8 @@ KT_298_KCAL = 0.592183          # kcal/mol per unit dimensionless potential at 2
 KBAR2_PER_MOLAR_298 = 8.486902807  # Angstrom^-2 per mol/L at 298 K
 COULOMB_KCAL_A = 332.06371      # e^2/(4 pi eps0) in kcal Angstrom / mol (CODATA)
 
-SCHEMES = ("LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2")
+SCHEMES = ("LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2", "AOSCN1", "AOSCN2",
+           "MAOSIE", "MAOSCN")
 
 
 def thermal_energy(T: float) -> float:
@@ -369,25 +375,59 @@ def lod_step(u, pb: Problem, dt: float, alpha: float, order: str = "LODIE2"):
 
 
 def aos_step(u, pb: Problem, dt: float, alpha: float, variant: str = "AOSIE2"):
-    """One AOSIE step (Eqs. (AOSIE1_1)-(AOSIE1_5); AOSIE2 replaces the three
-    sweeps by Eqs. (AOSIE2_2)-(AOSIE2_4)).  Four independent sub-solves from
-    u^n, then their arithmetic mean."""
+    """One AOS step (Eqs. (AOSIE1_1)-(AOSIE1_5); AOSIE2 replaces the three
+    sweeps by Eqs. (AOSIE2_2)-(AOSIE2_4); AOSCN1 / AOSCN2 by Eqs.
+    (AOSCN1_2)-(AOSCN1_4) / (AOSCN2_2)-(AOSCN2_4)).  Four independent
+    sub-solves from u^n, then their arithmetic mean.  In the Crank-Nicolson
+    forms the source stays outside the explicit half."""
     tau = dt / alpha
     h = pb.grid.h
     theta4 = 4.0 * pb.kbar2_node * dt / (2.0 * alpha)
-    if variant == "AOSIE1":
+    if variant in ("AOSIE1", "AOSCN1"):
         cx, cy, cz = 4.0, 0.0, 0.0
-    elif variant == "AOSIE2":
+    elif variant in ("AOSIE2", "AOSCN2"):
         cx = cy = cz = 4.0 / 3.0
     else:
         raise ValueError(variant)
     w = nonlinear_substep(u, theta4, pb.interior)
-    v = implicit_sweep(u + cx * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=2)
-    p = implicit_sweep(u + cy * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=1)
-    qq = implicit_sweep(u + cz * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=0)
+    if variant.startswith("AOSIE"):
+        v = implicit_sweep(u + cx * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=2)
+        p = implicit_sweep(u + cy * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=1)
+        qq = implicit_sweep(u + cz * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=0)
+    else:
+        def cn(axis, c):
+            rhs = explicit_half(u, pb.eps_node, 2.0 * tau, h, axis) + c * tau * pb.rho
+            return implicit_sweep(rhs, pb.eps_node, 2.0 * tau, h, axis)
+        v, p, qq = cn(2, cx), cn(1, cy), cn(0, cz)
     out = u.copy()
     I = pb.interior
     out[I] = 0.25 * (w[I] + v[I] + p[I] + qq[I])
+    return out
+
+
+def maos_step(u, pb: Problem, dt: float, alpha: float, variant: str = "MAOSIE"):
+    """One MAOS step (Sec. 3.3, Eqs. (MAOS1_1)-(MAOS1_5)): the exact flow of
+    the sinh term first (Eq. (ana3), theta = kbar^2 dt / (2 alpha)), then
+    three independent directional sub-solves of alpha v_t = 3 d/dx(eps dv/dx)
+    + rho from it -- implicit Euler, (1 - 3 tau delta^2) v = w + tau rho, or
+    Crank-Nicolson, (1 - 3 tau/2 delta^2) v = (1 + 3 tau/2 delta^2) w + tau rho
+    -- and their arithmetic mean."""
+    tau = dt / alpha
+    h = pb.grid.h
+    theta = pb.kbar2_node * dt / (2.0 * alpha)
+    w = nonlinear_substep(u, theta, pb.interior)
+    subs = []
+    for axis in (2, 1, 0):
+        if variant == "MAOSIE":
+            subs.append(implicit_sweep(w + tau * pb.rho, pb.eps_node, 3.0 * tau, h, axis))
+        elif variant == "MAOSCN":
+            rhs = explicit_half(w, pb.eps_node, 1.5 * tau, h, axis) + tau * pb.rho
+            subs.append(implicit_sweep(rhs, pb.eps_node, 1.5 * tau, h, axis))
+        else:
+            raise ValueError(variant)
+    out = u.copy()
+    I = pb.interior
+    out[I] = (subs[0][I] + subs[1][I] + subs[2][I]) / 3.0
     return out
 
 
@@ -398,6 +438,8 @@ def run(pb: Problem, dt: float, alpha: float, n_steps: int, scheme: str = "LODIE
     for _ in range(n_steps):
         if scheme in ("LODIE2", "LODIE1", "LODCN1", "LODCN2"):
             u = lod_step(u, pb, dt, alpha, scheme)
+        elif scheme.startswith("MAOS"):
+            u = maos_step(u, pb, dt, alpha, scheme)
         else:
             u = aos_step(u, pb, dt, alpha, scheme)
     return u

@@ -324,29 +324,53 @@ def _step_map_dense(pb, dt, alpha, scheme):
         if scheme == "LODCN2":
             return Minv, Minv @ (tau * rho)
         return Minv, tau * rho
-    c = {"AOSIE1": (4.0, 0.0, 0.0), "AOSIE2": (4.0 / 3, 4.0 / 3, 4.0 / 3)}[scheme]
+    if scheme in ("MAOSIE", "MAOSCN"):
+        # kbar = 0: the flow is the identity; mean of three directional solves
+        M = np.zeros((N, N))
+        cv = np.zeros(N)
+        for D in Ds:
+            if scheme == "MAOSIE":
+                Bi = np.linalg.inv(np.eye(N) - 3 * tau * D)
+                E = np.eye(N)
+            else:
+                Bi = np.linalg.inv(np.eye(N) - 1.5 * tau * D)
+                E = np.eye(N) + 1.5 * tau * D
+            M += Bi @ E / 3.0
+            cv += Bi @ (tau * rho) / 3.0
+        return M, cv
+    c = {"AOSIE1": (4.0, 0.0, 0.0), "AOSIE2": (4.0 / 3, 4.0 / 3, 4.0 / 3),
+         "AOSCN1": (4.0, 0.0, 0.0), "AOSCN2": (4.0 / 3, 4.0 / 3, 4.0 / 3)}[scheme]
     M = np.eye(N) * 0.25
     cv = np.zeros(N)
     for D, cd in zip(Ds, c):
-        Bi = np.linalg.inv(np.eye(N) - 4 * tau * D)
-        M += 0.25 * Bi
+        if scheme.startswith("AOSIE"):
+            Bi = np.linalg.inv(np.eye(N) - 4 * tau * D)
+            E = np.eye(N)
+        else:
+            Bi = np.linalg.inv(np.eye(N) - 2 * tau * D)
+            E = np.eye(N) + 2 * tau * D
+        M += 0.25 * Bi @ E
         cv += 0.25 * Bi @ (cd * tau * rho)
     return M, cv
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2",
+                                    "AOSCN1", "AOSCN2", "MAOSIE", "MAOSCN"])
 def test_linear_fixed_point_matches_dense_solve(scheme):
     grid = _tiny(9, 0.5)
     mol = _two_atoms()
     p = _params(scheme=scheme, ionic_molar=0.0, dt=0.1, alpha=1.0)
     pb = oracle.make_problem(mol, grid, p, "solvated")
-    u = oracle.run(pb, p.dt, p.alpha, 600, scheme)
+    # MAOSCN: the stiffest modes decay by ~0.99 per step (Crank-Nicolson
+    # factors near -1 in all three directions at once)
+    u = oracle.run(pb, p.dt, p.alpha, 8000 if scheme == "MAOSCN" else 600, scheme)
     M, c = _step_map_dense(pb, p.dt, p.alpha, scheme)
     ud = _dense.affine_fixed_point(M, c, pb.u0.ravel(), _dense.interior_flags(pb.u0.shape))
     assert np.max(np.abs(u.ravel() - ud)) <= 1e-10 * np.max(np.abs(ud))
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "LODCN1", "LODCN2"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "LODCN1", "LODCN2", "AOSCN1",
+                                    "AOSCN2", "MAOSIE", "MAOSCN"])
 def test_one_step_matches_dense_map(scheme):
     grid = _tiny(8, 0.5, ny=9, nz=7)
     mol = _two_atoms()
@@ -393,7 +417,7 @@ def test_lod_steady_state_converges_to_poisson_first_order_and_richardson_second
     assert re1 < errs[1] / 3 and 3.0 < re1 / re2 < 5.0
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "LODCN2"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "LODCN2", "AOSCN2", "MAOSIE"])
 def test_nonlinear_steady_state_converges_to_discrete_npb(scheme):
     grid = _tiny(9, 0.5)
     mol = _two_atoms()
