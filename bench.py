@@ -365,7 +365,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="f32", choices=["f32", "f32x", "f64"])
     ap.add_argument("--scheme", default="LODIE2",
-                    choices=["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2"])
+                    choices=["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2",
+                             "AOSCN1", "AOSCN2", "MAOSIE", "MAOSCN"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-kernel event timing pass")
@@ -475,7 +476,7 @@ def main():
         ach = bpl / (avg_ms * 1e-3) / 1e9
         tname = {"f32": "float, float", "f32x": "float, double", "f64": "double, double"}[args.precision]
         if kname == "x":
-            cn = "true" if args.scheme.startswith("LODCN") else "false"
+            cn = "true" if "CN" in args.scheme else "false"
             full = f"npb::sweep_x_kernel<{tname}, {shapes[0][0]}, {shapes[0][2]}, {cn}>"
         else:
             var = {"yz_plain": 0, "yz_flow": 1, "yz_general": 2}[kname]

@@ -53,7 +53,12 @@ typedef enum npb_scheme {
   NPB_AOSIE2 = 2,  /* additive, source split 1/3 per direction (Eqs. (AOSIE2_2)-(AOSIE2_4)) */
   NPB_AOSIE1 = 3,  /* additive, source on x only (Eqs. (AOSIE1_1)-(AOSIE1_5)) */
   NPB_LODCN1 = 4,  /* LODIE1 order with Crank-Nicolson sweeps (Eqs. (LODCN1_2)-(LODCN1_4)) */
-  NPB_LODCN2 = 5   /* LODIE2 order with Crank-Nicolson sweeps (Sec. 3.1, last paragraph) */
+  NPB_LODCN2 = 5,  /* LODIE2 order with Crank-Nicolson sweeps (Sec. 3.1, last paragraph) */
+  NPB_AOSCN1 = 6,  /* additive, Crank-Nicolson, source on x (Eqs. (AOSCN1_2)-(AOSCN1_4)) */
+  NPB_AOSCN2 = 7,  /* additive, Crank-Nicolson, source split (Eqs. (AOSCN2_2)-(AOSCN2_4)) */
+  NPB_MAOSIE = 8,  /* nonlinear sub-step, then the mean of three implicit-Euler
+                      directional solves (Sec. 3.3, Eqs. (MAOS1_1)-(MAOS1_5)) */
+  NPB_MAOSCN = 9   /* the same with Crank-Nicolson directional solves (Sec. 3.3) */
 } npb_scheme;
 
 typedef enum npb_precision {

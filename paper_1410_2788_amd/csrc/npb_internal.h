@@ -40,8 +40,11 @@ struct SweepArgs {
   const int* src_lin;     // linear node index of each entry
   const double* src_rho;  // source density at that node
   int mode;               // 0 in place, 1 acc = (W+V)/4, 2 acc += P/4, 3 u = acc + Q/4
-  int cn;                 // 1: Crank-Nicolson, the right-hand side is (1 + r delta^2) s
-                          // with the same face coefficients as the implicit side
+  int cn;                 // Crank-Nicolson: the right-hand side is (1 + r delta^2) s with
+                          // the implicit side's face coefficients; 1: of the input with
+                          // its sources (LOD), 2: before the sources are added (additive)
+  double aos_ww, aos_wv;  // additive modes: weights of W and of this direction's
+                          // solution in the mean (AOS 1/4 and 1/4, MAOS 0 and 1/3)
   // per (chunk, line) face class of this direction's launch shape: 0 = every
   // face of the chunk solvent-solvent, 2 = every face solute-solute, 1 =
   // mixed; nullptr for the uniform medium (all chunks uniform)

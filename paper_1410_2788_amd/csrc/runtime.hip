@@ -398,13 +398,37 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // Per-line source lists each scheme's y and z sweeps use: AOSIE2 adds
 // sources in both, LODIE1 after the z solve (LODIE2 and AOSIE1 add theirs
 // in the x sweep).
-bool needs_y_sources(int scheme) { return scheme == NPB_AOSIE2; }
-bool needs_z_sources(int scheme) {
-  return scheme == NPB_AOSIE2 || scheme == NPB_LODIE1 || scheme == NPB_LODCN1;
+bool is_maos(int scheme) { return scheme == NPB_MAOSIE || scheme == NPB_MAOSCN; }
+// schemes with an accumulator: AOS (W and three directions) and MAOS (three)
+bool is_aos(int scheme) {
+  return scheme == NPB_AOSIE1 || scheme == NPB_AOSIE2 || scheme == NPB_AOSCN1 ||
+         scheme == NPB_AOSCN2 || is_maos(scheme);
 }
-// Crank-Nicolson LOD schemes: the sweeps of the IE counterpart with half
-// the implicit coefficient and the explicit half on the right-hand side
-bool is_cn(int scheme) { return scheme == NPB_LODCN1 || scheme == NPB_LODCN2; }
+bool needs_y_sources(int scheme) {
+  return scheme == NPB_AOSIE2 || scheme == NPB_AOSCN2 || is_maos(scheme);
+}
+bool needs_z_sources(int scheme) {
+  return needs_y_sources(scheme) || scheme == NPB_LODIE1 || scheme == NPB_LODCN1;
+}
+// Crank-Nicolson forms: 1 = LOD (explicit half of the input with its
+// source), 2 = additive (explicit half of u^n or W, source added after)
+int cn_kind(int scheme) {
+  if (scheme == NPB_LODCN1 || scheme == NPB_LODCN2) return 1;
+  if (scheme == NPB_AOSCN1 || scheme == NPB_AOSCN2 || scheme == NPB_MAOSCN) return 2;
+  return 0;
+}
+// implicit coefficient of the directional solves in units of tau:
+// 1 (LODIE), 1/2 (LODCN), 4 (AOSIE), 2 (AOSCN), 3 (MAOSIE), 3/2 (MAOSCN)
+double sweep_tau_factor(int scheme) {
+  switch (scheme) {
+    case NPB_LODCN1: case NPB_LODCN2: return 0.5;
+    case NPB_AOSIE1: case NPB_AOSIE2: return 4.0;
+    case NPB_AOSCN1: case NPB_AOSCN2: return 2.0;
+    case NPB_MAOSIE: return 3.0;
+    case NPB_MAOSCN: return 1.5;
+    default: return 1.0;
+  }
+}
 
 Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params* p) {
   Layout L{};
@@ -414,7 +438,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   const int cap = 8 * na;
   const int nb = (cap + 255) / 256;
   const size_t ns = (size_t)shell_count(g->nx, g->ny, g->nz);
-  const bool aos = p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2;
+  const bool aos = is_aos(p->scheme);
   const bool ys = needs_y_sources(p->scheme), zs = needs_z_sources(p->scheme);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -470,7 +494,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
 }
 
 std::array<int, 5> tune_key(const npb_grid* g, const npb_params* p) {
-  const int aos = (p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2) ? 1 : 0;
+  const int aos = is_aos(p->scheme) ? 1 : 0;
   return {g->nx, g->ny, g->nz, p->precision, aos};
 }
 
@@ -478,7 +502,7 @@ std::array<int, 5> tune_key(const npb_grid* g, const npb_params* p) {
 void tuned_shapes(const npb_grid* g, const npb_params* p, const std::array<int, 6>& c,
                   LaunchShape out[3]) {
   const bool f64a = p->precision != NPB_FP32;
-  const bool aos = p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2;
+  const bool aos = is_aos(p->scheme);
   out[0] = plan_x(g->nx, g->ny, g->nz, f64a, aos, false, c[0], c[1]);
   out[1] = plan_yz(g->nx, g->ny, g->nz, f64a, c[2], c[3]);
   out[2] = plan_yz(g->nx, g->nz, g->ny, f64a, c[4], c[5]);
@@ -514,7 +538,7 @@ npb_status validate(const npb_molecule* mol, const npb_grid* g, const npb_params
   if (!(p->alpha > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->alpha) || !std::isfinite(p->dt))
     return fail(NPB_EINVAL, "alpha and dt must be positive");
   if (p->n_steps < 1) return fail(NPB_EINVAL, "n_steps must be >= 1");
-  if (p->scheme < 0 || p->scheme > 5) return fail(NPB_EINVAL, "unknown scheme");
+  if (p->scheme < 0 || p->scheme > 9) return fail(NPB_EINVAL, "unknown scheme");
   if (p->precision < 0 || p->precision > 2) return fail(NPB_EINVAL, "unknown precision");
   if (p->vacuum_direct != 0 && p->vacuum_direct != 1)
     return fail(NPB_EINVAL, "vacuum_direct must be 0 or 1");
@@ -568,7 +592,7 @@ struct Problem {
   Ptr* at(size_t off) const {
     return reinterpret_cast<Ptr*>(ws + off);
   }
-  bool aos() const { return p->scheme == NPB_AOSIE1 || p->scheme == NPB_AOSIE2; }
+  bool aos() const { return is_aos(p->scheme); }
 };
 
 // coefficients of one run (Sec. 3: tau = dt / alpha; AOS sub-steps take
@@ -584,9 +608,7 @@ Coefs run_coefs(const Problem& P, const Run& r) {
   const double dt = p->dt / double(1 << r.level);
   c.vacuum = r.medium == 1;
   c.tau = dt / p->alpha;
-  // implicit coefficient: 4 tau (AOS), tau / 2 (Crank-Nicolson), else tau
-  const double rc =
-      (P.aos() ? 4.0 * c.tau : (is_cn(p->scheme) ? 0.5 * c.tau : c.tau)) / (P.g->h * P.g->h);
+  const double rc = sweep_tau_factor(p->scheme) * c.tau / (P.g->h * P.g->h);
   const double ein = p->eps_in, eout = p->eps_out;
   const double emix = 2.0 * ein * eout / (ein + eout);
   const double eout_f = 2.0 * eout * eout / (eout + eout);
@@ -680,7 +702,7 @@ struct Engine {
       a.src_lin = P.at<int>(d == 1 ? L.ylin : L.zlin);
       a.src_rho = P.at<double>(d == 1 ? L.yrho : L.zrho);
     }
-    a.cn = is_cn(p->scheme) ? 1 : 0;
+    a.cn = cn_kind(p->scheme);
     if (p->scheme == NPB_LODIE2 || p->scheme == NPB_LODCN2) {
       if (d == 0) {
         a.src_stage = 1;
@@ -701,9 +723,25 @@ struct Engine {
         a.src_stage = 2;
         a.src_coef = c.tau;
       }
+    } else if (is_maos(p->scheme)) {
+      // Sec. 3.3: every direction starts from W = flow(u^n) with the source
+      // tau rho; U = (V + P + Q) / 3
+      a.mode = d == 0 ? MODE_AOS_FIRST : (d == 1 ? MODE_AOS_ADD : MODE_AOS_FINISH);
+      a.aos_ww = 0.0;
+      a.aos_wv = 1.0 / 3.0;
+      if (c.nl) {
+        a.pre_nl = 1;
+        a.pre_ka = c.t;
+        a.pre_kb = c.omt;
+      }
+      a.src_stage = 1;
+      a.src_coef = c.tau;
     } else {
-      const double cx = p->scheme == NPB_AOSIE2 ? 4.0 / 3.0 : 4.0;
-      const double cyz = p->scheme == NPB_AOSIE2 ? 4.0 / 3.0 : 0.0;
+      const bool split = p->scheme == NPB_AOSIE2 || p->scheme == NPB_AOSCN2;
+      const double cx = split ? 4.0 / 3.0 : 4.0;
+      const double cyz = split ? 4.0 / 3.0 : 0.0;
+      a.aos_ww = 0.25;
+      a.aos_wv = 0.25;
       if (d == 0) {
         a.mode = MODE_AOS_FIRST;
         a.aos_w = c.nl ? 1 : 0;
@@ -1294,6 +1332,13 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
     double best = 1e300;
     LaunchShape best_shape = P.L.shape[d];
     int bc0 = 0, bc1 = 0;
+    // The built-in shape (timed like the others) is kept unless a candidate
+    // is faster by more than kMargin: the candidates are timed one direction
+    // at a time with every run in one launch, while the solve runs the two
+    // media concurrently, so near ties do not predict the solve.
+    constexpr double kMargin = 0.03;
+    const LaunchShape builtin = P.L.shape[d];
+    double builtin_ms = -1.0;
     std::vector<std::array<int, 3>> tried;
     for (int mt : {12, 16, 20}) {
       for (int pref : {64, 32, 16, 8}) {
@@ -1358,6 +1403,7 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
         NPB_HIP(hipEventSynchronize(e1));
         float t = 0.f;
         NPB_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (sh.M == builtin.M && sh.P == builtin.P && sh.LW == builtin.LW) builtin_ms = t / kReps;
         if (t / kReps < best) {
           best = t / kReps;
           best_shape = sh;
@@ -1365,6 +1411,12 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
           bc1 = pref;
         }
       }
+    }
+    if (builtin_ms > 0.0 && best > (1.0 - kMargin) * builtin_ms) {
+      best_shape = builtin;
+      best = builtin_ms;
+      bc0 = 0;  // the built-in choice (planner defaults)
+      bc1 = 0;
     }
     P.L.shape[d] = best_shape;
     choice[2 * d] = bc0;

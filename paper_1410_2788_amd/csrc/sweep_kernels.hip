@@ -233,6 +233,40 @@ __device__ __forceinline__ void cn_rhs_uniform(A (&d)[M], A re, A left, A right)
   }
 }
 
+// Crank-Nicolson explicit half applied to a line held in LDS, before the
+// sources are added (additive schemes, whose source stays outside the
+// explicit half: Eqs. (AOSCN1_2)-(AOSCN2_4); Sec. 3.3).  Node r of the line
+// sits at v[r * vs] with solute flag f[r * fs]; the lane's rows 1+g0 ..
+// g0+M that are interior become (1 + r delta^2) v, the face coefficient
+// chosen from the two flags as in the implicit rows (uniform medium: reu).
+// The new values are formed in registers and written after a block
+// barrier, so every lane reads the unchanged line; every thread of the
+// block must call this.
+template <typename A, int M>
+__device__ __forceinline__ void cn_tile_rows(A* v, int vs, const uint8_t* f, int fs, int g0,
+                                             int nint, bool valid, bool uniform, A re0, A re1,
+                                             A re2, A reu) {
+  A e[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int r = 1 + g0 + k;
+    e[k] = A(0);
+    if (valid && r <= nint) {
+      const A c = v[r * vs], l = v[(r - 1) * vs], rt = v[(r + 1) * vs];
+      const A fl = uniform ? reu : pick3((int)f[(r - 1) * fs] + (int)f[r * fs], re0, re1, re2);
+      const A fr = uniform ? reu : pick3((int)f[r * fs] + (int)f[(r + 1) * fs], re0, re1, re2);
+      e[k] = fma(fl, l - c, fma(fr, rt - c, c));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int r = 1 + g0 + k;
+    if (valid && r <= nint) v[r * vs] = e[k];
+  }
+  __syncthreads();
+}
+
 // Uniform chunks (every face coefficient equal to re, leak 1): the pivots,
 // couplings and reduced-row coefficients are the tabulated constants of
 // ChunkTab (computed by the same recurrences in FP64), so only the
@@ -570,6 +604,12 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     }
     __syncthreads();
   }
+  if (CN && a.cn == 2) {
+    const int ql = tid % L;
+    cn_tile_rows<A, M>(tile + ql * S, 1, mt + ql * nx4, 1, (tid / L) * M, nx - 2,
+                       l0 + ql < nlines, uniform, (A)a.re[0], (A)a.re[1], (A)a.re[2],
+                       (A)a.re_uniform);
+  }
   if (src) {
     // one entry per thread; entries are distinct nodes
     auto add_entry = [&](int lin, double rho) {
@@ -611,7 +651,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
-    if (CN && a.cn) cn_rhs_uniform<A, M>(d, tb.re[t], col[-1], col[M]);
+    if (CN && a.cn == 1) cn_rhs_uniform<A, M>(d, tb.re[t], col[-1], col[M]);
     if (first) d[0] = fma(tb.re[t], gL, d[0]);
     fast_eliminate<A, M>(d, tb, t, first, rf, rl);
   } else {
@@ -628,7 +668,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
       reF[k] = pick3(c, re0, re1, re2);
       prev = cur;
     }
-    if (CN && a.cn) cn_rhs<A, M>(d, reF, col[-1], col[M], kR, gR);
+    if (CN && a.cn == 1) cn_rhs<A, M>(d, reF, col[-1], col[M], kR, gR);
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
   }
@@ -643,15 +683,18 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl);
   else
     chunk_finish<A, M>(d, al, ga, xf, xl);
-  // results back into the row; a full chunk stores without per-row checks
+  // results back into the row; a full chunk stores without per-row checks.
+  // Additive modes: acc = ww W + wv V (the weights of the mean)
+  const A ww = (A)a.aos_ww, wv = (A)a.aos_wv;
   if (lvalid) {
     if (g0 + M <= nint) {
 #pragma unroll
-      for (int k = 0; k < M; ++k) col[k] = aos ? A(0.25) * (wtile[ql * S + 1 + g0 + k] + d[k]) : d[k];
+      for (int k = 0; k < M; ++k)
+        col[k] = aos ? fma(ww, wtile[ql * S + 1 + g0 + k], wv * d[k]) : d[k];
     } else {
 #pragma unroll
       for (int k = 0; k < M; ++k)
-        if (g0 + k < nint) col[k] = aos ? A(0.25) * (wtile[ql * S + 1 + g0 + k] + d[k]) : d[k];
+        if (g0 + k < nint) col[k] = aos ? fma(ww, wtile[ql * S + 1 + g0 + k], wv * d[k]) : d[k];
     }
   }
   __syncthreads();
@@ -732,7 +775,8 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
-    if (VAR == kYzGeneral && a.cn) cn_rhs_uniform<A, M>(d, tb.re[t], col[-ts], col[M * ts]);
+    if (VAR == kYzGeneral && a.cn == 1)
+      cn_rhs_uniform<A, M>(d, tb.re[t], col[-ts], col[M * ts]);
     if (first) d[0] = fma(tb.re[t], gL, d[0]);
     fast_eliminate<A, M>(d, tb, t, first, rf, rl);
   } else {
@@ -749,7 +793,7 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
       reF[k] = pick3(c, re0, re1, re2);
       prev = cur;
     }
-    if (VAR == kYzGeneral && a.cn) cn_rhs<A, M>(d, reF, col[-ts], col[M * ts], kR, gR);
+    if (VAR == kYzGeneral && a.cn == 1) cn_rhs<A, M>(d, reF, col[-ts], col[M * ts], kR, gR);
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
     chunk_eliminate<A, M>(d, al, ga, rf, rl, reF, first, kR, gR);
   }
@@ -908,6 +952,26 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
     if (e_lin >= 0) add_entry(e_lin, e_rho);
     for (int e = sb + tid + nthreads; e < se; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
   };
+  // general variant: the leading nonlinear sub-step on the input (Sec. 3.3)
+  // and the Crank-Nicolson explicit half before the sources (additive schemes)
+  if (VAR == kYzGeneral && (a.pre_nl || a.cn == 2)) {
+    const int ql = tid % TW;
+    const int g0 = (tid / TW) * M;
+    const int x = xb + ql;
+    const bool lv = x >= 1 && x <= nx - 2;
+    if (a.pre_nl && !uniform && lv) {
+      const A ka = (A)a.pre_ka, kb = (A)a.pre_kb;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const int r = 1 + g0 + k;
+        if (r <= nint && mt[r * TW + ql] == 0) tile[r * TS + ql] = sinh_flow(tile[r * TS + ql], ka, kb);
+      }
+    }
+    __syncthreads();
+    if (a.cn == 2)
+      cn_tile_rows<A, M>(tile + ql, TS, mt + ql, TW, g0, nint, lv, uniform, (A)a.re[0],
+                         (A)a.re[1], (A)a.re[2], (A)a.re_uniform);
+  }
   if (VAR == kYzGeneral && a.src_stage == 1) {
     add_sources();
     __syncthreads();
@@ -937,7 +1001,7 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
           const A tv = tile[j * TS + cv * VX + i];
           const bool live = xi >= 1 && xi <= nx - 2;
           if (live)
-            w[i] = (T)((A)acc[i] + A(0.25) * tv);
+            w[i] = (T)((A)acc[i] + (A)a.aos_wv * tv);
           else
             w[i] = (mode == MODE_AOS_ADD) ? acc[i] : (T)tv;
         }
@@ -971,7 +1035,9 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, in
   const int es = fp64 ? 8 : 4;
   const int nx4 = row4(nx);
   if (mt <= 0) mt = 20;
-  if (lw <= 0) lw = 32;
+  // default lines per block: 16 for FP32 arithmetic (measured best for the
+  // 161^3 solve, whose two media sweep concurrently), 32 for FP64
+  if (lw <= 0) lw = fp64 ? 32 : 16;
   int P = next_pow2((nint + mt - 1) / mt);
   int M = pick_chunk((nint + P - 1) / P);
   if (M < 0 || P > 32) return s;  // unsupported length

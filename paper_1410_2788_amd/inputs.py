@@ -64,7 +64,8 @@ class RunParams:
     alpha: float
     dt: float
     n_steps: int
-    scheme: str = "LODIE2"      # LODIE2 | LODIE1 | AOSIE2 | AOSIE1 | LODCN1 | LODCN2
+    scheme: str = "LODIE2"      # LODIE2 | LODIE1 | AOSIE2 | AOSIE1 | LODCN1 | LODCN2 |
+                                # AOSCN1 | AOSCN2 | MAOSIE | MAOSCN
     richardson: bool = False
     vacuum: bool = True
     precision: str = "f64"      # f64 | f32 (GPU sweeps; the oracle is FP64)

@@ -21,7 +21,8 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "npb.h")
 NPB_OK, NPB_EINVAL, NPB_ERANGE, NPB_ENOMEM, NPB_EDEVICE, NPB_EDIVERGED, NPB_EBUSY = range(7)
 STATUS_NAMES = {0: "NPB_OK", 1: "NPB_EINVAL", 2: "NPB_ERANGE", 3: "NPB_ENOMEM",
                 4: "NPB_EDEVICE", 5: "NPB_EDIVERGED", 6: "NPB_EBUSY"}
-SCHEMES = {"LODIE2": 0, "LODIE1": 1, "AOSIE2": 2, "AOSIE1": 3, "LODCN1": 4, "LODCN2": 5}
+SCHEMES = {"LODIE2": 0, "LODIE1": 1, "AOSIE2": 2, "AOSIE1": 3, "LODCN1": 4, "LODCN2": 5,
+           "AOSCN1": 6, "AOSCN2": 7, "MAOSIE": 8, "MAOSCN": 9}
 PRECISIONS = {"f64": 0, "f32": 1, "f32x": 2}
 KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other", "direct"]
 # sweep launches split again by the kernel that ran them (npb_sweep_kernel)

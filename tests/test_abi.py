@@ -50,7 +50,7 @@ def test_validate_accepts_a_good_problem(npb):
 @pytest.mark.parametrize("field,value", [
     ("nx", 4), ("h", 0.0), ("h", -1.0), ("eps_in", 0.0), ("eps_out", -2.0),
     ("kappa_bar_sq", -1e-3), ("alpha", 0.0), ("dt", 0.0), ("n_steps", 0),
-    ("scheme", 7), ("precision", 5), ("field_select", 1)])
+    ("scheme", 10), ("precision", 5), ("field_select", 1)])
 def test_validate_rejects_bad_arguments(npb, field, value):
     w = inputs.small_globular(n=25, n_atoms=10)
     w.params.vacuum = field != "field_select"

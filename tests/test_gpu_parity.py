@@ -93,14 +93,15 @@ def test_born_sphere_fp64():
     assert g["steps_done"] == 200
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2",
+                                    "AOSCN1", "AOSCN2", "MAOSIE", "MAOSCN"])
 def test_small_globular_fp64_all_schemes(scheme):
     w = inputs.small_globular(scheme=scheme, n=41, n_atoms=120, n_steps=5)
     g, o, errs, fe = _compare(w)
     _assert_f64(errs, fe)
 
 
-@pytest.mark.parametrize("scheme", ["LODIE2", "AOSIE2", "LODCN2"])
+@pytest.mark.parametrize("scheme", ["LODIE2", "AOSIE2", "LODCN2", "AOSCN2", "MAOSIE"])
 def test_small_globular_fp32(scheme):
     w = inputs.small_globular(scheme=scheme, n=41, n_atoms=120, n_steps=5, precision="f32")
     g, o, errs, fe = _compare(w)
@@ -114,7 +115,7 @@ def test_ragged_noncubic_grid_fp64_vacuum_field():
     _assert_f64(errs, fe)
 
 
-@pytest.mark.parametrize("scheme", ["LODCN1", "LODCN2"])
+@pytest.mark.parametrize("scheme", ["LODCN1", "LODCN2", "AOSCN1", "AOSCN2", "MAOSCN", "MAOSIE"])
 def test_crank_nicolson_ragged_grid_fp64(scheme):
     # the explicit half at chunk ends, line ends and ragged tails on every
     # axis, and large steps (stiff modes flip sign under Crank-Nicolson)
