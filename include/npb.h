@@ -160,8 +160,10 @@ typedef struct npb_result {
 typedef struct npb_ctx npb_ctx;
 
 /* Per-kernel timing gathered while timing is enabled (npb_ctx_set_timing):
- * launches, summed device milliseconds and algorithmic bytes, measured with
- * HIP events recorded around each launch on the stream it runs on.
+ * launches, summed device milliseconds and algorithmic bytes.  Sweep
+ * launches carry HIP events that record the kernel's own start and stop
+ * (hipExtLaunchKernelGGL); other launches are bracketed by HIP events
+ * recorded on the stream they run on.
  * count/ms/bytes are indexed by npb_kernel_class (the sweeps by direction);
  * kcount/kms/kbytes split the sweep launches again by the kernel that ran
  * them, indexed by npb_sweep_kernel. */

@@ -170,6 +170,10 @@ int sweep_cn(const SweepArgs<T>* a, int n);       // 1 if any field is Crank-Nic
 template <typename T, typename A>
 hipError_t launch_sweep_x(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                           int cn, const LaunchShape& s, hipStream_t st);
+// Per-kernel timing of the sweeps: while (start, stop) are set (non-null),
+// sweep launches from this host thread record their kernel's own start and
+// stop in them.  Cleared by passing nullptrs.
+void set_sweep_launch_events(hipEvent_t start, hipEvent_t stop);
 template <typename T, typename A>
 hipError_t launch_sweep_yz(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                            int dir, int var, const LaunchShape& s, hipStream_t st);

@@ -657,6 +657,9 @@ struct Engine {
   npb_status timed(int cls, double bytes, F&& f) {
     return timed_on(st, cls, -1, bytes, f);
   }
+  // Timing: a sweep launch (sk >= 0) records its kernel's own start and
+  // stop in the events (the launcher's hipExtLaunchKernelGGL path); other
+  // launches are bracketed by events recorded on the stream.
   template <typename F>
   npb_status timed_on(hipStream_t s, int cls, int sk, double bytes, F&& f) {
     hipEvent_t a = nullptr, b = nullptr;
@@ -664,12 +667,16 @@ struct Engine {
       a = ev_get(ctx);
       b = ev_get(ctx);
       if (!a || !b) return fail(NPB_EDEVICE, "event creation failed");
-      NPB_HIP(hipEventRecord(a, s));
+      if (sk >= 0)
+        set_sweep_launch_events(a, b);
+      else
+        NPB_HIP(hipEventRecord(a, s));
     }
     hipError_t e = f();
+    if (ctx->timing && sk >= 0) set_sweep_launch_events(nullptr, nullptr);
     if (e != hipSuccess) return fail(NPB_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
     if (ctx->timing) {
-      NPB_HIP(hipEventRecord(b, s));
+      if (sk < 0) NPB_HIP(hipEventRecord(b, s));
       ctx->pending.push_back({cls, sk, a, b, bytes});
     }
     return NPB_OK;

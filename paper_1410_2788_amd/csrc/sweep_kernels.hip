@@ -29,6 +29,8 @@
 // registers or LDS, so they add no HBM traffic beyond the accumulator.
 //
 // T is the storage type of the field, A the arithmetic type of the solve.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "npb_internal.h"
@@ -1186,6 +1188,16 @@ int sweep_cn(const SweepArgs<T>* a, int n) {
 template int sweep_cn<float>(const SweepArgs<float>*, int);
 template int sweep_cn<double>(const SweepArgs<double>*, int);
 
+// Per-kernel timing: when set, the next sweep launches record the kernel's
+// own start and stop in these events (hipExtLaunchKernelGGL), so the
+// elapsed time excludes the dispatch of the launch.  Per host thread.
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+void set_sweep_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+
 // Dynamic LDS above 64 KB (up to the 160 KB of a CU) must be allowed per
 // kernel before the launch.
 template <typename K>
@@ -1206,8 +1218,12 @@ static hipError_t launch_x_l(const SweepArgs<T>* args, const int2* work, int nbu
   case MM: {                                                                           \
     hipError_t e = allow_lds(sweep_x_kernel<T, A, MM, L, CN>, s.lds);                  \
     if (e != hipSuccess) return e;                                                     \
-    hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L, CN>), g, blk, s.lds, st, args, work, \
-                       nbu);                                                           \
+    if (t_ev_start)                                                                    \
+      hipExtLaunchKernelGGL((sweep_x_kernel<T, A, MM, L, CN>), g, blk, (uint32_t)s.lds, st, \
+                            t_ev_start, t_ev_stop, 0u, args, work, nbu);               \
+    else                                                                               \
+      hipLaunchKernelGGL((sweep_x_kernel<T, A, MM, L, CN>), g, blk, s.lds, st, args, work, \
+                         nbu);                                                         \
   } break;
     NPB_X_CASE(4)
     NPB_X_CASE(8)
@@ -1249,8 +1265,12 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
   case MM: {                                                                                \
     hipError_t e = allow_lds(sweep_yz_kernel<T, A, MM, VAR, TW>, s.lds);                    \
     if (e != hipSuccess) return e;                                                          \
-    hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, args, work, \
-                       nbu, dir);                                                           \
+    if (t_ev_start)                                                                         \
+      hipExtLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, (uint32_t)s.lds,  \
+                            st, t_ev_start, t_ev_stop, 0u, args, work, nbu, dir);           \
+    else                                                                                    \
+      hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, args,     \
+                         work, nbu, dir);                                                   \
   } break;
     NPB_YZ_CASE(4)
     NPB_YZ_CASE(8)
@@ -1262,8 +1282,12 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
       if constexpr (sizeof(A) == 4) {
         hipError_t e = allow_lds(sweep_yz_kernel<T, A, 20, VAR, TW>, s.lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, args, work,
-                           nbu, dir);
+        if (t_ev_start)
+          hipExtLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, (uint32_t)s.lds,
+                                st, t_ev_start, t_ev_stop, 0u, args, work, nbu, dir);
+        else
+          hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, args,
+                             work, nbu, dir);
         break;
       }
       return hipErrorInvalidValue;
