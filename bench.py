@@ -493,8 +493,9 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": _traffic(full, args.precision),
                 "kernel": full, "avg_launch_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": bpl,
-                "timing": "HIP events around each launch of the timing pass; the two "
-                          "media's launches issued one after another on one stream",
+                "timing": "timing pass: every sweep launch carries HIP events that record the "
+                          "kernel's own start and stop (hipExtLaunchKernelGGL); the two media's "
+                          "launches issued one after another on one stream",
                 "per_kernel": {k: {"launches": bk[k]["count"],
                                    "avg_us": round(bk[k]["ms"] / max(bk[k]["count"], 1) * 1e3, 2),
                                    "GBps": round(bk[k]["bytes"] / max(bk[k]["ms"], 1e-12) / 1e6, 1)}
