@@ -283,6 +283,35 @@ npb_status npb_autotune(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* g
 npb_status npb_launch_shapes(const npb_ctx* ctx, const npb_grid* grid, const npb_params* params,
                              int32_t* out);
 
+/* ---- caller-given fields -------------------------------------------------
+ * The analytic benchmark of Sec. 4.1-4.2 (a charged spherical cavity with a
+ * known solution) is posed by fields rather than by a molecule: a dense
+ * source and an initial field whose outer shell carries the Dirichlet data
+ * (Eqs. (NPB_analytical_1), (NPB_analytical_2), (InitSolutions)).
+ *   solute  : the balls that form the solute region (eps_in, kbar = 0
+ *             inside); the charges are ignored; positions and radii as in
+ *             npb_solve
+ *   params  : as in npb_solve, with vacuum = vacuum_direct = field_select
+ *             = 0; richardson may be 1; temperature_K only scales the
+ *             reported energies
+ *   d_u0    : device, nx*ny*nz doubles [nz][ny][nx]: the dimensionless
+ *             initial field; its outer shell is the Dirichlet data
+ *   d_rho   : device, nx*ny*nz doubles: the dimensionless source rho of
+ *             alpha u_t = div(eps grad u) - kbar^2 sinh(u) + rho on the
+ *             interior nodes (shell entries are not read)
+ *   d_ws    : at least npb_fields_workspace_bytes (one source entry per
+ *             interior node)
+ *   d_u_out : NULL, or nx*ny*nz doubles receiving the dimensionless u
+ *             after n_steps (Richardson-combined when richardson = 1)
+ * out: steps and timings as in npb_solve; G_m is (1/2) kT sum rho u over
+ * the interior, dG NaN.  Errors as npb_solve, and EINVAL for a null field. */
+npb_status npb_fields_workspace_bytes(const npb_molecule* solute, const npb_grid* grid,
+                                      const npb_params* params, size_t* bytes);
+npb_status npb_solve_fields(npb_ctx* ctx, const npb_molecule* solute, const npb_grid* grid,
+                            const npb_params* params, const double* d_u0, const double* d_rho,
+                            void* d_ws, size_t ws_bytes, double* d_u_out, void* stream,
+                            npb_result* out);
+
 /* ---- request loop (serving) ----------------------------------------------
  * A server solves molecules as they arrive.  It owns a device arena of
  * hbm_budget bytes and one worker thread with its own context and stream.

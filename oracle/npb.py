@@ -340,6 +340,19 @@ def make_problem(mol, grid, params, medium: str = "solvated") -> Problem:
     return Problem(grid, eps_node, kbar2_node, Q, rho, u0, interior, T)
 
 
+def problem_from_fields(grid, solute, eps_in: float, eps_out: float, kbar2: float,
+                        rho: np.ndarray, u0: np.ndarray, T: float = 298.0) -> Problem:
+    """A problem posed by fields (the analytic benchmark of Sec. 4.1): the
+    solute balls set eps and kbar^2 as in make_problem, rho is the given
+    dense source and u0 the given initial field, whose shell is the
+    Dirichlet data.  Q is zero (no energies)."""
+    M = solute_mask(grid, solute.xyz, solute.radius)
+    interior = ~boundary_shell(grid)
+    return Problem(grid, np.where(M, eps_in, eps_out), np.where(M, 0.0, kbar2),
+                   np.zeros(shape_zyx(grid)), np.where(interior, rho, 0.0), u0.copy(), interior,
+                   T)
+
+
 def lod_step(u, pb: Problem, dt: float, alpha: float, order: str = "LODIE2"):
     """One LOD step.  LODIE1: N, X, Y, Z, S (Eqs. (LODIE1_1)-(LODIE1_5));
     LODIE2: S, X, Y, Z, N (Sec. 3.1, last paragraph); LODCN1 / LODCN2: the

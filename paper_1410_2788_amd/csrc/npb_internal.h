@@ -216,6 +216,13 @@ hipError_t launch_gather_entries(const int* id, const int* nq_dev, int cap, cons
 hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, double eps_v,
                            double lB, double* bc_s, double* bc_v, bool fp32_terms,
                            hipStream_t st);
+// caller-given fields (npb_solve_fields): one source-list entry per
+// interior node (key = pitched index, value = rho of the dense array), and
+// the shell values of a dense field in shell order
+hipError_t launch_dense_source(const double* rho, int nx, int nxp, int ny, int nz, int* key,
+                               int* id, double* val, hipStream_t st);
+hipError_t launch_shell_from_dense(const double* u0, int nx, int ny, int nz, double* bc,
+                                   hipStream_t st);
 // chunk classes of direction dir (0 = x, 1 = y, 2 = z) for chunks of M rows,
 // P per line; out[p * class_lines + line]
 hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
@@ -227,6 +234,10 @@ hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int nxp, int ny, in
 template <typename T>
 hipError_t launch_field_init(T* u, const double* bc, int nx, int nxp, int ny, int nz,
                              hipStream_t st);
+// pitched u = dense [nz][ny][nx] array (padding columns zero)
+template <typename T>
+hipError_t launch_field_from_dense(T* u, const double* src, int nx, int nxp, int ny, int nz,
+                                   hipStream_t st);
 template <typename T>
 hipError_t launch_energy(const T* u, const int* q_idx, const double* q_val, const int* nq_dev,
                          int cap, double* slot, hipStream_t st);

@@ -185,6 +185,28 @@ hipError_t launch_field_init(T* u, const double* bc, int nx, int nxp, int ny, in
   return hipGetLastError();
 }
 
+// pitched u = dense [nz][ny][nx] array, padding columns zero
+template <typename T>
+__global__ void field_from_dense_kernel(T* u, const double* src, int nx, int nxp, int ny, int nz) {
+  const long long n = (long long)nxp * ny * nz;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p % nxp);
+    const long long row = p / nxp;
+    u[p] = i < nx ? (T)src[row * nx + i] : T(0);
+  }
+}
+
+template <typename T>
+hipError_t launch_field_from_dense(T* u, const double* src, int nx, int nxp, int ny, int nz,
+                                   hipStream_t st) {
+  long long blocks = ((long long)nxp * ny * nz + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL((field_from_dense_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, u,
+                     src, nx, nxp, ny, nz);
+  return hipGetLastError();
+}
+
 // S = sum_k q_k u[idx_k] in double, fixed order (one block, tree reduction)
 template <typename T>
 __global__ __launch_bounds__(1024) void energy_kernel(const T* u, const int* q_idx,
@@ -282,6 +304,8 @@ template hipError_t launch_field_init<double>(double*, const double*, int, int, 
 struct GraphKey {
   void* ws;
   double* field_out;
+  const double* fu0;   // caller-given fields (npb_solve_fields), else null
+  const double* frho;
   npb_grid grid;
   npb_params params;
   int n_atoms;
@@ -430,12 +454,14 @@ double sweep_tau_factor(int scheme) {
   }
 }
 
-Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params* p) {
+// fields: the source list holds every interior node (npb_solve_fields)
+Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params* p,
+                   bool fields = false) {
   Layout L{};
   const size_t es = p->precision == NPB_FP64 ? 8 : 4;
   const size_t n = (size_t)pitch_of(g->nx, (int)es) * g->ny * g->nz;  // pitched node count
   const int na = mol->n_atoms;
-  const int cap = 8 * na;
+  const int cap = fields ? (g->nx - 2) * (g->ny - 2) * (g->nz - 2) : 8 * na;
   const int nb = (cap + 255) / 256;
   const size_t ns = (size_t)shell_count(g->nx, g->ny, g->nz);
   const bool aos = is_aos(p->scheme);
@@ -583,6 +609,10 @@ struct Problem {
   const npb_params* p;
   unsigned char* ws;
   double* fout;
+  // caller-given fields (npb_solve_fields): initial field with its shell as
+  // Dirichlet data, and a dense source; null for a molecule's problem
+  const double* fu0 = nullptr;
+  const double* frho = nullptr;
   Layout L;
   SetupArgs sa;
   double kT, lB;
@@ -593,6 +623,7 @@ struct Problem {
     return reinterpret_cast<Ptr*>(ws + off);
   }
   bool aos() const { return is_aos(p->scheme); }
+  bool fields() const { return fu0 != nullptr; }
 };
 
 // coefficients of one run (Sec. 3: tau = dt / alpha; AOS sub-steps take
@@ -944,13 +975,19 @@ struct Engine {
       if (e != hipSuccess) return e;
       e = launch_mask_raster(sa, P.at<uint8_t>(L.mask), st);
       if (e != hipSuccess) return e;
-      e = launch_stencil(sa, P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<double>(L.sval),
-                         ints + 1, st);
+      if (P.fields())
+        e = launch_dense_source(P.frho, nx, nxp, ny, nz, P.at<int>(L.key_a), P.at<int>(L.id_a),
+                                P.at<double>(L.sval), st);
+      else
+        e = launch_stencil(sa, P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<double>(L.sval),
+                           ints + 1, st);
       if (e != hipSuccess) return e;
       e = radix_sort_pairs(P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<int>(L.key_b),
                            P.at<int>(L.id_b), P.at<int>(L.hist), L.cap, (long long)n, st);
       if (e != hipSuccess) return e;
-      const double pref = 4.0 * M_PI * P.lB / (P.g->h * P.g->h * P.g->h);
+      // Eq. (RhoEq): rho = 4 pi l_B Q / h^3 of the trilinear charges; a
+      // caller-given source is rho itself
+      const double pref = P.fields() ? 1.0 : 4.0 * M_PI * P.lB / (P.g->h * P.g->h * P.g->h);
       e = launch_merge_charges(P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<double>(L.sval),
                                P.at<int>(L.heads), L.cap, ints, P.at<int>(L.q_idx),
                                P.at<double>(L.q_val), P.at<double>(L.q_rho), pref, st);
@@ -987,9 +1024,13 @@ struct Engine {
         e = launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.zptr), (size_t)ny * nx + 1, 0u, st);
         if (e != hipSuccess) return e;
       }
-      const double kappa = std::sqrt(p->kappa_bar_sq / p->eps_out);
-      e = launch_boundary(sa, p->eps_out, kappa, p->eps_in, P.lB, P.at<double>(L.bc_s),
-                          p->vacuum ? P.at<double>(L.bc_v) : nullptr, sizeof(A) == 4, st);
+      if (P.fields()) {
+        e = launch_shell_from_dense(P.fu0, nx, ny, nz, P.at<double>(L.bc_s), st);
+      } else {
+        const double kappa = std::sqrt(p->kappa_bar_sq / p->eps_out);
+        e = launch_boundary(sa, p->eps_out, kappa, p->eps_in, P.lB, P.at<double>(L.bc_s),
+                            p->vacuum ? P.at<double>(L.bc_v) : nullptr, sizeof(A) == 4, st);
+      }
       if (e != hipSuccess) return e;
       for (int d = 0; d < 3 && e == hipSuccess; ++d)
         e = launch_chunk_classes(P.at<uint8_t>(L.mask), nx, nxp, ny, nz, d, L.shape[d].M,
@@ -1008,7 +1049,11 @@ struct Engine {
         set.bc[r] = P.at<double>(P.L.runs[r].medium == 1 ? P.L.bc_v : P.L.bc_s);
       }
       npb_status s = timed(NPB_K_INIT, (double)nxp * ny * nz * sizeof(T) * P.L.n_runs, [&] {
-        return launch_field_init_multi<T>(set, P.L.n_runs, nx, nxp, ny, nz, st);
+        if (!P.fields()) return launch_field_init_multi<T>(set, P.L.n_runs, nx, nxp, ny, nz, st);
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < P.L.n_runs && e == hipSuccess; ++r)
+          e = launch_field_from_dense<T>(set.u[r], P.fu0, nx, nxp, ny, nz, st);
+        return e;
       });
       if (s != NPB_OK) return s;
     }
@@ -1151,7 +1196,9 @@ struct Engine {
             int r = 0;
             while (!(L.runs[r].medium == medium && L.runs[r].level == l)) ++r;
             const double beta = first ? 0.0 : 1.0;
-            const double gamma = sign * (p->richardson ? (l == 0 ? -P.kT : 2.0 * P.kT) : P.kT);
+            // caller-given fields: the dimensionless u itself
+            const double scale = P.fields() ? 1.0 : P.kT;
+            const double gamma = sign * (p->richardson ? (l == 0 ? -scale : 2.0 * scale) : scale);
             s = timed(NPB_K_OTHER, 0, [&] {
               return launch_field_out<T>(P.fout, P.at<T>(L.field[r]), P.g->nx,
                                          pitch_of(P.g->nx, (int)sizeof(T)), P.g->ny, P.g->nz,
@@ -1189,6 +1236,8 @@ struct Engine {
       std::memset(&g, 0, sizeof(g));
       g.ws = pr[i].ws;
       g.field_out = pr[i].fout;
+      g.fu0 = pr[i].fu0;
+      g.frho = pr[i].frho;
       g.grid = *pr[i].g;
       g.params = *pr[i].p;
       g.n_atoms = pr[i].mol->n_atoms;
@@ -1539,6 +1588,40 @@ npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
   return NPB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// the device work of checked problems (one precision)
+npb_status run_problems(npb_ctx* ctx, std::vector<Problem>& pr, void* stream, npb_result* out) {
+  // every argument checked: only now is the context read
+  for (Problem& P : pr) apply_tuning(ctx, P.g, P.p, P.L);
+  NPB_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int precision = pr[0].p->precision;
+  try {
+    if (precision == NPB_FP64) return solve_batch_t<double, double>(ctx, pr, st, out);
+    if (precision == NPB_FP32X) return solve_batch_t<float, double>(ctx, pr, st, out);
+    return solve_batch_t<float, float>(ctx, pr, st, out);
+  } catch (const std::exception& e) {
+    return fail(NPB_ENOMEM, e.what());
+  } catch (...) {
+    return fail(NPB_EDEVICE, "unexpected failure");
+  }
+}
+
+// npb_solve_fields runs one field: no vacuum problem, no direct solve, the
+// solvated field out
+npb_status validate_fields(const npb_params* p) {
+  if (p->vacuum || p->vacuum_direct || p->field_select != 0)
+    return fail(NPB_EINVAL, "caller-given fields need vacuum = vacuum_direct = field_select = 0");
+  return NPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols, const npb_grid* grids,
                            const npb_params* params, void* const* d_ws, const size_t* ws_bytes,
                            double* const* d_field_out, void* stream, npb_result* out) {
@@ -1571,19 +1654,47 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols, const 
         return fail(NPB_EINVAL, "problem " + std::to_string(i) + ": workspace shared with problem " +
                                     std::to_string(j));
   }
-  // every argument checked: only now is the context read
-  for (Problem& P : pr) apply_tuning(ctx, P.g, P.p, P.L);
-  NPB_HIP(hipSetDevice(ctx->device));
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  try {
-    if (params[0].precision == NPB_FP64) return solve_batch_t<double, double>(ctx, pr, st, out);
-    if (params[0].precision == NPB_FP32X) return solve_batch_t<float, double>(ctx, pr, st, out);
-    return solve_batch_t<float, float>(ctx, pr, st, out);
-  } catch (const std::exception& e) {
-    return fail(NPB_ENOMEM, e.what());
-  } catch (...) {
-    return fail(NPB_EDEVICE, "unexpected failure");
-  }
+  return run_problems(ctx, pr, stream, out);
+}
+
+npb_status npb_fields_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
+                                      const npb_params* params, size_t* bytes) {
+  if (!bytes) return fail(NPB_EINVAL, "null output pointer");
+  npb_status s = validate(mol, grid, params);
+  if (s != NPB_OK) return s;
+  s = validate_fields(params);
+  if (s != NPB_OK) return s;
+  *bytes = make_layout(mol, grid, params, true).total;
+  return NPB_OK;
+}
+
+npb_status npb_solve_fields(npb_ctx* ctx, const npb_molecule* solute, const npb_grid* grid,
+                            const npb_params* params, const double* d_u0, const double* d_rho,
+                            void* d_ws, size_t ws_bytes, double* d_u_out, void* stream,
+                            npb_result* out) {
+  if (!ctx || !out) return fail(NPB_EINVAL, "null context or result");
+  if (!solute || !grid || !params || !d_u0 || !d_rho) return fail(NPB_EINVAL, "null argument");
+  npb_status s = validate(solute, grid, params);
+  if (s != NPB_OK) return s;
+  s = validate_fields(params);
+  if (s != NPB_OK) return s;
+  std::vector<Problem> pr(1);
+  Problem& P = pr[0];
+  P.mol = solute;
+  P.g = grid;
+  P.p = params;
+  P.ws = reinterpret_cast<unsigned char*>(d_ws);
+  P.fout = d_u_out;
+  P.fu0 = d_u0;
+  P.frho = d_rho;
+  P.L = make_layout(solute, grid, params, true);
+  P.kT = thermal_energy(params->temperature_K);
+  P.lB = bjerrum(params->temperature_K);
+  if (!P.ws || ws_bytes < P.L.total)
+    return fail(NPB_EINVAL, "workspace missing or smaller than npb_fields_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(P.ws) % 256 != 0)
+    return fail(NPB_EINVAL, "workspace must be 256-byte aligned");
+  return run_problems(ctx, pr, stream, out);
 }
 
 npb_status npb_autotune(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,

@@ -124,6 +124,34 @@ hipError_t launch_stencil(const SetupArgs& a, int* key, int* id, double* val, in
   return hipGetLastError();
 }
 
+// Caller-given dense source (npb_solve_fields): one list entry per interior
+// node, in node order, key = pitched linear index, value = rho.
+__global__ void dense_source_kernel(const double* rho, int nx, int nxp, int ny, int nz, int* key,
+                                    int* id, double* val) {
+  const int X = nx - 2, Y = ny - 2;
+  const long long n = (long long)X * Y * (nz - 2);
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int i = 1 + (int)(c % X);
+    const long long t = c / X;
+    const int j = 1 + (int)(t % Y);
+    const int k = 1 + (int)(t / Y);
+    key[c] = (k * ny + j) * nxp + i;
+    id[c] = (int)c;
+    val[c] = rho[((long long)k * ny + j) * nx + i];
+  }
+}
+
+hipError_t launch_dense_source(const double* rho, int nx, int nxp, int ny, int nz, int* key,
+                               int* id, double* val, hipStream_t st) {
+  const long long n = (long long)(nx - 2) * (ny - 2) * (nz - 2);
+  long long blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(dense_source_kernel, dim3((unsigned)blocks), dim3(256), 0, st, rho, nx, nxp,
+                     ny, nz, key, id, val);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // stable LSD radix sort, 8-bit digits, 256 items per block
 
@@ -545,6 +573,28 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
                        dim3(kBcNodes * kBcSlices), 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
   else
     hipLaunchKernelGGL(boundary_kernel<double>, g, b, 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
+  return hipGetLastError();
+}
+
+// Dirichlet data of a caller-given field (npb_solve_fields): the shell
+// values of the dense [nz][ny][nx] array, in shell order
+__global__ void shell_from_dense_kernel(const double* u0, int nx, int ny, int nz, long long ns,
+                                        double* bc) {
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < ns;
+       s += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    shell_node(s, nx, ny, nz, i, j, k);
+    bc[s] = u0[((long long)k * ny + j) * nx + i];
+  }
+}
+
+hipError_t launch_shell_from_dense(const double* u0, int nx, int ny, int nz, double* bc,
+                                   hipStream_t st) {
+  const long long ns = shell_count(nx, ny, nz);
+  long long blocks = (ns + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(shell_from_dense_kernel, dim3((unsigned)blocks), dim3(256), 0, st, u0, nx, ny,
+                     nz, ns, bc);
   return hipGetLastError();
 }
 

@@ -229,3 +229,71 @@ def poisson_arrivals(rate_per_s: float, n_req: int, seed: int = 4) -> np.ndarray
     """Arrival times (s) of a Poisson stream."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate_per_s, n_req))
+
+
+# --------------------------------------------------------------------------
+# the analytic benchmark: a charged spherical cavity (Sec. 4.1)
+
+@dataclass
+class SphereBenchmark:
+    """Fields of the charged-cavity benchmark on [-L, L]^3 (dimensionless).
+
+    exact  : Eq. (NPB_analytical_1), 1/(eps R) - 1/R + 1/r inside the ball
+             of radius R, 1/(eps r) outside, eps = eps_out / eps_in
+    rho    : Eq. (NPB_analytical_2): kbar^2 sinh(1/(eps r)) outside the ball,
+             and the centred charge 4 pi eps_in delta as 4 pi eps_in / h^3 on
+             the centre node (a node-centred trilinear spread); zero on the
+             ball's surface nodes (they count as solute, where kbar = 0) and
+             on the outer shell
+    u0     : Eq. (InitSolutions), H cos(pi x/6) cos(pi y/6) cos(pi z/6) +
+             1/(eps r); the singular term is dropped at the centre node.  Its
+             outer shell equals the exact solution (the Dirichlet data).
+    valid  : nodes entering the error norms: all but the singular centre"""
+    grid: Grid
+    solute: Molecule
+    u0: np.ndarray
+    rho: np.ndarray
+    exact: np.ndarray
+    valid: np.ndarray
+    eps_in: float
+    eps_out: float
+    kbar_sq: float
+    radius: float
+    H: float
+
+
+def sphere_benchmark(h: float, H: float = 1.0, radius: float = 1.0, eps_in: float = 1.0,
+                     eps_out: float = 80.0, kbar_sq: float = 1.0, half_width: float = 3.0
+                     ) -> SphereBenchmark:
+    """Sec. 4.1: R = 1 Angstrom, eps_in = 1, eps_out = 80, kbar = 1 on the
+    cube [-3, 3]^3 with spacing h (h must divide 3)."""
+    n = int(round(2.0 * half_width / h)) + 1
+    if abs((n - 1) * h - 2.0 * half_width) > 1e-12:
+        raise ValueError("h must divide the box width")
+    grid = cubic_grid(n, h)
+    ax = grid.origin[0] + np.arange(n) * h
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    c = n // 2
+    eps = eps_out / eps_in
+    rs = r.copy()
+    rs[c, c, c] = 1.0  # placeholder at the singular node
+    exact = np.where(r < radius, 1.0 / (eps * radius) - 1.0 / radius + 1.0 / rs, 1.0 / (eps * rs))
+    exact[c, c, c] = 0.0
+    valid = np.ones(r.shape, dtype=bool)
+    valid[c, c, c] = False
+    # solute: nodes with r^2 <= R^2 (on the surface included)
+    solvent = (X * X + Y * Y) + Z * Z > radius * radius
+    rho = np.where(solvent, kbar_sq * np.sinh(1.0 / (eps * rs)), 0.0)
+    rho[c, c, c] = 4.0 * math.pi * eps_in / h ** 3
+    shell = np.zeros(r.shape, dtype=bool)
+    shell[0, :, :] = shell[-1, :, :] = shell[:, 0, :] = shell[:, -1, :] = True
+    shell[:, :, 0] = shell[:, :, -1] = True
+    rho[shell] = 0.0
+    u0 = H * np.cos(math.pi * X / 6.0) * np.cos(math.pi * Y / 6.0) * np.cos(math.pi * Z / 6.0) \
+        + 1.0 / (eps * rs)
+    u0[c, c, c] = H
+    u0[shell] = exact[shell]
+    solute = Molecule(xyz=np.zeros((1, 3)), q=np.zeros(1), radius=np.array([radius]))
+    return SphereBenchmark(grid, solute, u0, rho, exact, valid, eps_in, eps_out, kbar_sq, radius,
+                           H)

@@ -137,6 +137,13 @@ def load_library(path: str = LIB_PATH):
         lib.npb_solve.restype = C.c_int
         lib.npb_solve.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, P(npb_result)]
+        lib.npb_fields_workspace_bytes.restype = C.c_int
+        lib.npb_fields_workspace_bytes.argtypes = [P(npb_molecule), P(npb_grid), P(npb_params),
+                                                   P(C.c_size_t)]
+        lib.npb_solve_fields.restype = C.c_int
+        lib.npb_solve_fields.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                         C.c_void_p, C.c_void_p, P(npb_result)]
         _lib = lib
         return lib
 
@@ -258,6 +265,23 @@ def npb_launch_shapes(ctx, grid: npb_grid, params: npb_params) -> list:
     return [tuple(out[4 * d:4 * d + 4]) for d in range(3)]
 
 
+def npb_fields_workspace_bytes(mol: npb_molecule, grid: npb_grid, params: npb_params) -> int:
+    n = C.c_size_t()
+    _check(load_library().npb_fields_workspace_bytes(C.byref(mol), C.byref(grid),
+                                                     C.byref(params), C.byref(n)))
+    return int(n.value)
+
+
+def npb_solve_fields(ctx, solute: npb_molecule, grid: npb_grid, params: npb_params, d_u0: int,
+                     d_rho: int, d_ws: int, ws_bytes: int, d_u_out: Optional[int],
+                     stream: int) -> npb_result:
+    res = npb_result()
+    _check(load_library().npb_solve_fields(ctx, C.byref(solute), C.byref(grid), C.byref(params),
+                                           d_u0, d_rho, d_ws, ws_bytes, d_u_out, stream,
+                                           C.byref(res)))
+    return res
+
+
 def npb_server_create(ctx, hbm_budget: int, max_batch: int = 16, max_queue: int = 256):
     sv = C.c_void_p()
     _check(load_library().npb_server_create(ctx, hbm_budget, max_batch, max_queue,
@@ -364,6 +388,52 @@ class Solver:
                         self.ws_bytes, self.field.data_ptr() if self.field is not None else None,
                         stream)
         return result_dict(res)
+
+
+class FieldsSolver:
+    """npb_solve_fields on caller-given dense fields (numpy [nz][ny][nx],
+    dimensionless): the initial field u0 (its shell is the Dirichlet data)
+    and the source rho; `solute` gives the solute balls.  `params` is an
+    npb_params (built with make_params or make_params_raw)."""
+
+    def __init__(self, solute, grid, params: npb_params, u0, rho, device: int = 0,
+                 graphs: bool = True):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.device = device
+        self.mol = Molecule(solute.xyz, solute.q, solute.radius)
+        self.grid = make_grid(grid)
+        self.params = params
+        self.ctx = context(device)
+        dev = torch.device("cuda", device)
+        self.u0 = torch.from_numpy(np.ascontiguousarray(u0, dtype=np.float64)).to(dev)
+        self.rho = torch.from_numpy(np.ascontiguousarray(rho, dtype=np.float64)).to(dev)
+        self.ws_bytes = npb_fields_workspace_bytes(self.mol.c, self.grid, self.params)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.u = torch.empty_like(self.u0)
+        self.graphs = graphs
+
+    def run(self) -> dict:
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        npb_ctx_set_graph(self.ctx, self.graphs)
+        try:
+            res = npb_solve_fields(self.ctx, self.mol.c, self.grid, self.params,
+                                   self.u0.data_ptr(), self.rho.data_ptr(), self.ws.data_ptr(),
+                                   self.ws_bytes, self.u.data_ptr(), stream)
+        finally:
+            npb_ctx_set_graph(self.ctx, True)
+        out = result_dict(res)
+        out["u"] = self.u.cpu().numpy()
+        return out
+
+
+def make_params_raw(eps_in, eps_out, kappa_bar_sq, alpha, dt, n_steps, scheme="LODIE2",
+                    precision="f64", richardson=False, temperature_K=298.0) -> npb_params:
+    """npb_params with kbar^2 given directly (Angstrom^-2 or dimensionless)."""
+    return npb_params(float(eps_in), float(eps_out), float(kappa_bar_sq), float(temperature_K),
+                      float(alpha), float(dt), int(n_steps), SCHEMES[scheme],
+                      PRECISIONS[precision], 1 if richardson else 0, 0, 0, 0, 0)
 
 
 class BatchSolver:

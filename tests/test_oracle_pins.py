@@ -616,3 +616,48 @@ def test_cn_sweep_amplifies_an_eigenmode_by_the_crank_nicolson_factor():
     v = oracle.cn_sweep(s, eps_node, tau, h, axis=2)
     assert np.max(np.abs(v[1:-1, 1:-1, :] - g * s[1:-1, 1:-1, :])) <= 1e-13
     assert abs(g) < 1.0 and g < 0.0   # a stiff mode: damped with a sign flip
+
+
+# --------------------------------------------------------------------------
+# the analytic benchmark of Sec. 4.1 (charged cavity) against the paper's
+# printed spatial-convergence errors (Table LODspat)
+
+def _sphere_errors(h, scheme):
+    b = inputs.sphere_benchmark(h)
+    pb = oracle.problem_from_fields(b.grid, b.solute, b.eps_in, b.eps_out, b.kbar_sq, b.rho, b.u0)
+    dt = h * h / 20.0
+    u = oracle.run(pb, dt, 1.0, int(round(10.0 / dt)), scheme)
+    e = (u - b.exact)[b.valid]
+    ex = b.exact[b.valid]
+    return (float(np.sqrt(np.sum(e * e) / np.sum(ex * ex))),
+            float(np.max(np.abs(e)) / np.max(np.abs(ex))))
+
+
+def test_sphere_benchmark_fields_are_the_analytic_problem():
+    # the exact field is continuous across r = R; the initial field meets
+    # the Dirichlet data on the shell and carries the H term inside
+    b = inputs.sphere_benchmark(0.25, H=20.0)
+    n = b.grid.nx
+    c = n // 2
+    x = np.array([b.grid.origin[0] + i * b.grid.h for i in range(n)])
+    onR = np.argmin(np.abs(x - 1.0))
+    assert b.exact[c, c, onR] == pytest.approx(1.0 / 80.0, rel=1e-12)
+    B = oracle.boundary_shell(b.grid)
+    assert np.array_equal(b.u0[B], b.exact[B])
+    assert b.u0[c, c, c] == 20.0 and b.rho[c, c, c] == pytest.approx(4 * math.pi / 0.25 ** 3)
+
+
+@pytest.mark.parametrize("scheme,key", [("LODIE2", "LODIE"), ("LODCN2", "LODCN")])
+def test_sphere_spatial_errors_match_the_paper_table(scheme, key):
+    # h = 0.5 and 0.25 (Delta t = h^2 / 20, T = 10): the relative L2 and Linf
+    # errors against the analytic solution agree with the printed values to
+    # within 30 % (measured: within 26 %).  Parity at the printed digits is not expected: the paper
+    # sets eps at half points from an MSMS-derived surface, here it is the
+    # harmonic mean of nodal values, which matters most at the coarsest h
+    # (h = 1 is left out for that reason).
+    ref = json.load(open(os.path.join(GOLDEN, "paper_sphere_spatial.json")))
+    for h in (0.5, 0.25):
+        l2, linf = _sphere_errors(h, scheme)
+        i = ref["h"].index(h)
+        assert l2 == pytest.approx(ref[key]["L2"][i], rel=0.3), (h, l2)
+        assert linf == pytest.approx(ref[key]["Linf"][i], rel=0.3), (h, linf)
