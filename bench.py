@@ -13,6 +13,7 @@ Prints one JSON line.  Usage:
     python bench.py --serve                     request loop, p50/p99 latency
     python bench.py --large                     30000 atoms on 321^3 nodes
     python bench.py --direct                    direct vacuum Poisson solve, recovered potential
+    python bench.py --sphere                    analytic charged cavity: convergence, stability
 """
 from __future__ import annotations
 
@@ -221,6 +222,101 @@ def bench_large(args):
             "runs": out_runs}
 
 
+def bench_sphere(args):
+    """The analytic charged-cavity benchmark of Sec. 4.1 (caller-given fields,
+    FP64): spatial convergence of every scheme (Delta t = h^2/20, T = 10,
+    H = 1, h = 1 .. 0.0625; the paper's Tables LODspat .. MAOSspat), the
+    temporal convergence of LODIE2 at h = 0.125 against a Delta t = 2.5e-5
+    reference (Table LODtemp), and the stability sweep (Table stab: h = 0.5 and
+    0.25, H = 1 and 20, Delta t = 0.001 .. 5, T = 1e4 Delta t) of one scheme
+    per family.  Errors are relative L2 and Linf over all nodes but the
+    singular centre (Eq. (ErrorMeasure))."""
+    import math
+
+    import numpy as np
+
+    from paper_1410_2788_amd import inputs, npb
+
+    def run(b, scheme, dt, n):
+        p = npb.make_params_raw(b.eps_in, b.eps_out, b.kbar_sq, 1.0, dt, n, scheme=scheme)
+        return npb.FieldsSolver(b.solute, b.grid, p, b.u0, b.rho, graphs=False).run()
+
+    def norms(u, ref, valid):
+        e = (u - ref)[valid]
+        r = ref[valid]
+        return (float(np.sqrt(np.sum(e * e) / np.sum(r * r))),
+                float(np.max(np.abs(e)) / np.max(np.abs(r))))
+
+    t0 = time.perf_counter()
+    paper = _golden("paper_sphere_spatial.json")
+    hs = [1.0, 0.5, 0.25, 0.125, 0.0625]
+    schemes = ["LODIE2", "LODCN2", "AOSIE1", "AOSIE2", "AOSCN1", "AOSCN2", "MAOSIE", "MAOSCN"]
+    spatial = {}
+    ms_total = 0.0
+    pts_total = 0.0
+    for sc in schemes:
+        rows = []
+        for h in hs:
+            b = inputs.sphere_benchmark(h)
+            dt = h * h / 20.0
+            n = int(round(10.0 / dt))
+            print(f"[bench] sphere spatial {sc} h={h} steps={n}", file=sys.stderr, flush=True)
+            r = run(b, sc, dt, n)
+            l2, linf = norms(r["u"], b.exact, b.valid)
+            ms_total += r["device_ms"]
+            pts_total += r["grid_point_updates"]
+            rows.append({"h": h, "steps": n, "L2": l2, "Linf": linf, "device_ms": r["device_ms"]})
+        for i in range(len(rows) - 1):
+            rows[i]["L2_order"] = math.log2(rows[i]["L2"] / rows[i + 1]["L2"])
+            rows[i]["Linf_order"] = math.log2(rows[i]["Linf"] / rows[i + 1]["Linf"])
+        spatial[sc] = rows
+    # temporal: LODIE2, h = 0.125, against the dt = 2.5e-5 solution
+    b = inputs.sphere_benchmark(0.125)
+    print("[bench] sphere temporal reference", file=sys.stderr, flush=True)
+    ref = run(b, "LODIE2", 2.5e-5, 400000)["u"]
+    temporal = []
+    for dt in (8e-4, 4e-4, 2e-4, 1e-4, 5e-5):
+        n = int(round(10.0 / dt))
+        print(f"[bench] sphere temporal dt={dt} steps={n}", file=sys.stderr, flush=True)
+        u = run(b, "LODIE2", dt, n)["u"]
+        l2, linf = norms(u, ref, b.valid)
+        # against a numerical reference the centre node is finite: also
+        # over every node
+        l2a, linfa = norms(u, ref, np.ones_like(b.valid))
+        temporal.append({"dt": dt, "steps": n, "L2": l2, "Linf": linf, "L2_all_nodes": l2a,
+                         "Linf_all_nodes": linfa})
+    for i in range(len(temporal) - 1):
+        temporal[i]["L2_order"] = math.log2(temporal[i]["L2"] / temporal[i + 1]["L2"])
+        temporal[i]["Linf_order"] = math.log2(temporal[i]["Linf"] / temporal[i + 1]["Linf"])
+    # stability: one scheme per family, T = 1e4 dt
+    dts = [0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 5.0]
+    stability = {}
+    for fam, sc in (("LOD", "LODIE2"), ("AOS", "AOSIE2"), ("MAOS", "MAOSIE")):
+        for H in (1.0, 20.0):
+            for h in (0.5, 0.25):
+                b = inputs.sphere_benchmark(h, H=H)
+                errs = []
+                for dt in dts:
+                    print(f"[bench] sphere stability {sc} H={H} h={h} dt={dt}", file=sys.stderr,
+                          flush=True)
+                    errs.append(norms(run(b, sc, dt, 10000)["u"], b.exact, b.valid)[0])
+                finite = [dt for dt, e in zip(dts, errs) if math.isfinite(e)]
+                stability[f"{fam} H={H:g} h={h:g}"] = {
+                    "scheme": sc, "L2": errs,
+                    "stable_range": [min(finite), max(finite)] if finite else None}
+    wall = time.perf_counter() - t0
+    return {"metric": "analytic charged-cavity benchmark (Sec. 4.1-4.3): errors, orders, "
+                      "stability range", "value": pts_total / (ms_total * 1e-3),
+            "unit": "grid-point-updates/s (spatial study, device time)", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": ms_total, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "analytic",
+            "config": {"workload": "charged cavity R=1, eps 1/80, kbar=1, alpha=1, [-3,3]^3",
+                       "spatial": "dt = h^2/20, T = 10, H = 1", "temporal": "h = 0.125, T = 10",
+                       "stability": "T = 1e4 dt"},
+            "spatial": spatial, "temporal_LODIE2": temporal, "stability": stability,
+            "paper_LODspat": paper, "wall_s": wall}
+
+
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -379,6 +475,9 @@ def main():
     ap.add_argument("--direct", action="store_true",
                     help="time the direct vacuum Poisson solve and the recovered potential "
                          "(own JSON line)")
+    ap.add_argument("--sphere", action="store_true",
+                    help="the analytic charged-cavity benchmark: spatial / temporal "
+                         "convergence and stability of the schemes (own JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="time the request loop under Poisson arrivals instead (own JSON line)")
     ap.add_argument("--requests", type=int, default=48)
@@ -401,6 +500,9 @@ def main():
         return
     if args.direct:
         print(json.dumps(bench_direct(args)))
+        return
+    if args.sphere:
+        print(json.dumps(bench_sphere(args)))
         return
     if args.large:
         print(json.dumps(bench_large(args)))

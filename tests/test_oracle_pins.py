@@ -620,7 +620,7 @@ def test_cn_sweep_amplifies_an_eigenmode_by_the_crank_nicolson_factor():
 
 # --------------------------------------------------------------------------
 # the analytic benchmark of Sec. 4.1 (charged cavity) against the paper's
-# printed spatial-convergence errors (Table LODspat)
+# printed spatial-convergence errors (Tables LODspat, AOSIEspat, MAOSspat)
 
 def _sphere_errors(h, scheme):
     b = inputs.sphere_benchmark(h)
@@ -647,7 +647,8 @@ def test_sphere_benchmark_fields_are_the_analytic_problem():
     assert b.u0[c, c, c] == 20.0 and b.rho[c, c, c] == pytest.approx(4 * math.pi / 0.25 ** 3)
 
 
-@pytest.mark.parametrize("scheme,key", [("LODIE2", "LODIE"), ("LODCN2", "LODCN")])
+@pytest.mark.parametrize("scheme,key", [("LODIE2", "LODIE"), ("LODCN2", "LODCN"),
+                                        ("AOSIE2", "AOSIE2"), ("MAOSIE", "MAOSIE")])
 def test_sphere_spatial_errors_match_the_paper_table(scheme, key):
     # h = 0.5 and 0.25 (Delta t = h^2 / 20, T = 10): the relative L2 and Linf
     # errors against the analytic solution agree with the printed values to
