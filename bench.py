@@ -305,7 +305,7 @@ def bench_sphere(args):
                     "scheme": sc, "L2": errs,
                     "stable_range": [min(finite), max(finite)] if finite else None}
     wall = time.perf_counter() - t0
-    return {"metric": "analytic charged-cavity benchmark (Sec. 4.1-4.3): errors, orders, "
+    return {"metric": "analytic charged-cavity benchmark (Sec. 4.1-4.4): errors, orders, "
                       "stability range", "value": pts_total / (ms_total * 1e-3),
             "unit": "grid-point-updates/s (spatial study, device time)", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": ms_total, "higher_is_better": True,
@@ -357,7 +357,7 @@ def bench_direct(args):
     ms_direct = kt["ms"] / max(kt["count"], 1)
     tf = flops / (ms_direct * 1e-3) / 1e12
     r = out[True][1][0]
-    rec = {"metric": "direct vacuum Poisson solve (Sec. 4.1) beside the RE+V solve",
+    rec = {"metric": "direct vacuum Poisson solve (Sec. 5.1) beside the RE+V solve",
            "value": ms_direct, "unit": "ms per direct solve", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[True][0],
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,

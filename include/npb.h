@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NPB_ABI_VERSION 3
+#define NPB_ABI_VERSION 4
 
 typedef enum npb_status {
   NPB_OK = 0,
@@ -97,21 +97,22 @@ typedef struct npb_grid {
  *   n_steps         : steps at dt (the dt/2 level of Richardson runs 2 n_steps)
  *   scheme          : npb_scheme
  *   precision       : npb_precision
- *   richardson      : 1 = run dt and dt/2 and combine (Sec. 4.3, Eq. (rich))
+ *   richardson      : 1 = run dt and dt/2 and combine (Sec. 5.3, Eq. (rich))
  *   vacuum          : 1 = also solve the uniform-eps_in, kbar = 0 problem by
  *                     the same scheme and report the solvation energy
- *                     (Sec. 4.3, Eq. (deltaG3)); 0 = solvated potential only
+ *                     (Sec. 5.3, Eq. (deltaG3)); 0 = solvated potential only
  *   vacuum_direct   : 1 = also solve the vacuum Poisson problem directly
  *                     (no pseudo-time: the constant-eps_in 7-point problem
  *                     with the vacuum Dirichlet data, by type-I sine
- *                     transforms in FP64; the paper's "FFT" phi_0, Sec. 4.1)
+ *                     transforms in FP64; the paper's "FFT" phi_0, Sec. 5.1)
  *                     and report dG_direct (Eq. (deltaG2)); needs vacuum = 1
  *   field_select    : which potential d_field_out receives:
  *                     0 = solvated, 1 = vacuum by the scheme (needs vacuum),
  *                     2 = vacuum by the direct solve (needs vacuum_direct),
  *                     3 = recovered potential phi_m - phi_0 + phi_0^direct
- *                         (Sec. 4.4; needs vacuum_direct); phi_m and phi_0
+ *                         (Sec. 5.4; needs vacuum_direct); phi_m and phi_0
  *                         Richardson-combined when richardson = 1
+ *   field_units     : npb_field_units of d_field_out
  *   reserved        : must be 0                                             */
 typedef struct npb_params {
   double eps_in, eps_out, kappa_bar_sq, temperature_K, alpha, dt;
@@ -122,8 +123,14 @@ typedef struct npb_params {
   int32_t vacuum;
   int32_t field_select;
   int32_t vacuum_direct;
+  int32_t field_units;
   int32_t reserved;
 } npb_params;
+
+enum npb_field_units {
+  NPB_UNITS_KCAL = 0,          /* phi = kT u, kcal/mol/e */
+  NPB_UNITS_DIMENSIONLESS = 1  /* u */
+};
 
 /* Results, all energies in kcal/mol.
  *   G_m[l], G_0[l]  : (1/2) sum_p Q_p phi_p over the trilinear charge nodes
@@ -189,6 +196,13 @@ enum npb_sweep_kernel {
   NPB_SK_YZ_GENERAL = 3  /* y/z sweep with sources and AOS accumulation         */
 };
 
+/* A grid for a molecule: per axis, the atoms' extent (positions +- radii)
+ * plus `margin` Angstrom on both sides, an odd number of nodes at spacing h
+ * centred on it (n = 2 ceil(half / h) + 1, at least 5).  Pure; returns
+ * NPB_OK, or NPB_EINVAL (no atoms, h or margin not positive, or an axis
+ * beyond 514 nodes). */
+npb_status npb_default_grid(const npb_molecule* mol, double h, double margin, npb_grid* out);
+
 /* Returns NPB_ABI_VERSION.  Pure. */
 int npb_abi_version(void);
 
@@ -245,6 +259,18 @@ npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
 npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
                      const npb_params* params, void* d_ws, size_t ws_bytes,
                      double* d_field_out, void* stream, npb_result* out);
+
+/* npb_solve without the final wait: the device work and a last kernel that
+ * writes the result are enqueued on `stream`, and the call returns.
+ * pinned_out must be page-locked host memory the device can write (e.g.
+ * hipHostMalloc, or a torch tensor with pin_memory); it holds the result
+ * once the stream's work completes, with device_ms = NaN (not measured) and
+ * finite as in npb_solve (a non-finite energy is reported there, not as a
+ * status).  Argument and stencil errors are returned before any device
+ * work; EINVAL if pinned_out is not page-locked memory. */
+npb_status npb_solve_async(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                           const npb_params* params, void* d_ws, size_t ws_bytes,
+                           double* d_field_out, void* stream, npb_result* pinned_out);
 
 /* Solve n independent problems together (molecules, grids and parameters
  * may all differ; one precision per batch).  Same semantics per problem as

@@ -250,6 +250,10 @@ hipError_t launch_field_out(double* out, const T* u, int nx, int nxp, int ny, in
 hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum, int direct,
                           double* res, hipStream_t st);
 
+// the result of problem into page-locked host memory (npb_solve_async)
+hipError_t launch_result(const double* res, const int* ints, npb_result* out, double points,
+                         int steps, hipStream_t st);
+
 // number of nodes on the outer shell of an nx*ny*nz grid
 inline long long shell_count(int nx, int ny, int nz) {
   return (long long)nx * ny * nz - (long long)(nx - 2) * (ny - 2) * (nz - 2);

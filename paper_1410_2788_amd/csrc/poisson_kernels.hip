@@ -1,10 +1,10 @@
-// Vacuum potential without pseudo-time (Sec. 4.1, text after Eq. (deltaG)):
+// Vacuum potential without pseudo-time (Sec. 5.1, text after Eq. (deltaG)):
 // the Poisson problem with the constant dielectric eps_in,
 //     -eps_in delta^2 u = rho   on the interior nodes,   u = g on the shell,
 // delta^2 the 7-point operator of Eq. (SpatialOperators) and g the vacuum
 // Dirichlet data.  The paper obtains this phi_0 with an FFT fast Poisson
 // solver; it enters the energy of Eq. (deltaG2) and the recovered potential
-// of Sec. 4.4.  Everything here is FP64.
+// of Sec. 5.4.  Everything here is FP64.
 //
 // Method: the Dirichlet couplings move to the right-hand side, and the
 // type-I discrete sine transform along each axis diagonalises what remains:

@@ -289,6 +289,32 @@ hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum
   return hipGetLastError();
 }
 
+// npb_solve_async: the result straight into page-locked host memory
+__global__ void result_kernel(const double* res, const int* ints, npb_result* out,
+                              double points, int steps) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  npb_result r{};
+  r.dG = res[0];
+  r.dG_plain = res[1];
+  r.G_m[0] = res[2];
+  r.G_m[1] = res[3];
+  r.G_0[0] = res[4];
+  r.G_0[1] = res[5];
+  r.finite = res[6] != 0.0 ? 1 : 0;
+  r.dG_direct = res[7];
+  r.grid_point_updates = points;
+  r.device_ms = __longlong_as_double(0x7ff8000000000000LL);
+  r.steps_done = steps;
+  r.n_charge_nodes = ints[0];
+  *out = r;
+}
+
+hipError_t launch_result(const double* res, const int* ints, npb_result* out, double points,
+                         int steps, hipStream_t st) {
+  hipLaunchKernelGGL(result_kernel, dim3(1), dim3(64), 0, st, res, ints, out, points, steps);
+  return hipGetLastError();
+}
+
 template hipError_t launch_field_init<float>(float*, const double*, int, int, int, int,
                                              hipStream_t);
 template hipError_t launch_field_init<double>(double*, const double*, int, int, int, int,
@@ -569,7 +595,9 @@ npb_status validate(const npb_molecule* mol, const npb_grid* g, const npb_params
   if (p->vacuum_direct != 0 && p->vacuum_direct != 1)
     return fail(NPB_EINVAL, "vacuum_direct must be 0 or 1");
   if (p->vacuum_direct && !p->vacuum) return fail(NPB_EINVAL, "vacuum_direct needs vacuum = 1");
-  if (p->reserved != 0) return fail(NPB_EINVAL, "reserved parameter must be 0");
+  if (p->reserved != 0) return fail(NPB_EINVAL, "params.reserved must be 0");
+  if (p->field_units != NPB_UNITS_KCAL && p->field_units != NPB_UNITS_DIMENSIONLESS)
+    return fail(NPB_EINVAL, "unknown field_units");
   if (p->field_select < 0 || p->field_select > 3)
     return fail(NPB_EINVAL, "field_select must be 0, 1, 2 or 3");
   if (p->field_select == 1 && !p->vacuum) return fail(NPB_EINVAL, "field_select 1 needs vacuum = 1");
@@ -624,6 +652,9 @@ struct Problem {
   }
   bool aos() const { return is_aos(p->scheme); }
   bool fields() const { return fu0 != nullptr; }
+  double field_scale() const {
+    return (fields() || p->field_units == NPB_UNITS_DIMENSIONLESS) ? 1.0 : kT;
+  }
 };
 
 // coefficients of one run (Sec. 3: tau = dt / alpha; AOS sub-steps take
@@ -1164,7 +1195,7 @@ struct Engine {
       if (s != NPB_OK) return s;
       const npb_params* p = P.p;
       if (p->vacuum_direct) {
-        // Sec. 4.1: phi_0 from the Poisson equation solved directly
+        // Sec. 5.1: phi_0 from the Poisson equation solved directly
         DirectPoissonArgs da{};
         da.nx = P.g->nx;
         da.ny = P.g->ny;
@@ -1186,7 +1217,7 @@ struct Engine {
       if (P.fout) {
         // field_select 0 / 1: kT u of that medium (plain) or
         // kT (2 u(dt/2) - u(dt)) (Richardson); 2: kT u of the direct vacuum
-        // solve; 3: solvated - vacuum (as 0 and 1) + direct vacuum (Sec. 4.4)
+        // solve; 3: solvated - vacuum (as 0 and 1) + direct vacuum (Sec. 5.4)
         const int fs = p->field_select;
         bool first = true;
         for (int medium = 0; medium < 2; ++medium) {
@@ -1196,8 +1227,8 @@ struct Engine {
             int r = 0;
             while (!(L.runs[r].medium == medium && L.runs[r].level == l)) ++r;
             const double beta = first ? 0.0 : 1.0;
-            // caller-given fields: the dimensionless u itself
-            const double scale = P.fields() ? 1.0 : P.kT;
+            // dimensionless u (caller-given fields, or asked for), else kT u
+            const double scale = P.field_scale();
             const double gamma = sign * (p->richardson ? (l == 0 ? -scale : 2.0 * scale) : scale);
             s = timed(NPB_K_OTHER, 0, [&] {
               return launch_field_out<T>(P.fout, P.at<T>(L.field[r]), P.g->nx,
@@ -1211,8 +1242,8 @@ struct Engine {
         if (fs >= 2) {
           s = timed(NPB_K_OTHER, 0, [&] {
             return launch_direct_field_out(P.fout, P.at<double>(L.direct), P.at<double>(L.bc_v),
-                                           P.g->nx, P.g->ny, P.g->nz, first ? 0.0 : 1.0, P.kT,
-                                           st);
+                                           P.g->nx, P.g->ny, P.g->nz, first ? 0.0 : 1.0,
+                                           P.field_scale(), st);
           });
           if (s != NPB_OK) return s;
         }
@@ -1246,7 +1277,9 @@ struct Engine {
     return k;
   }
 
-  npb_status run(npb_result* out) {
+  // async: out is page-locked host memory written by a last kernel; the
+  // call returns once everything is enqueued
+  npb_status run(npb_result* out, bool async = false) {
     // A replay of the graph of the same batch needs only the atoms and the
     // chunk tables staged again; the launch tables in the context's buffer
     // are the ones the graph was captured with.
@@ -1291,6 +1324,17 @@ struct Engine {
     } else {
       s = device_work();
       if (s != NPB_OK) return s;
+    }
+    if (async) {
+      for (size_t i = 0; i < pr.size(); ++i) {
+        const Problem& P = pr[i];
+        const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
+        int steps = 0;
+        for (int r = 0; r < P.L.n_runs; ++r) steps += P.p->n_steps << P.L.runs[r].level;
+        NPB_HIP(launch_result(P.at<double>(P.L.slots) + 8, P.at<int>(P.L.ints), &out[i],
+                              pts * steps, steps, st));
+      }
+      return NPB_OK;
     }
     NPB_HIP(hipEventRecord(ctx->t1, st));
     // results to the host (first 128 bytes per problem of the staging buffer)
@@ -1484,9 +1528,10 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
 }
 
 template <typename T, typename A>
-npb_status solve_batch_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st, npb_result* out) {
+npb_status solve_batch_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st, npb_result* out,
+                         bool async) {
   Engine<T, A> E{ctx, st, pr, {}, {}, {}};
-  return E.run(out);
+  return E.run(out, async);
 }
 
 }  // namespace
@@ -1593,16 +1638,17 @@ npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
 namespace {
 
 // the device work of checked problems (one precision)
-npb_status run_problems(npb_ctx* ctx, std::vector<Problem>& pr, void* stream, npb_result* out) {
+npb_status run_problems(npb_ctx* ctx, std::vector<Problem>& pr, void* stream, npb_result* out,
+                        bool async = false) {
   // every argument checked: only now is the context read
   for (Problem& P : pr) apply_tuning(ctx, P.g, P.p, P.L);
   NPB_HIP(hipSetDevice(ctx->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int precision = pr[0].p->precision;
   try {
-    if (precision == NPB_FP64) return solve_batch_t<double, double>(ctx, pr, st, out);
-    if (precision == NPB_FP32X) return solve_batch_t<float, double>(ctx, pr, st, out);
-    return solve_batch_t<float, float>(ctx, pr, st, out);
+    if (precision == NPB_FP64) return solve_batch_t<double, double>(ctx, pr, st, out, async);
+    if (precision == NPB_FP32X) return solve_batch_t<float, double>(ctx, pr, st, out, async);
+    return solve_batch_t<float, float>(ctx, pr, st, out, async);
   } catch (const std::exception& e) {
     return fail(NPB_ENOMEM, e.what());
   } catch (...) {
@@ -1655,6 +1701,62 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols, const 
                                     std::to_string(j));
   }
   return run_problems(ctx, pr, stream, out);
+}
+
+npb_status npb_solve_async(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                           const npb_params* params, void* d_ws, size_t ws_bytes,
+                           double* d_field_out, void* stream, npb_result* pinned_out) {
+  if (!ctx || !pinned_out) return fail(NPB_EINVAL, "null context or result");
+  if (!mol || !grid || !params) return fail(NPB_EINVAL, "null argument");
+  npb_status s = validate(mol, grid, params);
+  if (s != NPB_OK) return s;
+  hipPointerAttribute_t attr{};
+  if (hipPointerGetAttributes(&attr, pinned_out) != hipSuccess || attr.type != hipMemoryTypeHost) {
+    (void)hipGetLastError();
+    return fail(NPB_EINVAL, "pinned_out must be page-locked host memory");
+  }
+  std::vector<Problem> pr(1);
+  Problem& P = pr[0];
+  P.mol = mol;
+  P.g = grid;
+  P.p = params;
+  P.ws = reinterpret_cast<unsigned char*>(d_ws);
+  P.fout = d_field_out;
+  P.L = make_layout(mol, grid, params);
+  P.kT = thermal_energy(params->temperature_K);
+  P.lB = bjerrum(params->temperature_K);
+  if (!P.ws || ws_bytes < P.L.total)
+    return fail(NPB_EINVAL, "workspace missing or smaller than npb_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(P.ws) % 256 != 0)
+    return fail(NPB_EINVAL, "workspace must be 256-byte aligned");
+  return run_problems(ctx, pr, stream, pinned_out, true);
+}
+
+npb_status npb_default_grid(const npb_molecule* mol, double h, double margin, npb_grid* out) {
+  if (!mol || !out) return fail(NPB_EINVAL, "null argument");
+  if (mol->n_atoms < 1 || !mol->xyz || !mol->radius) return fail(NPB_EINVAL, "no atoms");
+  if (!(h > 0.0) || !(margin > 0.0) || !std::isfinite(h) || !std::isfinite(margin))
+    return fail(NPB_EINVAL, "h and margin must be positive");
+  npb_grid g{};
+  g.h = h;
+  int* n[3] = {&g.nx, &g.ny, &g.nz};
+  for (int d = 0; d < 3; ++d) {
+    double lo = 1e300, hi = -1e300;
+    for (int a = 0; a < mol->n_atoms; ++a) {
+      const double c = mol->xyz[3 * a + d], r = mol->radius[a];
+      if (!std::isfinite(c) || !std::isfinite(r)) return fail(NPB_EINVAL, "bad atom");
+      lo = std::min(lo, c - r);
+      hi = std::max(hi, c + r);
+    }
+    const double half = 0.5 * (hi - lo) + margin;
+    const double cells = std::ceil(half / h - 1e-9);
+    if (cells > 256.0) return fail(NPB_EINVAL, "grid axis longer than 514 nodes");
+    const int nn = std::max(5, 2 * (int)cells + 1);
+    *n[d] = nn;
+    g.origin[d] = 0.5 * (lo + hi) - 0.5 * (nn - 1) * h;
+  }
+  *out = g;
+  return NPB_OK;
 }
 
 npb_status npb_fields_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,

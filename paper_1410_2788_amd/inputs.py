@@ -7,7 +7,7 @@ Both the CPU oracle (through the tests and the benchmark) and the HIP
 library consume what it returns, so it is the only code the two sides share.
 
 Physical quantities are given as the paper states them (Sec. 2.1 and
-Sec. 4.1): ionic strength in mol/L and temperature in K, not the derived
+Sec. 5.1): ionic strength in mol/L and temperature in K, not the derived
 modified Debye-Hueckel parameter, which each side computes for itself.
 
 Recipe (stand-ins for the paper's PDB proteins, which are not available):

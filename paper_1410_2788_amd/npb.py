@@ -27,7 +27,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "f32x": 2}
 KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other", "direct"]
 # sweep launches split again by the kernel that ran them (npb_sweep_kernel)
 SWEEP_KERNELS = ["x", "yz_plain", "yz_flow", "yz_general"]
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class npb_molecule(C.Structure):
@@ -45,7 +45,8 @@ class npb_params(C.Structure):
                 ("temperature_K", C.c_double), ("alpha", C.c_double), ("dt", C.c_double),
                 ("n_steps", C.c_int32), ("scheme", C.c_int32), ("precision", C.c_int32),
                 ("richardson", C.c_int32), ("vacuum", C.c_int32), ("field_select", C.c_int32),
-                ("vacuum_direct", C.c_int32), ("reserved", C.c_int32)]
+                ("vacuum_direct", C.c_int32), ("field_units", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class npb_result(C.Structure):
@@ -137,6 +138,12 @@ def load_library(path: str = LIB_PATH):
         lib.npb_solve.restype = C.c_int
         lib.npb_solve.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, P(npb_result)]
+        lib.npb_solve_async.restype = C.c_int
+        lib.npb_solve_async.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
+                                        C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]
+        lib.npb_default_grid.restype = C.c_int
+        lib.npb_default_grid.argtypes = [P(npb_molecule), C.c_double, C.c_double, P(npb_grid)]
         lib.npb_fields_workspace_bytes.restype = C.c_int
         lib.npb_fields_workspace_bytes.argtypes = [P(npb_molecule), P(npb_grid), P(npb_params),
                                                    P(C.c_size_t)]
@@ -265,6 +272,21 @@ def npb_launch_shapes(ctx, grid: npb_grid, params: npb_params) -> list:
     return [tuple(out[4 * d:4 * d + 4]) for d in range(3)]
 
 
+def npb_solve_async(ctx, mol: npb_molecule, grid: npb_grid, params: npb_params, d_ws: int,
+                    ws_bytes: int, d_field_out: Optional[int], stream: int,
+                    pinned_out: int) -> None:
+    """Enqueue a solve; the npb_result lands at pinned_out (page-locked host
+    memory) when the stream's work completes."""
+    _check(load_library().npb_solve_async(ctx, C.byref(mol), C.byref(grid), C.byref(params),
+                                          d_ws, ws_bytes, d_field_out, stream, pinned_out))
+
+
+def npb_default_grid(mol: npb_molecule, h: float, margin: float) -> npb_grid:
+    g = npb_grid()
+    _check(load_library().npb_default_grid(C.byref(mol), h, margin, C.byref(g)))
+    return g
+
+
 def npb_fields_workspace_bytes(mol: npb_molecule, grid: npb_grid, params: npb_params) -> int:
     n = C.c_size_t()
     _check(load_library().npb_fields_workspace_bytes(C.byref(mol), C.byref(grid),
@@ -337,12 +359,16 @@ def make_grid(g) -> npb_grid:
     return npb_grid(int(g.nx), int(g.ny), int(g.nz), 0, float(g.h), o)
 
 
-def make_params(p, field_select: int = 0, vacuum_direct: bool = False) -> npb_params:
+FIELD_UNITS = {"kcal": 0, "dimensionless": 1}
+
+
+def make_params(p, field_select: int = 0, vacuum_direct: bool = False,
+                field_units: str = "kcal") -> npb_params:
     kb2 = npb_kappa_bar_sq(p.ionic_molar, p.temperature_K)
     return npb_params(float(p.eps_in), float(p.eps_out), kb2, float(p.temperature_K),
                       float(p.alpha), float(p.dt), int(p.n_steps), SCHEMES[p.scheme],
                       PRECISIONS[p.precision], 1 if p.richardson else 0, 1 if p.vacuum else 0,
-                      int(field_select), 1 if vacuum_direct else 0, 0)
+                      int(field_select), 1 if vacuum_direct else 0, FIELD_UNITS[field_units], 0)
 
 
 _ctx_cache = {}
@@ -360,13 +386,13 @@ class Solver:
     npb_solve on the current torch stream."""
 
     def __init__(self, mol, grid, params, device: int = 0, want_field: bool = False,
-                 field_select: int = 0, vacuum_direct: bool = False):
+                 field_select: int = 0, vacuum_direct: bool = False, field_units: str = "kcal"):
         import torch
         self.torch = torch
         self.device = device
         self.mol = Molecule(mol.xyz, mol.q, mol.radius)
         self.grid = make_grid(grid)
-        self.params = make_params(params, field_select, vacuum_direct)
+        self.params = make_params(params, field_select, vacuum_direct, field_units)
         self.ctx = context(device)
         self.ws_bytes = npb_workspace_bytes(self.mol.c, self.grid, self.params)
         dev = torch.device("cuda", device)
@@ -433,7 +459,28 @@ def make_params_raw(eps_in, eps_out, kappa_bar_sq, alpha, dt, n_steps, scheme="L
     """npb_params with kbar^2 given directly (Angstrom^-2 or dimensionless)."""
     return npb_params(float(eps_in), float(eps_out), float(kappa_bar_sq), float(temperature_K),
                       float(alpha), float(dt), int(n_steps), SCHEMES[scheme],
-                      PRECISIONS[precision], 1 if richardson else 0, 0, 0, 0, 0)
+                      PRECISIONS[precision], 1 if richardson else 0, 0, 0, 0, 0, 0)
+
+
+class AsyncResult:
+    """A page-locked npb_result filled by npb_solve_async."""
+
+    def __init__(self):
+        import torch
+        self.buf = torch.zeros(C.sizeof(npb_result), dtype=torch.uint8).pin_memory()
+
+    def result(self) -> dict:
+        return result_dict(npb_result.from_address(self.buf.data_ptr()))
+
+
+def solve_async(solver: "Solver", out: AsyncResult) -> None:
+    """Enqueue solver's solve on the current torch stream without waiting;
+    out.result() is valid once the stream has completed."""
+    stream = solver.torch.cuda.current_stream(solver.device).cuda_stream
+    npb_solve_async(solver.ctx, solver.mol.c, solver.grid, solver.params, solver.ws.data_ptr(),
+                    solver.ws_bytes,
+                    solver.field.data_ptr() if solver.field is not None else None, stream,
+                    out.buf.data_ptr())
 
 
 class BatchSolver:
@@ -504,10 +551,10 @@ def result_dict(res: npb_result) -> dict:
 
 
 def solve(mol, grid, params, device: int = 0, want_field: bool = False,
-          field_select: int = 0, vacuum_direct: bool = False) -> dict:
+          field_select: int = 0, vacuum_direct: bool = False, field_units: str = "kcal") -> dict:
     """One solve; with want_field the result also holds 'phi' (numpy, FP64,
-    [nz][ny][nx], kcal/mol/e) as chosen by field_select."""
-    s = Solver(mol, grid, params, device, want_field, field_select, vacuum_direct)
+    [nz][ny][nx], kcal/mol/e or dimensionless) as chosen by field_select."""
+    s = Solver(mol, grid, params, device, want_field, field_select, vacuum_direct, field_units)
     out = s.run()
     if want_field:
         out["phi"] = s.field.cpu().numpy()

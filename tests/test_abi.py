@@ -29,7 +29,7 @@ def test_every_declared_function_is_exported(npb):
 
 
 def test_version_and_kappa_helper(npb):
-    assert npb.npb_abi_version() == npb.ABI_VERSION == 3
+    assert npb.npb_abi_version() == npb.ABI_VERSION == 4
     g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     assert npb.npb_kappa_bar_sq(1.0, 298.0) == pytest.approx(g["kbar2_per_molar_298_inv_A2"], rel=1e-15)
     assert npb.npb_kappa_bar_sq(0.1, 300.0) == pytest.approx(0.84303, rel=1e-5)
@@ -50,7 +50,8 @@ def test_validate_accepts_a_good_problem(npb):
 @pytest.mark.parametrize("field,value", [
     ("nx", 4), ("h", 0.0), ("h", -1.0), ("eps_in", 0.0), ("eps_out", -2.0),
     ("kappa_bar_sq", -1e-3), ("alpha", 0.0), ("dt", 0.0), ("n_steps", 0),
-    ("scheme", 10), ("precision", 5), ("field_select", 1)])
+    ("scheme", 10), ("precision", 5), ("field_select", 1), ("field_units", 2),
+    ("reserved", 1)])
 def test_validate_rejects_bad_arguments(npb, field, value):
     w = inputs.small_globular(n=25, n_atoms=10)
     w.params.vacuum = field != "field_select"
@@ -161,3 +162,33 @@ def test_direct_vacuum_parameters_are_validated(npb):
     b1 = npb.npb_workspace_bytes(mol.c, g, ok)
     n = 19
     assert b1 - b0 >= 8 * (n ** 3 + 3 * n * n + 3 * n)
+
+
+def test_default_grid_encloses_the_solute_with_its_margin(npb):
+    # one ball: radius 2 at the origin, h = 0.5, margin 10 -> half width 12 A
+    one = npb.Molecule(np.zeros((1, 3)), np.array([1.0]), np.array([2.0]))
+    g = npb.npb_default_grid(one.c, 0.5, 10.0)
+    assert (g.nx, g.ny, g.nz) == (49, 49, 49)
+    assert list(g.origin) == [-12.0, -12.0, -12.0] and g.h == 0.5
+    rng = np.random.default_rng(7)
+    xyz = rng.normal(size=(40, 3)) * np.array([6.0, 3.0, 1.5]) + np.array([1.0, -2.0, 3.0])
+    rad = rng.uniform(1.0, 2.0, 40)
+    mol = npb.Molecule(xyz, np.zeros(40), rad)
+    h, margin = 0.37, 4.0
+    g = npb.npb_default_grid(mol.c, h, margin)
+    n = np.array([g.nx, g.ny, g.nz])
+    lo, hi = (xyz - rad[:, None]).min(0), (xyz + rad[:, None]).max(0)
+    box_lo = np.array(g.origin[:])
+    box_hi = box_lo + (n - 1) * h
+    assert np.all(n % 2 == 1)
+    assert np.all(box_lo <= lo - margin + 1e-9) and np.all(box_hi >= hi + margin - 1e-9)
+    # the smallest odd size that does so, centred on the solute's extent
+    assert np.all((n - 3) * h < (hi - lo) + 2 * margin)
+    np.testing.assert_allclose(0.5 * (box_lo + box_hi), 0.5 * (lo + hi), atol=1e-12)
+    g2 = npb.make_grid(inputs.Grid(int(n[0]), int(n[1]), int(n[2]), h, tuple(box_lo)))
+    w = inputs.small_globular(n=25, n_atoms=10)
+    assert npb.npb_validate(mol.c, g2, npb.make_params(w.params)) == npb.NPB_OK
+    with pytest.raises(npb.NPBError):
+        npb.npb_default_grid(mol.c, 0.01, 4.0)
+    with pytest.raises(npb.NPBError):
+        npb.npb_default_grid(mol.c, 0.0, 4.0)

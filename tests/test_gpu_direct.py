@@ -1,6 +1,6 @@
 """GPU parity of the direct vacuum Poisson solve (vacuum_direct): the
-vacuum potential without pseudo-time (Sec. 4.1), the energy of Eq.
-(deltaG2) and the recovered potential of Sec. 4.4, against the FP64
+vacuum potential without pseudo-time (Sec. 5.1), the energy of Eq.
+(deltaG2) and the recovered potential of Sec. 5.4, against the FP64
 oracle (oracle.poisson_direct, scipy's type-I DST) on the same inputs.
 
 Tolerances: the direct solve is FP64 in every precision mode; its field is
