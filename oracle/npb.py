@@ -25,12 +25,16 @@ the electrostatic analysis of solvated biomolecules"):
   * MAOSIE / MAOSCN ............ Sec. 3.3, Eqs. (MAOS1_1)-(MAOS1_5), implicit
                                  Euler or Crank-Nicolson in the three
                                  directional sub-systems
-  * solvation energy ........... Sec. 4.1, Eq. (deltaG); vacuum by the same
-                                 scheme, Sec. 4.3, Eq. (deltaG3)
-  * Richardson extrapolation ... Sec. 4.3, Eq. (rich)
-  * vacuum potential by a fast   Sec. 4.1 (text after Eq. (deltaG)),
-    Poisson solver, energy and   Sec. 4.3, Eq. (deltaG2); recovered
-    recovered potential ........ potential, Sec. 4.4 (surface potential
+  * explicit Euler ............. Sec. 2.3 (the scheme the splittings
+                                 replace) and Sec. 5.2 / 5.4 (the reference
+                                 energies): Eq. (TimeDepNPB) stepped
+                                 explicitly with Eq. (SpatialOperators)
+  * solvation energy ........... Sec. 5.1, Eq. (deltaG); vacuum by the same
+                                 scheme, Sec. 5.3, Eq. (deltaG3)
+  * Richardson extrapolation ... Sec. 5.3, Eq. (rich)
+  * vacuum potential by a fast   Sec. 5.1 (text after Eq. (deltaG)),
+    Poisson solver, energy and   Sec. 5.3, Eq. (deltaG2); recovered
+    recovered potential ........ potential, Sec. 5.4 (surface potential
                                  paragraph)
 
 Readings of points the paper leaves open (each listed in the design notes):
@@ -67,7 +71,7 @@ KBAR2_PER_MOLAR_298 = 8.486902807  # Angstrom^-2 per mol/L at 298 K
 COULOMB_KCAL_A = 332.06371      # e^2/(4 pi eps0) in kcal Angstrom / mol (CODATA)
 
 SCHEMES = ("LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2", "AOSCN1", "AOSCN2",
-           "MAOSIE", "MAOSCN")
+           "MAOSIE", "MAOSCN", "EULER")
 
 
 def thermal_energy(T: float) -> float:
@@ -444,6 +448,28 @@ def maos_step(u, pb: Problem, dt: float, alpha: float, variant: str = "MAOSIE"):
     return out
 
 
+def euler_step(u, pb: Problem, dt: float, alpha: float):
+    """One explicit Euler step of Eq. (TimeDepNPB) with the spatial operator
+    of Eq. (SpatialOperators) (the paper's reference solver, Sec. 5.2 and
+    Sec. 5.4): u + tau (sum over x, y, z of delta(eps delta u) - kbar^2
+    sinh u + rho), tau = dt / alpha, on the interior nodes; the Dirichlet
+    shell is unchanged."""
+    tau = dt / alpha
+    h = pb.grid.h
+    div = np.zeros_like(u)
+    for axis in (2, 1, 0):
+        div += explicit_half(u, pb.eps_node, 1.0, h, axis) - u
+    # the sinh term exists only where kbar != 0 (solvent): elsewhere it is
+    # absent, not 0 * sinh(u) (which would overflow for |u| > 710)
+    nl = np.zeros_like(u)
+    sel = pb.interior & (pb.kbar2_node != 0.0)
+    nl[sel] = pb.kbar2_node[sel] * np.sinh(u[sel])
+    out = u.copy()
+    I = pb.interior
+    out[I] = u[I] + tau * (div[I] - nl[I] + pb.rho[I])
+    return out
+
+
 def run(pb: Problem, dt: float, alpha: float, n_steps: int, scheme: str = "LODIE2",
         u_init=None) -> np.ndarray:
     """Fixed number of pseudo-time steps from u^0 (zero inside)."""
@@ -453,6 +479,8 @@ def run(pb: Problem, dt: float, alpha: float, n_steps: int, scheme: str = "LODIE
             u = lod_step(u, pb, dt, alpha, scheme)
         elif scheme.startswith("MAOS"):
             u = maos_step(u, pb, dt, alpha, scheme)
+        elif scheme == "EULER":
+            u = euler_step(u, pb, dt, alpha)
         else:
             u = aos_step(u, pb, dt, alpha, scheme)
     return u
@@ -469,7 +497,7 @@ def richardson(u_dt: np.ndarray, u_half: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# the vacuum potential without pseudo-time (Sec. 4.1, text after Eq. (deltaG))
+# the vacuum potential without pseudo-time (Sec. 5.1, text after Eq. (deltaG))
 
 def poisson_direct(pb: Problem) -> np.ndarray:
     """phi_0 from the Poisson equation with a constant dielectric, solved

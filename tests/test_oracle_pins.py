@@ -438,6 +438,108 @@ def test_nonlinear_steady_state_converges_to_discrete_npb(scheme):
 
 
 # --------------------------------------------------------------------------
+# explicit Euler (the reference solver of Sec. 5.2 and Sec. 5.4)
+
+def test_euler_step_matches_a_node_by_node_operator():
+    # brute force: every interior node's six neighbours, harmonic faces and
+    # the sinh term written out with Python loops on a ragged tiny grid
+    grid = _tiny(7, 0.4, ny=6, nz=8)
+    mol = _two_atoms()
+    p = _params(ionic_molar=1.5, eps_in=2.0, eps_out=30.0, dt=0.003, alpha=0.5)
+    pb = oracle.make_problem(mol, grid, p, "solvated")
+    rng = np.random.default_rng(9)
+    u = pb.u0.copy()
+    u[1:-1, 1:-1, 1:-1] = rng.normal(0, 1.5, (6, 4, 5))
+    got = oracle.euler_step(u, pb, p.dt, p.alpha)
+    tau, h = p.dt / p.alpha, grid.h
+    e = pb.eps_node
+    want = u.copy()
+    nz, ny, nx = u.shape
+    for k in range(1, nz - 1):
+        for j in range(1, ny - 1):
+            for i in range(1, nx - 1):
+                acc = 0.0
+                for dk, dj, di in ((0, 0, 1), (0, 0, -1), (0, 1, 0), (0, -1, 0), (1, 0, 0),
+                                   (-1, 0, 0)):
+                    en = e[k + dk, j + dj, i + di]
+                    ef = 2.0 * e[k, j, i] * en / (e[k, j, i] + en)
+                    acc += ef * (u[k + dk, j + dj, i + di] - u[k, j, i]) / (h * h)
+                acc -= pb.kbar2_node[k, j, i] * math.sinh(u[k, j, i])
+                acc += pb.rho[k, j, i]
+                want[k, j, i] = u[k, j, i] + tau * acc
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+    assert np.array_equal(got[~pb.interior], u[~pb.interior])
+
+
+def _euler_steady(pb, tau, tol=1e-13, max_steps=40000):
+    u = pb.u0.copy()
+    for n in range(max_steps):
+        un = oracle.euler_step(u, pb, tau, 1.0)
+        if np.max(np.abs(un - u)) < tol * np.max(np.abs(un)):
+            return un, n + 1
+        u = un
+    raise AssertionError("no steady state")
+
+
+def _euler_tau(pb):
+    # 0.9 of the explicit limit 2 / lambda_max, lambda_max <= 2 * sum of a
+    # node's six face coefficients (Gershgorin)
+    return 0.9 * 2.0 / (2.0 * 6.0 * float(np.max(pb.eps_node)) / pb.grid.h ** 2)
+
+
+def test_euler_steady_state_is_the_direct_poisson_solution():
+    # uniform eps, kbar = 0: no splitting error, so the Euler fixed point is
+    # the discrete Poisson solution of the sine-transform solve itself
+    grid = _tiny(11, 0.5, ny=9, nz=10)
+    mol = _two_atoms()
+    pb = oracle.make_problem(mol, grid, _params(), "vacuum")
+    u, n = _euler_steady(pb, _euler_tau(pb))
+    ex = oracle.poisson_direct(pb)
+    assert np.max(np.abs(u - ex)) <= 1e-11 * np.max(np.abs(ex))
+
+
+def test_euler_steady_state_is_the_discrete_npb_solution():
+    # nonlinear, discontinuous eps: the Euler fixed point solves the discrete
+    # NPB equations exactly (dense Newton), unlike the split schemes whose
+    # steady states carry an O(dt) splitting error
+    grid = _tiny(9, 0.5)
+    mol = _two_atoms()
+    p = _params(ionic_molar=2.0, eps_in=2.0, eps_out=20.0)
+    pb = oracle.make_problem(mol, grid, p, "solvated")
+    D = sum(_dense.dense_second_difference(pb.eps_node, grid.h, ax) for ax in range(3))
+    I = _dense.interior_flags(pb.u0.shape)
+    ex = _dense.newton_npb(D, pb.kbar2_node.ravel(), pb.rho.ravel(), pb.u0.ravel(), I)
+    assert np.max(np.abs(pb.kbar2_node.ravel() * np.sinh(ex))) > 1.0
+    # linearised limit: the sinh term adds up to kbar^2 cosh(u) to lambda_max
+    lam = 2.0 * 6.0 * float(np.max(pb.eps_node)) / grid.h ** 2
+    lam += float(np.max(pb.kbar2_node.ravel() * np.cosh(ex)))
+    u, n = _euler_steady(pb, 0.9 * 2.0 / lam)
+    assert np.max(np.abs(u.ravel() - ex)) <= 1e-10 * np.max(np.abs(ex))
+
+
+def test_euler_is_unstable_just_above_the_explicit_limit():
+    # uniform eps: lambda_max of the 7-point operator is known exactly, so
+    # tau 2 % below 2 / lambda_max stays bounded and 2 % above grows
+    grid = _tiny(9, 0.5)
+    mol = _two_atoms()
+    pb = oracle.make_problem(mol, grid, _params(), "vacuum")
+    e, h, N = pb.eps_node.flat[0], grid.h, 7
+    lam_max = 3 * (e / h ** 2) * 4.0 * math.sin(math.pi * N / (2.0 * (N + 1))) ** 2
+    rng = np.random.default_rng(2)
+    u0 = pb.u0.copy()
+    u0[1:-1, 1:-1, 1:-1] += rng.normal(0, 1.0, (N, N, N))
+    ex = oracle.poisson_direct(pb)
+    dev0 = np.max(np.abs(u0 - ex))
+    amp = {}
+    for f in (0.98, 1.02):
+        u = u0.copy()
+        for _ in range(3000):
+            u = oracle.euler_step(u, pb, f * 2.0 / lam_max, 1.0)
+        amp[f] = np.max(np.abs(u - ex)) / dev0
+    assert amp[0.98] < 1.0 and amp[1.02] > 1e6
+
+
+# --------------------------------------------------------------------------
 # source prefactor and energy
 
 def test_vacuum_potential_approaches_coulomb_away_from_the_charge():
@@ -514,8 +616,8 @@ def test_mirror_symmetry_of_a_centred_ion():
 
 
 # --------------------------------------------------------------------------
-# vacuum potential by the direct (sine-transform) Poisson solve, Sec. 4.1;
-# Eq. (deltaG2) and the recovered potential of Sec. 4.4
+# vacuum potential by the direct (sine-transform) Poisson solve, Sec. 5.1;
+# Eq. (deltaG2) and the recovered potential of Sec. 5.4
 
 def _vacuum_problem(nx=8, ny=9, nz=7, eps_in=2.0):
     grid = _tiny(nx, 0.5, ny=ny, nz=nz)
