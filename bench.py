@@ -14,6 +14,7 @@ Prints one JSON line.  Usage:
     python bench.py --large                     30000 atoms on 321^3 nodes
     python bench.py --direct                    direct vacuum Poisson solve, recovered potential
     python bench.py --sphere                    analytic charged cavity: convergence, stability
+    python bench.py --euler                     explicit Euler reference: rate, energy at T = 10
 """
 from __future__ import annotations
 
@@ -381,6 +382,93 @@ def bench_direct(args):
     return rec
 
 
+def bench_euler(args):
+    """The explicit Euler reference solver (FP64) on the 2000-atom workload:
+    the step rate over --steps solves of 2000 steps each (vacuum by the
+    direct solve), the step kernel's own time from kernel-attached events
+    (roofline: 17 algorithmic bytes per interior node and step), parity of
+    a 40-step solve against stored oracle values, then reference runs to
+    T = euler_t / 2 and euler_t (dt 1e-5) whose Eq. (deltaG2) energy is set
+    beside the LODIE2 RE+V and RE energies of the same molecule."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2788_amd import inputs, npb
+    rate_steps = 2000
+    w = inputs.globular_2000_euler(n_steps=rate_steps)
+    X, Y, Z = w.grid.nx - 2, w.grid.ny - 2, w.grid.nz - 2
+    s = npb.Solver(w.molecule, w.grid, w.params, vacuum_direct=True)
+    for _ in range(max(1, args.warmup)):
+        s.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [s.run() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = float(np.median([r["device_ms"] for r in rs]))
+    updates = rs[0]["grid_point_updates"]
+    print(f"euler rate: {args.steps} solves of {rate_steps} steps, median {dev_ms:.2f} ms",
+          file=sys.stderr, flush=True)
+    npb.npb_ctx_set_timing(s.ctx, True)
+    s.run()
+    torch.cuda.synchronize()
+    kt = npb.npb_ctx_get_kernel_times(s.ctx)
+    npb.npb_ctx_set_timing(s.ctx, False)
+    ke = kt["by_kernel"]["euler"]
+    avg_us = 1e3 * ke["ms"] / max(ke["count"], 1)
+    bytes_per_launch = ke["bytes"] / max(ke["count"], 1)
+    gbps = bytes_per_launch / (avg_us * 1e-6) / 1e9
+    del s
+    # parity of a short full-size run
+    ref = _golden("globular_2000_161_euler40.json")
+    g40 = npb.solve(w.molecule, w.grid, inputs.globular_2000_euler(n_steps=40).params,
+                    want_field=True, vacuum_direct=True)
+    phi = g40["phi"].ravel()
+    d = np.array([phi[i] for i in ref["field_nodes"]]) - np.array(ref["phi_m"])
+    parity = {"dG_direct": g40["dG_direct"], "oracle_dG_direct": ref["dG_direct"],
+              "abs_err": abs(g40["dG_direct"] - ref["dG_direct"]),
+              "sampled_field_rel_err": float(np.max(np.abs(d)) / ref["phi_m_absmax"])}
+    # reference runs
+    refs = []
+    for T in (0.5 * args.euler_t, args.euler_t):
+        n = int(round(T / 1e-5))
+        we = inputs.globular_2000_euler(n_steps=n)
+        t1 = time.perf_counter()
+        r = npb.solve(we.molecule, we.grid, we.params, vacuum_direct=True)
+        el = time.perf_counter() - t1
+        print(f"euler reference T={T:g} ({n} steps): dG {r['dG_direct']:.4f} kcal/mol, "
+              f"{el:.1f} s", file=sys.stderr, flush=True)
+        refs.append({"T": T, "steps": n, "dG": r["dG_direct"], "G_m": r["G_m"][0],
+                     "device_s": r["device_ms"] * 1e-3, "wall_s": el, "finite": r["finite"]})
+    lod = {}
+    for prec in ("f64", "f32"):
+        wl = inputs.globular_2000(precision=prec)
+        r = npb.solve(wl.molecule, wl.grid, wl.params, vacuum_direct=True)
+        lod[prec] = {"RE+V": r["dG"], "RE (phi_0 direct)": r["dG_direct"],
+                     "RE+V minus Euler": r["dG"] - refs[-1]["dG"],
+                     "RE minus Euler": r["dG_direct"] - refs[-1]["dG"],
+                     "device_ms": r["device_ms"]}
+    return {"metric": "explicit Euler grid-point-updates/s (FP64 reference solver)",
+            "value": updates / (dev_ms * 1e-3), "unit": "grid-point-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": w.name, "grid": [w.grid.nx, w.grid.ny, w.grid.nz],
+                       "dt": 1e-5, "alpha": w.params.alpha, "euler_steps_per_solve": rate_steps,
+                       "vacuum": "direct Poisson solve (Eq. (deltaG2))"},
+            "device_ms_median": dev_ms,
+            "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4),
+                         "traffic": _traffic("npb::(anonymous namespace)::euler_step_kernel<32, 8>",
+                                             "f64"),
+                         "kernel": "npb::euler_step_kernel<32, 8>", "avg_launch_us": round(avg_us, 2),
+                         "algorithmic_bytes_per_launch": bytes_per_launch,
+                         "bytes_per_node": 17, "interior_nodes": X * Y * Z,
+                         "timing": "kernel-attached HIP events (hipExtLaunchKernelGGL) on every "
+                                   "step launch of one solve"},
+            "parity_40_steps": parity, "reference": refs, "lodie2": lod}
+
+
 def bench_serve(args):
     """Serving: requests with atom counts log-uniform 500..20000 (grids
     103..257 at h = 0.5), LODIE2 RE+V 20/40 steps, Poisson arrivals (seed 4)
@@ -478,6 +566,10 @@ def main():
     ap.add_argument("--sphere", action="store_true",
                     help="the analytic charged-cavity benchmark: spatial / temporal "
                          "convergence and stability of the schemes (own JSON line)")
+    ap.add_argument("--euler", action="store_true",
+                    help="the explicit Euler reference solver: step rate, roofline, and the "
+                         "reference energy at T = --euler-t (own JSON line)")
+    ap.add_argument("--euler-t", type=float, default=10.0)
     ap.add_argument("--serve", action="store_true",
                     help="time the request loop under Poisson arrivals instead (own JSON line)")
     ap.add_argument("--requests", type=int, default=48)
@@ -503,6 +595,9 @@ def main():
         return
     if args.sphere:
         print(json.dumps(bench_sphere(args)))
+        return
+    if args.euler:
+        print(json.dumps(bench_euler(args)))
         return
     if args.large:
         print(json.dumps(bench_large(args)))

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NPB_ABI_VERSION 4
+#define NPB_ABI_VERSION 5
 
 typedef enum npb_status {
   NPB_OK = 0,
@@ -58,7 +58,13 @@ typedef enum npb_scheme {
   NPB_AOSCN2 = 7,  /* additive, Crank-Nicolson, source split (Eqs. (AOSCN2_2)-(AOSCN2_4)) */
   NPB_MAOSIE = 8,  /* nonlinear sub-step, then the mean of three implicit-Euler
                       directional solves (Sec. 3.3, Eqs. (MAOS1_1)-(MAOS1_5)) */
-  NPB_MAOSCN = 9   /* the same with Crank-Nicolson directional solves (Sec. 3.3) */
+  NPB_MAOSCN = 9,  /* the same with Crank-Nicolson directional solves (Sec. 3.3) */
+  NPB_EULER = 10   /* explicit Euler step of Eq. (TimeDepNPB) with the operator of
+                      Eq. (SpatialOperators): u += tau (div eps grad u - kbar^2
+                      sinh u + rho), tau = dt / alpha.  The paper's reference
+                      solver (Sec. 2.3; Sec. 5.2 and 5.4: dt = 1e-5, T = 10).
+                      Stable only for tau below 2 / (largest eigenvalue of the
+                      linearised operator), about h^2 / (6 eps_out); FP64 only */
 } npb_scheme;
 
 typedef enum npb_precision {
@@ -105,12 +111,13 @@ typedef struct npb_grid {
  *                     (no pseudo-time: the constant-eps_in 7-point problem
  *                     with the vacuum Dirichlet data, by type-I sine
  *                     transforms in FP64; the paper's "FFT" phi_0, Sec. 5.1)
- *                     and report dG_direct (Eq. (deltaG2)); needs vacuum = 1
+ *                     and report dG_direct (Eq. (deltaG2)); with vacuum = 0
+ *                     the direct solve is the only vacuum problem
  *   field_select    : which potential d_field_out receives:
  *                     0 = solvated, 1 = vacuum by the scheme (needs vacuum),
  *                     2 = vacuum by the direct solve (needs vacuum_direct),
  *                     3 = recovered potential phi_m - phi_0 + phi_0^direct
- *                         (Sec. 5.4; needs vacuum_direct); phi_m and phi_0
+ *                         (Sec. 5.4; needs vacuum and vacuum_direct); phi_m and phi_0
  *                         Richardson-combined when richardson = 1
  *   field_units     : npb_field_units of d_field_out
  *   reserved        : must be 0                                             */
@@ -175,25 +182,27 @@ typedef struct npb_ctx npb_ctx;
  * kcount/kms/kbytes split the sweep launches again by the kernel that ran
  * them, indexed by npb_sweep_kernel. */
 typedef struct npb_kernel_times {
-  int64_t count[8];
-  double ms[8];
-  double bytes[8];   /* algorithmic bytes moved by those launches */
-  int64_t kcount[4];
-  double kms[4];
-  double kbytes[4];
+  int64_t count[12];
+  double ms[12];
+  double bytes[12];  /* algorithmic bytes moved by those launches */
+  int64_t kcount[8];
+  double kms[8];
+  double kbytes[8];
 } npb_kernel_times;
 
 enum npb_kernel_class {
   NPB_K_SWEEP_X = 0, NPB_K_SWEEP_Y = 1, NPB_K_SWEEP_Z = 2,
   NPB_K_SETUP = 3, NPB_K_INIT = 4, NPB_K_ENERGY = 5, NPB_K_OTHER = 6,
-  NPB_K_DIRECT = 7  /* the direct vacuum Poisson solve (vacuum_direct) */
+  NPB_K_DIRECT = 7, /* the direct vacuum Poisson solve (vacuum_direct) */
+  NPB_K_EULER = 8   /* explicit Euler steps (NPB_EULER) */
 };
 
 enum npb_sweep_kernel {
   NPB_SK_X = 0,          /* x sweep (every scheme)                              */
   NPB_SK_YZ_PLAIN = 1,   /* y/z sweep, line solves only                         */
   NPB_SK_YZ_FLOW = 2,    /* y/z sweep fused with the sinh sub-step (LODIE2 z)   */
-  NPB_SK_YZ_GENERAL = 3  /* y/z sweep with sources and AOS accumulation         */
+  NPB_SK_YZ_GENERAL = 3, /* y/z sweep with sources and AOS accumulation         */
+  NPB_SK_EULER = 4       /* explicit Euler step (kernel-attached events too)    */
 };
 
 /* A grid for a molecule: per axis, the atoms' extent (positions +- radii)

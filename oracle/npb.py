@@ -542,7 +542,8 @@ def solve(mol, grid, params, want_fields: bool = False, vacuum_direct: bool = Fa
       dG_plain        : (1/2) sum Q (phi_m - phi_0) at dt
       dG              : the same from the Richardson-combined potentials
                         (equal to dG_plain without Richardson).
-    With vacuum_direct (needs params.vacuum) also:
+    With vacuum_direct also (params.vacuum may be off: the direct solve is
+    then the only vacuum problem):
       dG_direct       : (1/2) sum Q (phi_m - phi_0^FFT), Eq. (deltaG2), with
                         phi_m Richardson-combined when Richardson is on and
                         phi_0^FFT from poisson_direct
@@ -577,14 +578,13 @@ def solve(mol, grid, params, want_fields: bool = False, vacuum_direct: bool = Fa
         out["dG_plain"] = float("nan")
         out["dG"] = float("nan")
     if vacuum_direct:
-        if not params.vacuum:
-            raise ValueError("vacuum_direct needs the vacuum problem")
         u_dir = poisson_direct(make_problem(mol, grid, params, "vacuum"))
         umf = fields["solvated"][1]
         out["dG_direct"] = 0.5 * float(np.sum(Qc * (kT * umf - kT * u_dir)))
         if want_fields:
             out["phi_0_direct"] = kT * u_dir
-            out["phi_rec"] = kT * umf - kT * fields["vacuum"][1] + kT * u_dir
+            if params.vacuum:
+                out["phi_rec"] = kT * umf - kT * fields["vacuum"][1] + kT * u_dir
     if want_fields:
         out["phi_m"] = kT * fields["solvated"][1]
         out["u_m_levels"] = fields["solvated"][0]

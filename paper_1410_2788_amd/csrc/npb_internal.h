@@ -297,4 +297,32 @@ hipError_t launch_direct_poisson(const DirectPoissonArgs& a, hipStream_t st);
 hipError_t launch_direct_field_out(double* out, const double* u, const double* bc, int nx, int ny,
                                    int nz, double beta, double gamma, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// explicit Euler steps (euler_kernels.hip), FP64
+
+struct EulerArgs {
+  const double* u;        // field at step n, [nz][ny][nxp]
+  double* v;              // field at step n + 1 (interior written; shell kept)
+  const uint8_t* flags;   // bit 0 solute node, bit 1 node with a source entry
+  const int* src_ptr;     // per-x-line offsets into q_idx / q_rho (line k*ny + j)
+  const int* q_idx;       // pitched linear index of each charge node, sorted
+  const double* q_rho;    // source density at it
+  int nx, ny, nz, nxp;
+  int zc;                 // z planes per block (euler_z_chunk)
+  int uniform;            // 1: uniform medium (vacuum), re_uniform on every face
+  int nl;                 // 1: kbar^2 sinh(u) term on solvent nodes
+  double re[3];           // tau eps_face / h^2 for (sum of the two solute bits) = 0, 1, 2
+  double re_uniform;
+  double tau;             // dt / alpha (source coefficient)
+  double tk;              // tau kbar^2
+};
+
+int euler_z_chunk(int nx, int ny, int nz);
+// flags from the solute mask (nullptr: none) and the charge list
+hipError_t launch_euler_flags(const uint8_t* mask, const int* q_idx, const int* nq, int cap,
+                              uint8_t* flags, size_t n, hipStream_t st);
+// one step; start / stop (both or neither) are recorded by the kernel itself
+hipError_t launch_euler_step(const EulerArgs& a, hipEvent_t start, hipEvent_t stop,
+                             hipStream_t st);
+
 }  // namespace npb

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "npb.h"
@@ -435,6 +436,7 @@ struct Layout {
   size_t mask, bc_s, bc_v, atoms, tabs, key_a, id_a, key_b, id_b, sval, hist, heads;
   size_t q_idx, q_val, q_rho, xptr, yptr, ylin, yrho, zptr, zlin, zrho, ccls[3], slots, ints, total;
   size_t direct;  // work of the direct vacuum Poisson solve (vacuum_direct)
+  size_t flags;   // explicit Euler node flags (solute bit, source bit)
   LaunchShape shape[3];
   Run runs[kMaxFields];
   int n_runs, cap, nblocks;
@@ -491,6 +493,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   const int nb = (cap + 255) / 256;
   const size_t ns = (size_t)shell_count(g->nx, g->ny, g->nz);
   const bool aos = is_aos(p->scheme);
+  const bool euler = p->scheme == NPB_EULER;
   const bool ys = needs_y_sources(p->scheme), zs = needs_z_sources(p->scheme);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -501,11 +504,12 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   L.n_runs = make_runs(p, L.runs);
   for (int r = 0; r < kMaxFields; ++r) {
     L.field[r] = take(r < L.n_runs ? n * es : 0);
-    L.acc[r] = take(r < L.n_runs && aos ? n * es : 0);
+    // AOS accumulator, or the second buffer of the explicit Euler steps
+    L.acc[r] = take(r < L.n_runs && (aos || euler) ? n * es : 0);
   }
   L.mask = take(n);
   L.bc_s = take(ns * 8);
-  L.bc_v = take(p->vacuum ? ns * 8 : 0);
+  L.bc_v = take(p->vacuum || p->vacuum_direct ? ns * 8 : 0);
   L.atoms = take((size_t)5 * na * 8);
   L.tabs = take(kTabBytes * 3 * kMaxFields);
   L.key_a = take((size_t)cap * 4);
@@ -539,6 +543,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   L.slots = take(32 * 8);
   L.ints = take(16 * 4);
   L.direct = take(p->vacuum_direct ? direct_poisson_bytes(g->nx, g->ny, g->nz) : 0);
+  L.flags = take(euler ? n : 0);
   L.total = off;
   L.cap = cap;
   L.nblocks = nb;
@@ -590,11 +595,12 @@ npb_status validate(const npb_molecule* mol, const npb_grid* g, const npb_params
   if (!(p->alpha > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->alpha) || !std::isfinite(p->dt))
     return fail(NPB_EINVAL, "alpha and dt must be positive");
   if (p->n_steps < 1) return fail(NPB_EINVAL, "n_steps must be >= 1");
-  if (p->scheme < 0 || p->scheme > 9) return fail(NPB_EINVAL, "unknown scheme");
+  if (p->scheme < 0 || p->scheme > 10) return fail(NPB_EINVAL, "unknown scheme");
   if (p->precision < 0 || p->precision > 2) return fail(NPB_EINVAL, "unknown precision");
+  if (p->scheme == NPB_EULER && p->precision != NPB_FP64)
+    return fail(NPB_EINVAL, "explicit Euler runs in FP64 only (precision 0)");
   if (p->vacuum_direct != 0 && p->vacuum_direct != 1)
     return fail(NPB_EINVAL, "vacuum_direct must be 0 or 1");
-  if (p->vacuum_direct && !p->vacuum) return fail(NPB_EINVAL, "vacuum_direct needs vacuum = 1");
   if (p->reserved != 0) return fail(NPB_EINVAL, "params.reserved must be 0");
   if (p->field_units != NPB_UNITS_KCAL && p->field_units != NPB_UNITS_DIMENSIONLESS)
     return fail(NPB_EINVAL, "unknown field_units");
@@ -603,6 +609,7 @@ npb_status validate(const npb_molecule* mol, const npb_grid* g, const npb_params
   if (p->field_select == 1 && !p->vacuum) return fail(NPB_EINVAL, "field_select 1 needs vacuum = 1");
   if (p->field_select >= 2 && !p->vacuum_direct)
     return fail(NPB_EINVAL, "field_select 2 and 3 need vacuum_direct = 1");
+  if (p->field_select == 3 && !p->vacuum) return fail(NPB_EINVAL, "field_select 3 needs vacuum = 1");
   if (mol->n_atoms < 0) return fail(NPB_EINVAL, "negative atom count");
   if (mol->n_atoms > 0 && (!mol->xyz || !mol->q || !mol->radius))
     return fail(NPB_EINVAL, "null atom arrays");
@@ -834,6 +841,7 @@ struct Engine {
   npb_status plan() {
     for (int i = 0; i < (int)pr.size(); ++i) {
       const Problem& P = pr[i];
+      if (P.p->scheme == NPB_EULER) continue;  // stepped by euler_loop
       const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
       for (int r = 0; r < P.L.n_runs; ++r) {
         Field f{};
@@ -1060,18 +1068,23 @@ struct Engine {
       } else {
         const double kappa = std::sqrt(p->kappa_bar_sq / p->eps_out);
         e = launch_boundary(sa, p->eps_out, kappa, p->eps_in, P.lB, P.at<double>(L.bc_s),
-                            p->vacuum ? P.at<double>(L.bc_v) : nullptr, sizeof(A) == 4, st);
+                            p->vacuum || p->vacuum_direct ? P.at<double>(L.bc_v) : nullptr,
+                            sizeof(A) == 4, st);
       }
       if (e != hipSuccess) return e;
       for (int d = 0; d < 3 && e == hipSuccess; ++d)
         e = launch_chunk_classes(P.at<uint8_t>(L.mask), nx, nxp, ny, nz, d, L.shape[d].M,
                                  L.shape[d].P, P.at<uint8_t>(L.ccls[d]), st);
+      if (e == hipSuccess && p->scheme == NPB_EULER)
+        e = launch_euler_flags(P.at<uint8_t>(L.mask), P.at<int>(L.q_idx), ints, L.cap,
+                               P.at<uint8_t>(L.flags), n, st);
       return e;
     });
   }
 
   npb_status time_loop() {
     for (const Problem& P : pr) {
+      if (P.p->scheme == NPB_EULER) continue;
       const int nx = P.g->nx, ny = P.g->ny, nz = P.g->nz;
       const int nxp = pitch_of(nx, (int)sizeof(T));
       InitSet<T> set{};
@@ -1166,6 +1179,89 @@ struct Engine {
     return NPB_OK;
   }
 
+  // Explicit Euler (NPB_EULER): both buffers of every run start from the
+  // initial field; a run of s steps starts in its field buffer when s is
+  // even and in the second buffer when s is odd, so that it ends in the
+  // field buffer.  One launch per step and run, steps outermost.
+  npb_status euler_loop() {
+    if constexpr (!std::is_same<T, double>::value) {
+      for (const Problem& P : pr)
+        if (P.p->scheme == NPB_EULER) return fail(NPB_EINVAL, "explicit Euler runs in FP64 only");
+      return NPB_OK;
+    } else {
+      struct ERun {
+        const Problem* P;
+        int r, steps;
+        EulerArgs a;
+        double bytes;
+      };
+      std::vector<ERun> runs;
+      int max_steps = 0;
+      for (const Problem& P : pr) {
+        if (P.p->scheme != NPB_EULER) continue;
+        const int nx = P.g->nx, ny = P.g->ny, nz = P.g->nz;
+        const int nxp = pitch_of(nx, (int)sizeof(T));
+        for (int r = 0; r < P.L.n_runs; ++r) {
+          const bool vac = P.L.runs[r].medium == 1;
+          for (int b = 0; b < 2; ++b) {
+            T* buf = P.at<T>(b == 0 ? P.L.field[r] : P.L.acc[r]);
+            npb_status s = timed(NPB_K_INIT, (double)nxp * ny * nz * sizeof(T), [&] {
+              return P.fields() ? launch_field_from_dense<T>(buf, P.fu0, nx, nxp, ny, nz, st)
+                                : launch_field_init<T>(buf, P.at<double>(vac ? P.L.bc_v : P.L.bc_s),
+                                                       nx, nxp, ny, nz, st);
+            });
+            if (s != NPB_OK) return s;
+          }
+          const Coefs c = run_coefs(P, P.L.runs[r]);
+          ERun e{};
+          e.P = &P;
+          e.r = r;
+          e.steps = P.p->n_steps << P.L.runs[r].level;
+          EulerArgs& a = e.a;
+          a.flags = P.at<uint8_t>(P.L.flags);
+          a.src_ptr = P.at<int>(P.L.xptr);
+          a.q_idx = P.at<int>(P.L.q_idx);
+          a.q_rho = P.at<double>(P.L.q_rho);
+          a.nx = nx;
+          a.ny = ny;
+          a.nz = nz;
+          a.nxp = nxp;
+          a.zc = euler_z_chunk(nx, ny, nz);
+          a.uniform = vac ? 1 : 0;
+          a.nl = c.nl ? 1 : 0;
+          for (int k = 0; k < 3; ++k) a.re[k] = c.re[k];
+          a.re_uniform = c.re_uniform;
+          a.tau = c.tau;
+          a.tk = c.nl ? c.tau * P.p->kappa_bar_sq : 0.0;
+          // field read + write and the flag byte per interior node
+          e.bytes = (double)(nx - 2) * (ny - 2) * (nz - 2) * (2.0 * sizeof(T) + 1.0);
+          runs.push_back(e);
+          max_steps = std::max(max_steps, e.steps);
+        }
+      }
+      for (int step = 0; step < max_steps; ++step)
+        for (ERun& e : runs) {
+          if (step >= e.steps) continue;
+          const bool from_field = ((step % 2) == 0) == ((e.steps % 2) == 0);
+          T* fld = e.P->template at<T>(e.P->L.field[e.r]);
+          T* alt = e.P->template at<T>(e.P->L.acc[e.r]);
+          e.a.u = from_field ? fld : alt;
+          e.a.v = from_field ? alt : fld;
+          hipEvent_t a0 = nullptr, a1 = nullptr;
+          if (ctx->timing) {
+            a0 = ev_get(ctx);
+            a1 = ev_get(ctx);
+            if (!a0 || !a1) return fail(NPB_EDEVICE, "event creation failed");
+          }
+          const hipError_t err = launch_euler_step(e.a, a0, a1, st);
+          if (err != hipSuccess)
+            return fail(NPB_EDEVICE, std::string("launch: ") + hipGetErrorString(err));
+          if (ctx->timing) ctx->pending.push_back({NPB_K_EULER, NPB_SK_EULER, a0, a1, e.bytes});
+        }
+      return NPB_OK;
+    }
+  }
+
   // The device work after staging, all on `st` (captured into a graph when
   // replay is on): setup, time loops, energies, optional fields,
   // combinations.  Launches only: no allocation, copy or synchronisation.
@@ -1180,6 +1276,8 @@ struct Engine {
       if (s != NPB_OK) return s;
     }
     npb_status s = time_loop();
+    if (s != NPB_OK) return s;
+    s = euler_loop();
     if (s != NPB_OK) return s;
     for (Problem& P : pr) {
       const Layout& L = P.L;
@@ -1277,13 +1375,21 @@ struct Engine {
     return k;
   }
 
+  static constexpr long long kMaxGraphEulerLaunches = 4096;
+
   // async: out is page-locked host memory written by a last kernel; the
   // call returns once everything is enqueued
   npb_status run(npb_result* out, bool async = false) {
     // A replay of the graph of the same batch needs only the atoms and the
     // chunk tables staged again; the launch tables in the context's buffer
     // are the ones the graph was captured with.
-    const bool graph = ctx->graphs && !ctx->timing;
+    // long explicit Euler runs launch once per step: no graph of that size
+    long long euler_launches = 0;
+    for (const Problem& P : pr)
+      if (P.p->scheme == NPB_EULER)
+        for (int r = 0; r < P.L.n_runs; ++r)
+          euler_launches += (long long)P.p->n_steps << P.L.runs[r].level;
+    const bool graph = ctx->graphs && !ctx->timing && euler_launches <= kMaxGraphEulerLaunches;
     std::vector<unsigned char> key = graph_key();
     const bool replay = graph && ctx->exec && key == ctx->key;
     npb_status s = NPB_OK;
@@ -1805,6 +1911,8 @@ npb_status npb_autotune(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* g
   if (!ctx || !mol || !grid || !params) return fail(NPB_EINVAL, "null argument");
   npb_status s = validate(mol, grid, params);
   if (s != NPB_OK) return s;
+  if (params->scheme == NPB_EULER)
+    return fail(NPB_EINVAL, "explicit Euler has no line-solver shapes to tune");
   std::vector<Problem> pr(1);
   Problem& P = pr[0];
   P.mol = mol;

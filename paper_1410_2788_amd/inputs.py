@@ -160,6 +160,19 @@ def globular_2000(precision: str = "f32", scheme: str = "LODIE2") -> Workload:
                          vacuum=True, precision=precision))
 
 
+def globular_2000_euler(n_steps: int = 1_000_000, dt: float = 1e-5) -> Workload:
+    """The 2000-atom workload for the explicit Euler reference solver: FP64,
+    dt = 1e-5 with alpha = 1/25 (T = n_steps dt; the paper's reference uses
+    T = 10), no Richardson; the vacuum potential comes from the direct
+    Poisson solve (vacuum_direct), as in Eq. (deltaG2)."""
+    w = globular_2000(precision="f64", scheme="EULER")
+    w.name = "globular_2000_161_euler"
+    w.params = RunParams(eps_in=2.0, eps_out=80.0, ionic_molar=0.15, temperature_K=298.0,
+                         alpha=1.0 / 25.0, dt=dt, n_steps=n_steps, scheme="EULER",
+                         richardson=False, vacuum=False, precision="f64")
+    return w
+
+
 def large_complex(precision: str = "f32", scheme: str = "LODIE2", dt: float = 0.4,
                   n_steps: int = 20) -> Workload:
     """30000 atoms in a 45:36:27 A ellipsoid (seed 5), net -12 e; eps 4/80;

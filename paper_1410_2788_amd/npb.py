@@ -22,12 +22,13 @@ NPB_OK, NPB_EINVAL, NPB_ERANGE, NPB_ENOMEM, NPB_EDEVICE, NPB_EDIVERGED, NPB_EBUS
 STATUS_NAMES = {0: "NPB_OK", 1: "NPB_EINVAL", 2: "NPB_ERANGE", 3: "NPB_ENOMEM",
                 4: "NPB_EDEVICE", 5: "NPB_EDIVERGED", 6: "NPB_EBUSY"}
 SCHEMES = {"LODIE2": 0, "LODIE1": 1, "AOSIE2": 2, "AOSIE1": 3, "LODCN1": 4, "LODCN2": 5,
-           "AOSCN1": 6, "AOSCN2": 7, "MAOSIE": 8, "MAOSCN": 9}
+           "AOSCN1": 6, "AOSCN2": 7, "MAOSIE": 8, "MAOSCN": 9, "EULER": 10}
 PRECISIONS = {"f64": 0, "f32": 1, "f32x": 2}
-KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other", "direct"]
+KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "other", "direct",
+                  "euler"]
 # sweep launches split again by the kernel that ran them (npb_sweep_kernel)
-SWEEP_KERNELS = ["x", "yz_plain", "yz_flow", "yz_general"]
-ABI_VERSION = 4
+SWEEP_KERNELS = ["x", "yz_plain", "yz_flow", "yz_general", "euler"]
+ABI_VERSION = 5
 
 
 class npb_molecule(C.Structure):
@@ -58,8 +59,8 @@ class npb_result(C.Structure):
 
 
 class npb_kernel_times(C.Structure):
-    _fields_ = [("count", C.c_int64 * 8), ("ms", C.c_double * 8), ("bytes", C.c_double * 8),
-                ("kcount", C.c_int64 * 4), ("kms", C.c_double * 4), ("kbytes", C.c_double * 4)]
+    _fields_ = [("count", C.c_int64 * 12), ("ms", C.c_double * 12), ("bytes", C.c_double * 12),
+                ("kcount", C.c_int64 * 8), ("kms", C.c_double * 8), ("kbytes", C.c_double * 8)]
 
 
 class npb_server_stats(C.Structure):

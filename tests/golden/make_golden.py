@@ -4,7 +4,8 @@ Calls only the FP64 oracle (and the seeded input generators); nothing here
 comes from the HIP library.
 
 Usage:  python tests/golden/make_golden.py [name ...]
-        names: globular_2000, globular_2000_direct, large_complex_lod04,
+        names: globular_2000, globular_2000_direct, globular_2000_euler,
+               large_complex_lod04,
                large_complex_lod02, large_complex_aos04, batch_mix_samples,
                serve_samples
         (no name: all of them; each writes its own JSON file)
@@ -105,6 +106,23 @@ def globular_2000_direct():
     _write("globular_2000_161_direct.json", out)
 
 
+def globular_2000_euler():
+    """40 explicit Euler steps (dt 1e-5, alpha 1/25) of the benchmark
+    molecule with the direct vacuum solve: G_m, Eq. (deltaG2) energy and
+    sampled nodes of phi_m."""
+    w = inputs.globular_2000_euler(n_steps=40)
+    t = time.time()
+    r = oracle.solve(w.molecule, w.grid, w.params, want_fields=True, vacuum_direct=True)
+    nodes = _sample_nodes(w.grid, r["phi_m"], 3)
+    out = {"_source": "oracle.solve(..., vacuum_direct=True) on inputs.globular_2000_euler("
+                      "n_steps=40) (seed 2, 161^3, explicit Euler, dt 1e-5, alpha 1/25)",
+           "G_m": r["G_m"], "dG_direct": r["dG_direct"], "field_nodes": nodes,
+           "phi_m": [float(r["phi_m"].ravel()[i]) for i in nodes],
+           "phi_m_absmax": float(np.max(np.abs(r["phi_m"]))),
+           "oracle_seconds": time.time() - t}
+    _write("globular_2000_161_euler40.json", out)
+
+
 def _large(scheme, dt, n_steps, tag):
     w = inputs.large_complex(precision="f64", scheme=scheme, dt=dt, n_steps=n_steps)
     out = _record(w, f"oracle.solve on inputs.large_complex(scheme={scheme!r}, dt={dt}, "
@@ -149,7 +167,7 @@ def serve_samples():
     _write("serve_48_samples.json", out)
 
 
-ALL = [globular_2000, globular_2000_direct, large_complex_lod04, large_complex_lod02, large_complex_aos04,
+ALL = [globular_2000, globular_2000_direct, globular_2000_euler, large_complex_lod04, large_complex_lod02, large_complex_aos04,
        batch_mix_samples, serve_samples]
 
 if __name__ == "__main__":

@@ -29,7 +29,7 @@ def test_every_declared_function_is_exported(npb):
 
 
 def test_version_and_kappa_helper(npb):
-    assert npb.npb_abi_version() == npb.ABI_VERSION == 4
+    assert npb.npb_abi_version() == npb.ABI_VERSION == 5
     g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     assert npb.npb_kappa_bar_sq(1.0, 298.0) == pytest.approx(g["kbar2_per_molar_298_inv_A2"], rel=1e-15)
     assert npb.npb_kappa_bar_sq(0.1, 300.0) == pytest.approx(0.84303, rel=1e-5)
@@ -50,7 +50,7 @@ def test_validate_accepts_a_good_problem(npb):
 @pytest.mark.parametrize("field,value", [
     ("nx", 4), ("h", 0.0), ("h", -1.0), ("eps_in", 0.0), ("eps_out", -2.0),
     ("kappa_bar_sq", -1e-3), ("alpha", 0.0), ("dt", 0.0), ("n_steps", 0),
-    ("scheme", 10), ("precision", 5), ("field_select", 1), ("field_units", 2),
+    ("scheme", 11), ("precision", 5), ("field_select", 1), ("field_units", 2),
     ("reserved", 1)])
 def test_validate_rejects_bad_arguments(npb, field, value):
     w = inputs.small_globular(n=25, n_atoms=10)
@@ -156,7 +156,10 @@ def test_direct_vacuum_parameters_are_validated(npb):
                                                       vacuum_direct=True)) == npb.NPB_EINVAL
     import dataclasses
     novac = dataclasses.replace(w.params, vacuum=False)
-    assert npb.npb_validate(mol.c, g, npb.make_params(novac, vacuum_direct=True)) == npb.NPB_EINVAL
+    # the direct solve alone as the vacuum problem; the recovered field needs both
+    assert npb.npb_validate(mol.c, g, npb.make_params(novac, vacuum_direct=True)) == npb.NPB_OK
+    assert npb.npb_validate(mol.c, g, npb.make_params(novac, field_select=3,
+                                                      vacuum_direct=True)) == npb.NPB_EINVAL
     # the workspace grows by the interior field and the transform tables
     b0 = npb.npb_workspace_bytes(mol.c, g, npb.make_params(w.params))
     b1 = npb.npb_workspace_bytes(mol.c, g, ok)

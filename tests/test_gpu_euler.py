@@ -1,0 +1,161 @@
+"""GPU parity of the explicit Euler reference solver (npb_scheme NPB_EULER,
+FP64) against the oracle's euler_step, through the C ABI.
+
+Tolerances as for the other FP64 paths: field max|d phi| <= 1e-10 max|phi|,
+energies within 1e-9 relative (1e-8 kcal/mol absolute).  Steps are taken at
+dt = 1e-5 with alpha = 1/25 (the paper's reference step; tau = 2.5e-4, half
+the explicit limit h^2 / (6 eps_out) at h = 0.5)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_2788_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _w(n=33, ny=None, nz=None, n_atoms=40, n_steps=30, seed=31, richardson=True, vacuum=True,
+       dt=1e-5):
+    w = inputs.small_globular(seed=seed, n=n, ny=ny, nz=nz, n_atoms=n_atoms, n_steps=n_steps,
+                              scheme="EULER", richardson=richardson, dt=dt)
+    w.params = dataclasses.replace(w.params, vacuum=vacuum)
+    return w
+
+
+def _close(got, ref, rel=1e-9, abs_=1e-8):
+    return abs(got - ref) <= max(abs_, rel * abs(ref))
+
+
+def _compare(w, field_select=0, vacuum_direct=False):
+    from paper_1410_2788_amd import npb
+    p = w.params
+    _say(f"case euler grid=({w.grid.nx},{w.grid.ny},{w.grid.nz}) atoms={w.molecule.n_atoms} "
+         f"steps={p.n_steps} rich={p.richardson} vac={p.vacuum} fs={field_select}")
+    g = npb.solve(w.molecule, w.grid, p, want_field=True, field_select=field_select,
+                  vacuum_direct=vacuum_direct)
+    o = oracle.solve(w.molecule, w.grid, p, want_fields=True, vacuum_direct=vacuum_direct)
+    keys = [("G_m", 0)] + ([("G_0", 0)] if p.vacuum else [])
+    if p.richardson:
+        keys += [("G_m", 1)] + ([("G_0", 1)] if p.vacuum else [])
+    for k, lv in keys:
+        assert _close(g[k][lv], o[k][lv]), (k, lv, g[k][lv], o[k][lv])
+    if p.vacuum:
+        for k in ("dG", "dG_plain"):
+            assert _close(g[k], o[k]), (k, g[k], o[k])
+    if vacuum_direct:
+        assert _close(g["dG_direct"], o["dG_direct"]), (g["dG_direct"], o["dG_direct"])
+    ref = {0: "phi_m", 1: "phi_0", 3: "phi_rec"}[field_select]
+    err = float(np.max(np.abs(g["phi"] - o[ref])) / np.max(np.abs(o[ref])))
+    _say(f"  dG gpu {g.get('dG')} oracle {o.get('dG')}  field rel err {err:.3e}")
+    assert err <= 1e-10
+    assert g["steps_done"] == sum(p.n_steps << lv for lv in range(2 if p.richardson else 1)) * \
+        (2 if p.vacuum else 1)
+    return g
+
+
+def test_euler_matches_oracle_on_ragged_tiles():
+    # 35 x 27 x 29 interior nodes: partial x and y tiles and a short last
+    # z chunk
+    _compare(_w(n=37, ny=29, nz=31))
+
+
+@pytest.mark.parametrize("n_steps", [1, 7])
+def test_euler_odd_and_single_step_counts_end_in_the_field(n_steps):
+    _compare(_w(n=25, n_atoms=15, n_steps=n_steps, richardson=False))
+
+
+def test_euler_vacuum_field_and_direct_recovery():
+    w = _w(n=29, n_atoms=25, n_steps=12)
+    _compare(w, field_select=1)
+    _compare(w, field_select=3, vacuum_direct=True)
+
+
+def test_euler_with_the_direct_solve_as_the_only_vacuum_problem():
+    # the paper's reference: phi_m by explicit Euler, phi_0 by the fast
+    # Poisson solver (Eq. (deltaG2)); no vacuum time loop
+    w = _w(n=27, n_atoms=20, n_steps=10, vacuum=False)
+    g = _compare(w, vacuum_direct=True)
+    assert np.isnan(g["dG"]) and g["G_0"] == [0.0, 0.0]
+
+
+def test_euler_without_salt_and_without_vacuum():
+    w = _w(n=27, n_atoms=20, n_steps=9, vacuum=False, richardson=False)
+    w.params = dataclasses.replace(w.params, ionic_molar=0.0)
+    _compare(w)
+
+
+def test_long_euler_run_launches_without_a_graph():
+    # 1200 + 2400 steps per medium (7200 launches) exceed the graph limit:
+    # the solve is issued eagerly; twice in a row gives the same result
+    from paper_1410_2788_amd import npb
+    w = _w(n=19, n_atoms=8, n_steps=1200, seed=5)
+    g = _compare(w)
+    again = npb.solve(w.molecule, w.grid, w.params, want_field=True)
+    assert again["dG"] == g["dG"] and np.array_equal(again["phi"], g["phi"])
+
+
+def test_euler_graph_replay_is_bit_identical():
+    from paper_1410_2788_amd import npb
+    w = _w(n=25, n_atoms=12, n_steps=40)
+    s = npb.Solver(w.molecule, w.grid, w.params, want_field=True)
+    first = s.run()
+    phi = s.field.cpu().numpy().copy()
+    for _ in range(3):
+        r = s.run()
+        assert r["dG"] == first["dG"]
+        assert np.array_equal(s.field.cpu().numpy(), phi)
+
+
+def test_batch_mixing_euler_and_split_schemes_equals_single_solves():
+    from paper_1410_2788_amd import npb
+    a = _w(n=29, n_atoms=30, n_steps=6, seed=41)
+    b = inputs.small_globular(seed=42, n=33, n_atoms=50, n_steps=4, scheme="LODIE2")
+    c = _w(n=25, n_atoms=12, n_steps=11, seed=43, richardson=False)
+    probs = [a, b, c]
+    bs = npb.BatchSolver([(w.molecule, w.grid, w.params) for w in probs], want_field=True)
+    res = bs.run()
+    for i, w in enumerate(probs):
+        one = npb.solve(w.molecule, w.grid, w.params, want_field=True)
+        for k in ("dG", "dG_plain", "G_m", "G_0", "steps_done"):
+            assert res[i][k] == one[k], (i, k)
+        assert np.array_equal(bs.fields[i].cpu().numpy(), one["phi"]), i
+
+
+def test_euler_rejects_fp32_and_tuning():
+    from paper_1410_2788_amd import npb
+    w = _w(n=21, n_atoms=5, n_steps=2)
+    mol = npb.Molecule(w.molecule.xyz, w.molecule.q, w.molecule.radius)
+    bad = npb.make_params(dataclasses.replace(w.params, precision="f32"))
+    assert npb.npb_validate(mol.c, npb.make_grid(w.grid), bad) == npb.NPB_EINVAL
+    s = npb.Solver(w.molecule, w.grid, w.params)
+    with pytest.raises(npb.NPBError):
+        s.autotune()
+
+
+def test_euler_full_size_against_stored_oracle_values():
+    # the 2000-atom workload on 161^3 nodes in the launch configuration the
+    # benchmark times: 40 steps, vacuum by the direct solve; energies and
+    # sampled nodes of phi_m against tests/golden/globular_2000_161_euler40.json
+    import json
+    import os
+    from paper_1410_2788_amd import npb
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "globular_2000_161_euler40.json")))
+    w = inputs.globular_2000_euler(n_steps=40)
+    _say("case euler full size 161^3, 40 steps, vacuum_direct")
+    g = npb.solve(w.molecule, w.grid, w.params, want_field=True, vacuum_direct=True)
+    assert _close(g["G_m"][0], ref["G_m"][0]), (g["G_m"][0], ref["G_m"][0])
+    assert _close(g["dG_direct"], ref["dG_direct"]), (g["dG_direct"], ref["dG_direct"])
+    phi = g["phi"].ravel()
+    d = np.array([phi[i] for i in ref["field_nodes"]]) - np.array(ref["phi_m"])
+    err = float(np.max(np.abs(d)) / ref["phi_m_absmax"])
+    _say(f"  dG_direct gpu {g['dG_direct']} oracle {ref['dG_direct']} sampled rel err {err:.3e}")
+    assert err <= 1e-10
