@@ -33,22 +33,22 @@ METRIC = "LOD grid-point-updates/s at ≤1e-3 kcal/mol energy err; p50/p99 solve
 HBM_PEAK_GBS = 8000.0
 
 
-def _sweep_source_sha():
-    p = os.path.join(ROOT, "paper_1410_2788_amd", "csrc", "sweep_kernels.hip")
+def _sweep_source_sha(source: str = "sweep_kernels.hip"):
+    p = os.path.join(ROOT, "paper_1410_2788_amd", "csrc", source)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def _traffic(kernel: str, precision: str):
+def _traffic(kernel: str, precision: str, source: str = "sweep_kernels.hip"):
     """HBM bytes per launch of `kernel` (the profiler's name of the template
     instance) from the committed PMC summary, if it was taken on the current
-    sweep source and the same instance ran there; else None."""
+    kernel source and the same instance ran there; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
         e = d.get(kernel)
-        if e and e.get("source_sha") == _sweep_source_sha():
+        if e and e.get("source_sha") == _sweep_source_sha(source):
             return e.get("bytes_per_launch")
     except (OSError, ValueError):
         return None
@@ -431,7 +431,7 @@ def bench_euler(args):
     # reference runs
     refs = []
     for T in (0.5 * args.euler_t, args.euler_t):
-        n = int(round(T / 1e-5))
+        n = max(1, int(round(T / 1e-5)))
         we = inputs.globular_2000_euler(n_steps=n)
         t1 = time.perf_counter()
         r = npb.solve(we.molecule, we.grid, we.params, vacuum_direct=True)
@@ -440,15 +440,33 @@ def bench_euler(args):
               f"{el:.1f} s", file=sys.stderr, flush=True)
         refs.append({"T": T, "steps": n, "dG": r["dG_direct"], "G_m": r["G_m"][0],
                      "device_s": r["device_ms"] * 1e-3, "wall_s": el, "finite": r["finite"]})
+    # LODIE2 on the same molecule: the benchmark's own setting (dt 0.2 / 0.1,
+    # 20 / 40 steps), then T = euler_t at falling dt (the paper's RE+V runs
+    # use T = 10), RE+V (Eq. (deltaG3)) and RE with the direct vacuum
+    # potential (Eq. (deltaG2)) beside the Euler energy
+    e_ref = refs[-1]["dG"]
     lod = {}
     for prec in ("f64", "f32"):
         wl = inputs.globular_2000(precision=prec)
         r = npb.solve(wl.molecule, wl.grid, wl.params, vacuum_direct=True)
-        lod[prec] = {"RE+V": r["dG"], "RE (phi_0 direct)": r["dG_direct"],
-                     "RE+V minus Euler": r["dG"] - refs[-1]["dG"],
-                     "RE minus Euler": r["dG_direct"] - refs[-1]["dG"],
-                     "device_ms": r["device_ms"]}
-    return {"metric": "explicit Euler grid-point-updates/s (FP64 reference solver)",
+        lod["benchmark_" + prec] = {"dt": wl.params.dt, "steps": wl.params.n_steps,
+                                    "RE+V": r["dG"], "RE (phi_0 direct)": r["dG_direct"],
+                                    "RE+V minus Euler": r["dG"] - e_ref,
+                                    "RE minus Euler": r["dG_direct"] - e_ref,
+                                    "device_ms": r["device_ms"]}
+    sweep = []
+    for dt in (0.4, 0.2, 0.1, 0.05, 0.025):
+        wl = inputs.globular_2000(precision="f64")
+        wl.params = dataclasses.replace(wl.params, dt=dt,
+                                        n_steps=max(1, int(round(args.euler_t / dt))))
+        r = npb.solve(wl.molecule, wl.grid, wl.params, vacuum_direct=True)
+        sweep.append({"dt": dt, "steps": wl.params.n_steps, "RE+V": r["dG"],
+                      "RE (phi_0 direct)": r["dG_direct"], "RE+V minus Euler": r["dG"] - e_ref,
+                      "RE minus Euler": r["dG_direct"] - e_ref, "device_ms": r["device_ms"]})
+        print(f"LODIE2 T={args.euler_t:g} dt={dt}: RE+V {r['dG']:.3f}, RE {r['dG_direct']:.3f} "
+              f"(Euler {e_ref:.3f})", file=sys.stderr, flush=True)
+    lod["T_sweep_f64"] = sweep
+    rec = {"metric": "explicit Euler grid-point-updates/s (FP64 reference solver)",
             "value": updates / (dev_ms * 1e-3), "unit": "grid-point-updates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -459,14 +477,21 @@ def bench_euler(args):
             "device_ms_median": dev_ms,
             "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4),
-                         "traffic": _traffic("npb::(anonymous namespace)::euler_step_kernel<32, 8>",
-                                             "f64"),
-                         "kernel": "npb::euler_step_kernel<32, 8>", "avg_launch_us": round(avg_us, 2),
+                         "traffic": _traffic("npb::euler_step_kernel", "f64", "euler_kernels.hip"),
+                         "kernel": "npb::euler_step_kernel", "avg_launch_us": round(avg_us, 2),
                          "algorithmic_bytes_per_launch": bytes_per_launch,
                          "bytes_per_node": 17, "interior_nodes": X * Y * Z,
                          "timing": "kernel-attached HIP events (hipExtLaunchKernelGGL) on every "
                                    "step launch of one solve"},
             "parity_40_steps": parity, "reference": refs, "lodie2": lod}
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+    return rec
 
 
 def bench_serve(args):

@@ -8,10 +8,8 @@
 // (ping-pong buffers; the Dirichlet shell of both holds the boundary data).
 // The step is bound by HBM traffic: per interior node one field value is
 // read, one written and one flag byte read (17 bytes); neighbours come from
-// the caches.  A block owns a TX x TY column of (x, y) nodes and walks a
-// range of z planes, keeping the planes below, at and above the node in
-// registers, so that each field value is fetched from memory once per
-// block.
+// the caches (the tiles an XCD works on are contiguous, so their halos meet
+// in that XCD's L2).
 #include <hip/hip_ext.h>
 
 #include "npb_internal.h"
@@ -20,9 +18,13 @@ namespace npb {
 
 namespace {
 
-__device__ __forceinline__ double pick_face(int s, double r0, double r1, double r2) {
-  return s == 0 ? r0 : (s == 1 ? r1 : r2);
-}
+constexpr int kTX = 32, kTY = 2, kZC = 4;
+
+// flags of an interior node: bit 0 its solute bit, bits 1..6 the solute
+// bits of its neighbours at x-1, x+1, y-1, y+1, z-1, z+1, bit 7 set when
+// the node has a charge-list entry.  One byte carries everything the step
+// needs about the dielectric and the source.
+constexpr int kSourceBit = 0x80;
 
 // tau-free source density at pitched node c of x line `line` (0 when the
 // line's sorted charge entries do not hold c)
@@ -39,86 +41,128 @@ __device__ __forceinline__ double node_source(const EulerArgs& a, long long c, i
   return (lo < end && (long long)a.q_idx[lo] == c) ? a.q_rho[lo] : 0.0;
 }
 
-template <int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void euler_step_kernel(EulerArgs a) {
-  const int i = 1 + (int)blockIdx.x * TX + (int)threadIdx.x % TX;
-  const int j = 1 + (int)blockIdx.y * TY + (int)threadIdx.x / TX;
-  // no barriers below: lanes outside the grid simply leave
+// sinh(u) = (e^u - e^-u) / 2 from one exponential: e^-u is the hardware
+// reciprocal estimate of e^u refined by two Newton-Raphson steps
+// (x <- x + x (1 - t x)).  Near u = 0 the difference loses relative
+// accuracy but keeps an absolute error of a few 1e-16, which is what the
+// additive update sees.  Non-finite for |u| beyond the exponential's range.
+__device__ __forceinline__ double sinh_by_exp(double u) {
+  const double t = exp(u);
+  double r = __builtin_amdgcn_rcp(t);
+  r = fma(fma(-t, r, 1.0), r, r);
+  r = fma(fma(-t, r, 1.0), r, r);
+  return 0.5 * (t - r);
+}
+
+// Block b of the launch takes tile xcd * per + b / 8 with xcd = b % 8: the
+// hardware hands consecutive blocks to the eight XCDs in turn, so each XCD
+// then works through one contiguous range of tiles (x fastest, then y,
+// then z), whose y and z neighbours it shares in its own L2.  A tile is
+// kTX x kTY (x, y) columns of kZC planes; all of a thread's loads are
+// issued before any arithmetic (planes past the last interior plane are
+// clamped to the boundary plane and not stored).
+__global__ __launch_bounds__(kTX * kTY) void euler_step_kernel(EulerArgs a) {
+  const int b0 = (int)blockIdx.x;
+  const int b = (b0 % 8) * a.per + b0 / 8;
+  if (b >= a.ntiles) return;  // no barriers below: whole blocks or lanes leave
+  const int tx = b % a.tiles_x, ty = (b / a.tiles_x) % a.tiles_y, tz = b / (a.tiles_x * a.tiles_y);
+  const int i = 1 + tx * kTX + (int)threadIdx.x % kTX;
+  const int j = 1 + ty * kTY + (int)threadIdx.x / kTX;
   if (i > a.nx - 2 || j > a.ny - 2) return;
-  const int k0 = 1 + (int)blockIdx.z * a.zc;
-  const int k1 = min(k0 + a.zc, a.nz - 1);
+  const int k0 = 1 + tz * kZC;
+  const int klast = a.nz - 2;  // last interior plane
   const long long row = a.nxp;
   const long long plane = (long long)a.nxp * a.ny;
   const double* __restrict__ u = a.u;
   double* __restrict__ v = a.v;
   const uint8_t* __restrict__ fl = a.flags;
-  long long c = (long long)k0 * plane + (long long)j * row + i;
-  double ub = u[c - plane], uc = u[c];
-  int fb = fl[c - plane], fc = fl[c];
-  const double r0 = a.re[0], r1 = a.re[1], r2 = a.re[2];
-  for (int k = k0; k < k1; ++k, c += plane) {
-    const double ua = u[c + plane];
-    const int fa = fl[c + plane];
-    const double uw = u[c - 1], ue = u[c + 1], us = u[c - row], un = u[c + row];
+  const long long c0 = (long long)j * row + i;
+  // planes k0 - 1 .. k0 + kZC of the column, x/y neighbours and flags of
+  // planes k0 .. k0 + kZC - 1
+  double col[kZC + 2], uw[kZC], ue[kZC], us[kZC], un[kZC];
+  int f[kZC];
+#pragma unroll
+  for (int z = 0; z < kZC + 2; ++z) col[z] = u[(long long)min(k0 - 1 + z, klast + 1) * plane + c0];
+#pragma unroll
+  for (int z = 0; z < kZC; ++z) {
+    const long long c = (long long)min(k0 + z, klast) * plane + c0;
+    uw[z] = u[c - 1];
+    ue[z] = u[c + 1];
+    us[z] = u[c - row];
+    un[z] = u[c + row];
+    f[z] = fl[c];
+  }
+#pragma unroll
+  for (int z = 0; z < kZC; ++z) {
+    const int k = k0 + z;
+    if (k > klast) break;
+    const double uc = col[z + 1];
+    const double dw = uw[z] - uc, de = ue[z] - uc, ds = us[z] - uc, dn = un[z] - uc;
+    const double db = col[z] - uc, da = col[z + 2] - uc;
+    const int fc = f[z];
     double r;
     if (a.uniform) {
-      r = a.re_uniform * (((uw - uc) + (ue - uc)) + ((us - uc) + (un - uc)) + ((ub - uc) + (ua - uc)));
+      r = a.re_uniform * (((dw + de) + (ds + dn)) + (db + da));
     } else {
+      // a solvent node's faces carry re[0] (solvent neighbour) or re[1]
+      // (solute neighbour), a solute node's re[1] or re[2]: base plus
+      // delta times the neighbour's solute bit
       const int s = fc & 1;
-      const int fw = fl[c - 1], fe = fl[c + 1], fs = fl[c - row], fn = fl[c + row];
-      r = pick_face(s + (fw & 1), r0, r1, r2) * (uw - uc);
-      r = fma(pick_face(s + (fe & 1), r0, r1, r2), ue - uc, r);
-      r = fma(pick_face(s + (fs & 1), r0, r1, r2), us - uc, r);
-      r = fma(pick_face(s + (fn & 1), r0, r1, r2), un - uc, r);
-      r = fma(pick_face(s + (fb & 1), r0, r1, r2), ub - uc, r);
-      r = fma(pick_face(s + (fa & 1), r0, r1, r2), ua - uc, r);
+      const double base = s ? a.re[1] : a.re[0];
+      const double delta = s ? a.re[2] - a.re[1] : a.re[1] - a.re[0];
+      double m = (double)((fc >> 1) & 1) * dw;
+      m = fma((double)((fc >> 2) & 1), de, m);
+      m = fma((double)((fc >> 3) & 1), ds, m);
+      m = fma((double)((fc >> 4) & 1), dn, m);
+      m = fma((double)((fc >> 5) & 1), db, m);
+      m = fma((double)((fc >> 6) & 1), da, m);
+      r = fma(base, ((dw + de) + (ds + dn)) + (db + da), delta * m);
       // kbar^2 sinh(u) on solvent nodes (kbar = 0 in the solute)
-      if (s == 0 && a.nl) r -= a.tk * sinh(uc);
+      if (s == 0 && a.nl) r = fma(-a.tk, sinh_by_exp(uc), r);
     }
-    if (fc & 2) r = fma(a.tau, node_source(a, c, k * a.ny + j), r);
+    const long long c = (long long)k * plane + c0;
+    if (fc & kSourceBit) r = fma(a.tau, node_source(a, c, k * a.ny + j), r);
     v[c] = uc + r;
-    ub = uc;
-    uc = ua;
-    fb = fc;
-    fc = fa;
   }
 }
 
-constexpr int kTX = 32, kTY = 8;
-
-// flags = solute bit of the mask (or 0 for none)
-__global__ __launch_bounds__(256) void euler_flags_kernel(const uint32_t* mask, uint32_t* flags,
-                                                          size_t n4) {
-  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < n4) flags[e] = mask ? (mask[e] & 0x01010101u) : 0u;
+// flags of every node from the solute mask (nullptr: no solute); shell and
+// padding nodes get 0
+__global__ __launch_bounds__(256) void euler_flags_kernel(const uint8_t* mask, uint8_t* flags,
+                                                          int nx, int nxp, int ny, int nz) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long plane = (long long)nxp * ny;
+  if (e >= plane * nz) return;
+  const int i = (int)(e % nxp);
+  const int j = (int)((e / nxp) % ny);
+  const int k = (int)(e / plane);
+  int f = 0;
+  if (mask && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2) {
+    f = (mask[e] & 1) | ((mask[e - 1] & 1) << 1) | ((mask[e + 1] & 1) << 2) |
+        ((mask[e - nxp] & 1) << 3) | ((mask[e + nxp] & 1) << 4) | ((mask[e - plane] & 1) << 5) |
+        ((mask[e + plane] & 1) << 6);
+  }
+  flags[e] = (uint8_t)f;
 }
 
-// bit 1 on every node with a trilinear source entry (entries are distinct
-// nodes, so each byte has one writer)
+// the source bit on every node with a trilinear source entry (entries are
+// distinct nodes, so each byte has one writer)
 __global__ __launch_bounds__(256) void euler_source_flags_kernel(const int* q_idx, const int* nq,
                                                                  int cap, uint8_t* flags) {
   const int e = (int)(blockIdx.x * 256 + threadIdx.x);
   const int n = min(*nq, cap);
-  if (e < n) flags[q_idx[e]] = (uint8_t)(flags[q_idx[e]] | 2u);
+  if (e < n) flags[q_idx[e]] = (uint8_t)(flags[q_idx[e]] | kSourceBit);
 }
 
 }  // namespace
 
-int euler_z_chunk(int nx, int ny, int nz) {
-  const long long bxy = (long long)((nx - 2 + kTX - 1) / kTX) * ((ny - 2 + kTY - 1) / kTY);
-  // about 2048 blocks (8 per CU) when the grid allows, 4..32 planes each
-  long long zc = (long long)(nz - 2) * bxy / 2048;
-  if (zc < 4) zc = 4;
-  if (zc > 32) zc = 32;
-  return (int)zc;
-}
+int euler_z_chunk(int, int, int) { return kZC; }
 
 hipError_t launch_euler_flags(const uint8_t* mask, const int* q_idx, const int* nq, int cap,
-                              uint8_t* flags, size_t n, hipStream_t st) {
-  const size_t n4 = (n + 3) / 4;
-  hipLaunchKernelGGL(euler_flags_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st,
-                     reinterpret_cast<const uint32_t*>(mask), reinterpret_cast<uint32_t*>(flags),
-                     n4);
+                              uint8_t* flags, int nx, int nxp, int ny, int nz, hipStream_t st) {
+  const long long n = (long long)nxp * ny * nz;
+  hipLaunchKernelGGL(euler_flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mask,
+                     flags, nx, nxp, ny, nz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || cap <= 0) return e;
   hipLaunchKernelGGL(euler_source_flags_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0,
@@ -126,16 +170,20 @@ hipError_t launch_euler_flags(const uint8_t* mask, const int* q_idx, const int* 
   return hipGetLastError();
 }
 
-hipError_t launch_euler_step(const EulerArgs& a, hipEvent_t start, hipEvent_t stop,
+hipError_t launch_euler_step(const EulerArgs& in, hipEvent_t start, hipEvent_t stop,
                              hipStream_t st) {
-  if (a.nx < 3 || a.ny < 3 || a.nz < 3 || a.zc < 1) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((a.nx - 2 + kTX - 1) / kTX), (unsigned)((a.ny - 2 + kTY - 1) / kTY),
-                  (unsigned)((a.nz - 2 + a.zc - 1) / a.zc));
+  if (in.nx < 3 || in.ny < 3 || in.nz < 3 || in.zc != kZC) return hipErrorInvalidValue;
+  EulerArgs a = in;
+  a.tiles_x = (a.nx - 2 + kTX - 1) / kTX;
+  a.tiles_y = (a.ny - 2 + kTY - 1) / kTY;
+  const int tiles_z = (a.nz - 2 + kZC - 1) / kZC;
+  a.ntiles = a.tiles_x * a.tiles_y * tiles_z;
+  a.per = (a.ntiles + 7) / 8;
+  const dim3 grid((unsigned)(8 * a.per));
   if (start)
-    hipExtLaunchKernelGGL((euler_step_kernel<kTX, kTY>), grid, dim3(kTX * kTY), 0, st, start,
-                          stop, 0u, a);
+    hipExtLaunchKernelGGL(euler_step_kernel, grid, dim3(kTX * kTY), 0, st, start, stop, 0u, a);
   else
-    hipLaunchKernelGGL((euler_step_kernel<kTX, kTY>), grid, dim3(kTX * kTY), 0, st, a);
+    hipLaunchKernelGGL(euler_step_kernel, grid, dim3(kTX * kTY), 0, st, a);
   return hipGetLastError();
 }
 

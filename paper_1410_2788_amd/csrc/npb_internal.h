@@ -303,7 +303,8 @@ hipError_t launch_direct_field_out(double* out, const double* u, const double* b
 struct EulerArgs {
   const double* u;        // field at step n, [nz][ny][nxp]
   double* v;              // field at step n + 1 (interior written; shell kept)
-  const uint8_t* flags;   // bit 0 solute node, bit 1 node with a source entry
+  const uint8_t* flags;   // bit 0 solute node, bits 1-6 its neighbours' solute bits,
+                          // bit 7 node with a source entry (launch_euler_flags)
   const int* src_ptr;     // per-x-line offsets into q_idx / q_rho (line k*ny + j)
   const int* q_idx;       // pitched linear index of each charge node, sorted
   const double* q_rho;    // source density at it
@@ -315,12 +316,13 @@ struct EulerArgs {
   double re_uniform;
   double tau;             // dt / alpha (source coefficient)
   double tk;              // tau kbar^2
+  int tiles_x, tiles_y, ntiles, per;  // filled by launch_euler_step
 };
 
 int euler_z_chunk(int nx, int ny, int nz);
 // flags from the solute mask (nullptr: none) and the charge list
 hipError_t launch_euler_flags(const uint8_t* mask, const int* q_idx, const int* nq, int cap,
-                              uint8_t* flags, size_t n, hipStream_t st);
+                              uint8_t* flags, int nx, int nxp, int ny, int nz, hipStream_t st);
 // one step; start / stop (both or neither) are recorded by the kernel itself
 hipError_t launch_euler_step(const EulerArgs& a, hipEvent_t start, hipEvent_t stop,
                              hipStream_t st);

@@ -1077,7 +1077,7 @@ struct Engine {
                                  L.shape[d].P, P.at<uint8_t>(L.ccls[d]), st);
       if (e == hipSuccess && p->scheme == NPB_EULER)
         e = launch_euler_flags(P.at<uint8_t>(L.mask), P.at<int>(L.q_idx), ints, L.cap,
-                               P.at<uint8_t>(L.flags), n, st);
+                               P.at<uint8_t>(L.flags), nx, nxp, ny, nz, st);
       return e;
     });
   }
