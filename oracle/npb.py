@@ -44,7 +44,10 @@ Readings of points the paper leaves open (each listed in the design notes):
   * the modified Debye-Hueckel parameter at temperature T is
     8.486902807 * (298 / T) * I (Angstrom^-2, I in mol/L);
   * solute region = union of atomic balls, a node on a sphere counts as
-    solute; face dielectric = harmonic mean of the two nodal values;
+    solute; face dielectric = harmonic mean of the two nodal values, or,
+    with face_rule "location", eps_in or eps_out by whether the half point
+    itself lies in the solute (the paper's own rule, applied to the same
+    union of balls);
   * the AOS nonlinear sub-step is the exact flow of alpha w_t = -4 kbar^2
     sinh(w) over dt, i.e. Eq. (ana3) with theta replaced by 4 theta (the
     printed leading factor 4 would map u to 4u when kbar = 0);
@@ -145,6 +148,42 @@ def solute_mask(grid, xyz, radius) -> np.ndarray:
     return M
 
 
+def face_solute(grid, xyz, radius, axis_xyz: int) -> np.ndarray:
+    """Half points between consecutive nodes along x (0), y (1) or z (2)
+    that lie inside or on an atomic sphere; the half point of nodes i and
+    i + 1 has coordinate origin + (i + 1/2) h, and |x - r_a|^2 is evaluated
+    as in solute_mask.  Shape: the node array with one fewer entry along
+    that axis."""
+    h = grid.h
+    n = (grid.nx, grid.ny, grid.nz)
+    C = []
+    for d in range(3):
+        if d == axis_xyz:
+            C.append(grid.origin[d] + (np.arange(n[d] - 1, dtype=np.float64) + 0.5) * h)
+        else:
+            C.append(axis_coords(grid, d))
+    shape = [len(C[2]), len(C[1]), len(C[0])]
+    F = np.zeros(shape, dtype=bool)
+    for a in range(xyz.shape[0]):
+        xa, ya, za = xyz[a]
+        R = radius[a]
+        sl = []
+        for d, c in enumerate((xa, ya, za)):
+            m = len(C[d])
+            lo = max(int(math.floor((c - R - grid.origin[d]) / h)) - 1, 0)
+            hi = min(int(math.ceil((c + R - grid.origin[d]) / h)) + 1, m - 1)
+            sl.append((lo, hi))
+        if any(l > u for l, u in sl):
+            continue
+        dx = C[0][sl[0][0]:sl[0][1] + 1] - xa
+        dy = C[1][sl[1][0]:sl[1][1] + 1] - ya
+        dz = C[2][sl[2][0]:sl[2][1] + 1] - za
+        d2 = (dx * dx)[None, None, :] + (dy * dy)[None, :, None]
+        d2 = d2 + (dz * dz)[:, None, None]
+        F[sl[2][0]:sl[2][1] + 1, sl[1][0]:sl[1][1] + 1, sl[0][0]:sl[0][1] + 1] |= d2 <= R * R
+    return F
+
+
 def spread_charges(grid, xyz, q) -> np.ndarray:
     """Trilinear distribution Q(x_i, y_j, z_k) of the point charges (Sec. 3.1,
     text after Eq. (SpatialOperators)): with g = (r_a - origin)/h, i0 =
@@ -204,7 +243,7 @@ def boundary_potential(grid, xyz, q, eps: float, kbar2: float, T: float,
 
 def face_eps(eps_node: np.ndarray, axis: int) -> np.ndarray:
     """eps at the half points between consecutive nodes along `axis` (array
-    axis), harmonic mean of the two nodal values."""
+    axis), harmonic mean of the two nodal values (the default face rule)."""
     n = eps_node.shape[axis]
     e0 = np.take(eps_node, np.arange(0, n - 1), axis=axis)
     e1 = np.take(eps_node, np.arange(1, n), axis=axis)
@@ -232,14 +271,15 @@ def thomas(a, b, c, d):
 
 
 def implicit_sweep(s: np.ndarray, eps_node: np.ndarray, tau: float, h: float,
-                   axis: int) -> np.ndarray:
+                   axis: int, faces=None) -> np.ndarray:
     """One implicit-Euler 1-D sub-step (Eqs. (LODIE1_2)-(LODIE1_4)):
     solve (1 - tau delta^2) v = s on every interior grid line along array
     axis `axis` (0 = z, 1 = y, 2 = x), with delta^2 the central difference of
     Eq. (SpatialOperators) and Dirichlet values taken from s at both ends.
-    Nodes not on an interior line are returned unchanged."""
+    Nodes not on an interior line are returned unchanged.  `faces` (eps at
+    the half points along `axis`) replaces the harmonic means when given."""
     S = np.moveaxis(s, axis, 0)                 # (n, A, B) view
-    E = np.moveaxis(face_eps(eps_node, axis), axis, 0)   # (n-1, A, B)
+    E = np.moveaxis(face_eps(eps_node, axis) if faces is None else faces, axis, 0)
     n = S.shape[0]
     Si = S[:, 1:-1, 1:-1]
     Ei = E[:, 1:-1, 1:-1]
@@ -262,12 +302,12 @@ def implicit_sweep(s: np.ndarray, eps_node: np.ndarray, tau: float, h: float,
 
 
 def explicit_half(s: np.ndarray, eps_node: np.ndarray, c: float, h: float,
-                  axis: int) -> np.ndarray:
+                  axis: int, faces=None) -> np.ndarray:
     """(1 + c delta^2) s along array axis `axis` on the interior nodes (the
     central difference of Eq. (SpatialOperators), neighbours on the shell
     included); other nodes are returned unchanged."""
     S = np.moveaxis(s, axis, 0)
-    E = np.moveaxis(face_eps(eps_node, axis), axis, 0)
+    E = np.moveaxis(face_eps(eps_node, axis) if faces is None else faces, axis, 0)
     out = s.copy()
     O = np.moveaxis(out, axis, 0)
     mid = S[1:-1, 1:-1, 1:-1]
@@ -279,12 +319,13 @@ def explicit_half(s: np.ndarray, eps_node: np.ndarray, c: float, h: float,
     return out
 
 
-def cn_sweep(s: np.ndarray, eps_node: np.ndarray, tau: float, h: float, axis: int) -> np.ndarray:
+def cn_sweep(s: np.ndarray, eps_node: np.ndarray, tau: float, h: float, axis: int,
+             faces=None) -> np.ndarray:
     """One Crank-Nicolson 1-D sub-step (Eqs. (LODCN1_2)-(LODCN1_4)):
     (1 - tau/2 delta^2) v = (1 + tau/2 delta^2) s on every interior line,
     Dirichlet values at both ends."""
-    return implicit_sweep(explicit_half(s, eps_node, 0.5 * tau, h, axis), eps_node, 0.5 * tau,
-                          h, axis)
+    return implicit_sweep(explicit_half(s, eps_node, 0.5 * tau, h, axis, faces), eps_node,
+                          0.5 * tau, h, axis, faces)
 
 
 def nonlinear_substep(u: np.ndarray, theta: np.ndarray, interior: np.ndarray) -> np.ndarray:
@@ -320,11 +361,28 @@ class Problem:
     u0: np.ndarray           # initial field: boundary data on the shell, 0 inside
     interior: np.ndarray
     T: float
+    # eps at the half points per array axis (z, y, x); None: harmonic means
+    # of eps_node (the default face rule)
+    faces: object = None
+
+    def face(self, axis: int):
+        return None if self.faces is None else self.faces[axis]
+
+
+def location_faces(grid, xyz, radius, eps_in: float, eps_out: float):
+    """eps at every half point by its own location (Sec. 3.1, text after
+    Eq. (SpatialOperators)): eps_in where the half point lies in the solute
+    (on or inside a sphere), eps_out elsewhere; per array axis (z, y, x)."""
+    return [np.where(face_solute(grid, xyz, radius, ax), float(eps_in), float(eps_out))
+            for ax in (2, 1, 0)]
 
 
 def make_problem(mol, grid, params, medium: str = "solvated") -> Problem:
     """Time-independent data of Sec. 3.1 (text after Eq. (SpatialOperators)):
-    Q and eps computed once; Dirichlet data from Eq. (BoundaryCond)."""
+    Q and eps computed once; Dirichlet data from Eq. (BoundaryCond).  The
+    face rule (params.face_rule): "harmonic" (harmonic mean of the nodal
+    values) or "location" (by the half point's own location); the vacuum
+    problem is uniform, so both rules agree there."""
     T = params.temperature_K
     Q = spread_charges(grid, mol.xyz, mol.q)
     rho = source_density(Q, grid.h, T)
@@ -335,6 +393,10 @@ def make_problem(mol, grid, params, medium: str = "solvated") -> Problem:
         eps_node = np.where(M, params.eps_in, params.eps_out)
         kbar2_node = np.where(M, 0.0, kb2)
         u0 = boundary_potential(grid, mol.xyz, mol.q, params.eps_out, kb2, T)
+        if getattr(params, "face_rule", "harmonic") == "location":
+            return Problem(grid, eps_node, kbar2_node, Q, rho, u0, interior, T,
+                           location_faces(grid, mol.xyz, mol.radius, params.eps_in,
+                                          params.eps_out))
     elif medium == "vacuum":
         eps_node = np.full(shape_zyx(grid), float(params.eps_in))
         kbar2_node = np.zeros(shape_zyx(grid))
@@ -345,16 +407,19 @@ def make_problem(mol, grid, params, medium: str = "solvated") -> Problem:
 
 
 def problem_from_fields(grid, solute, eps_in: float, eps_out: float, kbar2: float,
-                        rho: np.ndarray, u0: np.ndarray, T: float = 298.0) -> Problem:
+                        rho: np.ndarray, u0: np.ndarray, T: float = 298.0,
+                        face_rule: str = "harmonic") -> Problem:
     """A problem posed by fields (the analytic benchmark of Sec. 4.1): the
     solute balls set eps and kbar^2 as in make_problem, rho is the given
     dense source and u0 the given initial field, whose shell is the
     Dirichlet data.  Q is zero (no energies)."""
     M = solute_mask(grid, solute.xyz, solute.radius)
     interior = ~boundary_shell(grid)
+    faces = (location_faces(grid, solute.xyz, solute.radius, eps_in, eps_out)
+             if face_rule == "location" else None)
     return Problem(grid, np.where(M, eps_in, eps_out), np.where(M, 0.0, kbar2),
                    np.zeros(shape_zyx(grid)), np.where(interior, rho, 0.0), u0.copy(), interior,
-                   T)
+                   T, faces)
 
 
 def lod_step(u, pb: Problem, dt: float, alpha: float, order: str = "LODIE2"):
@@ -366,27 +431,27 @@ def lod_step(u, pb: Problem, dt: float, alpha: float, order: str = "LODIE2"):
     h = pb.grid.h
     if order == "LODIE2":
         s = u + tau * pb.rho
-        v = implicit_sweep(s, pb.eps_node, tau, h, axis=2)
-        p = implicit_sweep(v, pb.eps_node, tau, h, axis=1)
-        qq = implicit_sweep(p, pb.eps_node, tau, h, axis=0)
+        v = implicit_sweep(s, pb.eps_node, tau, h, axis=2, faces=pb.face(2))
+        p = implicit_sweep(v, pb.eps_node, tau, h, axis=1, faces=pb.face(1))
+        qq = implicit_sweep(p, pb.eps_node, tau, h, axis=0, faces=pb.face(0))
         return nonlinear_substep(qq, theta, pb.interior)
     if order == "LODIE1":
         w = nonlinear_substep(u, theta, pb.interior)
-        v = implicit_sweep(w, pb.eps_node, tau, h, axis=2)
-        p = implicit_sweep(v, pb.eps_node, tau, h, axis=1)
-        qq = implicit_sweep(p, pb.eps_node, tau, h, axis=0)
+        v = implicit_sweep(w, pb.eps_node, tau, h, axis=2, faces=pb.face(2))
+        p = implicit_sweep(v, pb.eps_node, tau, h, axis=1, faces=pb.face(1))
+        qq = implicit_sweep(p, pb.eps_node, tau, h, axis=0, faces=pb.face(0))
         return qq + tau * pb.rho
     if order == "LODCN2":
         s = u + tau * pb.rho
-        v = cn_sweep(s, pb.eps_node, tau, h, axis=2)
-        p = cn_sweep(v, pb.eps_node, tau, h, axis=1)
-        qq = cn_sweep(p, pb.eps_node, tau, h, axis=0)
+        v = cn_sweep(s, pb.eps_node, tau, h, axis=2, faces=pb.face(2))
+        p = cn_sweep(v, pb.eps_node, tau, h, axis=1, faces=pb.face(1))
+        qq = cn_sweep(p, pb.eps_node, tau, h, axis=0, faces=pb.face(0))
         return nonlinear_substep(qq, theta, pb.interior)
     if order == "LODCN1":
         w = nonlinear_substep(u, theta, pb.interior)
-        v = cn_sweep(w, pb.eps_node, tau, h, axis=2)
-        p = cn_sweep(v, pb.eps_node, tau, h, axis=1)
-        qq = cn_sweep(p, pb.eps_node, tau, h, axis=0)
+        v = cn_sweep(w, pb.eps_node, tau, h, axis=2, faces=pb.face(2))
+        p = cn_sweep(v, pb.eps_node, tau, h, axis=1, faces=pb.face(1))
+        qq = cn_sweep(p, pb.eps_node, tau, h, axis=0, faces=pb.face(0))
         return qq + tau * pb.rho
     raise ValueError(order)
 
@@ -408,13 +473,14 @@ def aos_step(u, pb: Problem, dt: float, alpha: float, variant: str = "AOSIE2"):
         raise ValueError(variant)
     w = nonlinear_substep(u, theta4, pb.interior)
     if variant.startswith("AOSIE"):
-        v = implicit_sweep(u + cx * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=2)
-        p = implicit_sweep(u + cy * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=1)
-        qq = implicit_sweep(u + cz * tau * pb.rho, pb.eps_node, 4.0 * tau, h, axis=0)
+        v = implicit_sweep(u + cx * tau * pb.rho, pb.eps_node, 4.0 * tau, h, 2, pb.face(2))
+        p = implicit_sweep(u + cy * tau * pb.rho, pb.eps_node, 4.0 * tau, h, 1, pb.face(1))
+        qq = implicit_sweep(u + cz * tau * pb.rho, pb.eps_node, 4.0 * tau, h, 0, pb.face(0))
     else:
         def cn(axis, c):
-            rhs = explicit_half(u, pb.eps_node, 2.0 * tau, h, axis) + c * tau * pb.rho
-            return implicit_sweep(rhs, pb.eps_node, 2.0 * tau, h, axis)
+            rhs = explicit_half(u, pb.eps_node, 2.0 * tau, h, axis, pb.face(axis))
+            rhs = rhs + c * tau * pb.rho
+            return implicit_sweep(rhs, pb.eps_node, 2.0 * tau, h, axis, pb.face(axis))
         v, p, qq = cn(2, cx), cn(1, cy), cn(0, cz)
     out = u.copy()
     I = pb.interior
@@ -436,10 +502,11 @@ def maos_step(u, pb: Problem, dt: float, alpha: float, variant: str = "MAOSIE"):
     subs = []
     for axis in (2, 1, 0):
         if variant == "MAOSIE":
-            subs.append(implicit_sweep(w + tau * pb.rho, pb.eps_node, 3.0 * tau, h, axis))
+            subs.append(implicit_sweep(w + tau * pb.rho, pb.eps_node, 3.0 * tau, h, axis,
+                                       pb.face(axis)))
         elif variant == "MAOSCN":
-            rhs = explicit_half(w, pb.eps_node, 1.5 * tau, h, axis) + tau * pb.rho
-            subs.append(implicit_sweep(rhs, pb.eps_node, 1.5 * tau, h, axis))
+            rhs = explicit_half(w, pb.eps_node, 1.5 * tau, h, axis, pb.face(axis)) + tau * pb.rho
+            subs.append(implicit_sweep(rhs, pb.eps_node, 1.5 * tau, h, axis, pb.face(axis)))
         else:
             raise ValueError(variant)
     out = u.copy()
@@ -458,7 +525,7 @@ def euler_step(u, pb: Problem, dt: float, alpha: float):
     h = pb.grid.h
     div = np.zeros_like(u)
     for axis in (2, 1, 0):
-        div += explicit_half(u, pb.eps_node, 1.0, h, axis) - u
+        div += explicit_half(u, pb.eps_node, 1.0, h, axis, pb.face(axis)) - u
     # the sinh term exists only where kbar != 0 (solvent): elsewhere it is
     # absent, not 0 * sinh(u) (which would overflow for |u| > 710)
     nl = np.zeros_like(u)

@@ -69,6 +69,7 @@ class RunParams:
     richardson: bool = False
     vacuum: bool = True
     precision: str = "f64"      # f64 | f32 (GPU sweeps; the oracle is FP64)
+    face_rule: str = "harmonic"  # harmonic (mean of the nodal eps) | location (eps at the half point)
 
 
 @dataclass

@@ -16,9 +16,12 @@ def _is_interior(idx, shape):
     return all(1 <= idx[d] <= shape[d] - 2 for d in range(3))
 
 
-def dense_second_difference(eps_node, h, axis):
+def dense_second_difference(eps_node, h, axis, faces=None):
     """Matrix D_axis over all nodes (zyx-flattened): rows of interior nodes
-    hold h^-2 (e+ (v+ - v) + e- (v- - v)); other rows are zero."""
+    hold h^-2 (e+ (v+ - v) + e- (v- - v)); other rows are zero.  e+- are
+    harmonic means of the nodal values, or read from `faces` (eps at the
+    half point between a node and its successor along the axis, stored at
+    the node's index) when given."""
     shape = eps_node.shape
     N = eps_node.size
     D = np.zeros((N, N))
@@ -34,8 +37,12 @@ def dense_second_difference(eps_node, h, axis):
                 dn = list(idx)
                 up[axis] += 1
                 dn[axis] -= 1
-                e_up = harmonic(eps_node[k, j, i], eps_node[tuple(up)])
-                e_dn = harmonic(eps_node[k, j, i], eps_node[tuple(dn)])
+                if faces is None:
+                    e_up = harmonic(eps_node[k, j, i], eps_node[tuple(up)])
+                    e_dn = harmonic(eps_node[k, j, i], eps_node[tuple(dn)])
+                else:
+                    e_up = faces[tuple(idx)]
+                    e_dn = faces[tuple(dn)]
                 D[p, lin[tuple(up)]] += e_up / h ** 2
                 D[p, lin[tuple(dn)]] += e_dn / h ** 2
                 D[p, p] -= (e_up + e_dn) / h ** 2

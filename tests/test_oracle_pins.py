@@ -308,7 +308,8 @@ def _step_map_dense(pb, dt, alpha, scheme):
     tau = dt / alpha
     h = pb.grid.h
     N = pb.u0.size
-    Ds = [_dense.dense_second_difference(pb.eps_node, h, ax) for ax in (2, 1, 0)]  # x, y, z
+    Ds = [_dense.dense_second_difference(pb.eps_node, h, ax, pb.face(ax))
+          for ax in (2, 1, 0)]  # x, y, z
     rho = pb.rho.ravel()
     if scheme in ("LODIE2", "LODIE1"):
         A = [np.eye(N) - tau * D for D in Ds]
@@ -435,6 +436,90 @@ def test_nonlinear_steady_state_converges_to_discrete_npb(scheme):
     assert 1.6 < errs[0] / errs[1] < 2.5
     re = np.max(np.abs(oracle.richardson(sols[0], sols[1]) - ex))
     assert re < 0.5 * errs[1]
+
+
+# --------------------------------------------------------------------------
+# the face rule by location (Sec. 3.1, text after Eq. (SpatialOperators))
+
+def _three_atoms():
+    return inputs.Molecule(xyz=np.array([[0.13, -0.21, 0.07], [-0.4, 0.35, 0.3],
+                                         [0.61, 0.5, -0.45]]),
+                           q=np.array([1.0, -0.6, 0.3]), radius=np.array([1.1, 0.8, 0.55]))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_face_solute_matches_brute_force(axis):
+    grid = inputs.Grid(9, 8, 10, 0.3, (-1.3, -1.1, -1.45))
+    mol = _three_atoms()
+    F = oracle.face_solute(grid, mol.xyz, mol.radius, axis)
+    n = [grid.nx, grid.ny, grid.nz]
+    m = list(n)
+    m[axis] -= 1
+    assert F.shape == (m[2], m[1], m[0])
+    for k in range(m[2]):
+        for j in range(m[1]):
+            for i in range(m[0]):
+                idx = [i, j, k]
+                p = [grid.origin[d] + float(idx[d]) * grid.h for d in range(3)]
+                p[axis] = grid.origin[axis] + (float(idx[axis]) + 0.5) * grid.h
+                inside = False
+                for a in range(mol.xyz.shape[0]):
+                    dx, dy, dz = (p[d] - mol.xyz[a, d] for d in range(3))
+                    inside = inside or ((dx * dx + dy * dy) + dz * dz <= mol.radius[a] ** 2)
+                assert F[k, j, i] == inside, (axis, i, j, k)
+    assert F.any() and not F.all()
+
+
+def _location_problem(grid, mol, **kw):
+    p = _params(face_rule="location", **kw)
+    pb = oracle.make_problem(mol, grid, p, "solvated")
+    assert pb.faces is not None
+    return p, pb
+
+
+def test_location_faces_take_only_the_two_media_values_and_differ_from_harmonic():
+    grid = _tiny(11, 0.35)
+    mol = _three_atoms()
+    p, pb = _location_problem(grid, mol)
+    for ax in range(3):
+        f = pb.faces[ax]
+        assert set(np.unique(f)) <= {p.eps_in, p.eps_out}
+        hm = oracle.face_eps(pb.eps_node, ax)
+        same = (pb.eps_node.take(range(f.shape[ax]), axis=ax) ==
+                pb.eps_node.take(range(1, f.shape[ax] + 1), axis=ax))
+        # between two nodes of one medium both rules mostly agree; across
+        # the surface the location rule never gives the harmonic value
+        assert np.mean(f[same] == hm[same]) > 0.9
+        assert not np.any(f[~same] == hm[~same])
+
+
+def test_location_faces_euler_steady_state_is_the_dense_poisson_solution():
+    grid = _tiny(9, 0.35, ny=8, nz=10)
+    mol = _three_atoms()
+    p, pb = _location_problem(grid, mol)
+    D = sum(_dense.dense_second_difference(pb.eps_node, grid.h, ax, pb.faces[ax])
+            for ax in range(3))
+    I = _dense.interior_flags(pb.u0.shape)
+    # linear: -D u = rho on the interior, u = g on the shell
+    g = pb.u0.ravel()
+    ex = g.copy()
+    ex[I] = np.linalg.solve(-D[np.ix_(I, I)], pb.rho.ravel()[I] + D[np.ix_(I, ~I)] @ g[~I])
+    u, n = _euler_steady(pb, _euler_tau(pb))
+    assert np.max(np.abs(u.ravel() - ex)) <= 1e-10 * np.max(np.abs(ex))
+
+
+@pytest.mark.parametrize("scheme", ["LODIE2", "AOSIE2", "LODCN2", "MAOSCN"])
+def test_location_faces_one_step_matches_dense_map(scheme):
+    grid = _tiny(8, 0.35, ny=9, nz=7)
+    mol = _three_atoms()
+    p, pb = _location_problem(grid, mol, scheme=scheme, dt=0.7, alpha=0.5)
+    rng = np.random.default_rng(6)
+    u = pb.u0.copy()
+    u[1:-1, 1:-1, 1:-1] = rng.normal(0, 20, (5, 7, 6))
+    u1 = oracle.run(pb, p.dt, p.alpha, 1, scheme, u_init=u)
+    M, c = _step_map_dense(pb, p.dt, p.alpha, scheme)
+    ud = M @ u.ravel() + c
+    assert np.max(np.abs(u1.ravel() - ud)) <= 1e-11 * np.max(np.abs(ud))
 
 
 # --------------------------------------------------------------------------
