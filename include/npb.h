@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NPB_ABI_VERSION 5
+#define NPB_ABI_VERSION 6
 
 typedef enum npb_status {
   NPB_OK = 0,
@@ -120,7 +120,8 @@ typedef struct npb_grid {
  *                         (Sec. 5.4; needs vacuum and vacuum_direct); phi_m and phi_0
  *                         Richardson-combined when richardson = 1
  *   field_units     : npb_field_units of d_field_out
- *   reserved        : must be 0                                             */
+ *   face_rule       : npb_face_rule: eps at the half points of the solvated
+ *                     problem (the vacuum problem is uniform)               */
 typedef struct npb_params {
   double eps_in, eps_out, kappa_bar_sq, temperature_K, alpha, dt;
   int32_t n_steps;
@@ -131,8 +132,15 @@ typedef struct npb_params {
   int32_t field_select;
   int32_t vacuum_direct;
   int32_t field_units;
-  int32_t reserved;
+  int32_t face_rule;
 } npb_params;
+
+enum npb_face_rule {
+  NPB_FACE_HARMONIC = 0,  /* harmonic mean of the two nodal values */
+  NPB_FACE_LOCATION = 1   /* the half point's own location (Sec. 3.1, text after Eq.
+                             (SpatialOperators)): eps_in on or inside a sphere, else
+                             eps_out; applied to the union of balls */
+};
 
 enum npb_field_units {
   NPB_UNITS_KCAL = 0,          /* phi = kT u, kcal/mol/e */

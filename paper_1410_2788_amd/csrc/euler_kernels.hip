@@ -21,9 +21,10 @@ namespace {
 constexpr int kTX = 32, kTY = 2, kZC = 4;
 
 // flags of an interior node: bit 0 its solute bit, bits 1..6 the solute
-// bits of its neighbours at x-1, x+1, y-1, y+1, z-1, z+1, bit 7 set when
-// the node has a charge-list entry.  One byte carries everything the step
-// needs about the dielectric and the source.
+// bits of its neighbours at x-1, x+1, y-1, y+1, z-1, z+1 (face rule by
+// location: the solute bits of the six half points themselves), bit 7 set
+// when the node has a charge-list entry.  One byte carries everything the
+// step needs about the dielectric and the source.
 constexpr int kSourceBit = 0x80;
 
 // tau-free source density at pitched node c of x line `line` (0 when the
@@ -107,9 +108,11 @@ __global__ __launch_bounds__(kTX * kTY) void euler_step_kernel(EulerArgs a) {
       // a solvent node's faces carry re[0] (solvent neighbour) or re[1]
       // (solute neighbour), a solute node's re[1] or re[2]: base plus
       // delta times the neighbour's solute bit
+      // (by location: re[0] or re[2] by the face's own bit)
       const int s = fc & 1;
-      const double base = s ? a.re[1] : a.re[0];
-      const double delta = s ? a.re[2] - a.re[1] : a.re[1] - a.re[0];
+      const double base = a.face_loc ? a.re[0] : (s ? a.re[1] : a.re[0]);
+      const double delta = a.face_loc ? a.re[2] - a.re[0]
+                                      : (s ? a.re[2] - a.re[1] : a.re[1] - a.re[0]);
       double m = (double)((fc >> 1) & 1) * dw;
       m = fma((double)((fc >> 2) & 1), de, m);
       m = fma((double)((fc >> 3) & 1), ds, m);
@@ -126,10 +129,13 @@ __global__ __launch_bounds__(kTX * kTY) void euler_step_kernel(EulerArgs a) {
   }
 }
 
-// flags of every node from the solute mask (nullptr: no solute); shell and
-// padding nodes get 0
-__global__ __launch_bounds__(256) void euler_flags_kernel(const uint8_t* mask, uint8_t* flags,
-                                                          int nx, int nxp, int ny, int nz) {
+// flags of every node from the solute mask (nullptr: no solute) and, for
+// the face rule by location, the half-point bits fx, fy, fz (bit 1 of the
+// lower node's byte); shell and padding nodes get 0
+__global__ __launch_bounds__(256) void euler_flags_kernel(const uint8_t* mask, const uint8_t* fx,
+                                                          const uint8_t* fy, const uint8_t* fz,
+                                                          uint8_t* flags, int nx, int nxp, int ny,
+                                                          int nz) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long plane = (long long)nxp * ny;
   if (e >= plane * nz) return;
@@ -138,9 +144,13 @@ __global__ __launch_bounds__(256) void euler_flags_kernel(const uint8_t* mask, u
   const int k = (int)(e / plane);
   int f = 0;
   if (mask && i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2 && k >= 1 && k <= nz - 2) {
-    f = (mask[e] & 1) | ((mask[e - 1] & 1) << 1) | ((mask[e + 1] & 1) << 2) |
-        ((mask[e - nxp] & 1) << 3) | ((mask[e + nxp] & 1) << 4) | ((mask[e - plane] & 1) << 5) |
-        ((mask[e + plane] & 1) << 6);
+    if (fx)
+      f = (mask[e] & 1) | (fx[e - 1] & 2) | ((fx[e] & 2) << 1) | ((fy[e - nxp] & 2) << 2) |
+          ((fy[e] & 2) << 3) | ((fz[e - plane] & 2) << 4) | ((fz[e] & 2) << 5);
+    else
+      f = (mask[e] & 1) | ((mask[e - 1] & 1) << 1) | ((mask[e + 1] & 1) << 2) |
+          ((mask[e - nxp] & 1) << 3) | ((mask[e + nxp] & 1) << 4) |
+          ((mask[e - plane] & 1) << 5) | ((mask[e + plane] & 1) << 6);
   }
   flags[e] = (uint8_t)f;
 }
@@ -158,11 +168,15 @@ __global__ __launch_bounds__(256) void euler_source_flags_kernel(const int* q_id
 
 int euler_z_chunk(int, int, int) { return kZC; }
 
-hipError_t launch_euler_flags(const uint8_t* mask, const int* q_idx, const int* nq, int cap,
-                              uint8_t* flags, int nx, int nxp, int ny, int nz, hipStream_t st) {
+hipError_t launch_euler_flags(const uint8_t* mask, const uint8_t* const* fmask, const int* q_idx,
+                              const int* nq, int cap, uint8_t* flags, int nx, int nxp, int ny,
+                              int nz, hipStream_t st) {
   const long long n = (long long)nxp * ny * nz;
+  const uint8_t* f3[3] = {nullptr, nullptr, nullptr};
+  if (fmask)
+    for (int d = 0; d < 3; ++d) f3[d] = fmask[d];
   hipLaunchKernelGGL(euler_flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mask,
-                     flags, nx, nxp, ny, nz);
+                     f3[0], f3[1], f3[2], flags, nx, nxp, ny, nz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || cap <= 0) return e;
   hipLaunchKernelGGL(euler_source_flags_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0,

@@ -24,7 +24,9 @@ template <typename T>
 struct SweepArgs {
   T* u;                   // field, [nz][ny][nxp]; read, and written in place
   T* acc;                 // additive-splitting accumulator (AOS modes)
-  const uint8_t* mask;    // 1 = solute node, [nz][ny][nxp]; nullptr = uniform medium
+  const uint8_t* mask;    // bit 0: solute node, [nz][ny][nxp]; nullptr = uniform medium;
+                          // face rule by location: bit 1 = the half point to the next
+                          // node along this sweep's direction is solute
   int nx, ny, nz;
   int nxp;                // row pitch in elements: nx rounded up to a multiple of 4
   double re[3];           // r*eps_face for (sum of the two flags) = 0, 1, 2
@@ -45,6 +47,7 @@ struct SweepArgs {
                           // its sources (LOD), 2: before the sources are added (additive)
   double aos_ww, aos_wv;  // additive modes: weights of W and of this direction's
                           // solution in the mean (AOS 1/4 and 1/4, MAOS 0 and 1/3)
+  int face_loc;           // 1: face class from bit 1 of the lower node's flag (0 or 2)
   // per (chunk, line) face class of this direction's launch shape: 0 = every
   // face of the chunk solvent-solvent, 2 = every face solute-solute, 1 =
   // mixed; nullptr for the uniform medium (all chunks uniform)
@@ -189,7 +192,12 @@ struct SetupArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, size_t n, hipStream_t st);
 hipError_t launch_mask_raster(const SetupArgs& a, uint8_t* mask, hipStream_t st);
+// face rule by location: bit 1 of fmask (a copy of the mask) on every node
+// whose half point to the next node along dir (0 x, 1 y, 2 z) is solute
+hipError_t launch_face_raster(const SetupArgs& a, int dir, const uint8_t* mask, uint8_t* fmask,
+                              hipStream_t st);
 hipError_t launch_stencil(const SetupArgs& a, int* key, int* id, double* val, int* err,
                           hipStream_t st);
 // Stable LSD radix sort of (key, id) pairs by key; n items, keys < key_limit.
@@ -226,7 +234,7 @@ hipError_t launch_shell_from_dense(const double* u0, int nx, int ny, int nz, dou
 // chunk classes of direction dir (0 = x, 1 = y, 2 = z) for chunks of M rows,
 // P per line; out[p * class_lines + line]
 hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
-                                int M, int P, uint8_t* out, hipStream_t st);
+                                int M, int P, int face_loc, uint8_t* out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // field / energy helpers
@@ -316,13 +324,18 @@ struct EulerArgs {
   double re_uniform;
   double tau;             // dt / alpha (source coefficient)
   double tk;              // tau kbar^2
+  int face_loc;           // 1: flag bits 1-6 are the faces' own solute bits (face rule
+                          // by location): face = re[0] or re[2]
   int tiles_x, tiles_y, ntiles, per;  // filled by launch_euler_step
 };
 
 int euler_z_chunk(int nx, int ny, int nz);
-// flags from the solute mask (nullptr: none) and the charge list
-hipError_t launch_euler_flags(const uint8_t* mask, const int* q_idx, const int* nq, int cap,
-                              uint8_t* flags, int nx, int nxp, int ny, int nz, hipStream_t st);
+// flags from the solute mask (nullptr: none) and the charge list; with
+// the face rule by location, fmask[3] (x, y, z half-point bits in bit 1)
+// give the six face bits instead of the neighbours' solute bits
+hipError_t launch_euler_flags(const uint8_t* mask, const uint8_t* const* fmask, const int* q_idx,
+                              const int* nq, int cap, uint8_t* flags, int nx, int nxp, int ny,
+                              int nz, hipStream_t st);
 // one step; start / stop (both or neither) are recorded by the kernel itself
 hipError_t launch_euler_step(const EulerArgs& a, hipEvent_t start, hipEvent_t stop,
                              hipStream_t st);

@@ -436,7 +436,8 @@ struct Layout {
   size_t mask, bc_s, bc_v, atoms, tabs, key_a, id_a, key_b, id_b, sval, hist, heads;
   size_t q_idx, q_val, q_rho, xptr, yptr, ylin, yrho, zptr, zlin, zrho, ccls[3], slots, ints, total;
   size_t direct;  // work of the direct vacuum Poisson solve (vacuum_direct)
-  size_t flags;   // explicit Euler node flags (solute bit, source bit)
+  size_t flags;   // explicit Euler node flags (solute bits, source bit)
+  size_t fmask[3];  // face rule by location: mask | half-point bit per direction
   LaunchShape shape[3];
   Run runs[kMaxFields];
   int n_runs, cap, nblocks;
@@ -544,6 +545,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   L.ints = take(16 * 4);
   L.direct = take(p->vacuum_direct ? direct_poisson_bytes(g->nx, g->ny, g->nz) : 0);
   L.flags = take(euler ? n : 0);
+  for (int d = 0; d < 3; ++d) L.fmask[d] = take(p->face_rule == NPB_FACE_LOCATION ? n : 0);
   L.total = off;
   L.cap = cap;
   L.nblocks = nb;
@@ -601,7 +603,8 @@ npb_status validate(const npb_molecule* mol, const npb_grid* g, const npb_params
     return fail(NPB_EINVAL, "explicit Euler runs in FP64 only (precision 0)");
   if (p->vacuum_direct != 0 && p->vacuum_direct != 1)
     return fail(NPB_EINVAL, "vacuum_direct must be 0 or 1");
-  if (p->reserved != 0) return fail(NPB_EINVAL, "params.reserved must be 0");
+  if (p->face_rule != NPB_FACE_HARMONIC && p->face_rule != NPB_FACE_LOCATION)
+    return fail(NPB_EINVAL, "unknown face_rule");
   if (p->field_units != NPB_UNITS_KCAL && p->field_units != NPB_UNITS_DIMENSIONLESS)
     return fail(NPB_EINVAL, "unknown field_units");
   if (p->field_select < 0 || p->field_select > 3)
@@ -658,6 +661,12 @@ struct Problem {
     return reinterpret_cast<Ptr*>(ws + off);
   }
   bool aos() const { return is_aos(p->scheme); }
+  bool location() const { return p->face_rule == NPB_FACE_LOCATION; }
+  // the solvated sweeps' flags in direction d: the mask, or under the face
+  // rule by location the mask with that direction's half-point bits
+  uint8_t* sweep_mask(int d) const {
+    return location() ? ws + L.fmask[d] : ws + L.mask;
+  }
   bool fields() const { return fu0 != nullptr; }
   double field_scale() const {
     return (fields() || p->field_units == NPB_UNITS_DIMENSIONLESS) ? 1.0 : kT;
@@ -760,7 +769,8 @@ struct Engine {
     SweepArgs<T> a{};
     a.u = P.at<T>(L.field[r]);
     a.acc = P.aos() ? P.at<T>(L.acc[r]) : nullptr;
-    a.mask = c.vacuum ? nullptr : P.at<uint8_t>(L.mask);
+    a.mask = c.vacuum ? nullptr : P.sweep_mask(d);
+    a.face_loc = (!c.vacuum && P.location()) ? 1 : 0;
     a.nx = P.g->nx;
     a.ny = P.g->ny;
     a.nz = P.g->nz;
@@ -1014,6 +1024,17 @@ struct Engine {
       if (e != hipSuccess) return e;
       e = launch_mask_raster(sa, P.at<uint8_t>(L.mask), st);
       if (e != hipSuccess) return e;
+      if (P.location()) {
+        // per direction: the mask with bit 1 on nodes whose half point to
+        // the next node is solute
+        for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+          e = launch_copy_u32(reinterpret_cast<const uint32_t*>(ws + L.mask),
+                              reinterpret_cast<uint32_t*>(ws + L.fmask[d]), (n + 3) / 4, st);
+          if (e == hipSuccess)
+            e = launch_face_raster(sa, d, P.at<uint8_t>(L.mask), P.at<uint8_t>(L.fmask[d]), st);
+        }
+        if (e != hipSuccess) return e;
+      }
       if (P.fields())
         e = launch_dense_source(P.frho, nx, nxp, ny, nz, P.at<int>(L.key_a), P.at<int>(L.id_a),
                                 P.at<double>(L.sval), st);
@@ -1073,11 +1094,15 @@ struct Engine {
       }
       if (e != hipSuccess) return e;
       for (int d = 0; d < 3 && e == hipSuccess; ++d)
-        e = launch_chunk_classes(P.at<uint8_t>(L.mask), nx, nxp, ny, nz, d, L.shape[d].M,
-                                 L.shape[d].P, P.at<uint8_t>(L.ccls[d]), st);
-      if (e == hipSuccess && p->scheme == NPB_EULER)
-        e = launch_euler_flags(P.at<uint8_t>(L.mask), P.at<int>(L.q_idx), ints, L.cap,
-                               P.at<uint8_t>(L.flags), nx, nxp, ny, nz, st);
+        e = launch_chunk_classes(P.sweep_mask(d), nx, nxp, ny, nz, d, L.shape[d].M,
+                                 L.shape[d].P, P.location() ? 1 : 0, P.at<uint8_t>(L.ccls[d]),
+                                 st);
+      if (e == hipSuccess && p->scheme == NPB_EULER) {
+        const uint8_t* fm[3] = {P.sweep_mask(0), P.sweep_mask(1), P.sweep_mask(2)};
+        e = launch_euler_flags(P.at<uint8_t>(L.mask), P.location() ? fm : nullptr,
+                               P.at<int>(L.q_idx), ints, L.cap, P.at<uint8_t>(L.flags), nx, nxp,
+                               ny, nz, st);
+      }
       return e;
     });
   }
@@ -1228,6 +1253,7 @@ struct Engine {
           a.nxp = nxp;
           a.zc = euler_z_chunk(nx, ny, nz);
           a.uniform = vac ? 1 : 0;
+          a.face_loc = (!vac && P.location()) ? 1 : 0;
           a.nl = c.nl ? 1 : 0;
           for (int k = 0; k < 3; ++k) a.re[k] = c.re[k];
           a.re_uniform = c.re_uniform;
@@ -1557,8 +1583,8 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
         if (std::find(tried.begin(), tried.end(), id) != tried.end()) continue;
         tried.push_back(id);
         P.L.shape[d] = sh;
-        NPB_HIP(launch_chunk_classes(P.at<uint8_t>(P.L.mask), nx, nxp, ny, nz, d, sh.M, sh.P,
-                                     P.at<uint8_t>(P.L.ccls[d]), st));
+        NPB_HIP(launch_chunk_classes(P.sweep_mask(d), nx, nxp, ny, nz, d, sh.M, sh.P,
+                                     P.location() ? 1 : 0, P.at<uint8_t>(P.L.ccls[d]), st));
         // chunk tables of this chunk length for every run
         NPB_HIP(hipStreamSynchronize(st));
         unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);

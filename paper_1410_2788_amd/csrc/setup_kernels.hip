@@ -16,6 +16,20 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
   for (; i < n; i += step) p[i] = v;
 }
 
+__global__ void copy_u32_kernel(const uint32_t* src, uint32_t* dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
   if (n == 0) return hipSuccess;
   size_t blocks = (n + 255) / 256;
@@ -61,6 +75,59 @@ __global__ __launch_bounds__(256) void mask_raster_kernel(SetupArgs a, uint8_t* 
     d2 = d2 + dz * dz;
     if (d2 <= R2) mask[((long long)k * a.ny + j) * a.nxp + i] = 1;
   }
+}
+
+// Face rule by location (Sec. 3.1, text after Eq. (SpatialOperators)):
+// the half point between node g and its successor along `dir` takes
+// eps_in when it lies on or inside a sphere.  fmask already holds the
+// solute mask; every such half point sets bit 1 of node g's byte there
+// (each writer stores the same value, mask | 2).  Coordinates and distance
+// are evaluated as in the node raster, with the half point at
+// origin + (i + 1/2) h along `dir`.
+__global__ __launch_bounds__(256) void face_raster_kernel(SetupArgs a, int dir, const uint8_t* mask,
+                                                          uint8_t* fmask) {
+#pragma clang fp contract(off)
+  const int at = blockIdx.x;
+  const int na = a.n_atoms;
+  const double c[3] = {a.atoms[at], a.atoms[na + at], a.atoms[2 * na + at]};
+  const double R = a.atoms[4 * na + at];
+  const double o[3] = {a.ox, a.oy, a.oz};
+  int n[3] = {a.nx, a.ny, a.nz};
+  n[dir] -= 1;  // half points along dir: 0 .. n_dir - 2
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (int)floor((c[d] - R - o[d]) / a.h) - 1;
+    hi[d] = (int)ceil((c[d] + R - o[d]) / a.h) + 1;
+    if (lo[d] < 0) lo[d] = 0;
+    if (hi[d] > n[d] - 1) hi[d] = n[d] - 1;
+    if (lo[d] > hi[d]) return;
+  }
+  const int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
+  const long long tot = (long long)bx * by * bz;
+  const double R2 = R * R;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int idx[3] = {lo[0] + (int)(e % bx), lo[1] + (int)((e / bx) % by),
+                        lo[2] + (int)(e / ((long long)bx * by))};
+    double p[3];
+    for (int d = 0; d < 3; ++d) {
+      double t = d == dir ? ((double)idx[d] + 0.5) * a.h : (double)idx[d] * a.h;
+      p[d] = o[d] + t;
+    }
+    double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
+    double d2 = dx * dx + dy * dy;
+    d2 = d2 + dz * dz;
+    if (d2 <= R2) {
+      const long long g = ((long long)idx[2] * a.ny + idx[1]) * a.nxp + idx[0];
+      fmask[g] = (uint8_t)(mask[g] | 2u);
+    }
+  }
+}
+
+hipError_t launch_face_raster(const SetupArgs& a, int dir, const uint8_t* mask, uint8_t* fmask,
+                              hipStream_t st) {
+  if (a.n_atoms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(face_raster_kernel, dim3(a.n_atoms), dim3(256), 0, st, a, dir, mask, fmask);
+  return hipGetLastError();
 }
 
 hipError_t launch_mask_raster(const SetupArgs& a, uint8_t* mask, hipStream_t st) {
@@ -601,9 +668,11 @@ hipError_t launch_shell_from_dense(const double* u0, int nx, int ny, int nz, dou
 // Face class of every (chunk, line) of one sweep direction: 0 if all nodes
 // from the chunk's left neighbour to its right neighbour are solvent, 2 if
 // all are solute, 1 otherwise (and for chunks that reach the line end).
-// Lines are numbered as class_lines describes.
+// Face rule by location (face_loc): 0 / 2 if the chunk's M + 1 half points
+// (bit 1 of the flags of the left neighbour .. the last row) are all
+// solvent / all solute.  Lines are numbered as class_lines describes.
 __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
-                                   int M, int P, long long nlines, uint8_t* out) {
+                                   int M, int P, long long nlines, int face_loc, uint8_t* out) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nlines * P) return;
   const int p = (int)(idx / nlines);
@@ -625,7 +694,12 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny,
   }
   const int j0 = p * M, j1 = p * M + M + 1;
   uint8_t c = 1;
-  if (j1 <= n - 1) {
+  if (j1 <= n - 1 && face_loc) {
+    const int v0 = mask[base + (long long)j0 * stride] & 2;
+    bool same = true;
+    for (int j = j0 + 1; j < j1; ++j) same = same && ((mask[base + (long long)j * stride] & 2) == v0);
+    if (same) c = v0 ? 2 : 0;
+  } else if (j1 <= n - 1) {
     const uint8_t v0 = mask[base + (long long)j0 * stride];
     bool same = true;
     for (int j = j0 + 1; j <= j1; ++j) same = same && (mask[base + (long long)j * stride] == v0);
@@ -635,11 +709,11 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny,
 }
 
 hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
-                                int M, int P, uint8_t* out, hipStream_t st) {
+                                int M, int P, int face_loc, uint8_t* out, hipStream_t st) {
   const long long nlines = class_lines(nx, ny, nz, dir);
   const long long tot = nlines * P;
   hipLaunchKernelGGL(chunk_class_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                     mask, nx, nxp, ny, nz, dir, M, P, nlines, out);
+                     mask, nx, nxp, ny, nz, dir, M, P, nlines, face_loc, out);
   return hipGetLastError();
 }
 

@@ -240,14 +240,15 @@ __device__ __forceinline__ void cn_rhs_uniform(A (&d)[M], A re, A left, A right)
 // explicit half: Eqs. (AOSCN1_2)-(AOSCN2_4); Sec. 3.3).  Node r of the line
 // sits at v[r * vs] with solute flag f[r * fs]; the lane's rows 1+g0 ..
 // g0+M that are interior become (1 + r delta^2) v, the face coefficient
-// chosen from the two flags as in the implicit rows (uniform medium: reu).
+// chosen from the two flags as in the implicit rows (uniform medium: reu;
+// face rule by location, fm: bit 1 of the lower node's flag).
 // The new values are formed in registers and written after a block
 // barrier, so every lane reads the unchanged line; every thread of the
 // block must call this.
 template <typename A, int M>
 __device__ __forceinline__ void cn_tile_rows(A* v, int vs, const uint8_t* f, int fs, int g0,
-                                             int nint, bool valid, bool uniform, A re0, A re1,
-                                             A re2, A reu) {
+                                             int nint, bool valid, bool uniform, bool fm, A re0,
+                                             A re1, A re2, A reu) {
   A e[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -255,8 +256,9 @@ __device__ __forceinline__ void cn_tile_rows(A* v, int vs, const uint8_t* f, int
     e[k] = A(0);
     if (valid && r <= nint) {
       const A c = v[r * vs], l = v[(r - 1) * vs], rt = v[(r + 1) * vs];
-      const A fl = uniform ? reu : pick3((int)f[(r - 1) * fs] + (int)f[r * fs], re0, re1, re2);
-      const A fr = uniform ? reu : pick3((int)f[r * fs] + (int)f[(r + 1) * fs], re0, re1, re2);
+      const int fa = f[(r - 1) * fs], fb = f[r * fs];
+      const A fl = uniform ? reu : pick3(fm ? (fa & 2) : fa + fb, re0, re1, re2);
+      const A fr = uniform ? reu : pick3(fm ? (fb & 2) : fb + (int)f[(r + 1) * fs], re0, re1, re2);
       e[k] = fma(fl, l - c, fma(fr, rt - c, c));
     }
   }
@@ -593,7 +595,9 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     for (int e = tid; e < total; e += nthreads) {
       if (l0 + q < nlines && x >= 1 && x <= nx - 2) {
         A v = tile[q * S + x];
-        bool solvent = !uniform && mt[q * nx4 + x] == 0;
+        // the face rule by location runs in the CN-capable variant, whose
+        // flags carry half-point bits above bit 0
+        bool solvent = !uniform && (CN ? (mt[q * nx4 + x] & 1) == 0 : mt[q * nx4 + x] == 0);
         if (aos) wtile[q * S + x] = (solvent && a.aos_w) ? sinh_flow(v, wka, wkb) : v;
         if (a.pre_nl && solvent) tile[q * S + x] = sinh_flow(v, pka, pkb);
       }
@@ -609,8 +613,8 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   if (CN && a.cn == 2) {
     const int ql = tid % L;
     cn_tile_rows<A, M>(tile + ql * S, 1, mt + ql * nx4, 1, (tid / L) * M, nx - 2,
-                       l0 + ql < nlines, uniform, (A)a.re[0], (A)a.re[1], (A)a.re[2],
-                       (A)a.re_uniform);
+                       l0 + ql < nlines, uniform, a.face_loc != 0, (A)a.re[0], (A)a.re[1],
+                       (A)a.re[2], (A)a.re_uniform);
   }
   if (src) {
     // one entry per thread; entries are distinct nodes
@@ -662,11 +666,13 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
     A reF[M + 1];
     int prev = uniform ? 1 : (int)mrow[g0];
+    const bool fm = CN && a.face_loc != 0;
 #pragma unroll
     for (int k = 0; k <= M; ++k) {
-      // face between nodes g0 + k and g0 + k + 1
+      // face between nodes g0 + k and g0 + k + 1 (by location: bit 1 of the
+      // lower node's flag)
       const int cur = uniform ? 1 : (int)mrow[g0 + k + 1];
-      const int c = (g0 + k + 1 > nx - 1) ? 2 : prev + cur;
+      const int c = (g0 + k + 1 > nx - 1) ? 2 : (fm ? (prev & 2) : prev + cur);
       reF[k] = pick3(c, re0, re1, re2);
       prev = cur;
     }
@@ -787,11 +793,13 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
     const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
     A reF[M + 1];
     int prev = uniform ? 1 : (int)mcol[0];
+    const bool fm = VAR == kYzGeneral && a.face_loc != 0;
 #pragma unroll
     for (int k = 0; k <= M; ++k) {
-      // face between along nodes g0 + k and g0 + k + 1
+      // face between along nodes g0 + k and g0 + k + 1 (by location: bit 1
+      // of the lower node's flag)
       const int cur = uniform ? 1 : (int)mcol[(k + 1) * TW];
-      const int c = (g0 + k + 1 > n - 1) ? 2 : prev + cur;
+      const int c = (g0 + k + 1 > n - 1) ? 2 : (fm ? (prev & 2) : prev + cur);
       reF[k] = pick3(c, re0, re1, re2);
       prev = cur;
     }
@@ -813,7 +821,9 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
 
   if ((VAR == kYzFlow || (VAR == kYzGeneral && a.post_nl)) && !uniform) {
     const A ka = (A)a.post_ka, kb = (A)a.post_kb;
-    if (fast) {
+    // a uniform chunk's face class tells its nodes' medium only under the
+    // harmonic rule (the face rule by location runs in the general variant)
+    if (fast && (VAR != kYzGeneral || a.face_loc == 0)) {
       if (t == 0) {
 #pragma unroll
         for (int k = 0; k < M; ++k) d[k] = sinh_flow(d[k], ka, kb);
@@ -821,7 +831,8 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
     } else {
 #pragma unroll
       for (int k = 0; k < M; ++k)
-        if (mcol[(k + 1) * TW] == 0) d[k] = sinh_flow(d[k], ka, kb);
+        if (VAR == kYzGeneral ? (mcol[(k + 1) * TW] & 1) == 0 : mcol[(k + 1) * TW] == 0)
+          d[k] = sinh_flow(d[k], ka, kb);
     }
   }
   // rows past the line end land in rows n-1.. of the tile, which are
@@ -966,13 +977,14 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         const int r = 1 + g0 + k;
-        if (r <= nint && mt[r * TW + ql] == 0) tile[r * TS + ql] = sinh_flow(tile[r * TS + ql], ka, kb);
+        if (r <= nint && (mt[r * TW + ql] & 1) == 0)
+          tile[r * TS + ql] = sinh_flow(tile[r * TS + ql], ka, kb);
       }
     }
     __syncthreads();
     if (a.cn == 2)
-      cn_tile_rows<A, M>(tile + ql, TS, mt + ql, TW, g0, nint, lv, uniform, (A)a.re[0],
-                         (A)a.re[1], (A)a.re[2], (A)a.re_uniform);
+      cn_tile_rows<A, M>(tile + ql, TS, mt + ql, TW, g0, nint, lv, uniform, a.face_loc != 0,
+                         (A)a.re[0], (A)a.re[1], (A)a.re[2], (A)a.re_uniform);
   }
   if (VAR == kYzGeneral && a.src_stage == 1) {
     add_sources();
@@ -1171,7 +1183,9 @@ template <typename T>
 int sweep_variant(const SweepArgs<T>* a, int n) {
   bool general = false, flow = false;
   for (int f = 0; f < n; ++f) {
-    general = general || a[f].src_stage != 0 || a[f].mode != MODE_INPLACE || a[f].cn;
+    // the face rule by location is decoded only in the general variant
+    general = general || a[f].src_stage != 0 || a[f].mode != MODE_INPLACE || a[f].cn ||
+              a[f].face_loc;
     flow = flow || (a[f].post_nl && a[f].mask);
   }
   return general ? kYzGeneral : (flow ? kYzFlow : kYzPlain);
@@ -1181,8 +1195,9 @@ template int sweep_variant<double>(const SweepArgs<double>*, int);
 
 template <typename T>
 int sweep_cn(const SweepArgs<T>* a, int n) {
+  // the CN-capable x kernel also decodes the face rule by location
   for (int f = 0; f < n; ++f)
-    if (a[f].cn) return 1;
+    if (a[f].cn || a[f].face_loc) return 1;
   return 0;
 }
 template int sweep_cn<float>(const SweepArgs<float>*, int);

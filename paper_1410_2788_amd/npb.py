@@ -28,7 +28,7 @@ KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "o
                   "euler"]
 # sweep launches split again by the kernel that ran them (npb_sweep_kernel)
 SWEEP_KERNELS = ["x", "yz_plain", "yz_flow", "yz_general", "euler"]
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class npb_molecule(C.Structure):
@@ -47,7 +47,7 @@ class npb_params(C.Structure):
                 ("n_steps", C.c_int32), ("scheme", C.c_int32), ("precision", C.c_int32),
                 ("richardson", C.c_int32), ("vacuum", C.c_int32), ("field_select", C.c_int32),
                 ("vacuum_direct", C.c_int32), ("field_units", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("face_rule", C.c_int32)]
 
 
 class npb_result(C.Structure):
@@ -361,6 +361,7 @@ def make_grid(g) -> npb_grid:
 
 
 FIELD_UNITS = {"kcal": 0, "dimensionless": 1}
+FACE_RULES = {"harmonic": 0, "location": 1}
 
 
 def make_params(p, field_select: int = 0, vacuum_direct: bool = False,
@@ -369,7 +370,8 @@ def make_params(p, field_select: int = 0, vacuum_direct: bool = False,
     return npb_params(float(p.eps_in), float(p.eps_out), kb2, float(p.temperature_K),
                       float(p.alpha), float(p.dt), int(p.n_steps), SCHEMES[p.scheme],
                       PRECISIONS[p.precision], 1 if p.richardson else 0, 1 if p.vacuum else 0,
-                      int(field_select), 1 if vacuum_direct else 0, FIELD_UNITS[field_units], 0)
+                      int(field_select), 1 if vacuum_direct else 0, FIELD_UNITS[field_units],
+                      FACE_RULES[getattr(p, "face_rule", "harmonic")])
 
 
 _ctx_cache = {}
@@ -456,11 +458,13 @@ class FieldsSolver:
 
 
 def make_params_raw(eps_in, eps_out, kappa_bar_sq, alpha, dt, n_steps, scheme="LODIE2",
-                    precision="f64", richardson=False, temperature_K=298.0) -> npb_params:
+                    precision="f64", richardson=False, temperature_K=298.0,
+                    face_rule="harmonic") -> npb_params:
     """npb_params with kbar^2 given directly (Angstrom^-2 or dimensionless)."""
     return npb_params(float(eps_in), float(eps_out), float(kappa_bar_sq), float(temperature_K),
                       float(alpha), float(dt), int(n_steps), SCHEMES[scheme],
-                      PRECISIONS[precision], 1 if richardson else 0, 0, 0, 0, 0, 0)
+                      PRECISIONS[precision], 1 if richardson else 0, 0, 0, 0, 0,
+                      FACE_RULES[face_rule])
 
 
 class AsyncResult:

@@ -29,7 +29,7 @@ def test_every_declared_function_is_exported(npb):
 
 
 def test_version_and_kappa_helper(npb):
-    assert npb.npb_abi_version() == npb.ABI_VERSION == 5
+    assert npb.npb_abi_version() == npb.ABI_VERSION == 6
     g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     assert npb.npb_kappa_bar_sq(1.0, 298.0) == pytest.approx(g["kbar2_per_molar_298_inv_A2"], rel=1e-15)
     assert npb.npb_kappa_bar_sq(0.1, 300.0) == pytest.approx(0.84303, rel=1e-5)
@@ -51,7 +51,7 @@ def test_validate_accepts_a_good_problem(npb):
     ("nx", 4), ("h", 0.0), ("h", -1.0), ("eps_in", 0.0), ("eps_out", -2.0),
     ("kappa_bar_sq", -1e-3), ("alpha", 0.0), ("dt", 0.0), ("n_steps", 0),
     ("scheme", 11), ("precision", 5), ("field_select", 1), ("field_units", 2),
-    ("reserved", 1)])
+    ("face_rule", 2)])
 def test_validate_rejects_bad_arguments(npb, field, value):
     w = inputs.small_globular(n=25, n_atoms=10)
     w.params.vacuum = field != "field_select"
