@@ -239,7 +239,8 @@ def bench_sphere(args):
     from paper_1410_2788_amd import inputs, npb
 
     def run(b, scheme, dt, n):
-        p = npb.make_params_raw(b.eps_in, b.eps_out, b.kbar_sq, 1.0, dt, n, scheme=scheme)
+        p = npb.make_params_raw(b.eps_in, b.eps_out, b.kbar_sq, 1.0, dt, n, scheme=scheme,
+                                face_rule=args.face_rule)
         return npb.FieldsSolver(b.solute, b.grid, p, b.u0, b.rho, graphs=False).run()
 
     def norms(u, ref, valid):
@@ -271,6 +272,16 @@ def bench_sphere(args):
             rows[i]["L2_order"] = math.log2(rows[i]["L2"] / rows[i + 1]["L2"])
             rows[i]["Linf_order"] = math.log2(rows[i]["Linf"] / rows[i + 1]["Linf"])
         spatial[sc] = rows
+    if args.sphere_spatial_only:
+        wall = time.perf_counter() - t0
+        return {"metric": "analytic charged-cavity benchmark (Sec. 4.3): spatial errors and "
+                          "orders", "value": pts_total / (ms_total * 1e-3),
+                "unit": "grid-point-updates/s (spatial study, device time)", "n_gpus": 1,
+                "steps": 1, "warmup": 0, "ms_per_step": ms_total, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "analytic",
+                "config": {"workload": "charged cavity R=1, eps 1/80, kbar=1, alpha=1, [-3,3]^3",
+                           "spatial": "dt = h^2/20, T = 10, H = 1", "face_rule": args.face_rule},
+                "spatial": spatial, "paper_LODspat": paper, "wall_s": wall}
     # temporal: LODIE2, h = 0.125, against the dt = 2.5e-5 solution
     b = inputs.sphere_benchmark(0.125)
     print("[bench] sphere temporal reference", file=sys.stderr, flush=True)
@@ -313,7 +324,7 @@ def bench_sphere(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "analytic",
             "config": {"workload": "charged cavity R=1, eps 1/80, kbar=1, alpha=1, [-3,3]^3",
                        "spatial": "dt = h^2/20, T = 10, H = 1", "temporal": "h = 0.125, T = 10",
-                       "stability": "T = 1e4 dt"},
+                       "stability": "T = 1e4 dt", "face_rule": args.face_rule},
             "spatial": spatial, "temporal_LODIE2": temporal, "stability": stability,
             "paper_LODspat": paper, "wall_s": wall}
 
@@ -591,6 +602,10 @@ def main():
     ap.add_argument("--sphere", action="store_true",
                     help="the analytic charged-cavity benchmark: spatial / temporal "
                          "convergence and stability of the schemes (own JSON line)")
+    ap.add_argument("--face-rule", default="harmonic", choices=["harmonic", "location"],
+                    help="eps at the half points for --sphere")
+    ap.add_argument("--sphere-spatial-only", action="store_true",
+                    help="--sphere: the spatial-convergence study only")
     ap.add_argument("--euler", action="store_true",
                     help="the explicit Euler reference solver: step rate, roofline, and the "
                          "reference energy at T = --euler-t (own JSON line)")

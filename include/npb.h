@@ -267,10 +267,14 @@ npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
 /* Solve one problem.  Enqueues setup (solute mask, trilinear charges,
  * boundary data), the time loops, the FP64 energy reductions and
  * combinations on `stream`, then waits for that stream and fills *out.
+ * The device work is captured once as a graph and replayed (see
+ * npb_ctx_set_graph), except explicit Euler runs of more than 4096 step
+ * launches in all, which are launched directly.
  *   d_ws, ws_bytes : device workspace, at least npb_workspace_bytes
  *   d_field_out    : NULL, or a device array of nx*ny*nz doubles that
  *                    receives the potential chosen by field_select
- *                    (kcal/mol/e), Richardson-combined when richardson = 1
+ *                    (kcal/mol/e, or u with field_units = dimensionless),
+ *                    Richardson-combined when richardson = 1
  * Errors: EINVAL, ERANGE (before any device work), EDEVICE, EDIVERGED (the
  * energies are still written to *out). */
 npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,

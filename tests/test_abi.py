@@ -195,3 +195,23 @@ def test_default_grid_encloses_the_solute_with_its_margin(npb):
         npb.npb_default_grid(mol.c, 0.01, 4.0)
     with pytest.raises(npb.NPBError):
         npb.npb_default_grid(mol.c, 0.0, 4.0)
+
+
+def test_scheme_specific_validation_and_workspace(npb):
+    import dataclasses
+    w = inputs.small_globular(n=25, n_atoms=10)
+    mol = npb.Molecule(w.molecule.xyz, w.molecule.q, w.molecule.radius)
+    g = npb.make_grid(w.grid)
+    base = npb.npb_workspace_bytes(mol.c, g, npb.make_params(w.params))
+    # explicit Euler: FP64 only; a second field buffer per run and a flag byte per node
+    eu = dataclasses.replace(w.params, scheme="EULER")
+    assert npb.npb_validate(mol.c, g, npb.make_params(eu)) == npb.NPB_OK
+    for prec in ("f32", "f32x"):
+        bad = npb.make_params(dataclasses.replace(eu, precision=prec))
+        assert npb.npb_validate(mol.c, g, bad) == npb.NPB_EINVAL
+    n_runs = 4  # Richardson x (solvated, vacuum)
+    assert npb.npb_workspace_bytes(mol.c, g, npb.make_params(eu)) >= base + n_runs * 8 * 25 ** 3
+    # face rule by location: three more flag bytes per node
+    loc = npb.make_params(dataclasses.replace(w.params, face_rule="location"))
+    assert npb.npb_validate(mol.c, g, loc) == npb.NPB_OK
+    assert npb.npb_workspace_bytes(mol.c, g, loc) >= base + 3 * 25 ** 3
