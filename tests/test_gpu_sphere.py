@@ -67,3 +67,33 @@ def test_sphere_fields_fp32_and_richardson():
     err = float(np.max(np.abs(g["u"] - o)) / np.max(np.abs(o)))
     _say("f32 RE rel err", err)
     assert err <= 2e-5
+
+
+@pytest.mark.parametrize("scheme,key", [("LODIE2", "LODIE"), ("LODCN2", "LODCN"),
+                                        ("MAOSCN", "MAOSCN")])
+def test_sphere_location_rule_errors_match_the_paper_table(scheme, key):
+    # the GPU under the face rule by location: relative L2 and Linf errors
+    # against the analytic solution at h = 0.5 and 0.25 equal the paper's
+    # printed values to their three digits (0.6 %)
+    import json
+    import os
+    from paper_1410_2788_amd import npb
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "paper_sphere_spatial.json")))
+    for h in (0.5, 0.25):
+        b = inputs.sphere_benchmark(h)
+        dt = h * h / 20.0
+        n = int(round(10.0 / dt))
+        _say(f"case sphere location rule {scheme} h={h} steps={n}")
+        p = npb.make_params_raw(b.eps_in, b.eps_out, b.kbar_sq, 1.0, dt, n, scheme=scheme,
+                                face_rule="location")
+        u = npb.FieldsSolver(b.solute, b.grid, p, b.u0, b.rho, graphs=False).run()["u"]
+        e = (u - b.exact)[b.valid]
+        ex = b.exact[b.valid]
+        l2 = float(np.sqrt(np.sum(e * e) / np.sum(ex * ex)))
+        linf = float(np.max(np.abs(e)) / np.max(np.abs(ex)))
+        i = ref["h"].index(h)
+        _say(f"  L2 {l2:.4g} (paper {ref[key]['L2'][i]}), Linf {linf:.4g} "
+             f"(paper {ref[key]['Linf'][i]})")
+        assert l2 == pytest.approx(ref[key]["L2"][i], rel=0.006)
+        assert linf == pytest.approx(ref[key]["Linf"][i], rel=0.006)
