@@ -862,15 +862,22 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
 template <typename T, typename A, int M, int VAR, int TW>
 __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __restrict__ args,
                                                        const int2* __restrict__ work, int nbu,
-                                                       int dir) {
+                                                       int dir, int nblocks) {
   constexpr int VX = 16 / (int)sizeof(T);  // elements per vector access
   constexpr int TS = TW + 1;                // LDS elements per tile row
   constexpr int VPR = TW / VX;              // vectors per full tile row
   extern __shared__ __align__(16) unsigned char smem[];
+  // Work item bi of the launch: the hardware hands consecutive blocks to
+  // the eight XCDs in turn, so block b takes item (b % 8) * per + b / 8 and
+  // each XCD works through one contiguous range of items; neighbouring
+  // tiles of a plane then share their mask lines in that XCD's L2.  Blocks
+  // past the last item leave before any barrier.
+  const int per = (nblocks + 7) >> 3;
+  const int bi = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+  if (bi >= nblocks) return;
   // (field, block of that field): arithmetic when every field of the
   // launch has nbu blocks, else from the work list
-  const int2 w = nbu > 0 ? make_int2((int)blockIdx.x / nbu, (int)blockIdx.x % nbu)
-                         : work[blockIdx.x];
+  const int2 w = nbu > 0 ? make_int2(bi / nbu, bi % nbu) : work[bi];
   const SweepArgs<T>& a = args[w.x];
   const int nx = a.nx, ny = a.ny, nxp = a.nxp;
   const int P = a.P, nrow = a.S;
@@ -1274,7 +1281,7 @@ template <typename T, typename A, int VAR, int TW>
 static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int nbu, int nblocks,
                                int dir, const LaunchShape& s, hipStream_t st) {
   if (s.threads > 512 || s.threads != TW * s.P) return hipErrorInvalidValue;
-  dim3 g(nblocks), blk(s.threads);
+  dim3 g(8 * ((nblocks + 7) / 8)), blk(s.threads);
   switch (s.M) {
 #define NPB_YZ_CASE(MM)                                                                      \
   case MM: {                                                                                \
@@ -1282,10 +1289,10 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
     if (e != hipSuccess) return e;                                                          \
     if (t_ev_start)                                                                         \
       hipExtLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, (uint32_t)s.lds,  \
-                            st, t_ev_start, t_ev_stop, 0u, args, work, nbu, dir);           \
+                            st, t_ev_start, t_ev_stop, 0u, args, work, nbu, dir, nblocks);  \
     else                                                                                    \
       hipLaunchKernelGGL((sweep_yz_kernel<T, A, MM, VAR, TW>), g, blk, s.lds, st, args,     \
-                         work, nbu, dir);                                                   \
+                         work, nbu, dir, nblocks);                                          \
   } break;
     NPB_YZ_CASE(4)
     NPB_YZ_CASE(8)
@@ -1299,10 +1306,10 @@ static hipError_t launch_yz_tw(const SweepArgs<T>* args, const int2* work, int n
         if (e != hipSuccess) return e;
         if (t_ev_start)
           hipExtLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, (uint32_t)s.lds,
-                                st, t_ev_start, t_ev_stop, 0u, args, work, nbu, dir);
+                                st, t_ev_start, t_ev_stop, 0u, args, work, nbu, dir, nblocks);
         else
           hipLaunchKernelGGL((sweep_yz_kernel<T, A, 20, VAR, TW>), g, blk, s.lds, st, args,
-                             work, nbu, dir);
+                             work, nbu, dir, nblocks);
         break;
       }
       return hipErrorInvalidValue;
