@@ -666,15 +666,23 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
     A reF[M + 1];
     int prev = uniform ? 1 : (int)mrow[g0];
-    const bool fm = CN && a.face_loc != 0;
+    if (CN && a.face_loc != 0) {
 #pragma unroll
-    for (int k = 0; k <= M; ++k) {
-      // face between nodes g0 + k and g0 + k + 1 (by location: bit 1 of the
-      // lower node's flag)
-      const int cur = uniform ? 1 : (int)mrow[g0 + k + 1];
-      const int c = (g0 + k + 1 > nx - 1) ? 2 : (fm ? (prev & 2) : prev + cur);
-      reF[k] = pick3(c, re0, re1, re2);
-      prev = cur;
+      for (int k = 0; k <= M; ++k) {
+        // face between nodes g0 + k and g0 + k + 1 by location: bit 1 of
+        // the lower node's flag
+        const int cur = uniform ? 1 : (int)mrow[g0 + k + 1];
+        reF[k] = pick3((g0 + k + 1 > nx - 1) ? 2 : (prev & 2), re0, re1, re2);
+        prev = cur;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k <= M; ++k) {
+        // face between nodes g0 + k and g0 + k + 1
+        const int cur = uniform ? 1 : (int)mrow[g0 + k + 1];
+        reF[k] = pick3((g0 + k + 1 > nx - 1) ? 2 : prev + cur, re0, re1, re2);
+        prev = cur;
+      }
     }
     if (CN && a.cn == 1) cn_rhs<A, M>(d, reF, col[-1], col[M], kR, gR);
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
@@ -793,15 +801,23 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
     const A re2 = (A)(uniform ? a.re_uniform : a.re[2]);
     A reF[M + 1];
     int prev = uniform ? 1 : (int)mcol[0];
-    const bool fm = VAR == kYzGeneral && a.face_loc != 0;
+    if (VAR == kYzGeneral && a.face_loc != 0) {
 #pragma unroll
-    for (int k = 0; k <= M; ++k) {
-      // face between along nodes g0 + k and g0 + k + 1 (by location: bit 1
-      // of the lower node's flag)
-      const int cur = uniform ? 1 : (int)mcol[(k + 1) * TW];
-      const int c = (g0 + k + 1 > n - 1) ? 2 : (fm ? (prev & 2) : prev + cur);
-      reF[k] = pick3(c, re0, re1, re2);
-      prev = cur;
+      for (int k = 0; k <= M; ++k) {
+        // face between along nodes g0 + k and g0 + k + 1 by location: bit 1
+        // of the lower node's flag
+        const int cur = uniform ? 1 : (int)mcol[(k + 1) * TW];
+        reF[k] = pick3((g0 + k + 1 > n - 1) ? 2 : (prev & 2), re0, re1, re2);
+        prev = cur;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k <= M; ++k) {
+        // face between along nodes g0 + k and g0 + k + 1
+        const int cur = uniform ? 1 : (int)mcol[(k + 1) * TW];
+        reF[k] = pick3((g0 + k + 1 > n - 1) ? 2 : prev + cur, re0, re1, re2);
+        prev = cur;
+      }
     }
     if (VAR == kYzGeneral && a.cn == 1) cn_rhs<A, M>(d, reF, col[-ts], col[M * ts], kR, gR);
     if (first && lvalid) d[0] = fma(reF[0], gL, d[0]);
