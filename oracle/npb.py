@@ -54,6 +54,8 @@ Readings of points the paper leaves open (each listed in the design notes):
   * the vacuum problem uses eps_in everywhere, kbar = 0 and Coulomb
     boundary data in eps_in;
   * a charge stencil (8 trilinear nodes) must lie in the interior;
+  * explicit Euler evaluates kbar^2 sinh(u) at the old step, and the term
+    is absent (not 0 * sinh) where kbar = 0;
   * the recovered potential is phi_m - phi_0^LOD + phi_0^FFT (the printed
     "+ phi_0^LOD - phi_0^FFT" is the only other sign pattern; with it
     (1/2) sum Q (phi_rec - phi_0^FFT) would not equal the RE+V energy).
