@@ -1,7 +1,7 @@
 """GPU parity of the explicit Euler reference solver (npb_scheme NPB_EULER,
 FP64) against the oracle's euler_step, through the C ABI.
 
-Tolerances as for the other FP64 paths: field max|d phi| <= 1e-10 max|phi|,
+Tolerances as for the other FP64 paths: field max|d phi| <= 1e-11 max|phi|,
 energies within 1e-9 relative (1e-8 kcal/mol absolute).  Steps are taken at
 dt = 1e-5 with alpha = 1/25 (the paper's reference step; tau = 2.5e-4, half
 the explicit limit h^2 / (6 eps_out) at h = 0.5)."""
@@ -55,7 +55,7 @@ def _compare(w, field_select=0, vacuum_direct=False):
     ref = {0: "phi_m", 1: "phi_0", 3: "phi_rec"}[field_select]
     err = float(np.max(np.abs(g["phi"] - o[ref])) / np.max(np.abs(o[ref])))
     _say(f"  dG gpu {g.get('dG')} oracle {o.get('dG')}  field rel err {err:.3e}")
-    assert err <= 1e-10
+    assert err <= 1e-11
     assert g["steps_done"] == sum(p.n_steps << lv for lv in range(2 if p.richardson else 1)) * \
         (2 if p.vacuum else 1)
     return g
@@ -158,4 +158,4 @@ def test_euler_full_size_against_stored_oracle_values():
     d = np.array([phi[i] for i in ref["field_nodes"]]) - np.array(ref["phi_m"])
     err = float(np.max(np.abs(d)) / ref["phi_m_absmax"])
     _say(f"  dG_direct gpu {g['dG_direct']} oracle {ref['dG_direct']} sampled rel err {err:.3e}")
-    assert err <= 1e-10
+    assert err <= 1e-11

@@ -1,7 +1,7 @@
 """GPU parity on caller-given fields (npb_solve_fields): the analytic
 charged-cavity benchmark of Sec. 4.1 (dense source, initial field with the
 Dirichlet data on its shell), against the FP64 oracle run on the same
-fields.  FP64: field within 1e-10 of max|u|.  Also checked: the GPU's
+fields.  FP64: field within 1e-11 of max|u|.  Also checked: the GPU's
 errors against the analytic solution at h = 0.5 equal the oracle's."""
 import sys
 
@@ -40,7 +40,7 @@ def test_sphere_fields_fp64_against_oracle(scheme):
     o = _oracle(b, scheme, dt, n)
     err = float(np.max(np.abs(g["u"] - o)) / np.max(np.abs(o)))
     _say("  rel err", err)
-    assert err <= 1e-10
+    assert err <= 1e-11
     assert g["steps_done"] == n
 
 
