@@ -1,17 +1,20 @@
 """Benchmark: LOD grid-point-updates/s of the full RE+V solve on one MI355X.
 
-One "step" is one complete solve of the 2000-atom globular workload
-(161^3 nodes, h = 0.5 A): setup, solvated and vacuum LODIE2 loops at
-dt = 0.2 (20 steps) and dt = 0.1 (40 steps), FP64 energy reductions and the
-Richardson + vacuum combination.  Inputs are resident in device memory
-before the timed region (atoms are copied in by the solve itself, 80 kB).
+One "step" is one complete solve of the 30000-atom complex (321^3 nodes,
+h = 0.35 A, 33 M nodes, ~0.6 GB of FP32 fields: beyond the 256 MB
+Infinity Cache, so the sweeps stream from HBM): setup, solvated and vacuum
+LODIE2 loops at dt = 0.4 (20 steps) and dt = 0.2 (40 steps), FP64 energy
+reductions and the Richardson + vacuum combination.  Inputs are resident in
+device memory before the timed region (the solve itself copies the atoms in,
+1.2 MB).  Beside the headline: the same solves on the plain FP64 path, and
+the 2000-atom globular workload (161^3) as an extra key.
 
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f32x|f64]
-                    [--no-cpu-baseline]
+                    [--workload large_complex_321|globular_2000_161] [--no-cpu-baseline]
     python bench.py --batch [--scheme AOSIE2]   64 uneven grids in one batch
     python bench.py --serve                     request loop, p50/p99 latency
-    python bench.py --large                     30000 atoms on 321^3 nodes
+    python bench.py --large                     30000 atoms on 321^3: LOD, AOS, FP64, dt 0.2
     python bench.py --direct                    direct vacuum Poisson solve, recovered potential
     python bench.py --sphere                    analytic charged cavity: convergence, stability
     python bench.py --euler                     explicit Euler reference: rate, energy at T = 10
@@ -38,21 +41,26 @@ def _sweep_source_sha(source: str = "sweep_kernels.hip"):
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def _traffic(kernel: str, precision: str, source: str = "sweep_kernels.hip"):
+def _traffic(workload: str, kernel: str, source: str = "sweep_kernels.hip"):
     """HBM bytes per launch of `kernel` (the profiler's name of the template
-    instance) from the committed PMC summary, if it was taken on the current
-    kernel source and the same instance ran there; else None."""
+    instance) on `workload`, from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (profiles/traffic.json), if those counters were taken
+    on the current kernel source; else None.  Returns (bytes, label)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
-        return None
+        return None, None
     try:
         d = json.load(open(p))
-        e = d.get(kernel)
-        if e and e.get("source_sha") == _sweep_source_sha(source):
-            return e.get("bytes_per_launch")
+        e = d.get(workload, {}).get(kernel)
+        sha = _sweep_source_sha(source)
+        if e and e.get("source_sha") == sha:
+            return e.get("bytes_per_launch"), (
+                f"profiles/traffic.json: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of {workload}, "
+                f"{e.get('dispatches')} dispatches, calibrated on a plain copy; kernel source "
+                f"sha256[:16] {sha}")
     except (OSError, ValueError):
-        return None
-    return None
+        return None, None
+    return None, None
 
 
 def cpu_baseline(workload, n_steps_meas: int = 2):
@@ -73,15 +81,58 @@ def cpu_baseline(workload, n_steps_meas: int = 2):
         for _ in range(n_steps_meas):
             u = oracle.lod_step(u, pb_m, p.dt, p.alpha, "LODIE2")
         t_step = (time.perf_counter() - t1) / n_steps_meas
+    del pb_v
     steps = p.n_steps * (3 if p.richardson else 1) * (2 if p.vacuum else 1)
     pts = w.grid.interior_points
     est = t_setup + steps * t_step
     return {"value": steps * pts / est, "unit": "grid-point-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"{w.name}: setup of both media ({t_setup:.1f} s) + {n_steps_meas} "
-                       f"solvated LODIE2 steps ({t_step:.2f} s/step), extrapolated to the "
-                       f"{steps} steps of one solve; numpy FP64, 1 thread"),
+            "host_cpu_count": os.cpu_count(), "kind": "oracle",
+            "sample": (f"{w.name}: setup of both media ({t_setup:.1f} s) + the first "
+                       f"{n_steps_meas} solvated LODIE2 steps ({t_step:.2f} s/step), "
+                       f"extrapolated to the {steps} steps of one solve; numpy FP64, 1 thread"),
             "seconds_measured": t_setup + n_steps_meas * t_step}
+
+
+def cpu_baseline_large(workload, n_steps_meas: int = 5):
+    """The FP64 oracle on the host, on the full 321^3 grid: the first
+    `n_steps_meas` solvated LODIE2 steps, timed and extrapolated to the
+    solve's step count.  The oracle's own setup functions build the step's
+    data (solute mask, trilinear charges, source density) outside the
+    timed steps; its Dirichlet data of 30000 atoms on 6.2e5 shell nodes
+    (1.9e10 pair terms, several minutes in NumPy) are left at zero, which
+    does not change what a step costs.  The paper also leaves setup out of
+    its CPU times."""
+    import numpy as np
+    import threadpoolctl
+
+    from oracle import npb as O
+    w = workload
+    p = w.params
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        Q = O.spread_charges(w.grid, w.molecule.xyz, w.molecule.q)
+        rho = O.source_density(Q, w.grid.h, p.temperature_K)
+        kb2 = O.kappa_bar_sq(p.ionic_molar, p.temperature_K)
+        pb = O.problem_from_fields(w.grid, w.molecule, p.eps_in, p.eps_out, kb2, rho,
+                                   np.zeros(O.shape_zyx(w.grid)), p.temperature_K)
+        t_setup = time.perf_counter() - t0
+        u = pb.u0
+        t1 = time.perf_counter()
+        for _ in range(n_steps_meas):
+            u = O.lod_step(u, pb, p.dt, p.alpha, "LODIE2")
+        t_step = (time.perf_counter() - t1) / n_steps_meas
+    steps = p.n_steps * (3 if p.richardson else 1) * (2 if p.vacuum else 1)
+    pts = w.grid.interior_points
+    return {"value": pts / t_step, "unit": "grid-point-updates/s", "cores": 1,
+            "host_cpu_count": os.cpu_count(), "kind": "oracle",
+            "sample": (f"{w.name}: the first {n_steps_meas} solvated LODIE2 steps of the FP64 "
+                       f"oracle on the full {w.grid.nx}^3 grid ({t_step:.2f} s/step), "
+                       f"extrapolated to the {steps} steps of one RE+V solve "
+                       f"({steps * t_step:.0f} s); setup ({t_setup:.1f} s for mask, charges and "
+                       f"source; Dirichlet data left at zero) not timed; every step timed as a "
+                       f"solvated one (the vacuum steps have no mask and no sinh); "
+                       f"numpy FP64, 1 thread"),
+            "seconds_measured": n_steps_meas * t_step}
 
 
 def _energy_tol(ref):
@@ -488,7 +539,7 @@ def bench_euler(args):
             "device_ms_median": dev_ms,
             "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4),
-                         "traffic": _traffic("npb::euler_step_kernel", "f64", "euler_kernels.hip"),
+                         "traffic": _traffic(w.name, "npb::euler_step_kernel", "euler_kernels.hip")[0],
                          "kernel": "npb::euler_step_kernel", "avg_launch_us": round(avg_us, 2),
                          "algorithmic_bytes_per_launch": bytes_per_launch,
                          "bytes_per_node": 17, "interior_nodes": X * Y * Z,
@@ -578,6 +629,203 @@ def bench_serve(args):
                        for k in after}}
 
 
+_TNAME = {"f32": "float, float", "f32x": "float, double", "f64": "double, double"}
+
+
+def _kernel_instance(kname, shapes, precision, scheme):
+    """The profiler's name of the sweep kernel instance a timing-pass key
+    ("x", "yz_plain", "yz_flow", "yz_general") ran as, from the launch
+    shapes [rows per chunk, chunks, lines per block or tile width, threads]."""
+    tname = _TNAME[precision]
+    if kname == "x":
+        cn = "true" if "CN" in scheme else "false"
+        return f"npb::sweep_x_kernel<{tname}, {shapes[0][0]}, {shapes[0][2]}, {cn}>"
+    var = {"yz_plain": 0, "yz_flow": 1, "yz_general": 2}[kname]
+    d = 1 if var != 1 else 2
+    return f"npb::sweep_yz_kernel<{tname}, {shapes[d][0]}, {var}, {shapes[d][2]}>"
+
+
+def _measure(w, args, ref, steps, timing, tune, label):
+    """Solves of workload w as a caller runs them (graph replay, inputs
+    resident): `steps` timed solves between two stream events after the
+    warm-up, then optionally a timing pass with kernel-attached events.
+    Energies against ref["dG"] under the contract max(1e-3, 1e-5 |dG|)."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2788_amd import npb
+    solver = npb.Solver(w.molecule, w.grid, w.params, device=0)
+    print(f"[bench] {label}: {w.name} {w.params.precision} {w.params.scheme} "
+          f"warmup={args.warmup} steps={steps}", file=sys.stderr, flush=True)
+    tune_ms = solver.autotune() if tune else None
+    shapes = npb.npb_launch_shapes(solver.ctx, solver.grid, solver.params)
+    for _ in range(max(1, args.warmup)):
+        solver.run()
+    stream = torch.cuda.current_stream()
+    lat, results = [], []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        t = time.perf_counter()
+        results.append(solver.run())
+        lat.append((time.perf_counter() - t) * 1e3)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ktimes = None
+    if timing:
+        # the same solves once more with every sweep launch carrying events
+        # that record its kernel's own start and stop (direct launches, the
+        # two media's launches one after another on the solve's stream)
+        print(f"[bench] {label}: per-kernel timing pass", file=sys.stderr, flush=True)
+        npb.npb_ctx_set_timing(solver.ctx, True)
+        for _ in range(min(steps, 5)):
+            solver.run()
+        torch.cuda.synchronize()
+        ktimes = npb.npb_ctx_get_kernel_times(solver.ctx)
+        npb.npb_ctx_set_timing(solver.ctx, False)
+    del solver
+    tol = _energy_tol(ref["dG"])
+    errs = [abs(r["dG"] - ref["dG"]) for r in results]
+    good = sum(e <= tol for e in errs)
+    per_solve = results[0]["grid_point_updates"]
+    return {"results": results, "total_ms": total_ms, "ms_per_solve": total_ms / steps,
+            "lat": lat, "ktimes": ktimes, "shapes": shapes, "tuned": tune_ms is not None,
+            "tol": tol, "errs": errs, "good": good, "per_solve": per_solve,
+            "value": per_solve * good / (total_ms * 1e-3),
+            "value_all": per_solve * len(results) / (total_ms * 1e-3)}
+
+
+def _roofline(m, w, precision, scheme, steps):
+    """Roofline of the dominant sweep kernel (largest summed duration in the
+    timing pass): its algorithmic bytes per launch over its mean
+    kernel-attached-event duration; and the whole solve's sweep bytes over
+    its device time."""
+    import numpy as np
+    ktimes = m["ktimes"]
+    bk = ktimes["by_kernel"]
+    kname = max(bk, key=lambda k: bk[k]["ms"])
+    kt = bk[kname]
+    avg_ms = kt["ms"] / max(kt["count"], 1)
+    bpl = kt["bytes"] / max(kt["count"], 1)
+    ach = bpl / (avg_ms * 1e-3) / 1e9
+    full = _kernel_instance(kname, m["shapes"], precision, scheme)
+    traffic, tlabel = _traffic(w.name, full)
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_source": tlabel,
+            "kernel": full, "avg_launch_us": round(avg_ms * 1e3, 2),
+            "algorithmic_bytes_per_launch": bpl,
+            "timing": "timing pass: every sweep launch carries HIP events that record the "
+                      "kernel's own start and stop (hipExtLaunchKernelGGL); the two media's "
+                      "launches issued one after another on one stream",
+            "per_kernel": {_kernel_instance(k, m["shapes"], precision, scheme): {
+                "launches": bk[k]["count"],
+                "avg_us": round(bk[k]["ms"] / max(bk[k]["count"], 1) * 1e3, 2),
+                "GBps": round(bk[k]["bytes"] / max(bk[k]["ms"], 1e-12) / 1e6, 1),
+                "frac": round(bk[k]["bytes"] / max(bk[k]["ms"], 1e-12) / 1e6 / HBM_PEAK_GBS, 4)}
+                for k in bk if bk[k]["count"] and k != "euler"},
+            "per_class": {c: {"launches": ktimes[c]["count"],
+                              "avg_us": round(ktimes[c]["ms"] / max(ktimes[c]["count"], 1) * 1e3, 2),
+                              "GBps": round(ktimes[c]["bytes"] / max(ktimes[c]["ms"], 1e-12) / 1e6, 1)}
+                          for c in ("sweep_x", "sweep_y", "sweep_z", "init", "setup", "energy")}}
+    # whole solve, as timed (the two media's sweeps on concurrent streams):
+    # algorithmic bytes of every sweep of one solve over its device time
+    sweep_bytes = sum(ktimes[c]["bytes"] for c in ("sweep_x", "sweep_y", "sweep_z"))
+    nsolves = max(min(steps, 5), 1)
+    dev_ms = float(np.median([r["device_ms"] for r in m["results"]]))
+    pg = sweep_bytes / nsolves / (dev_ms * 1e-3) / 1e9
+    roof["solve_pipeline"] = {"algorithmic_sweep_bytes_per_solve": sweep_bytes / nsolves,
+                              "solve_device_ms": dev_ms, "achieved": round(pg, 1),
+                              "frac": round(pg / HBM_PEAK_GBS, 4)}
+    return roof
+
+
+def bench_solve(args):
+    """The headline line: one RE+V solve per step on the chosen workload
+    (default: the 30000-atom complex on 321^3, FP32 LODIE2, dt 0.4 / 0.2 with
+    20 / 40 steps), energies held to the stored FP64-oracle values; the plain
+    FP64 path on the same workload beside it; the 161^3 globular workload
+    as an extra key; the oracle's rate on the host."""
+    import numpy as np
+    import torch
+
+    from paper_1410_2788_amd import inputs, npb
+    large = args.workload == "large_complex_321"
+    mk = ((lambda prec: inputs.large_complex(precision=prec, scheme=args.scheme)) if large
+          else (lambda prec: inputs.globular_2000(precision=prec, scheme=args.scheme)))
+    w = mk(args.precision)
+    gname = {("large_complex_321", "LODIE2"): "large_complex_321_lodie2_dt04.json",
+             ("large_complex_321", "AOSIE2"): "large_complex_321_aosie2_dt04.json",
+             ("globular_2000_161", "LODIE2"): "globular_2000_161.json"}.get((w.name, args.scheme))
+    ref = _golden(gname) if gname else None
+    ref_kind = "FP64 oracle (stored, tests/golden/" + gname + ")" if ref else None
+    if ref is None:
+        # other schemes: the FP64 GPU path of the same scheme (held to the
+        # oracle by the parity tests) as the reference
+        ref = npb.solve(w.molecule, w.grid, dataclasses.replace(w.params, precision="f64"))
+        ref_kind = "FP64 GPU path, same scheme"
+    m = _measure(w, args, ref, args.steps, not args.no_timing, not args.no_autotune, "headline")
+    roof = _roofline(m, w, args.precision, args.scheme, args.steps) if m["ktimes"] else None
+    results = m["results"]
+    out = {
+        "metric": METRIC, "value": m["value"], "unit": "grid-point-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_solve"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f32x": "f32-storage/f64-solve", "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.grid.nx, w.grid.ny, w.grid.nz], "h": w.grid.h,
+                   "atoms": w.molecule.n_atoms, "scheme": args.scheme, "richardson": True,
+                   "vacuum": True, "dt": [w.params.dt, w.params.dt / 2],
+                   "steps_per_solve": results[0]["steps_done"],
+                   "launch_shapes": {"x": m["shapes"][0], "y": m["shapes"][1],
+                                     "z": m["shapes"][2], "autotuned": m["tuned"]},
+                   "grid_point_updates_per_solve": m["per_solve"]},
+        "latency_ms": {"p50": float(np.percentile(m["lat"], 50)),
+                       "p99": float(np.percentile(m["lat"], 99)),
+                       "device_ms_median": float(np.median([r["device_ms"] for r in results]))},
+        "energy": {"dG": results[0]["dG"], "reference": ref_kind, "oracle_dG": ref["dG"],
+                   "abs_err": m["errs"][0], "max_abs_err": max(m["errs"]),
+                   "tolerance": m["tol"], "solves_within_tolerance": m["good"],
+                   "dG_err_bound": results[0].get("dG_err_bound")},
+        "roofline": roof,
+    }
+    if args.precision != "f64" and not args.no_f64:
+        # the plain single-solve FP64 GPU path on the same workload
+        w64 = mk("f64")
+        n64 = max(1, min(args.steps, 5))
+        m64 = _measure(w64, args, ref, n64, False, False, "fp64")
+        out["fp64_same_workload"] = {
+            "value": m64["value"], "ms_per_solve": m64["ms_per_solve"], "solves": n64,
+            "abs_err": m64["errs"][0], "solves_within_tolerance": m64["good"],
+            "speedup_of_headline": m["value"] / m64["value"] if m64["value"] else None}
+    if large and not args.no_extra:
+        wg = inputs.globular_2000(precision=args.precision, scheme=args.scheme)
+        rg = _golden("globular_2000_161.json") if args.scheme == "LODIE2" else None
+        if rg is not None:
+            mg = _measure(wg, args, rg, args.steps, False, not args.no_autotune, "extra")
+            out["globular_2000_161"] = {
+                "value": mg["value"], "ms_per_solve": mg["ms_per_solve"],
+                "grid": [wg.grid.nx, wg.grid.ny, wg.grid.nz],
+                "abs_err": mg["errs"][0], "solves_within_tolerance": mg["good"],
+                "note": "4 FP32 fields of 24 MB: the working set fits the 256 MB Infinity "
+                        "Cache, so this rate is not an HBM figure"}
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = (cpu_baseline_large(inputs.large_complex(precision="f64"))
+                               if large else cpu_baseline(inputs.globular_2000(precision="f64")))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -587,6 +835,14 @@ def main():
     ap.add_argument("--scheme", default="LODIE2",
                     choices=["LODIE2", "LODIE1", "AOSIE2", "AOSIE1", "LODCN1", "LODCN2",
                              "AOSCN1", "AOSCN2", "MAOSIE", "MAOSCN"])
+    ap.add_argument("--workload", default="large_complex_321",
+                    choices=["large_complex_321", "globular_2000_161"],
+                    help="headline workload: the 30000-atom complex on 321^3 (default) or the "
+                         "2000-atom globular molecule on 161^3")
+    ap.add_argument("--no-f64", action="store_true",
+                    help="skip the FP64 solves of the same workload beside the headline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 161^3 globular workload beside the 321^3 headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-kernel event timing pass")
@@ -643,147 +899,7 @@ def main():
         print(json.dumps(bench_large(args)))
         return
 
-    import numpy as np
-    import torch
-
-    from paper_1410_2788_amd import inputs, npb
-
-    w = inputs.globular_2000(precision=args.precision, scheme=args.scheme)
-    if args.scheme == "LODIE2":
-        ref = json.load(open(os.path.join(ROOT, "tests", "golden", "globular_2000_161.json")))
-        ref_kind = "FP64 oracle (stored)"
-    else:
-        # other schemes: the FP64 GPU path of the same scheme (held to the
-        # oracle by the parity tests) as the reference
-        ref = npb.solve(w.molecule, w.grid, dataclasses.replace(w.params, precision="f64"))
-        ref_kind = "FP64 GPU path, same scheme"
-    solver = npb.Solver(w.molecule, w.grid, w.params, device=0)
-    print(f"[bench] {w.name} precision={args.precision} scheme={args.scheme} "
-          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    # launch shapes: tuned for this grid size once, before any timing
-    tune_ms = None if args.no_autotune else solver.autotune()
-    shapes = npb.npb_launch_shapes(solver.ctx, solver.grid, solver.params)
-    for _ in range(args.warmup):
-        solver.run()
-    torch.cuda.synchronize()
-
-    # timed region: solves as a caller runs them (graph replay of the
-    # device work, inputs already resident)
-    stream = torch.cuda.current_stream()
-    lat = []
-    results = []
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        t = time.perf_counter()
-        r = solver.run()
-        lat.append((time.perf_counter() - t) * 1e3)
-        results.append(r)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-
-    # per-kernel durations: the same solves once more with every launch
-    # bracketed by HIP events (direct launches, the launches of the two
-    # media one after another on the solve's stream, so that each duration
-    # is the kernel's own and not shared with a concurrent launch)
-    ktimes = None
-    if not args.no_timing:
-        print("[bench] per-kernel timing pass", file=sys.stderr, flush=True)
-        npb.npb_ctx_set_timing(solver.ctx, True)
-        for _ in range(min(args.steps, 5)):
-            solver.run()
-        torch.cuda.synchronize()
-        ktimes = npb.npb_ctx_get_kernel_times(solver.ctx)
-        npb.npb_ctx_set_timing(solver.ctx, False)
-
-    # accuracy gate: the FP64 oracle's energies for this workload
-    tol = max(1e-3, 1e-5 * abs(ref["dG"]))
-    errs = [abs(r["dG"] - ref["dG"]) for r in results]
-    ok = [e <= tol for e in errs] if errs else [False] * len(results)
-    per_solve = results[0]["grid_point_updates"]
-    ms_per_step = total_ms / args.steps
-    good = sum(ok)
-    value = per_solve * good / (total_ms * 1e-3)
-
-    roof = None
-    if ktimes:
-        # dominant sweep kernel (the one with the largest summed duration),
-        # named as the profiler names the template instance that ran it
-        bk = ktimes["by_kernel"]
-        kname = max(bk, key=lambda k: bk[k]["ms"])
-        kt = bk[kname]
-        avg_ms = kt["ms"] / max(kt["count"], 1)
-        bpl = kt["bytes"] / max(kt["count"], 1)
-        ach = bpl / (avg_ms * 1e-3) / 1e9
-        tname = {"f32": "float, float", "f32x": "float, double", "f64": "double, double"}[args.precision]
-        if kname == "x":
-            cn = "true" if "CN" in args.scheme else "false"
-            full = f"npb::sweep_x_kernel<{tname}, {shapes[0][0]}, {shapes[0][2]}, {cn}>"
-        else:
-            var = {"yz_plain": 0, "yz_flow": 1, "yz_general": 2}[kname]
-            d = 1 if var != 1 else 2
-            full = f"npb::sweep_yz_kernel<{tname}, {shapes[d][0]}, {var}, {shapes[d][2]}>"
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": _traffic(full, args.precision),
-                "kernel": full, "avg_launch_us": round(avg_ms * 1e3, 2),
-                "algorithmic_bytes_per_launch": bpl,
-                "timing": "timing pass: every sweep launch carries HIP events that record the "
-                          "kernel's own start and stop (hipExtLaunchKernelGGL); the two media's "
-                          "launches issued one after another on one stream",
-                "per_kernel": {k: {"launches": bk[k]["count"],
-                                   "avg_us": round(bk[k]["ms"] / max(bk[k]["count"], 1) * 1e3, 2),
-                                   "GBps": round(bk[k]["bytes"] / max(bk[k]["ms"], 1e-12) / 1e6, 1)}
-                               for k in bk if bk[k]["count"]},
-                "per_class": {c: {"launches": ktimes[c]["count"],
-                                  "avg_us": round(ktimes[c]["ms"] / max(ktimes[c]["count"], 1) * 1e3, 2),
-                                  "GBps": round(ktimes[c]["bytes"] / max(ktimes[c]["ms"], 1e-12) / 1e6, 1)}
-                              for c in ("sweep_x", "sweep_y", "sweep_z", "init", "setup", "energy")}}
-
-    if roof is not None:
-        # Whole-solve figure for the timed solves, whose two media sweep on
-        # concurrent streams: algorithmic bytes of every sweep of one solve
-        # over the solve's device time (setup and energies included).
-        sweep_bytes = sum(ktimes[c]["bytes"] for c in ("sweep_x", "sweep_y", "sweep_z"))
-        nsolves = max(min(args.steps, 5), 1)
-        dev_ms = float(np.median([r["device_ms"] for r in results]))
-        pg = sweep_bytes / nsolves / (dev_ms * 1e-3) / 1e9
-        roof["solve_pipeline"] = {"algorithmic_sweep_bytes_per_solve": sweep_bytes / nsolves,
-                                  "solve_device_ms": dev_ms, "achieved": round(pg, 1),
-                                  "frac": round(pg / HBM_PEAK_GBS, 4)}
-    out = {
-        "metric": METRIC, "value": value, "unit": "grid-point-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f32": "f32", "f32x": "f32-storage/f64-solve", "f64": "f64"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": w.name, "grid": [w.grid.nx, w.grid.ny, w.grid.nz], "h": w.grid.h,
-                   "atoms": w.molecule.n_atoms, "scheme": args.scheme, "richardson": True,
-                   "vacuum": True, "dt": [w.params.dt, w.params.dt / 2],
-                   "steps_per_solve": results[0]["steps_done"],
-                   "launch_shapes": {"x": shapes[0], "y": shapes[1], "z": shapes[2],
-                                     "autotuned": tune_ms is not None},
-                   "grid_point_updates_per_solve": per_solve},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "device_ms_median": float(np.median([r["device_ms"] for r in results]))},
-        "energy": {"dG": results[0]["dG"], "reference": ref_kind, "oracle_dG": ref["dG"],
-                   "abs_err": errs[0] if errs else None, "tolerance": tol,
-                   "solves_within_tolerance": good},
-        "roofline": roof,
-    }
-    if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(inputs.globular_2000(precision="f64"))
-    print(json.dumps(out))
+    print(json.dumps(bench_solve(args)))
 
 
 if __name__ == "__main__":
