@@ -371,8 +371,19 @@ struct npb_ctx {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
-  void* pinned = nullptr;
-  size_t pinned_bytes = 0;
+  // Host staging: two page-locked buffers used in turn.  Each carries the
+  // event recorded after the last enqueue whose copies read it, so a call
+  // never rewrites bytes that an earlier call's copies (on any stream)
+  // still read, and back-to-back asynchronous calls do not wait for each
+  // other's solves.
+  void* pin[2] = {nullptr, nullptr};
+  size_t pin_bytes[2] = {0, 0};
+  hipEvent_t pin_ev[2] = {nullptr, nullptr};
+  bool pin_used[2] = {false, false};
+  int pin_next = 0;
+  // event after the last enqueue that read the launch tables (ctx->meta)
+  hipEvent_t meta_ev = nullptr;
+  bool meta_used = false;
   hipEvent_t t0 = nullptr, t1 = nullptr;
 };
 
@@ -730,6 +741,9 @@ struct Engine {
   };
   std::vector<Group> groups[3];
   std::vector<unsigned char> meta;  // host image of the launch tables
+  unsigned char* hb = nullptr;     // host staging of this call
+  unsigned char* dmeta = nullptr;  // device launch tables of this call
+  int pin_slot = -1;               // ctx->pin buffer staged into (-1: none)
 
   template <typename F>
   npb_status timed(int cls, double bytes, F&& f) {
@@ -936,13 +950,13 @@ struct Engine {
     return NPB_OK;
   }
 
-  // Pinned staging: [results: 128 B per problem][launch tables][per problem:
-  // chunk tables, atom planes].  The host fills it (after the stream has
-  // drained earlier copies out of it), then one copy per region moves it to
-  // the device.  with_meta = false keeps the launch tables already in the
-  // context's device buffer (a graph replay of the same batch).
+  // Host staging: [results: 128 B per problem][launch tables][per problem:
+  // chunk tables, atom planes].  The host fills it, then one copy per
+  // region moves it to the device.  with_meta = false keeps the launch
+  // tables already in the context's device buffer (a graph replay of the
+  // same batch).  The staging buffer is one of the context's two
+  // page-locked buffers, taken once the last enqueue that read it is done.
   npb_status stage(bool with_meta) {
-    NPB_HIP(hipStreamSynchronize(st));
     const size_t res_bytes = 128 * pr.size();
     size_t need = res_bytes + (with_meta ? meta.size() : 0);
     for (Problem& P : pr) {
@@ -951,28 +965,41 @@ struct Engine {
       P.atoms_pinned = need;
       need += (size_t)5 * P.mol->n_atoms * 8;
     }
-    if (ctx->pinned_bytes < need) {
-      if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-      ctx->pinned = nullptr;
-      ctx->pinned_bytes = 0;
-      NPB_HIP(hipHostMalloc(&ctx->pinned, need, hipHostMallocDefault));
-      ctx->pinned_bytes = need;
-    }
-    unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
-    if (with_meta) {
-      // the captured graph reads the launch tables being replaced: drop it
-      if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
-      ctx->exec = nullptr;
-      ctx->key.clear();
-      if (ctx->meta_bytes < meta.size()) {
-        if (ctx->meta) (void)hipFree(ctx->meta);
-        ctx->meta = nullptr;
-        ctx->meta_bytes = 0;
-        NPB_HIP(hipMalloc(&ctx->meta, meta.size()));
-        ctx->meta_bytes = meta.size();
+    {
+      const int b = ctx->pin_next;
+      ctx->pin_next ^= 1;
+      if (ctx->pin_used[b]) NPB_HIP(hipEventSynchronize(ctx->pin_ev[b]));
+      ctx->pin_used[b] = false;
+      if (ctx->pin_bytes[b] < need) {
+        if (ctx->pin[b]) (void)hipHostFree(ctx->pin[b]);
+        ctx->pin[b] = nullptr;
+        ctx->pin_bytes[b] = 0;
+        NPB_HIP(hipHostMalloc(&ctx->pin[b], need, hipHostMallocDefault));
+        ctx->pin_bytes[b] = need;
       }
+      hb = reinterpret_cast<unsigned char*>(ctx->pin[b]);
+      pin_slot = b;
+      if (with_meta) {
+        // the captured graph and earlier enqueues read the launch tables
+        // being replaced: wait for them, then drop the graph
+        if (ctx->meta_used) NPB_HIP(hipEventSynchronize(ctx->meta_ev));
+        ctx->meta_used = false;
+        if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+        ctx->exec = nullptr;
+        ctx->key.clear();
+        if (ctx->meta_bytes < meta.size()) {
+          if (ctx->meta) (void)hipFree(ctx->meta);
+          ctx->meta = nullptr;
+          ctx->meta_bytes = 0;
+          NPB_HIP(hipMalloc(&ctx->meta, meta.size()));
+          ctx->meta_bytes = meta.size();
+        }
+      }
+      dmeta = reinterpret_cast<unsigned char*>(ctx->meta);
+    }
+    if (with_meta) {
       std::memcpy(hb + res_bytes, meta.data(), meta.size());
-      NPB_HIP(hipMemcpyAsync(ctx->meta, hb + res_bytes, meta.size(), hipMemcpyHostToDevice, st));
+      NPB_HIP(hipMemcpyAsync(dmeta, hb + res_bytes, meta.size(), hipMemcpyHostToDevice, st));
     }
     for (Problem& P : pr) {
       for (int r = 0; r < P.L.n_runs; ++r) {
@@ -1167,7 +1194,7 @@ struct Engine {
         }
     // stagger of one sweep measured best (0, 2 and 3 sweeps: 2-3 % slower)
     const int lag = 1;
-    unsigned char* dm = reinterpret_cast<unsigned char*>(ctx->meta);
+    unsigned char* dm = dmeta;
     size_t total = 0;
     for (int l = 0; l < nl; ++l) total = std::max(total, seq[l].size() + (size_t)l * lag);
     for (size_t i = 0; i < total; ++i) {
@@ -1401,6 +1428,18 @@ struct Engine {
     return k;
   }
 
+  // After the last launch or copy of a call: the events that let later
+  // calls reuse this call's staging buffer and launch tables.
+  npb_status mark_enqueued() {
+    if (pin_slot >= 0) {
+      NPB_HIP(hipEventRecord(ctx->pin_ev[pin_slot], st));
+      ctx->pin_used[pin_slot] = true;
+    }
+    NPB_HIP(hipEventRecord(ctx->meta_ev, st));
+    ctx->meta_used = true;
+    return NPB_OK;
+  }
+
   static constexpr long long kMaxGraphEulerLaunches = 4096;
 
   // async: out is page-locked host memory written by a last kernel; the
@@ -1466,17 +1505,18 @@ struct Engine {
         NPB_HIP(launch_result(P.at<double>(P.L.slots) + 8, P.at<int>(P.L.ints), &out[i],
                               pts * steps, steps, st));
       }
-      return NPB_OK;
+      return mark_enqueued();
     }
     NPB_HIP(hipEventRecord(ctx->t1, st));
     // results to the host (first 128 bytes per problem of the staging buffer)
-    unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
     for (size_t i = 0; i < pr.size(); ++i) {
       NPB_HIP(hipMemcpyAsync(hb + 128 * i, pr[i].ws + pr[i].L.slots + 8 * 8, 8 * 8,
                              hipMemcpyDeviceToHost, st));
       NPB_HIP(hipMemcpyAsync(hb + 128 * i + 64, pr[i].ws + pr[i].L.ints, 8, hipMemcpyDeviceToHost,
                              st));
     }
+    npb_status sm = mark_enqueued();
+    if (sm != NPB_OK) return sm;
     NPB_HIP(hipStreamSynchronize(st));
     float ms = 0.f;
     NPB_HIP(hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
@@ -1587,7 +1627,7 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
                                      P.location() ? 1 : 0, P.at<uint8_t>(P.L.ccls[d]), st));
         // chunk tables of this chunk length for every run
         NPB_HIP(hipStreamSynchronize(st));
-        unsigned char* hb = reinterpret_cast<unsigned char*>(ctx->pinned);
+        unsigned char* hb = E.hb;
         for (int r = 0; r < nr; ++r) {
           const Coefs c = run_coefs(P, P.L.runs[r]);
           ChunkTab<A>& tb =
@@ -1683,7 +1723,7 @@ double npb_kappa_bar_sq(double ionic_molar, double temperature_K) {
 
 // streams and events of a context, then the context itself
 static void ctx_release(npb_ctx* c) {
-  for (hipEvent_t e : {c->t0, c->t1, c->fork})
+  for (hipEvent_t e : {c->t0, c->t1, c->fork, c->meta_ev, c->pin_ev[0], c->pin_ev[1]})
     if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < npb_ctx::kLanes - 1; ++i) {
     if (c->lag[i]) (void)hipEventDestroy(c->lag[i]);
@@ -1706,6 +1746,9 @@ npb_status npb_ctx_create(int device, npb_ctx** out) {
   c->device = device;
   bool ok = hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess &&
             hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->meta_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->pin_ev[0], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->pin_ev[1], hipEventDisableTiming) == hipSuccess &&
             hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; ok && i < npb_ctx::kLanes - 1; ++i)
     ok = hipEventCreateWithFlags(&c->lag[i], hipEventDisableTiming) == hipSuccess &&
@@ -1722,6 +1765,10 @@ npb_status npb_ctx_create(int device, npb_ctx** out) {
 void npb_ctx_destroy(npb_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  // enqueued copies may still read the staging buffers and launch tables
+  for (int b = 0; b < 2; ++b)
+    if (c->pin_used[b]) (void)hipEventSynchronize(c->pin_ev[b]);
+  if (c->meta_used) (void)hipEventSynchronize(c->meta_ev);
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -1729,7 +1776,8 @@ void npb_ctx_destroy(npb_ctx* c) {
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->exec) (void)hipGraphExecDestroy(c->exec);
   if (c->meta) (void)hipFree(c->meta);
-  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (int b = 0; b < 2; ++b)
+    if (c->pin[b]) (void)hipHostFree(c->pin[b]);
   ctx_release(c);
 }
 
