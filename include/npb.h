@@ -310,6 +310,27 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols,
                            void* const* d_ws, const size_t* ws_bytes,
                            double* const* d_field_out, void* stream, npb_result* out);
 
+/* ---- no device allocation ------------------------------------------------
+ * For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * npb_solve without a workspace argument.  The problem's workspace and its
+ * launch tables live in a static device array of NPB_NOALLOC_BYTES that the
+ * library's code object carries (each device the library runs on holds its
+ * own copy until the process ends); the atoms are staged through pageable
+ * host memory, every kernel is launched directly (no graph), and no
+ * hipMalloc, hipFree, hipHostMalloc or other allocating routine is called.
+ * The caller still passes the molecule and the optional d_field_out.
+ * Semantics, results and errors as npb_solve (per-kernel timing is not
+ * collected), plus EINVAL when npb_workspace_bytes of the problem and its
+ * launch tables exceed NPB_NOALLOC_BYTES (a 161^3 FP32 RE+V solve needs
+ * 85 MiB).  Every call on a device shares that device's array and leaves
+ * its contents behind (each solve initialises what it reads): calls that
+ * overlap on one device, from any context, stream or thread, race. */
+#define NPB_NOALLOC_BYTES (96u << 20)
+npb_status npb_solve_noalloc(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                             const npb_params* params, double* d_field_out, void* stream,
+                             npb_result* out);
+
 /* Choose the line-solver launch shapes for this grid size, precision and
  * splitting family (LOD / AOS) by timing: the problem is set up in d_ws
  * (as npb_solve would), then for each sweep direction every candidate shape

@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -324,6 +325,38 @@ template hipError_t launch_field_init<double>(double*, const double*, int, int, 
 }  // namespace npb
 
 // ---------------------------------------------------------------------------
+// Static scratch of npb_solve_noalloc: the workspace of one problem and its
+// launch tables live in this array, which the code object brings with it,
+// so that call allocates no device memory.  Every device the library runs
+// on holds its own copy until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[NPB_NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_addr;  // device -> address of `scratch`
+
+// With `device` current: this device's address of the static scratch.
+hipError_t scratch_address(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  *out = static_cast<unsigned char*>(ptr);
+  g_scratch_addr[device] = *out;
+  return hipSuccess;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // context
 
 // Everything a captured solve graph depends on besides the staged bytes,
@@ -384,6 +417,8 @@ struct npb_ctx {
   // event after the last enqueue that read the launch tables (ctx->meta)
   hipEvent_t meta_ev = nullptr;
   bool meta_used = false;
+  // this device's static scratch (npb_solve_noalloc)
+  unsigned char* scratch = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
 };
 
@@ -741,9 +776,14 @@ struct Engine {
   };
   std::vector<Group> groups[3];
   std::vector<unsigned char> meta;  // host image of the launch tables
+  // npb_solve_noalloc: the problem's workspace is the device's static
+  // scratch, the launch tables follow it there, the host staging is
+  // pageable memory of this call, and nothing is captured into a graph
+  bool noalloc = false;
   unsigned char* hb = nullptr;     // host staging of this call
   unsigned char* dmeta = nullptr;  // device launch tables of this call
   int pin_slot = -1;               // ctx->pin buffer staged into (-1: none)
+  std::vector<unsigned char> hvec;
 
   template <typename F>
   npb_status timed(int cls, double bytes, F&& f) {
@@ -955,7 +995,9 @@ struct Engine {
   // region moves it to the device.  with_meta = false keeps the launch
   // tables already in the context's device buffer (a graph replay of the
   // same batch).  The staging buffer is one of the context's two
-  // page-locked buffers, taken once the last enqueue that read it is done.
+  // page-locked buffers, taken once the last enqueue that read it is done;
+  // the no-allocation path stages in pageable memory of its own and puts
+  // the launch tables into the static scratch after the workspace.
   npb_status stage(bool with_meta) {
     const size_t res_bytes = 128 * pr.size();
     size_t need = res_bytes + (with_meta ? meta.size() : 0);
@@ -965,7 +1007,17 @@ struct Engine {
       P.atoms_pinned = need;
       need += (size_t)5 * P.mol->n_atoms * 8;
     }
-    {
+    if (noalloc) {
+      hvec.assign(need, 0);
+      hb = hvec.data();
+      const size_t moff = align256(pr[0].L.total);
+      if (moff + meta.size() > (size_t)NPB_NOALLOC_BYTES)
+        return fail(NPB_EINVAL, "workspace (" + std::to_string(pr[0].L.total) +
+                                    " bytes) and launch tables (" + std::to_string(meta.size()) +
+                                    " bytes) exceed the static scratch of " +
+                                    std::to_string((size_t)NPB_NOALLOC_BYTES) + " bytes");
+      dmeta = ctx->scratch + moff;
+    } else {
       const int b = ctx->pin_next;
       ctx->pin_next ^= 1;
       if (ctx->pin_used[b]) NPB_HIP(hipEventSynchronize(ctx->pin_ev[b]));
@@ -1431,6 +1483,7 @@ struct Engine {
   // After the last launch or copy of a call: the events that let later
   // calls reuse this call's staging buffer and launch tables.
   npb_status mark_enqueued() {
+    if (noalloc) return NPB_OK;
     if (pin_slot >= 0) {
       NPB_HIP(hipEventRecord(ctx->pin_ev[pin_slot], st));
       ctx->pin_used[pin_slot] = true;
@@ -1454,7 +1507,8 @@ struct Engine {
       if (P.p->scheme == NPB_EULER)
         for (int r = 0; r < P.L.n_runs; ++r)
           euler_launches += (long long)P.p->n_steps << P.L.runs[r].level;
-    const bool graph = ctx->graphs && !ctx->timing && euler_launches <= kMaxGraphEulerLaunches;
+    const bool graph =
+        ctx->graphs && !ctx->timing && !noalloc && euler_launches <= kMaxGraphEulerLaunches;
     std::vector<unsigned char> key = graph_key();
     const bool replay = graph && ctx->exec && key == ctx->key;
     npb_status s = NPB_OK;
@@ -1701,8 +1755,9 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
 
 template <typename T, typename A>
 npb_status solve_batch_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st, npb_result* out,
-                         bool async) {
+                         bool async, bool noalloc) {
   Engine<T, A> E{ctx, st, pr, {}, {}, {}};
+  E.noalloc = noalloc;
   return E.run(out, async);
 }
 
@@ -1757,6 +1812,12 @@ npb_status npb_ctx_create(int device, npb_ctx** out) {
   if (!ok) {
     ctx_release(c);
     return fail(NPB_EDEVICE, "event or stream creation failed");
+  }
+  const hipError_t se = scratch_address(device, &c->scratch);
+  if (se != hipSuccess) {
+    ctx_release(c);
+    return fail(NPB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(se));
   }
   *out = c;
   return NPB_OK;
@@ -1819,16 +1880,25 @@ namespace {
 
 // the device work of checked problems (one precision)
 npb_status run_problems(npb_ctx* ctx, std::vector<Problem>& pr, void* stream, npb_result* out,
-                        bool async = false) {
+                        bool async = false, bool noalloc = false) {
   // every argument checked: only now is the context read
   for (Problem& P : pr) apply_tuning(ctx, P.g, P.p, P.L);
   NPB_HIP(hipSetDevice(ctx->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int precision = pr[0].p->precision;
+  // the no-allocation path takes no timing events either
+  struct TimingOff {
+    npb_ctx* c;
+    bool was;
+    ~TimingOff() { c->timing = was; }
+  } keep{ctx, ctx->timing};
+  if (noalloc) ctx->timing = false;
   try {
-    if (precision == NPB_FP64) return solve_batch_t<double, double>(ctx, pr, st, out, async);
-    if (precision == NPB_FP32X) return solve_batch_t<float, double>(ctx, pr, st, out, async);
-    return solve_batch_t<float, float>(ctx, pr, st, out, async);
+    if (precision == NPB_FP64)
+      return solve_batch_t<double, double>(ctx, pr, st, out, async, noalloc);
+    if (precision == NPB_FP32X)
+      return solve_batch_t<float, double>(ctx, pr, st, out, async, noalloc);
+    return solve_batch_t<float, float>(ctx, pr, st, out, async, noalloc);
   } catch (const std::exception& e) {
     return fail(NPB_ENOMEM, e.what());
   } catch (...) {
@@ -2051,6 +2121,31 @@ npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid
   const npb_status s = npb_solve_batch(ctx, 1, mol, grid, params, ws, wb, fo, stream, out);
   if (s != NPB_OK && g_err.rfind("problem 0: ", 0) == 0) g_err = g_err.substr(11);
   return s;
+}
+
+npb_status npb_solve_noalloc(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid,
+                             const npb_params* params, double* d_field_out, void* stream,
+                             npb_result* out) {
+  if (!ctx || !out) return fail(NPB_EINVAL, "null context or result");
+  if (!mol || !grid || !params) return fail(NPB_EINVAL, "null argument");
+  npb_status s = validate(mol, grid, params);
+  if (s != NPB_OK) return s;
+  if (!ctx->scratch) return fail(NPB_EDEVICE, "no static scratch on this device");
+  std::vector<Problem> pr(1);
+  Problem& P = pr[0];
+  P.mol = mol;
+  P.g = grid;
+  P.p = params;
+  P.ws = ctx->scratch;
+  P.fout = d_field_out;
+  P.L = make_layout(mol, grid, params);
+  P.kT = thermal_energy(params->temperature_K);
+  P.lB = bjerrum(params->temperature_K);
+  if (P.L.total > (size_t)NPB_NOALLOC_BYTES)
+    return fail(NPB_EINVAL, "workspace of " + std::to_string(P.L.total) +
+                                " bytes exceeds the static scratch of " +
+                                std::to_string((size_t)NPB_NOALLOC_BYTES) + " bytes");
+  return run_problems(ctx, pr, stream, out, false, true);
 }
 
 }  // extern "C"

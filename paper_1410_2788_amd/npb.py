@@ -139,6 +139,9 @@ def load_library(path: str = LIB_PATH):
         lib.npb_solve.restype = C.c_int
         lib.npb_solve.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, P(npb_result)]
+        lib.npb_solve_noalloc.restype = C.c_int
+        lib.npb_solve_noalloc.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid),
+                                          P(npb_params), C.c_void_p, C.c_void_p, P(npb_result)]
         lib.npb_solve_async.restype = C.c_int
         lib.npb_solve_async.argtypes = [C.c_void_p, P(npb_molecule), P(npb_grid), P(npb_params),
                                         C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
@@ -231,6 +234,20 @@ def npb_solve(ctx, mol: npb_molecule, grid: npb_grid, params: npb_params, d_ws: 
                                   C.c_void_p(d_ws), ws_bytes,
                                   C.c_void_p(d_field_out) if d_field_out else None,
                                   C.c_void_p(stream), C.byref(res))
+    if st != NPB_OK:
+        err = NPBError(st, npb_last_error())
+        err.result = res
+        raise err
+    return res
+
+
+def npb_solve_noalloc(ctx, mol: npb_molecule, grid: npb_grid, params: npb_params,
+                      d_field_out: Optional[int], stream: int) -> npb_result:
+    """npb_solve with the workspace in the library's static device scratch."""
+    res = npb_result()
+    st = load_library().npb_solve_noalloc(ctx, C.byref(mol), C.byref(grid), C.byref(params),
+                                          C.c_void_p(d_field_out) if d_field_out else None,
+                                          C.c_void_p(stream), C.byref(res))
     if st != NPB_OK:
         err = NPBError(st, npb_last_error())
         err.result = res
