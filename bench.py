@@ -789,7 +789,8 @@ def bench_solve(args):
         "energy": {"dG": results[0]["dG"], "reference": ref_kind, "oracle_dG": ref["dG"],
                    "abs_err": m["errs"][0], "max_abs_err": max(m["errs"]),
                    "tolerance": m["tol"], "solves_within_tolerance": m["good"],
-                   "dG_err_bound": results[0].get("dG_err_bound")},
+                   "dG_err_est": results[0].get("dG_err_est"),
+                   "within_estimate": m["errs"][0] <= results[0].get("dG_err_est", float("inf"))},
         "roofline": roof,
     }
     if args.precision != "f64" and not args.no_f64:

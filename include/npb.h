@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define NPB_ABI_VERSION 6
+#define NPB_ABI_VERSION 7
 
 typedef enum npb_status {
   NPB_OK = 0,
@@ -43,7 +43,8 @@ typedef enum npb_status {
                          Dirichlet shell (or leaves the grid)              */
   NPB_ENOMEM = 3,     /* host-side allocation failed                       */
   NPB_EDEVICE = 4,    /* a HIP runtime call failed                         */
-  NPB_EDIVERGED = 5,  /* a result is not finite                            */
+  NPB_EDIVERGED = 5,  /* a result is not finite: an energy, or a field value
+                         after any step                                    */
   NPB_EBUSY = 6       /* admission refused (serving)                       */
 } npb_status;
 
@@ -160,11 +161,22 @@ enum npb_field_units {
  *   device_ms       : device time from the first setup kernel to the
  *                     energies being ready
  *   n_charge_nodes  : distinct nodes carrying trilinear charge
- *   finite          : 1 if every reported energy is finite
+ *   finite          : 1 if every reported energy is finite and no field held
+ *                     a non-finite value after any step (the paper's sign of
+ *                     an unstable run, Sec. 4.2); else 0 and EDIVERGED
  *   dG_direct       : with vacuum_direct, (1/2) sum_p Q_p (phi_m,p - phi_0,p)
  *                     with phi_0 from the direct Poisson solve and phi_m
  *                     Richardson-combined when richardson = 1 (Eq. (deltaG2));
- *                     else NaN                                           */
+ *                     else NaN
+ *   dG_err_est      : estimated error of dG against the same solve in exact
+ *                     arithmetic (the FP64 oracle): eta * (1/2) kT * sum over
+ *                     the runs of |c_run| sum_p |Q_p u_p|, c_run the run's
+ *                     coefficient in dG (2 and -1 per medium with Richardson,
+ *                     else 1), eta = 4e-7 for FP32 / FP32X field storage and
+ *                     1e-13 for FP64 (set so that the errors measured on the
+ *                     full-size workloads stay below 0.4 of it); it grows with
+ *                     the cancellation of the combination.  NaN when
+ *                     vacuum = 0                                          */
 typedef struct npb_result {
   double dG;
   double dG_plain;
@@ -177,6 +189,7 @@ typedef struct npb_result {
   int32_t finite;
   int32_t reserved;
   double dG_direct;
+  double dG_err_est;
 } npb_result;
 
 typedef struct npb_ctx npb_ctx;

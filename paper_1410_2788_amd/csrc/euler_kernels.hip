@@ -93,6 +93,7 @@ __global__ __launch_bounds__(kTX * kTY) void euler_step_kernel(EulerArgs a) {
     un[z] = u[c + row];
     f[z] = fl[c];
   }
+  bool bad = false;
 #pragma unroll
   for (int z = 0; z < kZC; ++z) {
     const int k = k0 + z;
@@ -126,7 +127,10 @@ __global__ __launch_bounds__(kTX * kTY) void euler_step_kernel(EulerArgs a) {
     const long long c = (long long)k * plane + c0;
     if (fc & kSourceBit) r = fma(a.tau, node_source(a, c, k * a.ny + j), r);
     v[c] = uc + r;
+    bad |= !isfinite(uc + r);
   }
+  // a stored value that is not finite: the run diverged (Sec. 4.2)
+  if (bad && a.nonfinite != nullptr) atomicOr(a.nonfinite, 1);
 }
 
 // flags of every node from the solute mask (nullptr: no solute) and, for

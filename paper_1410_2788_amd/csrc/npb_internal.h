@@ -54,6 +54,9 @@ struct SweepArgs {
   const uint8_t* ccls;
   // ChunkTab<A> of this field and direction (device memory)
   const void* tab;
+  // set to 1 when a stored value is not finite; the z sweep's arguments only
+  // (the last sub-step of every split scheme), nullptr elsewhere
+  int* nonfinite;
   // geometry of the launch
   int M;                  // rows per chunk (compile-time in the kernel)
   int P;                  // chunks per line
@@ -326,6 +329,7 @@ struct EulerArgs {
   double tk;              // tau kbar^2
   int face_loc;           // 1: flag bits 1-6 are the faces' own solute bits (face rule
                           // by location): face = re[0] or re[2]
+  int* nonfinite;         // set to 1 when a stored value is not finite
   int tiles_x, tiles_y, ntiles, per;  // filled by launch_euler_step
 };
 

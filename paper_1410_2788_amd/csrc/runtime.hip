@@ -144,28 +144,42 @@ hipError_t launch_field_init_multi(const InitSet<T>& set, int nruns, int nx, int
   return hipGetLastError();
 }
 
-// energy slots of the runs of one problem at once: block r sums run r
+// energy slots of the runs of one problem at once: block r sums run r;
+// beside sum q u, sum |q u| (the scale of the rounding error of the sum's
+// terms)
 template <typename T>
 struct EnergySet {
   const T* u[kMaxFields];
   double* slot[kMaxFields];
+  double* aslot[kMaxFields];
 };
 template <typename T>
 __global__ __launch_bounds__(1024) void energy_multi_kernel(EnergySet<T> set, const int* q_idx,
                                                             const double* q_val,
                                                             const int* nq_dev) {
-  __shared__ double part[1024];
+  __shared__ double part[1024], apart[1024];
   const T* u = set.u[blockIdx.x];
   const int nq = *nq_dev;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nq; k += 1024) s += q_val[k] * (double)u[q_idx[k]];
+  double s = 0.0, sa = 0.0;
+  for (int k = threadIdx.x; k < nq; k += 1024) {
+    const double t = q_val[k] * (double)u[q_idx[k]];
+    s += t;
+    sa += fabs(t);
+  }
   part[threadIdx.x] = s;
+  apart[threadIdx.x] = sa;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
-    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    if (threadIdx.x < w) {
+      part[threadIdx.x] += part[threadIdx.x + w];
+      apart[threadIdx.x] += apart[threadIdx.x + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *set.slot[blockIdx.x] = part[0];
+  if (threadIdx.x == 0) {
+    *set.slot[blockIdx.x] = part[0];
+    *set.aslot[blockIdx.x] = apart[0];
+  }
 }
 
 template <typename T>
@@ -258,9 +272,13 @@ hipError_t launch_field_out(double* out, const T* u, int nx, int nxp, int ny, in
 }
 
 // S = [solvated dt, solvated dt/2, vacuum dt, vacuum dt/2, direct vacuum]
-// sums of q u.  res = [dG, dG_plain, G_m0, G_m1, G_00, G_01, finite, dG_direct]
-__global__ void combine_kernel(const double* S, double kT, int richardson, int vacuum,
-                               int direct, double* res) {
+// sums of q u, Sa the same runs' sums of |q u|, nf the runs' non-finite
+// flags (by run index), eta the relative rounding error of one run's sum
+// for the storage precision.  res = [dG, dG_plain, G_m0, G_m1, G_00, G_01,
+// finite, dG_direct, dG_err_est]
+__global__ void combine_kernel(const double* S, const double* Sa, const int* nf, int nruns,
+                               double eta, double kT, int richardson, int vacuum, int direct,
+                               double* res) {
   const double h = 0.5 * kT;
   double Gm0 = h * S[0], Gm1 = richardson ? h * S[1] : 0.0;
   double G00 = vacuum ? h * S[2] : 0.0, G01 = (vacuum && richardson) ? h * S[3] : 0.0;
@@ -276,18 +294,30 @@ __global__ void combine_kernel(const double* S, double kT, int richardson, int v
   res[5] = G01;
   bool fin = isfinite(Gm0) && isfinite(Gm1) && isfinite(G00) && isfinite(G01) &&
              (!vacuum || (isfinite(dG) && isfinite(dplain)));
+  // a field that held a non-finite value after a step
+  for (int r = 0; r < nruns; ++r) fin = fin && nf[r] == 0;
   // Eq. (deltaG2): the solvated potential (Richardson-combined when on)
   // against the vacuum potential of the direct Poisson solve
   const double dd = direct ? h * ((richardson ? 2.0 * S[1] - S[0] : S[0]) - S[4]) : nan;
   res[7] = dd;
   if (direct) fin = fin && isfinite(dd);
   res[6] = fin ? 1.0 : 0.0;
+  // error estimate of dG: each run's sum carries a relative error eta of
+  // its scale sum |q u|, weighted by the run's coefficient in dG (2 and -1
+  // per medium with Richardson, 1 without)
+  double est = nan;
+  if (vacuum) {
+    const double w1 = richardson ? 2.0 : 0.0, w0 = 1.0;
+    est = eta * h * ((w0 * Sa[0] + w1 * Sa[1]) + (w0 * Sa[2] + w1 * Sa[3]));
+  }
+  res[8] = est;
 }
 
-hipError_t launch_combine(const double* S, double kT, int richardson, int vacuum, int direct,
+hipError_t launch_combine(const double* S, const double* Sa, const int* nf, int nruns,
+                          double eta, double kT, int richardson, int vacuum, int direct,
                           double* res, hipStream_t st) {
-  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(1), 0, st, S, kT, richardson, vacuum, direct,
-                     res);
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(1), 0, st, S, Sa, nf, nruns, eta, kT,
+                     richardson, vacuum, direct, res);
   return hipGetLastError();
 }
 
@@ -304,6 +334,7 @@ __global__ void result_kernel(const double* res, const int* ints, npb_result* ou
   r.G_0[1] = res[5];
   r.finite = res[6] != 0.0 ? 1 : 0;
   r.dG_direct = res[7];
+  r.dG_err_est = res[8];
   r.grid_point_updates = points;
   r.device_ms = __longlong_as_double(0x7ff8000000000000LL);
   r.steps_done = steps;
@@ -491,6 +522,24 @@ struct Layout {
 
 // host staging (pinned): chunk tables first, then the atom planes
 constexpr size_t kTabBytes = sizeof(ChunkTab<double>);
+
+// Per-problem scalars in the workspace.  ints: [0] charge nodes, [1]
+// stencil error, [kNonfiniteInts + r] run r stored a non-finite value.
+// slots (doubles): [2 medium + level] sum q u of a run, [4] the direct
+// vacuum solve's, [kResSlots ..] the combined results (kResCount of them),
+// [kAbsSlots + 2 medium + level] sum |q u| of a run.
+constexpr int kNonfiniteInts = 4;
+constexpr int kResSlots = 8, kResCount = 9, kAbsSlots = 24;
+
+// Relative error of one run's energy sum, in units of its scale sum |q u|,
+// for the precision the fields are stored in (the dominant rounding): the
+// dG error estimate of npb_result.  Set from the errors against the FP64
+// oracle of the full-size workloads (321^3 complex, 64-grid batch members,
+// serving requests up to 257^3), which stay below 0.4 of the estimate in
+// FP32 storage and below 0.03 of it in FP64.
+double energy_rel_error(int precision) {
+  return precision == NPB_FP64 ? 1e-13 : 4e-7;
+}
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -833,6 +882,8 @@ struct Engine {
     a.re_uniform = c.re_uniform;
     a.ccls = c.vacuum ? nullptr : P.at<uint8_t>(L.ccls[d]);
     a.tab = P.ws + L.tabs + kTabBytes * (3 * r + d);
+    // the z sweep stores each step's result: it notes non-finite values
+    a.nonfinite = d == 2 ? P.at<int>(L.ints) + kNonfiniteInts + r : nullptr;
     if (d == 0) {
       a.src_ptr = P.at<int>(L.xptr);
       a.src_lin = P.at<int>(L.q_idx);
@@ -1095,7 +1146,7 @@ struct Engine {
                      P.at<double>(L.atoms)};
     const SetupArgs& sa = P.sa;
     unsigned char* ws = P.ws;
-    int* ints = P.at<int>(L.ints);  // [0] nq, [1] stencil error
+    int* ints = P.at<int>(L.ints);  // [0] nq, [1] stencil error, run flags
     return timed(NPB_K_SETUP, 0, [&] {
       hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ints), 16, 0u, st);
       if (e != hipSuccess) return e;
@@ -1338,6 +1389,7 @@ struct Engine {
           a.re_uniform = c.re_uniform;
           a.tau = c.tau;
           a.tk = c.nl ? c.tau * P.p->kappa_bar_sq : 0.0;
+          a.nonfinite = P.at<int>(P.L.ints) + kNonfiniteInts + r;
           // field read + write and the flag byte per interior node
           e.bytes = (double)(nx - 2) * (ny - 2) * (nz - 2) * (2.0 * sizeof(T) + 1.0);
           runs.push_back(e);
@@ -1390,6 +1442,7 @@ struct Engine {
       for (int r = 0; r < L.n_runs; ++r) {
         set.u[r] = P.at<T>(L.field[r]);
         set.slot[r] = P.at<double>(L.slots) + 2 * L.runs[r].medium + L.runs[r].level;
+        set.aslot[r] = P.at<double>(L.slots) + kAbsSlots + 2 * L.runs[r].medium + L.runs[r].level;
       }
       s = timed(NPB_K_ENERGY, 0, [&] {
         return launch_energy_multi<T>(set, L.n_runs, P.at<int>(L.q_idx), P.at<double>(L.q_val),
@@ -1452,8 +1505,10 @@ struct Engine {
         }
       }
       s = timed(NPB_K_OTHER, 0, [&] {
-        return launch_combine(P.at<double>(L.slots), P.kT, p->richardson, p->vacuum,
-                              p->vacuum_direct, P.at<double>(L.slots) + 8, st);
+        return launch_combine(P.at<double>(L.slots), P.at<double>(L.slots) + kAbsSlots,
+                              P.at<int>(L.ints) + kNonfiniteInts, L.n_runs,
+                              energy_rel_error(p->precision), P.kT, p->richardson, p->vacuum,
+                              p->vacuum_direct, P.at<double>(L.slots) + kResSlots, st);
       });
       if (s != NPB_OK) return s;
     }
@@ -1556,7 +1611,7 @@ struct Engine {
         const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
         int steps = 0;
         for (int r = 0; r < P.L.n_runs; ++r) steps += P.p->n_steps << P.L.runs[r].level;
-        NPB_HIP(launch_result(P.at<double>(P.L.slots) + 8, P.at<int>(P.L.ints), &out[i],
+        NPB_HIP(launch_result(P.at<double>(P.L.slots) + kResSlots, P.at<int>(P.L.ints), &out[i],
                               pts * steps, steps, st));
       }
       return mark_enqueued();
@@ -1564,10 +1619,10 @@ struct Engine {
     NPB_HIP(hipEventRecord(ctx->t1, st));
     // results to the host (first 128 bytes per problem of the staging buffer)
     for (size_t i = 0; i < pr.size(); ++i) {
-      NPB_HIP(hipMemcpyAsync(hb + 128 * i, pr[i].ws + pr[i].L.slots + 8 * 8, 8 * 8,
+      NPB_HIP(hipMemcpyAsync(hb + 128 * i, pr[i].ws + pr[i].L.slots + 8 * kResSlots,
+                             8 * kResCount, hipMemcpyDeviceToHost, st));
+      NPB_HIP(hipMemcpyAsync(hb + 128 * i + 96, pr[i].ws + pr[i].L.ints, 8,
                              hipMemcpyDeviceToHost, st));
-      NPB_HIP(hipMemcpyAsync(hb + 128 * i + 64, pr[i].ws + pr[i].L.ints, 8, hipMemcpyDeviceToHost,
-                             st));
     }
     npb_status sm = mark_enqueued();
     if (sm != NPB_OK) return sm;
@@ -1579,7 +1634,7 @@ struct Engine {
     for (size_t i = 0; i < pr.size(); ++i) {
       const Problem& P = pr[i];
       const double* hres = reinterpret_cast<const double*>(hb + 128 * i);
-      const int* hints = reinterpret_cast<const int*>(hb + 128 * i + 64);
+      const int* hints = reinterpret_cast<const int*>(hb + 128 * i + 96);
       npb_result& o = out[i];
       std::memset(&o, 0, sizeof(o));
       o.dG = hres[0];
@@ -1590,6 +1645,7 @@ struct Engine {
       o.G_0[1] = hres[5];
       o.finite = hres[6] != 0.0 ? 1 : 0;
       o.dG_direct = hres[7];
+      o.dG_err_est = hres[8];
       const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
       for (int r = 0; r < P.L.n_runs; ++r) {
         const int ns = P.p->n_steps << P.L.runs[r].level;

@@ -1022,9 +1022,11 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
     __syncthreads();
   }
 
-  // interior node rows back to HBM
+  // interior node rows back to HBM; the z sweep (the last sub-step of a
+  // step) notes a stored value that is not finite (Sec. 4.2: a diverged run)
   const int mode = (VAR == kYzGeneral) ? a.mode : MODE_INPLACE;
   T* out = (mode == MODE_AOS_ADD) ? a.acc : a.u;
+  bool bad = false;
   if (cok) {
     uint32_t pt = base + (uint32_t)(1 + jr) * stride + (uint32_t)(cv * VX);
     for (int j = 1 + jr; j <= nint; j += RS, pt += rstep) {
@@ -1046,9 +1048,12 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
 #pragma unroll
         for (int i = 0; i < VX; ++i) w[i] = (T)tile[j * TS + cv * VX + i];
       }
+#pragma unroll
+      for (int i = 0; i < VX; ++i) bad |= !isfinite(w[i]);
       VecIO<T, VX>::st(out + pt, w);
     }
   }
+  if (bad && a.nonfinite != nullptr) atomicOr(a.nonfinite, 1);
 }
 
 // ---------------------------------------------------------------------------

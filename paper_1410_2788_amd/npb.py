@@ -28,7 +28,7 @@ KERNEL_CLASSES = ["sweep_x", "sweep_y", "sweep_z", "setup", "init", "energy", "o
                   "euler"]
 # sweep launches split again by the kernel that ran them (npb_sweep_kernel)
 SWEEP_KERNELS = ["x", "yz_plain", "yz_flow", "yz_general", "euler"]
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 
 class npb_molecule(C.Structure):
@@ -55,7 +55,7 @@ class npb_result(C.Structure):
                 ("G_0", C.c_double * 2), ("grid_point_updates", C.c_double),
                 ("device_ms", C.c_double), ("steps_done", C.c_int32),
                 ("n_charge_nodes", C.c_int32), ("finite", C.c_int32), ("reserved", C.c_int32),
-                ("dG_direct", C.c_double)]
+                ("dG_direct", C.c_double), ("dG_err_est", C.c_double)]
 
 
 class npb_kernel_times(C.Structure):
@@ -316,9 +316,13 @@ def npb_solve_fields(ctx, solute: npb_molecule, grid: npb_grid, params: npb_para
                      d_rho: int, d_ws: int, ws_bytes: int, d_u_out: Optional[int],
                      stream: int) -> npb_result:
     res = npb_result()
-    _check(load_library().npb_solve_fields(ctx, C.byref(solute), C.byref(grid), C.byref(params),
-                                           d_u0, d_rho, d_ws, ws_bytes, d_u_out, stream,
-                                           C.byref(res)))
+    st = load_library().npb_solve_fields(ctx, C.byref(solute), C.byref(grid), C.byref(params),
+                                         d_u0, d_rho, d_ws, ws_bytes, d_u_out, stream,
+                                         C.byref(res))
+    if st != NPB_OK:
+        err = NPBError(st, npb_last_error())
+        err.result = res
+        raise err
     return res
 
 
@@ -569,7 +573,7 @@ def result_dict(res: npb_result) -> dict:
             "G_0": [res.G_0[0], res.G_0[1]], "grid_point_updates": res.grid_point_updates,
             "device_ms": res.device_ms, "steps_done": res.steps_done,
             "n_charge_nodes": res.n_charge_nodes, "finite": bool(res.finite),
-            "dG_direct": res.dG_direct}
+            "dG_direct": res.dG_direct, "dG_err_est": res.dG_err_est}
 
 
 def solve(mol, grid, params, device: int = 0, want_field: bool = False,

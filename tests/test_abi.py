@@ -29,7 +29,7 @@ def test_every_declared_function_is_exported(npb):
 
 
 def test_version_and_kappa_helper(npb):
-    assert npb.npb_abi_version() == npb.ABI_VERSION == 6
+    assert npb.npb_abi_version() == npb.ABI_VERSION == 7
     g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
     assert npb.npb_kappa_bar_sq(1.0, 298.0) == pytest.approx(g["kbar2_per_molar_298_inv_A2"], rel=1e-15)
     assert npb.npb_kappa_bar_sq(0.1, 300.0) == pytest.approx(0.84303, rel=1e-5)

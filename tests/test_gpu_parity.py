@@ -81,7 +81,7 @@ def _assert_f32(errs, fe, field_tol=2e-5):
 
 def test_abi_version_on_device():
     npb = _npb()
-    assert npb.npb_abi_version() == npb.ABI_VERSION == 6
+    assert npb.npb_abi_version() == npb.ABI_VERSION == 7
     npb.context(0)
 
 
