@@ -562,70 +562,101 @@ __global__ __launch_bounds__(256) void boundary_kernel(SetupArgs a, double scale
   }
 }
 
-// FP32 terms: a block takes 64 shell nodes and splits the atoms four ways
-// (thread = node t % 64, slice t / 64), so that a small shell still fills
-// the device; atoms are staged as (x, y, z, q) in LDS (one 16-byte read per
-// pair), the terms of up to 32 atoms are summed in FP32 before they join
-// the FP64 sums (the per-term rounding of FP32 terms is of the same
-// order), and the four slices' FP64 sums are added in LDS at the end.
-constexpr int kBcNodes = 64, kBcSlices = 4;
+// FP32 terms.  Block: 256 threads = 64 node groups x 4 atom slices (one
+// wave per slice).  A thread takes kBcK shell nodes (group g: nodes
+// g, g + 64, ... of the block's range) and the atoms sl, sl + 4, ... of
+// every 256-atom tile staged in LDS as (x, y, z, q): each staged atom is
+// read once (a broadcast LDS read) and used for kBcK nodes, which also
+// gives every thread kBcK independent chains.  Per pair: d^2 by FMAs,
+// 1/d by the hardware reciprocal square root (d^2 >= h^2 on the shell:
+// no denormal inputs), e^{-kappa d} = 2^{-kappa log2(e) d} by the hardware
+// base-2 exponential.  The terms of up to 32 atoms are summed in FP32
+// before they join the FP64 sums (the per-term rounding of FP32 terms is of
+// the same order), and the four slices' FP64 sums are added in a fixed
+// order at the end.
+constexpr int kBcGroups = 64, kBcSlices = 4, kBcK = 4;
+constexpr int kBcNodes = kBcGroups * kBcK;  // shell nodes per block
 __global__ __launch_bounds__(256) void boundary_f32_kernel(SetupArgs a, double scale_s,
                                                            double kappa, double scale_v,
                                                            double* bc_s, double* bc_v,
                                                            long long nshell) {
   __shared__ float4 sa[256];
   __shared__ double rs[kBcSlices][kBcNodes], rv[kBcSlices][kBcNodes];
-  const int tn = threadIdx.x % kBcNodes, sl = threadIdx.x / kBcNodes;
-  const long long s = (long long)blockIdx.x * kBcNodes + tn;
-  const bool valid = s < nshell;
-  float X = 0.0f, Y = 0.0f, Z = 0.0f;
-  if (valid) {
-    int i, j, k;
-    shell_node(s, a.nx, a.ny, a.nz, i, j, k);
-    X = (float)(a.ox + (double)i * a.h);
-    Y = (float)(a.oy + (double)j * a.h);
-    Z = (float)(a.oz + (double)k * a.h);
+  const int g = threadIdx.x % kBcGroups;
+  const int sl = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kBcGroups);
+  const long long s0 = (long long)blockIdx.x * kBcNodes + g;
+  float X[kBcK], Y[kBcK], Z[kBcK];
+#pragma unroll
+  for (int k = 0; k < kBcK; ++k) {
+    const long long s = s0 + (long long)k * kBcGroups;
+    // past the shell: a far point, so that every term stays finite
+    X[k] = Y[k] = Z[k] = 1.0e4f;
+    if (s < nshell) {
+      int i, j, kk;
+      shell_node(s, a.nx, a.ny, a.nz, i, j, kk);
+      X[k] = (float)(a.ox + (double)i * a.h);
+      Y[k] = (float)(a.oy + (double)j * a.h);
+      Z[k] = (float)(a.oz + (double)kk * a.h);
+    }
   }
   const int na = a.n_atoms;
-  const float nk = -(float)kappa;
-  double acc_s = 0.0, acc_v = 0.0;
+  const float c = (float)(-kappa * 1.4426950408889634);  // -kappa log2(e)
+  double acc_s[kBcK], acc_v[kBcK];
+#pragma unroll
+  for (int k = 0; k < kBcK; ++k) acc_s[k] = acc_v[k] = 0.0;
   for (int t0 = 0; t0 < na; t0 += 256) {
-    const int t = t0 + threadIdx.x;
+    const int t = t0 + (int)threadIdx.x;
     if (t < na)
       sa[threadIdx.x] = make_float4((float)a.atoms[t], (float)a.atoms[na + t],
                                     (float)a.atoms[2 * na + t], (float)a.atoms[3 * na + t]);
     __syncthreads();
-    // this slice's atoms of the tile: sl, sl + 4, ...
     const int cnt = min(256, na - t0);
     for (int j0 = sl; j0 < cnt; j0 += 32 * kBcSlices) {
-      float ps = 0.0f, pv = 0.0f;
+      float ps[kBcK], pv[kBcK];
+#pragma unroll
+      for (int k = 0; k < kBcK; ++k) ps[k] = pv[k] = 0.0f;
       const int je = min(j0 + 32 * kBcSlices, cnt);
+#pragma unroll 4
       for (int jj = j0; jj < je; jj += kBcSlices) {
         const float4 at = sa[jj];
-        const float dx = X - at.x, dy = Y - at.y, dz = Z - at.z;
-        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const float ri = rsqrtf(d2);
-        const float tv = at.w * ri;
-        pv += tv;
-        ps = fmaf(tv, __expf(nk * (d2 * ri)), ps);
+#pragma unroll
+        for (int k = 0; k < kBcK; ++k) {
+          const float dx = X[k] - at.x, dy = Y[k] - at.y, dz = Z[k] - at.z;
+          const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          const float ri = __builtin_amdgcn_rsqf(d2);
+          const float tv = at.w * ri;
+          pv[k] += tv;
+          ps[k] = fmaf(tv, __builtin_amdgcn_exp2f(c * (d2 * ri)), ps[k]);
+        }
       }
-      acc_s += (double)ps;
-      acc_v += (double)pv;
+#pragma unroll
+      for (int k = 0; k < kBcK; ++k) {
+        acc_s[k] += (double)ps[k];
+        acc_v[k] += (double)pv[k];
+      }
     }
     __syncthreads();
   }
-  rs[sl][tn] = acc_s;
-  rv[sl][tn] = acc_v;
-  __syncthreads();
-  if (sl == 0 && valid) {
-    double ts = 0.0, tv = 0.0;
 #pragma unroll
-    for (int q = 0; q < kBcSlices; ++q) {
-      ts += rs[q][tn];
-      tv += rv[q][tn];
+  for (int k = 0; k < kBcK; ++k) {
+    rs[sl][g + k * kBcGroups] = acc_s[k];
+    rv[sl][g + k * kBcGroups] = acc_v[k];
+  }
+  __syncthreads();
+  if (sl == 0) {
+#pragma unroll
+    for (int k = 0; k < kBcK; ++k) {
+      const long long s = s0 + (long long)k * kBcGroups;
+      if (s >= nshell) continue;
+      double ts = 0.0, tv = 0.0;
+#pragma unroll
+      for (int q = 0; q < kBcSlices; ++q) {
+        ts += rs[q][g + k * kBcGroups];
+        tv += rv[q][g + k * kBcGroups];
+      }
+      bc_s[s] = scale_s * ts;
+      if (bc_v) bc_v[s] = scale_v * tv;
     }
-    bc_s[s] = scale_s * ts;
-    if (bc_v) bc_v[s] = scale_v * tv;
   }
 }
 
@@ -637,7 +668,7 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
   const double ss = lB / eps_s, sv = lB / eps_v;
   if (fp32_terms)
     hipLaunchKernelGGL(boundary_f32_kernel, dim3((unsigned)((ns + kBcNodes - 1) / kBcNodes)),
-                       dim3(kBcNodes * kBcSlices), 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
+                       dim3(kBcGroups * kBcSlices), 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
   else
     hipLaunchKernelGGL(boundary_kernel<double>, g, b, 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
   return hipGetLastError();
