@@ -57,6 +57,10 @@ struct SweepArgs {
   // set to 1 when a stored value is not finite; the z sweep's arguments only
   // (the last sub-step of every split scheme), nullptr elsewhere
   int* nonfinite;
+  // x sweep: the run's Dirichlet data in shell order (FP64), from which the
+  // right end of each x-line is read when node nx-1 would be the only node
+  // of its row's last cache line (the row loads then stop before it)
+  const double* bcx;
   // geometry of the launch
   int M;                  // rows per chunk (compile-time in the kernel)
   int P;                  // chunks per line

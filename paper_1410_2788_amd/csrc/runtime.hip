@@ -144,49 +144,70 @@ hipError_t launch_field_init_multi(const InitSet<T>& set, int nruns, int nx, int
   return hipGetLastError();
 }
 
-// energy slots of the runs of one problem at once: block r sums run r;
-// beside sum q u, sum |q u| (the scale of the rounding error of the sum's
-// terms)
+// Energy sums of the runs of one problem: sum q u and, beside it, sum |q u|
+// (the scale of the rounding error of the sum's terms).  Block (b, r) sums
+// entries b*1024 + t, b*1024 + t + nb*1024, ... of run r into partial (b, r)
+// by a fixed tree; a second kernel adds each run's nb partials in a fixed
+// order, so the result does not depend on scheduling.
 template <typename T>
 struct EnergySet {
   const T* u[kMaxFields];
   double* slot[kMaxFields];
   double* aslot[kMaxFields];
 };
+constexpr int kEnergyMaxBlocks = 64;
 template <typename T>
-__global__ __launch_bounds__(1024) void energy_multi_kernel(EnergySet<T> set, const int* q_idx,
-                                                            const double* q_val,
-                                                            const int* nq_dev) {
-  __shared__ double part[1024], apart[1024];
-  const T* u = set.u[blockIdx.x];
+__global__ __launch_bounds__(1024) void energy_part_kernel(EnergySet<T> set, const int* q_idx,
+                                                           const double* q_val,
+                                                           const int* nq_dev, double* part) {
+  __shared__ double ps[1024], pa[1024];
+  const int r = blockIdx.y, nb = gridDim.x;
+  const T* u = set.u[r];
   const int nq = *nq_dev;
   double s = 0.0, sa = 0.0;
-  for (int k = threadIdx.x; k < nq; k += 1024) {
+  for (int k = blockIdx.x * 1024 + threadIdx.x; k < nq; k += nb * 1024) {
     const double t = q_val[k] * (double)u[q_idx[k]];
     s += t;
     sa += fabs(t);
   }
-  part[threadIdx.x] = s;
-  apart[threadIdx.x] = sa;
+  ps[threadIdx.x] = s;
+  pa[threadIdx.x] = sa;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
-      part[threadIdx.x] += part[threadIdx.x + w];
-      apart[threadIdx.x] += apart[threadIdx.x + w];
+      ps[threadIdx.x] += ps[threadIdx.x + w];
+      pa[threadIdx.x] += pa[threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    *set.slot[blockIdx.x] = part[0];
-    *set.aslot[blockIdx.x] = apart[0];
+    part[2 * (r * nb + blockIdx.x)] = ps[0];
+    part[2 * (r * nb + blockIdx.x) + 1] = pa[0];
   }
+}
+template <typename T>
+__global__ void energy_finish_kernel(EnergySet<T> set, const double* part, int nb) {
+  const int r = threadIdx.x;
+  if (r >= (int)blockDim.x) return;
+  double s = 0.0, sa = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    s += part[2 * (r * nb + b)];
+    sa += part[2 * (r * nb + b) + 1];
+  }
+  *set.slot[r] = s;
+  *set.aslot[r] = sa;
 }
 
 template <typename T>
 hipError_t launch_energy_multi(const EnergySet<T>& set, int nruns, const int* q_idx,
-                               const double* q_val, const int* nq_dev, hipStream_t st) {
-  hipLaunchKernelGGL((energy_multi_kernel<T>), dim3(nruns), dim3(1024), 0, st, set, q_idx, q_val,
-                     nq_dev);
+                               const double* q_val, const int* nq_dev, int cap, double* part,
+                               hipStream_t st) {
+  const int nb = std::max(1, std::min(kEnergyMaxBlocks, (cap + 4095) / 4096));
+  hipLaunchKernelGGL((energy_part_kernel<T>), dim3(nb, nruns), dim3(1024), 0, st, set, q_idx,
+                     q_val, nq_dev, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((energy_finish_kernel<T>), dim3(1), dim3(nruns), 0, st, set, part, nb);
   return hipGetLastError();
 }
 
@@ -514,6 +535,7 @@ struct Layout {
   size_t q_idx, q_val, q_rho, xptr, yptr, ylin, yrho, zptr, zlin, zrho, ccls[3], slots, ints, total;
   size_t direct;  // work of the direct vacuum Poisson solve (vacuum_direct)
   size_t flags;   // explicit Euler node flags (solute bits, source bit)
+  size_t epart;   // per-block partial energy sums
   size_t fmask[3];  // face rule by location: mask | half-point bit per direction
   LaunchShape shape[3];
   Run runs[kMaxFields];
@@ -637,6 +659,7 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
     }
   }
   L.slots = take(32 * 8);
+  L.epart = take((size_t)2 * kMaxFields * 64 * 8);  // energy partial sums
   L.ints = take(16 * 4);
   L.direct = take(p->vacuum_direct ? direct_poisson_bytes(g->nx, g->ny, g->nz) : 0);
   L.flags = take(euler ? n : 0);
@@ -884,6 +907,7 @@ struct Engine {
     a.tab = P.ws + L.tabs + kTabBytes * (3 * r + d);
     // the z sweep stores each step's result: it notes non-finite values
     a.nonfinite = d == 2 ? P.at<int>(L.ints) + kNonfiniteInts + r : nullptr;
+    a.bcx = d == 0 ? P.at<double>(c.vacuum ? L.bc_v : L.bc_s) : nullptr;
     if (d == 0) {
       a.src_ptr = P.at<int>(L.xptr);
       a.src_lin = P.at<int>(L.q_idx);
@@ -1446,7 +1470,7 @@ struct Engine {
       }
       s = timed(NPB_K_ENERGY, 0, [&] {
         return launch_energy_multi<T>(set, L.n_runs, P.at<int>(L.q_idx), P.at<double>(L.q_val),
-                                      P.at<int>(L.ints), st);
+                                      P.at<int>(L.ints), L.cap, P.at<double>(L.epart), st);
       });
       if (s != NPB_OK) return s;
       const npb_params* p = P.p;

@@ -505,9 +505,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
     return ((1 + zi) * ny + 1 + (l - zi * nyi)) * nxp;
   };
 
-  size_t off = 0;
-  int* srng = reinterpret_cast<int*>(smem + off);  // source entry range of the block
-  off += 16;
+  size_t off = 16;
   A* red = reinterpret_cast<A*>(smem + off);  // reduced systems
   off += sizeof(A) * (size_t)(L + 1) * 2 * P * 4;
   // the tile and the mask rows carry P*M+2 spare elements at their end:
@@ -523,65 +521,102 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   uint8_t* mt = smem + off;  // L rows of nx4 bytes
   const int nx4 = row4(nx);
 
-  // The block's lines are consecutive rows of the per-row source lists:
-  // one contiguous entry range, whose bounds are requested before the rows.
-  const bool src = a.src_stage == 1;
-  if (src && tid == 0) {
-    srng[0] = a.src_ptr[row_base(0) / nxp];
-    srng[1] = a.src_ptr[row_base(min(L, nlines - l0) - 1) / nxp + 1];
-  }
-
-  // Row loads.  Lane t of the block takes vector column cv = t % 8 of rows
-  // t / 8, t / 8 + RQ, ... and column groups cv, cv + 8, ...: a wave moves
-  // 8 rows x 8 vectors (128 contiguous bytes of each row) per instruction,
-  // and with the LDS row stride S (x_tile_stride) the element writes of a
-  // half-wave's four rows fall in distinct banks.  All vector loads of a
-  // batch are in flight before its LDS stores.
+  // Field elements moved per row: the first row4(nx), or the first nx - 1
+  // when node nx - 1 would be the only node of the row's last 128-byte line
+  // (nx - 1 a multiple of 128 / sizeof(T)); that right Dirichlet value then
+  // comes from the run's shell data, and the line is neither fetched nor
+  // written.  The mask rows always move row4(nx) bytes (their last face).
+  const int nxl = (a.bcx != nullptr && (nx - 1) % (128 / (int)sizeof(T)) == 0) ? nx - 1 : nx4;
+  // Row loads.  The block's row traffic is L rows x ncg column groups of
+  // eight 16-byte vectors; item w = (row w % L, group w / L).  Lane t takes
+  // vector column cv = t % 8 of items t / 8, t / 8 + RQ, ... (RQ = lanes / 8):
+  // a half-wave moves four rows x eight vectors (128 contiguous bytes of
+  // each row), and with the LDS row stride S (x_tile_stride) its element
+  // writes fall in distinct banks; every lane takes a share even when the
+  // block has more lanes than rows x 8.  All vector loads of a batch are in
+  // flight before its LDS stores.
   const int vpr = nx4 / VX;         // vectors per row
   const int ncg = (vpr + 7) >> 3;   // 8-vector column groups per row
   const int cv = tid & 7;
-  const int RQ = nthreads >> 3;     // rows per pass
+  const int RQ = nthreads >> 3;     // item slots per pass
   const int rq = tid >> 3;
-  const int nsteps = rq < L ? ((L - rq + RQ - 1) / RQ) * ncg : 0;
+  const int nitems = L * ncg;
+  // The block's lines are consecutive rows of the per-row source lists:
+  // one contiguous entry range [eb, ee), whose bounds are block-uniform.
+  // Each lane fetches its entry (usually at most one) with the first batch
+  // of row loads and adds it once the rows are in LDS.
+  const bool src = a.src_stage == 1;
+  int eb = 0, ee = 0, e_lin = -1;
+  double e_rho = 0.0;
+  // Lane t < L fetches the right Dirichlet value of line t when the rows
+  // stop before node nx - 1: node (nx-1, j, k) of the shell (shell order:
+  // the two z faces, then per interior z the y = 0 and y = ny-1 rows and
+  // the x = 0, nx-1 pairs of each interior y).
+  const bool gr_line = nxl < nx && tid < L && l0 + tid < nlines;
+  A gRv = A(0);
+  bool first_batch = true;
+  // with the first batch of row loads in flight: the source entries and
+  // the right ends, so that their latency overlaps the rows'
+  auto fetch_first = [&]() {
+    first_batch = false;
+    if (src) {
+      eb = a.src_ptr[row_base(0) / nxp];
+      ee = a.src_ptr[row_base(min(L, nlines - l0) - 1) / nxp + 1];
+      if (eb + tid < ee) {
+        e_lin = a.src_lin[eb + tid];
+        e_rho = a.src_rho[eb + tid];
+      }
+    }
+    if (gr_line) {
+      const int l = l0 + tid, zi = l / nyi;
+      const int s = 2 * nx * ny + zi * (2 * nx + 2 * nyi) + 2 * nx + 2 * (l - zi * nyi) + 1;
+      gRv = (A)(T)a.bcx[s];
+    }
+  };
   {
     constexpr int kU = 8;
-    int q = rq, g = 0, rb = row_base(rq);
-    for (int s0 = 0; s0 < nsteps; s0 += kU) {
+    for (int w0 = rq; w0 < nitems; w0 += kU * RQ) {
       T v[kU][VX];
       uint32_t m[kU];
       int lo[kU], mo[kU];
 #pragma unroll
       for (int j = 0; j < kU; ++j) {
         lo[j] = -1;
-        if (s0 + j < nsteps) {
+        const int w = w0 + j * RQ;
+        if (w < nitems) {
+          const int q = w % L, g = w / L;
           const int c = (cv + 8 * g) * VX;
+          const int rb = row_base(q);
           if (c < nx4 && rb >= 0) {
-            lo[j] = q * S + c;
+            lo[j] = c < nxl ? q * S + c : -1;
             mo[j] = q * nx4 + c;
-            VecIO<T, VX>::ld(a.u + rb + c, v[j]);
+            if (c < nxl) VecIO<T, VX>::ld(a.u + rb + c, v[j]);
             if (!uniform) m[j] = ld_mask<VX>(a.mask + rb + c);
+          } else {
+            mo[j] = -1;
           }
-        }
-        if (++g == ncg) {
-          g = 0;
-          q += RQ;
-          rb = row_base(q);
+        } else {
+          mo[j] = -1;
         }
       }
+      if (first_batch) fetch_first();
 #pragma unroll
       for (int j = 0; j < kU; ++j) {
         if (lo[j] >= 0) {
 #pragma unroll
           for (int i = 0; i < VX; ++i) tile[lo[j] + i] = (A)v[j][i];
-          if (!uniform) {
-            if constexpr (VX == 4)
-              *reinterpret_cast<uint32_t*>(mt + mo[j]) = m[j];
-            else
-              *reinterpret_cast<uint16_t*>(mt + mo[j]) = (uint16_t)m[j];
-          }
+        }
+        if (!uniform && mo[j] >= 0) {
+          if constexpr (VX == 4)
+            *reinterpret_cast<uint32_t*>(mt + mo[j]) = m[j];
+          else
+            *reinterpret_cast<uint16_t*>(mt + mo[j]) = (uint16_t)m[j];
         }
       }
     }
+    // lanes without row items
+    if (first_batch) fetch_first();
+    if (gr_line) tile[tid * S + nx - 1] = gRv;
   }
   __syncthreads();
 
@@ -617,13 +652,14 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
                        (A)a.re[2], (A)a.re_uniform);
   }
   if (src) {
-    // one entry per thread; entries are distinct nodes
+    // entries are distinct nodes: the adds do not collide
     auto add_entry = [&](int lin, double rho) {
       const int row = lin / nxp;
       const int q = (row / ny - 1) * nyi + (row % ny - 1) - l0;
       tile[q * S + (lin - row * nxp)] += (A)(a.src_coef * rho);
     };
-    for (int e = srng[0] + tid; e < srng[1]; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
+    if (e_lin >= 0) add_entry(e_lin, e_rho);
+    for (int e = eb + tid + nthreads; e < ee; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
     __syncthreads();
   }
 
@@ -717,17 +753,15 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
 
   // row stores (boundary columns carry their loaded values), same lane map
   T* out = aos ? a.acc : a.u;
-  for (int q = rq; q < L; q += RQ) {
+  for (int w = rq; w < nitems; w += RQ) {
+    const int q = w % L, g = w / L;
+    const int c = (cv + 8 * g) * VX;
     const int rb = row_base(q);
-    if (rb < 0) break;
-    for (int g = 0; g < ncg; ++g) {
-      const int c = (cv + 8 * g) * VX;
-      if (c < nx4) {
-        T v[VX];
+    if (c < nxl && rb >= 0) {
+      T v[VX];
 #pragma unroll
-        for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c + i];
-        VecIO<T, VX>::st(out + rb + c, v);
-      }
+      for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c + i];
+      VecIO<T, VX>::st(out + rb + c, v);
     }
   }
 }
@@ -915,16 +949,26 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   A* red = reinterpret_cast<A*>(smem);  // reduced systems
   A* tile = red + (size_t)(TW + 1) * 2 * P * 4;
   uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)nrow * TS);  // [nrow][TW]
-  int* srng = reinterpret_cast<int*>(mt + (size_t)nrow * TW);          // source entry range
 
-  // Trilinear sources of the tile's lines form one contiguous range of the
-  // per-line lists; its bounds are requested before the node rows.
+  // Trilinear sources of the tile's lines form one contiguous range
+  // [sb, se) of the per-line lists (tile-uniform bounds); each lane fetches
+  // its entry (usually at most one) with the first batch of node rows and
+  // adds it when needed (before the solve for stage 1, after it for stage
+  // 2); entries are distinct nodes, so the adds do not collide.
   const bool src = VAR == kYzGeneral && a.src_stage != 0;
-  if (src && tid == 0) {
+  int sb = 0, se = 0, e_lin = -1;
+  double e_rho = 0.0;
+  bool fetch = src;
+  auto fetch_entries = [&]() {
     const int xlo = max(xb, 1), xhi = min(xb + TW - 1, nx - 2);
-    srng[0] = a.src_ptr[o * nx + xlo];
-    srng[1] = a.src_ptr[o * nx + xhi + 1];
-  }
+    sb = a.src_ptr[o * nx + xlo];
+    se = a.src_ptr[o * nx + xhi + 1];
+    if (sb + tid < se) {
+      e_lin = a.src_lin[sb + tid];
+      e_rho = a.src_rho[sb + tid];
+    }
+    fetch = false;
+  };
 
   // Node-row traffic: thread = (vector column cv, first row jr); rows step
   // by RS = nthreads / VPR.  Columns past row4(nx) stay untouched.
@@ -946,6 +990,7 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
           if (!uniform) m[u] = ld_mask<VX>(a.mask + pt + (uint32_t)u * rstep);
         }
       }
+      if (fetch) fetch_entries();
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int j = j0 + u * RS;
@@ -963,21 +1008,10 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
       pt += (uint32_t)kU * rstep;
     }
   }
+  // lanes without node rows to move
+  if (fetch) fetch_entries();
   __syncthreads();
 
-  // source entries: one per thread, requested now and added when needed
-  // (before the solve for stage 1, after it for stage 2); entries are
-  // distinct nodes, so the adds do not collide
-  int sb = 0, se = 0, e_lin = -1;
-  double e_rho = 0.0;
-  if (src) {
-    sb = srng[0];
-    se = srng[1];
-    if (sb + tid < se) {
-      e_lin = a.src_lin[sb + tid];
-      e_rho = a.src_rho[sb + tid];
-    }
-  }
   auto add_entry = [&](int lin, double rho) {
     const uint32_t off = (uint32_t)lin - plane;
     const uint32_t jj = off / stride;
