@@ -190,8 +190,12 @@ def bench_batch(args):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
     del bs
-    print("[bench] FP64 single solves of the same problems", file=sys.stderr, flush=True)
-    single = _single_f64(probs, npb)
+    if args.no_f64:
+        # no FP64 reference solves (a profiler pass): every member counted
+        single = [(0.0, r) for r in res]
+    else:
+        print("[bench] FP64 single solves of the same problems", file=sys.stderr, flush=True)
+        single = _single_f64(probs, npb)
     single_ms = sum(t for t, _ in single)
     errs = [abs(res[i]["dG"] - single[i][1]["dG"]) for i in range(len(probs))]
     ok = [res[i]["finite"] and errs[i] <= _energy_tol(single[i][1]["dG"]) for i in range(len(probs))]
@@ -218,8 +222,9 @@ def bench_batch(args):
             "accuracy": {"reference": "FP64 single-solve GPU path, same inputs",
                          "within_tolerance": int(sum(ok)), "members": len(probs),
                          "max_abs_err": max(errs), "oracle_samples": sampled},
-            "single_f64": {"ms_total": single_ms, "grid_point_updates_per_s": pts / (single_ms * 1e-3),
-                           "speedup_of_batch": single_ms / ms}}
+            "single_f64": ({"ms_total": single_ms,
+                            "grid_point_updates_per_s": pts / (single_ms * 1e-3),
+                            "speedup_of_batch": single_ms / ms} if not args.no_f64 else None)}
 
 
 def bench_large(args):
@@ -882,7 +887,16 @@ def main():
         sys.exit(2)
 
     if args.batch:
-        print(json.dumps(bench_batch(args)))
+        out = bench_batch(args)
+        if args.copy_calibration:
+            import torch
+            src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        print(json.dumps(out))
         return
     if args.serve:
         print(json.dumps(bench_serve(args)))
