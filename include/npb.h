@@ -394,20 +394,29 @@ npb_status npb_solve_fields(npb_ctx* ctx, const npb_molecule* solute, const npb_
                             npb_result* out);
 
 /* ---- request loop (serving) ----------------------------------------------
- * A server solves molecules as they arrive.  It owns a device arena of
- * hbm_budget bytes and one worker thread with its own context and stream.
- * Requests are admitted in arrival order while their workspaces
- * (npb_workspace_bytes) fit the arena, at most max_batch at a time, and
- * each admitted set is solved by npb_solve_batch; when it finishes the next
- * set is formed from whatever is waiting (continuous batching).  No field is
- * returned, only npb_result.  Callers for whom the step-by-step path of one
- * molecule matters use npb_solve. */
+ * A server solves molecules as they arrive (the problem of Sec. 2.1 per
+ * request; RE+V energies of Sec. 5.3, Eqs. (rich) and (deltaG3), as
+ * npb_solve) with continuous batching.  It owns a device arena of
+ * hbm_budget bytes and one worker thread with its own contexts and stream.
+ * A request is admitted in arrival order as soon as a free region of the
+ * arena holds its workspace (npb_workspace_bytes) and fewer than max_batch
+ * requests are active; it joins the running launches at the next tick
+ * boundary (every few pseudo-time steps), and it leaves, reporting its
+ * result and returning its region, as soon as its own last step is done
+ * while the other requests keep stepping.  Every run is swept with the
+ * arithmetic of its single solve (only launches are shared), so each
+ * result equals npb_solve of the same request bit for bit (device_ms is
+ * NaN: requests share the device).  No field is returned, only npb_result.
+ * Callers for whom the step-by-step path of one molecule matters use
+ * npb_solve. */
 typedef struct npb_server npb_server;
 
 typedef struct npb_server_stats {
   int64_t submitted, completed, failed, refused, batches, queued;
-  double busy_ms;          /* wall time of the worker inside npb_solve_batch */
-  double p50_ms, p99_ms;   /* submit -> result latency of finished requests */
+  /* batches: ticks issued (each advances every active request a few steps) */
+  double busy_ms;          /* wall time with at least one request active */
+  double p50_ms, p99_ms;   /* submit -> result latency of the requests finished
+                              since creation or the last npb_server_reset_stats */
 } npb_server_stats;
 
 /* Create a server on ctx's device (ctx is only read; the server keeps its
@@ -430,6 +439,10 @@ npb_status npb_submit(npb_server* server, const npb_molecule* mol, const npb_gri
 npb_status npb_poll(npb_server* server, uint64_t ticket, npb_result* out, int* done);
 
 npb_status npb_server_get_stats(npb_server* server, npb_server_stats* out);
+
+/* Clear the counters and the latency record (e.g. after a warm-up or a
+ * capacity run), so later statistics cover later requests only. */
+npb_status npb_server_reset_stats(npb_server* server);
 
 /* Finishes every queued request, then frees the arena and the worker. */
 void npb_server_destroy(npb_server* server);

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "npb.h"
 
@@ -14,6 +15,40 @@ namespace npb {
 // tuned line-solver shapes it hands to a server's own context
 int ctx_device(const npb_ctx* ctx);
 void copy_tuning(const npb_ctx* from, npb_ctx* to);
+
+// Continuous stepping for the request loop (one precision): problems join
+// at tick boundaries and leave as soon as their last step is done.
+struct RollingDone {
+  uint64_t id;
+  npb_status status;
+  npb_result res;
+};
+struct RollingEngine {
+  virtual ~RollingEngine() {}
+  // a problem checked by npb_workspace_bytes, with its own workspace (>= its
+  // npb_workspace_bytes, 256-byte aligned); mol, grid and params stay valid
+  // until the problem is reported by poll; its setup is enqueued by the
+  // next tick
+  virtual npb_status add(uint64_t id, const npb_molecule* mol, const npb_grid* grid,
+                         const npb_params* params, void* ws, size_t ws_bytes) = 0;
+  // enqueue the setup of added problems, up to `steps` steps of every
+  // active run, and the energies and result copy of each problem whose last
+  // step that was; waits while two earlier ticks are still on the device
+  virtual npb_status tick(int steps) = 0;
+  // problems whose results are on the host: appended to out, then forgotten
+  virtual void poll(std::vector<RollingDone>& out) = 0;
+  // problems added and not yet reported; of these, those with steps left
+  virtual int active() const = 0;
+  virtual int stepping() const = 0;
+  // wait for everything enqueued
+  virtual npb_status drain() = 0;
+  // after a failed tick: wait for the device, then report every problem
+  // with status s and forget it
+  virtual void abort_all(npb_status s, std::vector<RollingDone>& out) = 0;
+};
+// tuned: a context whose tuned launch shapes the engine's contexts copy
+npb_status rolling_create(const npb_ctx* tuned, int precision, void* stream, int max_items,
+                          RollingEngine** out);
 
 // ---------------------------------------------------------------------------
 // Arguments of one implicit line sweep (one of the 1-D sub-steps of the

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <list>
 #include <map>
 #include <mutex>
 #include <cstdio>
@@ -475,6 +476,10 @@ struct npb_ctx {
 };
 
 int npb::ctx_device(const npb_ctx* ctx) { return ctx->device; }
+namespace npb {
+npb_status rolling_create(const npb_ctx* tuned, int precision, void* stream, int max_items,
+                          RollingEngine** out);
+}
 void npb::copy_tuning(const npb_ctx* from, npb_ctx* to) {
   to->tune = from->tune;
   to->tune_gen += 1;
@@ -772,6 +777,9 @@ struct Problem {
   Layout L;
   SetupArgs sa;
   double kT, lB;
+  // steps a launch sequence takes each run through: -1 = all of the run's
+  // steps (a solve); the request loop's engine sets the steps of one tick
+  int steps_now[kMaxFields] = {-1, -1, -1, -1};
   size_t tabs_pinned, atoms_pinned;  // offsets of its staged bytes in the pinned buffer
 
   template <typename Ptr>
@@ -986,7 +994,8 @@ struct Engine {
         Field f{};
         f.prob = i;
         f.run = r;
-        f.steps = P.p->n_steps << P.L.runs[r].level;
+        f.steps = P.steps_now[r] >= 0 ? P.steps_now[r] : P.p->n_steps << P.L.runs[r].level;
+        if (f.steps == 0) continue;  // a run of the request loop that is already done
         // field read + write (+ mask) (+ accumulator)
         const double mb = P.L.runs[r].medium == 1 ? 0.0 : 1.0;
         const double ab = P.aos() ? sizeof(T) : 0.0;
@@ -1073,6 +1082,7 @@ struct Engine {
   // page-locked buffers, taken once the last enqueue that read it is done;
   // the no-allocation path stages in pageable memory of its own and puts
   // the launch tables into the static scratch after the workspace.
+  bool stage_problems = true;  // false: launch tables only (the request loop's ticks)
   npb_status stage(bool with_meta) {
     const size_t res_bytes = 128 * pr.size();
     size_t need = res_bytes + (with_meta ? meta.size() : 0);
@@ -1129,6 +1139,7 @@ struct Engine {
       NPB_HIP(hipMemcpyAsync(dmeta, hb + res_bytes, meta.size(), hipMemcpyHostToDevice, st));
     }
     for (Problem& P : pr) {
+      if (!stage_problems) break;
       for (int r = 0; r < P.L.n_runs; ++r) {
         const Coefs c = run_coefs(P, P.L.runs[r]);
         for (int d = 0; d < 3; ++d) {
@@ -1261,7 +1272,17 @@ struct Engine {
     });
   }
 
-  npb_status time_loop() {
+  npb_status time_loop(bool init = true) {
+    if (init) {
+      npb_status s = init_fields();
+      if (s != NPB_OK) return s;
+    }
+    return step_loop();
+  }
+
+  // field initialisation of every run of the problems (Dirichlet shell,
+  // zero interior; or the caller-given initial field)
+  npb_status init_fields() {
     for (const Problem& P : pr) {
       if (P.p->scheme == NPB_EULER) continue;
       const int nx = P.g->nx, ny = P.g->ny, nz = P.g->nz;
@@ -1280,6 +1301,10 @@ struct Engine {
       });
       if (s != NPB_OK) return s;
     }
+    return NPB_OK;
+  }
+
+  npb_status step_loop() {
     // Lanes: the runs of each medium (and, with four lanes, each level) are
     // independent problems; lane 0 sweeps on `st`, lane k > 0 on a side
     // stream of the context, started one sweep after lane k-1.  Sweeps of
@@ -1447,20 +1472,37 @@ struct Engine {
   // replay is on): setup, time loops, energies, optional fields,
   // combinations.  Launches only: no allocation, copy or synchronisation.
   npb_status device_work() {
+    npb_status s = setup_all();
+    if (s != NPB_OK) return s;
+    s = time_loop();
+    if (s != NPB_OK) return s;
+    s = euler_loop();
+    if (s != NPB_OK) return s;
+    for (Problem& P : pr) {
+      s = finish(P);
+      if (s != NPB_OK) return s;
+    }
+    return NPB_OK;
+  }
+
+  // setup of every problem and its cleared energy slots
+  npb_status setup_all() {
     for (Problem& P : pr) {
       npb_status s = setup(P);
       if (s != NPB_OK) return s;
-      // zero the energy slots
       s = timed(NPB_K_OTHER, 0, [&] {
         return launch_fill_u32(reinterpret_cast<uint32_t*>(P.ws + P.L.slots), 64, 0u, st);
       });
       if (s != NPB_OK) return s;
     }
-    npb_status s = time_loop();
-    if (s != NPB_OK) return s;
-    s = euler_loop();
-    if (s != NPB_OK) return s;
-    for (Problem& P : pr) {
+    return NPB_OK;
+  }
+
+  // after a problem's time loops: energies, the direct vacuum solve, the
+  // requested field and the FP64 combinations
+  npb_status finish(Problem& P) {
+    npb_status s = NPB_OK;
+    {
       const Layout& L = P.L;
       EnergySet<T> set{};
       for (int r = 0; r < L.n_runs; ++r) {
@@ -1840,6 +1882,254 @@ npb_status solve_batch_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
   E.noalloc = noalloc;
   return E.run(out, async);
 }
+
+
+// ---------------------------------------------------------------------------
+// Continuous stepping for the request loop.  A tick enqueues, on one stream:
+// the setup and field initialisation of the problems added since the last
+// tick; up to K steps of every active run in the shared launches of the
+// batch path (one per sweep direction and launch shape per step, over the
+// runs that still have steps, so that each run's arithmetic is that of its
+// single solve); and, for each problem whose last step that was, its
+// energies and combinations and a copy of its result into page-locked host
+// memory behind an event.  Problems therefore join between two ticks and
+// leave as soon as their last step is done.  Two contexts alternate between
+// ticks: one tick's launch tables and staging are written while the
+// previous tick's launches run, and a tick waits only for the tick two
+// before it.  Explicit Euler problems take all their steps in the tick that
+// sets them up.
+template <typename T, typename A>
+struct RollingT final : RollingEngine {
+  npb_ctx* cx[2] = {nullptr, nullptr};
+  hipStream_t st = nullptr;
+  int tick_no = 0;
+  hipEvent_t tick_ev[2] = {nullptr, nullptr};
+  bool tick_used[2] = {false, false};
+  // page-locked results: kSlot bytes per item slot (results, then the ints)
+  static constexpr size_t kSlot = 128;
+  unsigned char* hres = nullptr;
+  std::vector<int> free_slots;
+  struct Item {
+    uint64_t id = 0;
+    Problem P;
+    int left[kMaxFields] = {0, 0, 0, 0};
+    int slot = -1;
+    bool started = false, finishing = false, enqueued = false;
+    hipEvent_t ev = nullptr;
+  };
+  std::list<Item> items;
+
+  ~RollingT() override {
+    (void)drain();
+    for (Item& it : items)
+      if (it.ev) (void)hipEventDestroy(it.ev);
+    for (int c = 0; c < 2; ++c) {
+      if (tick_ev[c]) (void)hipEventDestroy(tick_ev[c]);
+      if (cx[c]) npb_ctx_destroy(cx[c]);
+    }
+    if (hres) (void)hipHostFree(hres);
+  }
+
+  npb_status init(const npb_ctx* tuned, hipStream_t stream, int max_items) {
+    st = stream;
+    for (int c = 0; c < 2; ++c) {
+      npb_status s = npb_ctx_create(tuned->device, &cx[c]);
+      if (s != NPB_OK) return s;
+      cx[c]->tune = tuned->tune;
+      cx[c]->graphs = false;
+      NPB_HIP(hipEventCreateWithFlags(&tick_ev[c], hipEventDisableTiming));
+    }
+    NPB_HIP(hipHostMalloc(reinterpret_cast<void**>(&hres), kSlot * (size_t)max_items,
+                          hipHostMallocDefault));
+    for (int k = max_items - 1; k >= 0; --k) free_slots.push_back(k);
+    return NPB_OK;
+  }
+
+  npb_status add(uint64_t id, const npb_molecule* mol, const npb_grid* grid,
+                 const npb_params* params, void* ws, size_t ws_bytes) override {
+    if (free_slots.empty()) return fail(NPB_EBUSY, "request loop: no free result slot");
+    Item it;
+    it.id = id;
+    Problem& P = it.P;
+    P.mol = mol;
+    P.g = grid;
+    P.p = params;
+    P.ws = reinterpret_cast<unsigned char*>(ws);
+    P.fout = nullptr;
+    P.L = make_layout(mol, grid, params);
+    P.kT = thermal_energy(params->temperature_K);
+    P.lB = bjerrum(params->temperature_K);
+    if (!P.ws || ws_bytes < P.L.total || reinterpret_cast<uintptr_t>(P.ws) % 256 != 0)
+      return fail(NPB_EINVAL, "request loop: workspace too small or misaligned");
+    apply_tuning(cx[0], grid, params, P.L);
+    for (int r = 0; r < P.L.n_runs; ++r) it.left[r] = params->n_steps << P.L.runs[r].level;
+    NPB_HIP(hipEventCreateWithFlags(&it.ev, hipEventDisableTiming));
+    it.slot = free_slots.back();
+    free_slots.pop_back();
+    items.push_back(it);
+    return NPB_OK;
+  }
+
+  static bool has_steps(const Item& it) {
+    for (int r = 0; r < it.P.L.n_runs; ++r)
+      if (it.left[r] > 0) return true;
+    return false;
+  }
+
+  npb_status tick(int K) override {
+    const int c = tick_no & 1;
+    npb_ctx* ctx = cx[c];
+    NPB_HIP(hipSetDevice(ctx->device));
+    // at most two ticks on the device
+    if (tick_used[c]) NPB_HIP(hipEventSynchronize(tick_ev[c]));
+    bool any = false;
+    // 1. setup of the problems added since the last tick (explicit Euler
+    // problems also take all their steps here)
+    {
+      std::vector<Problem> np;
+      std::vector<Item*> ni;
+      for (Item& it : items)
+        if (!it.started) {
+          np.push_back(it.P);
+          ni.push_back(&it);
+        }
+      if (!np.empty()) {
+        Engine<T, A> E{ctx, st, np, {}, {}, {}};
+        npb_status s = E.stage(false);
+        if (s == NPB_OK) s = E.setup_all();
+        if (s == NPB_OK) s = E.init_fields();
+        if (s == NPB_OK) s = E.euler_loop();
+        if (s == NPB_OK) s = E.mark_enqueued();
+        if (s != NPB_OK) return s;
+        for (Item* it : ni) {
+          it->started = true;
+          if (it->P.p->scheme == NPB_EULER)
+            for (int r = 0; r < it->P.L.n_runs; ++r) it->left[r] = 0;
+        }
+        any = true;
+      }
+    }
+    // 2. up to K steps of every run with steps left
+    {
+      std::vector<Problem> ap;
+      std::vector<Item*> ai;
+      for (Item& it : items)
+        if (it.started && has_steps(it)) {
+          Problem P = it.P;
+          for (int r = 0; r < kMaxFields; ++r)
+            P.steps_now[r] = r < P.L.n_runs ? std::min(it.left[r], K) : 0;
+          ap.push_back(P);
+          ai.push_back(&it);
+        }
+      if (!ap.empty()) {
+        Engine<T, A> E{ctx, st, ap, {}, {}, {}};
+        E.stage_problems = false;
+        npb_status s = E.plan();
+        if (s == NPB_OK) s = E.stage(true);
+        if (s == NPB_OK) s = E.step_loop();
+        if (s == NPB_OK) s = E.mark_enqueued();
+        if (s != NPB_OK) return s;
+        for (size_t k = 0; k < ai.size(); ++k)
+          for (int r = 0; r < ai[k]->P.L.n_runs; ++r) ai[k]->left[r] -= ap[k].steps_now[r];
+        any = true;
+      }
+    }
+    // 3. problems whose last step is enqueued: energies, combinations, result
+    {
+      std::vector<Problem> fp;
+      std::vector<Item*> fi;
+      for (Item& it : items)
+        if (it.started && !it.enqueued && !has_steps(it)) {
+          fp.push_back(it.P);
+          fi.push_back(&it);
+        }
+      if (!fp.empty()) {
+        Engine<T, A> E{ctx, st, fp, {}, {}, {}};
+        for (size_t k = 0; k < fp.size(); ++k) {
+          npb_status s = E.finish(fp[k]);
+          if (s != NPB_OK) return s;
+          const Problem& P = fp[k];
+          unsigned char* h = hres + kSlot * (size_t)fi[k]->slot;
+          NPB_HIP(hipMemcpyAsync(h, P.ws + P.L.slots + 8 * kResSlots, 8 * kResCount,
+                                 hipMemcpyDeviceToHost, st));
+          NPB_HIP(hipMemcpyAsync(h + 96, P.ws + P.L.ints, 8, hipMemcpyDeviceToHost, st));
+          NPB_HIP(hipEventRecord(fi[k]->ev, st));
+          fi[k]->enqueued = true;
+        }
+        any = true;
+      }
+    }
+    if (any) {
+      NPB_HIP(hipEventRecord(tick_ev[c], st));
+      tick_used[c] = true;
+      tick_no += 1;
+    }
+    return NPB_OK;
+  }
+
+  void poll(std::vector<RollingDone>& out) override {
+    for (auto it = items.begin(); it != items.end();) {
+      if (!it->enqueued || hipEventQuery(it->ev) != hipSuccess) {
+        ++it;
+        continue;
+      }
+      const Problem& P = it->P;
+      const unsigned char* h = hres + kSlot * (size_t)it->slot;
+      const double* r = reinterpret_cast<const double*>(h);
+      const int* ints = reinterpret_cast<const int*>(h + 96);
+      RollingDone d{};
+      d.id = it->id;
+      npb_result& o = d.res;
+      o.dG = r[0];
+      o.dG_plain = r[1];
+      o.G_m[0] = r[2];
+      o.G_m[1] = r[3];
+      o.G_0[0] = r[4];
+      o.G_0[1] = r[5];
+      o.finite = r[6] != 0.0 ? 1 : 0;
+      o.dG_direct = r[7];
+      o.dG_err_est = r[8];
+      const double pts = (double)(P.g->nx - 2) * (P.g->ny - 2) * (P.g->nz - 2);
+      for (int k = 0; k < P.L.n_runs; ++k) {
+        const int ns = P.p->n_steps << P.L.runs[k].level;
+        o.steps_done += ns;
+        o.grid_point_updates += pts * ns;
+      }
+      o.device_ms = std::nan("");
+      o.n_charge_nodes = ints[0];
+      d.status = ints[1] != 0 ? NPB_ERANGE : (o.finite ? NPB_OK : NPB_EDIVERGED);
+      out.push_back(d);
+      (void)hipEventDestroy(it->ev);
+      free_slots.push_back(it->slot);
+      it = items.erase(it);
+    }
+  }
+
+  int active() const override { return (int)items.size(); }
+  int stepping() const override {
+    int n = 0;
+    for (const Item& it : items)
+      if (!it.started || has_steps(it)) ++n;
+    return n;
+  }
+  npb_status drain() override {
+    NPB_HIP(hipStreamSynchronize(st));
+    return NPB_OK;
+  }
+  void abort_all(npb_status s, std::vector<RollingDone>& out) override {
+    (void)hipStreamSynchronize(st);
+    for (Item& it : items) {
+      RollingDone d{};
+      d.id = it.id;
+      d.status = s;
+      d.res.dG = d.res.dG_plain = d.res.dG_direct = d.res.dG_err_est = std::nan("");
+      out.push_back(d);
+      (void)hipEventDestroy(it.ev);
+      free_slots.push_back(it.slot);
+    }
+    items.clear();
+  }
+};
 
 }  // namespace
 
@@ -2229,3 +2519,40 @@ npb_status npb_solve_noalloc(npb_ctx* ctx, const npb_molecule* mol, const npb_gr
 }
 
 }  // extern "C"
+
+npb_status npb::rolling_create(const npb_ctx* tuned, int precision, void* stream, int max_items,
+                               RollingEngine** out) {
+  *out = nullptr;
+  if (!tuned || max_items < 1) return fail(NPB_EINVAL, "request loop: bad engine arguments");
+  try {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (precision == NPB_FP64) {
+      auto* e = new RollingT<double, double>();
+      npb_status s = e->init(tuned, st, max_items);
+      if (s != NPB_OK) {
+        delete e;
+        return s;
+      }
+      *out = e;
+    } else if (precision == NPB_FP32X) {
+      auto* e = new RollingT<float, double>();
+      npb_status s = e->init(tuned, st, max_items);
+      if (s != NPB_OK) {
+        delete e;
+        return s;
+      }
+      *out = e;
+    } else {
+      auto* e = new RollingT<float, float>();
+      npb_status s = e->init(tuned, st, max_items);
+      if (s != NPB_OK) {
+        delete e;
+        return s;
+      }
+      *out = e;
+    }
+  } catch (const std::exception& e) {
+    return fail(NPB_ENOMEM, e.what());
+  }
+  return NPB_OK;
+}

@@ -1,10 +1,15 @@
 // Request loop of the NPB library: molecules of different sizes arrive at
-// any time, are admitted by their HBM footprint into a device arena the
-// server owns, and are solved together by npb_solve_batch.  Batching is
-// continuous: when a batch finishes, the next one is formed from whatever
-// is waiting, in arrival order, up to the arena size and the batch limit.
+// any time and are solved with continuous batching.  A request is admitted
+// (arrival order) as soon as a workspace for it fits into a free region of
+// the device arena the server owns and fewer than max_batch requests are
+// active; it joins the running launches at the next tick boundary (a few
+// pseudo-time steps), and it leaves, reporting its result and returning its
+// arena region, as soon as its own last step is done, while the others keep
+// stepping.  Each result equals the single solve of the same request bit for
+// bit: every run of every request is swept with the arithmetic of its
+// single solve, only the launches are shared.
 //
-// One worker thread per server drives the device through its own context
+// One worker thread per server drives the device through its own contexts
 // and stream; submit / poll / stats may be called from any thread.
 #include <hip/hip_runtime.h>
 
@@ -14,6 +19,8 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -32,25 +39,68 @@ double now_s() {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// pseudo-time steps per tick: the granularity at which requests join
+constexpr int kTickSteps = 4;
+
 struct Request {
   std::vector<double> xyz, q, radius;  // copies taken at submit
   npb_molecule mol{};
   npb_grid grid{};
   npb_params params{};
   size_t ws_bytes = 0;
+  size_t ws_off = 0;
   double t_submit = 0.0, t_done = 0.0;
   bool done = false;
   npb_status status = NPB_OK;
   npb_result res{};
 };
 
+// First-fit allocator of 256-byte aligned regions of the arena; freed
+// regions merge with free neighbours.
+struct Arena {
+  std::map<size_t, size_t> free;  // offset -> bytes
+  void reset(size_t bytes) {
+    free.clear();
+    free[0] = bytes;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align256(bytes);
+    for (auto it = free.begin(); it != free.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t noff = it->first + bytes;
+      free.erase(it);
+      if (rest) free[noff] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align256(bytes);
+    auto it = free.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free.erase(nx);
+    }
+    if (it != free.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free.erase(it);
+      }
+    }
+  }
+};
+
 }  // namespace
 
 struct npb_server {
   int device = 0;
-  npb_ctx* ctx = nullptr;  // the worker's own
+  npb_ctx* tuned = nullptr;  // launch shapes the engines copy
   hipStream_t stream = nullptr;
-  void* arena = nullptr;
+  unsigned char* arena = nullptr;
   size_t arena_bytes = 0;
   int max_batch = 0;
   size_t max_queue = 0;
@@ -61,8 +111,10 @@ struct npb_server {
   uint64_t next_ticket = 1;
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, Request> reqs;  // node-based: references stay valid
-  std::vector<double> latency_s;               // submit -> done, completed requests
+  std::vector<double> latency_s;               // submit -> done, since the last reset
   npb_server_stats st{};
+  Arena free_regions;
+  int active = 0;
   std::thread worker;
 
   void run();
@@ -70,72 +122,93 @@ struct npb_server {
 
 void npb_server::run() {
   (void)hipSetDevice(device);
-  std::vector<npb_molecule> mols;
-  std::vector<npb_grid> grids;
-  std::vector<npb_params> params;
-  std::vector<void*> ws;
-  std::vector<size_t> wsb;
-  std::vector<npb_result> out;
-  std::vector<Request*> batch;
+  // one engine per precision, created on first use
+  std::unique_ptr<npb::RollingEngine> eng[3];
+  std::vector<npb::RollingDone> done;
+  std::vector<Request*> admitted;
+  double busy_from = -1.0;
   for (;;) {
-    batch.clear();
+    admitted.clear();
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !queue.empty(); });
-      if (stop && queue.empty()) return;
-      // admission: arrival order, while the workspaces fit the arena
-      size_t used = 0;
-      int prec = -1;
-      while (!queue.empty() && (int)batch.size() < max_batch) {
+      if (active == 0) {
+        if (busy_from >= 0.0) {
+          st.busy_ms += (now_s() - busy_from) * 1e3;
+          busy_from = -1.0;
+        }
+        cv.wait(lk, [&] { return stop || !queue.empty(); });
+        if (stop && queue.empty()) return;
+      }
+      // admission in arrival order: while a region of the arena holds the
+      // request's workspace and fewer than max_batch requests are active
+      while (!queue.empty() && active < max_batch) {
         Request& r = reqs.at(queue.front());
-        const size_t need = align256(r.ws_bytes);
-        if (used + need > arena_bytes) break;
-        if (prec >= 0 && r.params.precision != prec) break;
-        prec = r.params.precision;
-        used += need;
-        batch.push_back(&r);
+        size_t off = 0;
+        if (!free_regions.alloc(r.ws_bytes, &off)) break;
+        r.ws_off = off;
+        admitted.push_back(&r);
         queue.pop_front();
+        active += 1;
       }
     }
-    const int n = (int)batch.size();
-    mols.resize(n);
-    grids.resize(n);
-    params.resize(n);
-    ws.resize(n);
-    wsb.resize(n);
-    out.assign(n, npb_result{});
-    size_t off = 0;
-    for (int i = 0; i < n; ++i) {
-      mols[i] = batch[i]->mol;
-      grids[i] = batch[i]->grid;
-      params[i] = batch[i]->params;
-      ws[i] = static_cast<unsigned char*>(arena) + off;
-      wsb[i] = batch[i]->ws_bytes;
-      off += align256(batch[i]->ws_bytes);
-    }
-    const double t0 = now_s();
-    const npb_status s = npb_solve_batch(ctx, n, mols.data(), grids.data(), params.data(),
-                                         ws.data(), wsb.data(), nullptr, stream, out.data());
-    const double t1 = now_s();
-    std::lock_guard<std::mutex> lk(mu);
-    st.batches += 1;
-    st.busy_ms += (t1 - t0) * 1e3;
-    for (int i = 0; i < n; ++i) {
-      Request& r = *batch[i];
-      r.res = out[i];
-      // a batch-level failure fails every request of it; after the solves
-      // each request carries its own outcome
-      if (s == NPB_OK || s == NPB_EDIVERGED || s == NPB_ERANGE)
-        r.status = !out[i].finite ? NPB_EDIVERGED : NPB_OK;
-      else
-        r.status = s;
-      r.t_done = t1;
-      r.done = true;
-      latency_s.push_back(t1 - r.t_submit);
-      if (r.status == NPB_OK)
-        st.completed += 1;
-      else
+    if (busy_from < 0.0) busy_from = now_s();
+    for (Request* r : admitted) {
+      const int prec = r->params.precision;
+      npb_status s = NPB_OK;
+      if (!eng[prec]) {
+        npb::RollingEngine* e = nullptr;
+        s = npb::rolling_create(tuned, prec, stream, max_batch, &e);
+        eng[prec].reset(e);
+      }
+      if (s == NPB_OK)
+        s = eng[prec]->add(reinterpret_cast<uint64_t>(r), &r->mol, &r->grid, &r->params,
+                           arena + r->ws_off, r->ws_bytes);
+      if (s != NPB_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        r->status = s;
+        r->done = true;
+        r->t_done = now_s();
+        latency_s.push_back(r->t_done - r->t_submit);
         st.failed += 1;
+        free_regions.release(r->ws_off, r->ws_bytes);
+        active -= 1;
+      }
+    }
+    // one tick of every engine with problems; then whatever has finished
+    done.clear();
+    bool stepping = false;
+    for (auto& e : eng) {
+      if (!e || e->active() == 0) continue;
+      const npb_status ts = e->tick(kTickSteps);
+      // a failed enqueue ends every request of this engine with its status
+      if (ts != NPB_OK) e->abort_all(ts, done);
+      stepping = stepping || e->stepping() > 0;
+      std::lock_guard<std::mutex> lk(mu);
+      st.batches += 1;
+    }
+    for (auto& e : eng) {
+      if (!e) continue;
+      // nothing left to enqueue: wait for the device before polling
+      if (!stepping && e->active() > 0) (void)e->drain();
+      e->poll(done);
+    }
+    if (!done.empty()) {
+      std::lock_guard<std::mutex> lk(mu);
+      const double t = now_s();
+      for (const npb::RollingDone& d : done) {
+        Request& r = *reinterpret_cast<Request*>(d.id);
+        r.res = d.res;
+        r.status = d.status;
+        r.t_done = t;
+        r.done = true;
+        latency_s.push_back(t - r.t_submit);
+        if (r.status == NPB_OK)
+          st.completed += 1;
+        else
+          st.failed += 1;
+        free_regions.release(r.ws_off, r.ws_bytes);
+        active -= 1;
+      }
     }
   }
 }
@@ -152,33 +225,32 @@ npb_status npb_server_create(npb_ctx* ctx, size_t hbm_budget, int max_batch, int
   sv->device = device;
   sv->max_batch = max_batch;
   sv->max_queue = (size_t)max_queue;
-  npb_status s = npb_ctx_create(device, &sv->ctx);
+  npb_status s = npb_ctx_create(device, &sv->tuned);
   if (s != NPB_OK) {
     delete sv;
     return s;
   }
-  // batches differ from one to the next: direct launches, no graph capture
-  (void)npb_ctx_set_graph(sv->ctx, 0);
-  npb::copy_tuning(ctx, sv->ctx);
+  npb::copy_tuning(ctx, sv->tuned);
   if (hipSetDevice(device) != hipSuccess ||
       hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess) {
-    npb_ctx_destroy(sv->ctx);
+    npb_ctx_destroy(sv->tuned);
     delete sv;
     return NPB_EDEVICE;
   }
-  if (hipMalloc(&sv->arena, hbm_budget) != hipSuccess) {
+  if (hipMalloc(reinterpret_cast<void**>(&sv->arena), hbm_budget) != hipSuccess) {
     (void)hipStreamDestroy(sv->stream);
-    npb_ctx_destroy(sv->ctx);
+    npb_ctx_destroy(sv->tuned);
     delete sv;
     return NPB_ENOMEM;
   }
   sv->arena_bytes = hbm_budget;
+  sv->free_regions.reset(hbm_budget & ~size_t(255));
   try {
     sv->worker = std::thread([sv] { sv->run(); });
   } catch (...) {
     (void)hipFree(sv->arena);
     (void)hipStreamDestroy(sv->stream);
-    npb_ctx_destroy(sv->ctx);
+    npb_ctx_destroy(sv->tuned);
     delete sv;
     return NPB_ENOMEM;
   }
@@ -192,7 +264,7 @@ npb_status npb_submit(npb_server* sv, const npb_molecule* mol, const npb_grid* g
   size_t bytes = 0;
   const npb_status s = npb_workspace_bytes(mol, grid, params, &bytes);  // validates
   if (s != NPB_OK) return s;
-  if (align256(bytes) > sv->arena_bytes) return NPB_EBUSY;  // can never be admitted
+  if (align256(bytes) > (sv->arena_bytes & ~size_t(255))) return NPB_EBUSY;  // never fits
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->stop) return NPB_EINVAL;
   if (sv->queue.size() >= sv->max_queue) {
@@ -254,6 +326,16 @@ npb_status npb_server_get_stats(npb_server* sv, npb_server_stats* out) {
   return NPB_OK;
 }
 
+npb_status npb_server_reset_stats(npb_server* sv) {
+  if (!sv) return NPB_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  const int64_t queued = sv->st.queued;
+  sv->st = npb_server_stats{};
+  sv->st.queued = queued;
+  sv->latency_s.clear();
+  return NPB_OK;
+}
+
 void npb_server_destroy(npb_server* sv) {
   if (!sv) return;
   {
@@ -266,7 +348,7 @@ void npb_server_destroy(npb_server* sv) {
   (void)hipStreamSynchronize(sv->stream);
   (void)hipFree(sv->arena);
   (void)hipStreamDestroy(sv->stream);
-  npb_ctx_destroy(sv->ctx);
+  npb_ctx_destroy(sv->tuned);
   delete sv;
 }
 

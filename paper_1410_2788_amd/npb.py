@@ -129,6 +129,8 @@ def load_library(path: str = LIB_PATH):
         lib.npb_poll.argtypes = [C.c_void_p, C.c_uint64, P(npb_result), P(C.c_int)]
         lib.npb_server_get_stats.restype = C.c_int
         lib.npb_server_get_stats.argtypes = [C.c_void_p, P(npb_server_stats)]
+        lib.npb_server_reset_stats.restype = C.c_int
+        lib.npb_server_reset_stats.argtypes = [C.c_void_p]
         lib.npb_server_destroy.restype = None
         lib.npb_server_destroy.argtypes = [C.c_void_p]
         lib.npb_autotune.restype = C.c_int
@@ -357,6 +359,10 @@ def npb_server_get_stats(server) -> dict:
     return {k: getattr(s, k) for k, _ in npb_server_stats._fields_}
 
 
+def npb_server_reset_stats(server) -> None:
+    _check(load_library().npb_server_reset_stats(server))
+
+
 def npb_server_destroy(server) -> None:
     load_library().npb_server_destroy(server)
 
@@ -561,6 +567,9 @@ class Server:
 
     def stats(self) -> dict:
         return npb_server_get_stats(self.handle)
+
+    def reset_stats(self) -> None:
+        npb_server_reset_stats(self.handle)
 
     def close(self) -> None:
         if self.handle:

@@ -85,3 +85,46 @@ def test_server_refuses_what_cannot_fit_and_bad_requests():
         assert status == npb.NPB_OK and np.isfinite(r["dG"])
     finally:
         sv.close()
+
+
+def test_request_joining_mid_loop_finishes_first():
+    """Continuous batching: a 103^3 request submitted while a 257^3 request
+    (60 / 120 steps) is mid-loop joins the running launches and finishes
+    first; both results equal their single solves bit for bit."""
+    import dataclasses
+    npb = _npb()
+    big = inputs.serve_requests(1, precision="f32")[0]
+    big.params = dataclasses.replace(big.params, n_steps=60)
+    small = inputs.small_globular(seed=81, n_atoms=500, n=103, n_steps=20, precision="f32")
+    _say(f"case server join: {big.grid.nx}^3 60/120 steps, then {small.grid.nx}^3 20/40 steps")
+    ref_big = npb.solve(big.molecule, big.grid, big.params)
+    ref_small = npb.solve(small.molecule, small.grid, small.params)
+    sv = npb.Server(2 << 30, max_batch=4, max_queue=8)
+    try:
+        tb = sv.submit(big.molecule, big.grid, big.params)
+        t0 = time.time()
+        while sv.stats()["batches"] < 3:
+            assert time.time() - t0 < 30.0, "the first request did not start"
+            time.sleep(0.0005)
+        ts = sv.submit(small.molecule, small.grid, small.params)
+        order, out = [], {}
+        while len(out) < 2:
+            for t in (tb, ts):
+                if t not in out:
+                    r = sv.poll(t)
+                    if r is not None:
+                        out[t] = r
+                        order.append(t)
+            assert time.time() - t0 < 60.0, "server did not finish in time"
+            time.sleep(0.0005)
+        st = sv.stats()
+    finally:
+        sv.close()
+    _say(f"  completion order {'small, big' if order == [ts, tb] else 'big, small'}; stats {st}")
+    assert order == [ts, tb]
+    for t, ref in ((tb, ref_big), (ts, ref_small)):
+        status, r = out[t]
+        assert status == npb.NPB_OK
+        for k in ("dG", "dG_plain", "G_m", "G_0", "n_charge_nodes", "steps_done",
+                  "grid_point_updates", "dG_err_est"):
+            assert r[k] == ref[k], k
