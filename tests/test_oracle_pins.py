@@ -853,15 +853,19 @@ def test_sphere_spatial_errors_match_the_paper_table(scheme, key):
 
 
 @pytest.mark.parametrize("scheme,key", [("LODIE2", "LODIE"), ("LODCN2", "LODCN"),
-                                        ("MAOSCN", "MAOSCN"), ("AOSIE2", "AOSIE2"),
+                                        ("MAOSCN", "MAOSCN"), ("AOSCN1", "AOSCN1"),
+                                        ("AOSCN2", "AOSCN2"), ("AOSIE2", "AOSIE2"),
                                         ("MAOSIE", "MAOSIE")])
 def test_sphere_spatial_errors_with_the_location_rule_reproduce_the_paper_table(scheme, key):
     # with eps at each half point by its own location (the paper's rule),
     # the printed errors come back at every h down to the coarsest: the LOD
-    # schemes and MAOSCN to the printed 3 digits (h = 1 L2 within 3 %), the
-    # AOSIE2 / MAOSIE family within 2 % for h <= 0.5
+    # schemes, AOSCN1, AOSCN2 and MAOSCN to the printed 3 digits (at h = 1
+    # AOSCN1/2 and MAOSCN to 3 digits too, LODIE/LODCN L2 within 3 %), the
+    # implicit-Euler additive family (AOSIE2, MAOSIE) within 2 % for h <= 0.5
+    # only: at h = 1 it sits about a third below the printed row under every
+    # reading tried (see the design notes)
     ref = json.load(open(os.path.join(GOLDEN, "paper_sphere_spatial.json")))
-    exact3 = key in ("LODIE", "LODCN", "MAOSCN")
+    exact3 = key in ("LODIE", "LODCN", "MAOSCN", "AOSCN1", "AOSCN2")
     for h in ((1.0, 0.5, 0.25) if exact3 else (0.5, 0.25)):
         l2, linf = _sphere_errors(h, scheme, "location")
         i = ref["h"].index(h)
