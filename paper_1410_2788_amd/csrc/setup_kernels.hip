@@ -6,6 +6,8 @@
 // give bit-identical inputs to the time loop.  FP64 throughout; expression
 // order follows the definitions so that contraction into fused
 // multiply-adds is switched off where a predicate or a weight is formed.
+#include <type_traits>
+
 #include "npb_internal.h"
 
 namespace npb {
@@ -501,161 +503,214 @@ __device__ __forceinline__ void shell_node(long long s, int nx, int ny, int nz, 
   }
 }
 
-// Both media in one pass: the solvated value with eps_s and kappa, the
-// vacuum value (kappa = 0) with eps_v, sharing the distance of every
-// (shell node, atom) pair.  R is the arithmetic type of one pair's term
-// (FP64 here; FP32 terms use boundary_f32_kernel below); the sums over
-// atoms are FP64, and the constant factor l_B / eps is applied once at the
-// end.
+// ---------------------------------------------------------------------------
+// Dirichlet data of both media in one pass (Eq. (BoundaryCond)): the
+// solvated value l_B/eps_s sum q e^{-kappa d}/d and the vacuum value
+// l_B/eps_v sum q/d, sharing the distance of every (shell node, atom) pair.
+//
+// The shell is walked as rows of nodes along one axis: x on the two z faces
+// (every row j) and on the two y faces (every interior z), y on the two x
+// faces (interior y of every interior z).  A thread takes kBcK consecutive
+// nodes of a row: for each atom the part of the squared distance across the
+// row, (f1 - a_f1)^2 + (z - a_z)^2, is formed once and shared by the
+// thread's nodes, which then need one subtraction and one FMA each.  Block:
+// 256 threads = 64 row segments x 4 atom slices (one wave per slice); atoms
+// are staged 256 at a time in LDS as (x, y, z, q) and read by broadcast; the
+// slices' sums are added in a fixed order at the end.
+//
+// Per pair, 1/d comes from the hardware reciprocal square root (FP32 as is;
+// FP64 refined by two Newton steps) and e^{-kappa d} from a base-2
+// exponential (FP32: the hardware one; FP64: written below).  FP32 terms are
+// summed in FP32 over up to 32 atoms before they join FP64 sums (the
+// per-term rounding of FP32 terms is of the same order); FP64 terms go
+// straight into FP64 sums.
+constexpr int kBcGroups = 64, kBcSlices = 4, kBcK = 8;
+
+// e^x for x <= 0 in FP64: Cody and Waite's range reduction x = k ln2 + r
+// (ln2 split into a head with 31 fraction bits, so that k * head is exact,
+// and the rest), |r| <= ln2 / 2, e^r by its Taylor series to degree 13
+// (truncation below 5e-18 relative), then the exponent k added back.
+__device__ __forceinline__ double exp_neg(double x) {
+  constexpr double kLog2e = 1.4426950408889634;
+  constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
+  constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+  const double k = __builtin_rint(x * kLog2e);
+  double r = fma(-k, kLn2Hi, x);
+  r = fma(-k, kLn2Lo, r);
+  // 1/n!, n = 13 .. 0
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)k);
+}
+
 template <typename R>
-__device__ __forceinline__ void pair_terms(R dx, R dy, R dz, R q, R kappa, R& ts, R& tv);
+struct BcPair;
 template <>
-__device__ __forceinline__ void pair_terms<double>(double dx, double dy, double dz, double q,
-                                                   double kappa, double& ts, double& tv) {
-  const double d = sqrt(dx * dx + dy * dy + dz * dz);
-  tv = q / d;
-  ts = tv * exp(-kappa * d);
+struct BcPair<float> {
+  // c = -kappa log2(e); ts += q e^{-kappa d} / d, tv += q / d
+  static __device__ __forceinline__ void add(float d2, float q, float c, float& ts, float& tv) {
+    const float ri = __builtin_amdgcn_rsqf(d2);
+    const float t = q * ri;
+    tv += t;
+    ts = fmaf(t, __builtin_amdgcn_exp2f(c * (d2 * ri)), ts);
+  }
+};
+template <>
+struct BcPair<double> {
+  // c = -kappa
+  static __device__ __forceinline__ void add(double d2, double q, double c, double& ts,
+                                             double& tv) {
+    double ri = __builtin_amdgcn_rsq(d2);
+    ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
+    ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
+    const double t = q * ri;
+    tv += t;
+    ts = fma(t, exp_neg(c * (d2 * ri)), ts);
+  }
+};
+
+// shell row segments of kBcK nodes: faces z0, z1 (rows j, along x), y0, y1
+// (rows k, along x), x0, x1 (rows k, along interior y)
+struct BcSeg {
+  long long nz2, ny2, nx2;  // segments of the z, y and x face pairs
+};
+__device__ __forceinline__ BcSeg bc_segments(int nx, int ny, int nz) {
+  const long long sx = (nx + kBcK - 1) / kBcK, sy = (ny - 2 + kBcK - 1) / kBcK;
+  return BcSeg{2LL * ny * sx, 2LL * (nz - 2) * sx, 2LL * (nz - 2) * sy};
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void boundary_kernel(SetupArgs a, double scale_s, double kappa,
-                                                       double scale_v, double* bc_s, double* bc_v,
-                                                       long long nshell) {
-#pragma clang fp contract(off)
-  __shared__ R sx[256], sy[256], sz[256], sq[256];
-  const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
-  const bool valid = s < nshell;
-  R X = 0, Y = 0, Z = 0;
-  if (valid) {
-    int i, j, k;
-    shell_node(s, a.nx, a.ny, a.nz, i, j, k);
-    X = (R)(a.ox + (double)i * a.h);
-    Y = (R)(a.oy + (double)j * a.h);
-    Z = (R)(a.oz + (double)k * a.h);
-  }
-  const int na = a.n_atoms;
-  const R kap = (R)kappa;
-  double acc_s = 0.0, acc_v = 0.0;
-  for (int t0 = 0; t0 < na; t0 += 256) {
-    int t = t0 + threadIdx.x;
-    if (t < na) {
-      sx[threadIdx.x] = (R)a.atoms[t];
-      sy[threadIdx.x] = (R)a.atoms[na + t];
-      sz[threadIdx.x] = (R)a.atoms[2 * na + t];
-      sq[threadIdx.x] = (R)a.atoms[3 * na + t];
-    }
-    __syncthreads();
-    const int cnt = min(256, na - t0);
-    if (valid) {
-      for (int jj = 0; jj < cnt; ++jj) {
-        R ts, tv;
-        pair_terms<R>(X - sx[jj], Y - sy[jj], Z - sz[jj], sq[jj], kap, ts, tv);
-        acc_s += (double)ts;
-        acc_v += (double)tv;
-      }
-    }
-    __syncthreads();
-  }
-  if (valid) {
-    bc_s[s] = scale_s * acc_s;
-    if (bc_v) bc_v[s] = scale_v * acc_v;
-  }
-}
-
-// FP32 terms.  Block: 256 threads = 64 node groups x 4 atom slices (one
-// wave per slice).  A thread takes kBcK shell nodes (group g: nodes
-// g, g + 64, ... of the block's range) and the atoms sl, sl + 4, ... of
-// every 256-atom tile staged in LDS as (x, y, z, q): each staged atom is
-// read once (a broadcast LDS read) and used for kBcK nodes, which also
-// gives every thread kBcK independent chains.  Per pair: d^2 by FMAs,
-// 1/d by the hardware reciprocal square root (d^2 >= h^2 on the shell:
-// no denormal inputs), e^{-kappa d} = 2^{-kappa log2(e) d} by the hardware
-// base-2 exponential.  The terms of up to 32 atoms are summed in FP32
-// before they join the FP64 sums (the per-term rounding of FP32 terms is of
-// the same order), and the four slices' FP64 sums are added in a fixed
-// order at the end.
-constexpr int kBcGroups = 64, kBcSlices = 4, kBcK = 4;
-constexpr int kBcNodes = kBcGroups * kBcK;  // shell nodes per block
-__global__ __launch_bounds__(256) void boundary_f32_kernel(SetupArgs a, double scale_s,
-                                                           double kappa, double scale_v,
-                                                           double* bc_s, double* bc_v,
-                                                           long long nshell) {
-  __shared__ float4 sa[256];
-  __shared__ double rs[kBcSlices][kBcNodes], rv[kBcSlices][kBcNodes];
+__global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double scale_s,
+                                                            double c_exp, double scale_v,
+                                                            double* bc_s, double* bc_v) {
+  using R4 = typename std::conditional<std::is_same<R, float>::value, float4, double4>::type;
+  __shared__ R4 sa[256];
+  __shared__ double rs[kBcSlices][kBcGroups * kBcK], rv[kBcSlices][kBcGroups * kBcK];
   const int g = threadIdx.x % kBcGroups;
   const int sl = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kBcGroups);
-  const long long s0 = (long long)blockIdx.x * kBcNodes + g;
-  float X[kBcK], Y[kBcK], Z[kBcK];
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long long nxy = (long long)nx * ny, ring = 2LL * nx + 2LL * (ny - 2);
+  const BcSeg sg = bc_segments(nx, ny, nz);
+  const long long sxr = (nx + kBcK - 1) / kBcK, syr = (ny - 2 + kBcK - 1) / kBcK;
+  // this thread's segment: face, row, first node along the row
+  long long sid = (long long)blockIdx.x * kBcGroups + g;
+  int face = -1, row = 0, u0 = 0;
+  if (sid < sg.nz2) {
+    face = (int)(sid / (ny * sxr));
+    const long long t = sid - face * ny * sxr;
+    row = (int)(t / sxr);
+    u0 = (int)(t % sxr) * kBcK;
+  } else if ((sid -= sg.nz2) < sg.ny2) {
+    face = 2 + (int)(sid / ((nz - 2) * sxr));
+    const long long t = sid - (face - 2) * (nz - 2) * sxr;
+    row = (int)(t / sxr);
+    u0 = (int)(t % sxr) * kBcK;
+  } else if ((sid -= sg.ny2) < sg.nx2) {
+    face = 4 + (int)(sid / ((nz - 2) * syr));
+    const long long t = sid - (face - 4) * (nz - 2) * syr;
+    row = (int)(t / syr);
+    u0 = (int)(t % syr) * kBcK;
+  }
+  const bool vy = face >= 4;  // the row runs along y
+  const int len = face < 0 ? 0 : (vy ? ny - 2 : nx);
+  // fixed coordinates across the row, varying one per node
+  R F1 = R(1e4), F2 = R(1e4), V[kBcK];
+  int cnt = 0;
+  if (face >= 0) {
+    const int kz = face < 2 ? (face == 1 ? nz - 1 : 0) : row + 1;
+    F2 = (R)(a.oz + (double)kz * a.h);
+    if (face < 2)
+      F1 = (R)(a.oy + (double)row * a.h);
+    else if (face < 4)
+      F1 = (R)(a.oy + (double)(face == 3 ? ny - 1 : 0) * a.h);
+    else
+      F1 = (R)(a.ox + (double)(face == 5 ? nx - 1 : 0) * a.h);
+    cnt = min(kBcK, len - u0);
+  }
 #pragma unroll
-  for (int k = 0; k < kBcK; ++k) {
-    const long long s = s0 + (long long)k * kBcGroups;
-    // past the shell: a far point, so that every term stays finite
-    X[k] = Y[k] = Z[k] = 1.0e4f;
-    if (s < nshell) {
-      int i, j, kk;
-      shell_node(s, a.nx, a.ny, a.nz, i, j, kk);
-      X[k] = (float)(a.ox + (double)i * a.h);
-      Y[k] = (float)(a.oy + (double)j * a.h);
-      Z[k] = (float)(a.oz + (double)kk * a.h);
-    }
+  for (int t = 0; t < kBcK; ++t) {
+    const int u = u0 + t;
+    V[t] = R(1e4);
+    if (t < cnt) V[t] = vy ? (R)(a.oy + (double)(1 + u) * a.h) : (R)(a.ox + (double)u * a.h);
   }
   const int na = a.n_atoms;
-  const float c = (float)(-kappa * 1.4426950408889634);  // -kappa log2(e)
+  const R c = (R)c_exp;
   double acc_s[kBcK], acc_v[kBcK];
 #pragma unroll
-  for (int k = 0; k < kBcK; ++k) acc_s[k] = acc_v[k] = 0.0;
+  for (int t = 0; t < kBcK; ++t) acc_s[t] = acc_v[t] = 0.0;
   for (int t0 = 0; t0 < na; t0 += 256) {
     const int t = t0 + (int)threadIdx.x;
-    if (t < na)
-      sa[threadIdx.x] = make_float4((float)a.atoms[t], (float)a.atoms[na + t],
-                                    (float)a.atoms[2 * na + t], (float)a.atoms[3 * na + t]);
+    if (t < na) {
+      R4 at;
+      at.x = (R)a.atoms[t];
+      at.y = (R)a.atoms[na + t];
+      at.z = (R)a.atoms[2 * na + t];
+      at.w = (R)a.atoms[3 * na + t];
+      sa[threadIdx.x] = at;
+    }
     __syncthreads();
-    const int cnt = min(256, na - t0);
-    for (int j0 = sl; j0 < cnt; j0 += 32 * kBcSlices) {
-      float ps[kBcK], pv[kBcK];
+    const int n = min(256, na - t0);
+    // FP32: partial sums over 32 atoms of the slice; FP64: one run
+    constexpr int kRun = std::is_same<R, float>::value ? 32 * kBcSlices : 256;
+    for (int j0 = sl; j0 < n; j0 += kRun) {
+      R ps[kBcK], pv[kBcK];
 #pragma unroll
-      for (int k = 0; k < kBcK; ++k) ps[k] = pv[k] = 0.0f;
-      const int je = min(j0 + 32 * kBcSlices, cnt);
-#pragma unroll 4
+      for (int q = 0; q < kBcK; ++q) ps[q] = pv[q] = R(0);
+      const int je = min(j0 + kRun, n);
+#pragma unroll 2
       for (int jj = j0; jj < je; jj += kBcSlices) {
-        const float4 at = sa[jj];
+        const R4 at = sa[jj];
+        const R d1 = F1 - (vy ? at.x : at.y), d3 = F2 - at.z;
+        const R b2 = d1 * d1 + d3 * d3;
+        const R av = vy ? at.y : at.x;
 #pragma unroll
-        for (int k = 0; k < kBcK; ++k) {
-          const float dx = X[k] - at.x, dy = Y[k] - at.y, dz = Z[k] - at.z;
-          const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          const float ri = __builtin_amdgcn_rsqf(d2);
-          const float tv = at.w * ri;
-          pv[k] += tv;
-          ps[k] = fmaf(tv, __builtin_amdgcn_exp2f(c * (d2 * ri)), ps[k]);
+        for (int q = 0; q < kBcK; ++q) {
+          const R dv = V[q] - av;
+          BcPair<R>::add(dv * dv + b2, at.w, c, ps[q], pv[q]);
         }
       }
 #pragma unroll
-      for (int k = 0; k < kBcK; ++k) {
-        acc_s[k] += (double)ps[k];
-        acc_v[k] += (double)pv[k];
+      for (int q = 0; q < kBcK; ++q) {
+        acc_s[q] += (double)ps[q];
+        acc_v[q] += (double)pv[q];
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int k = 0; k < kBcK; ++k) {
-    rs[sl][g + k * kBcGroups] = acc_s[k];
-    rv[sl][g + k * kBcGroups] = acc_v[k];
+  for (int t = 0; t < kBcK; ++t) {
+    rs[sl][g * kBcK + t] = acc_s[t];
+    rv[sl][g * kBcK + t] = acc_v[t];
   }
   __syncthreads();
   if (sl == 0) {
-#pragma unroll
-    for (int k = 0; k < kBcK; ++k) {
-      const long long s = s0 + (long long)k * kBcGroups;
-      if (s >= nshell) continue;
+    for (int t = 0; t < cnt; ++t) {
+      // shell index of node u (the order shell_node enumerates)
+      const int u = u0 + t;
+      const long long si =
+          vy ? 2 * nxy + (long long)row * ring + 2LL * nx + 2LL * u + (face == 5 ? 1 : 0)
+          : face < 2 ? (face == 1 ? nxy : 0) + (long long)row * nx + u
+                     : 2 * nxy + (long long)row * ring + (face == 3 ? nx : 0) + u;
       double ts = 0.0, tv = 0.0;
 #pragma unroll
       for (int q = 0; q < kBcSlices; ++q) {
-        ts += rs[q][g + k * kBcGroups];
-        tv += rv[q][g + k * kBcGroups];
+        ts += rs[q][g * kBcK + t];
+        tv += rv[q][g * kBcK + t];
       }
-      bc_s[s] = scale_s * ts;
-      if (bc_v) bc_v[s] = scale_v * tv;
+      bc_s[si] = scale_s * ts;
+      if (bc_v) bc_v[si] = scale_v * tv;
     }
   }
 }
@@ -663,14 +718,15 @@ __global__ __launch_bounds__(256) void boundary_f32_kernel(SetupArgs a, double s
 hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, double eps_v,
                            double lB, double* bc_s, double* bc_v, bool fp32_terms,
                            hipStream_t st) {
-  const long long ns = shell_count(a.nx, a.ny, a.nz);
-  const dim3 g((unsigned)((ns + 255) / 256)), b(256);
+  const long long sx = (a.nx + kBcK - 1) / kBcK, sy = (a.ny - 2 + kBcK - 1) / kBcK;
+  const long long nseg = 2LL * a.ny * sx + 2LL * (a.nz - 2) * sx + 2LL * (a.nz - 2) * sy;
+  const dim3 g((unsigned)((nseg + kBcGroups - 1) / kBcGroups)), b(kBcGroups * kBcSlices);
   const double ss = lB / eps_s, sv = lB / eps_v;
   if (fp32_terms)
-    hipLaunchKernelGGL(boundary_f32_kernel, dim3((unsigned)((ns + kBcNodes - 1) / kBcNodes)),
-                       dim3(kBcGroups * kBcSlices), 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
+    hipLaunchKernelGGL(boundary_rows_kernel<float>, g, b, 0, st, a, ss, -kappa * 1.4426950408889634,
+                       sv, bc_s, bc_v);
   else
-    hipLaunchKernelGGL(boundary_kernel<double>, g, b, 0, st, a, ss, kappa, sv, bc_s, bc_v, ns);
+    hipLaunchKernelGGL(boundary_rows_kernel<double>, g, b, 0, st, a, ss, -kappa, sv, bc_s, bc_v);
   return hipGetLastError();
 }
 
