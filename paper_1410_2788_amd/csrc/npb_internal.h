@@ -11,6 +11,81 @@
 
 namespace npb {
 
+// ---------------------------------------------------------------------------
+// FP64 elementary functions of the hot kernels, written from their series
+// (no library calls): accurate to a few units in the last place over the
+// ranges the kernels use.
+
+// e^x for x <= 0: Cody and Waite's range reduction x = k ln2 + r (ln2 split
+// into a head with 31 fraction bits, so that k * head is exact, and the
+// rest), |r| <= ln2 / 2, e^r by its Taylor series to degree 13 (truncation
+// below 5e-18 relative), then the exponent k added back.
+__device__ __forceinline__ double exp_neg(double x) {
+  constexpr double kLog2e = 1.4426950408889634;
+  constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
+  constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+  const double k = __builtin_rint(x * kLog2e);
+  double r = fma(-k, kLn2Hi, x);
+  r = fma(-k, kLn2Lo, r);
+  // 1/n!, n = 13 .. 0
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)k);
+}
+
+// 1/x for x > 0 (normal): the hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp_newton(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// ln(1 + x) for x >= 0: 2 atanh(s) with s = x / (2 + x) while 1 + x < sqrt 2
+// (no cancellation for small x); beyond, 1 + x = 2^e f with f in
+// [sqrt(1/2), sqrt 2) and s = (f - 1) / (f + 1).  |s| <= 0.1716, so the
+// odd series s + s^3/3 + ... + s^19/19 leaves a truncation below 1e-17.
+__device__ __forceinline__ double log1p_nonneg(double x) {
+  constexpr double kLn2 = 0.6931471805599453;
+  double s, e = 0.0;
+  if (x < 0.41421356237309503) {
+    s = x * rcp_newton(2.0 + x);
+  } else {
+    const double y = 1.0 + x;
+    int ex = 0;
+    double f = __builtin_frexp(y, &ex);  // y = f 2^ex, f in [1/2, 1)
+    if (f < 0.70710678118654752) {
+      f *= 2.0;
+      ex -= 1;
+    }
+    e = (double)ex;
+    s = (f - 1.0) * rcp_newton(f + 1.0);
+  }
+  const double s2 = s * s;
+  double p = 1.0 / 19.0;
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  p = fma(p, s2, 1.0);
+  return fma(e, kLn2, 2.0 * s * p);
+}
+
 // device of a context (the server's worker uses the same device), and the
 // tuned line-solver shapes it hands to a server's own context
 int ctx_device(const npb_ctx* ctx);
@@ -247,10 +322,12 @@ hipError_t launch_stencil(const SetupArgs& a, int* key, int* id, double* val, in
 // 256 * ceil(n/256) ints.
 hipError_t radix_sort_pairs(int* key_a, int* id_a, int* key_b, int* id_b, int* hist,
                             int n, long long key_limit, hipStream_t st);
-hipError_t launch_exclusive_scan(int* data, int n, int* total, hipStream_t st);
+// aux: scan_aux_ints(n) ints of scratch (multi-block scan), or nullptr
+hipError_t launch_exclusive_scan(int* data, int n, int* total, int* aux, hipStream_t st);
+int scan_aux_ints(int n);
 hipError_t launch_merge_charges(const int* key, const int* id, const double* val, int* heads,
                                 int n, int* nq_dev, int* q_idx, double* q_val,
-                                double* q_rho, double rho_pref, hipStream_t st);
+                                double* q_rho, double rho_pref, int* scan_aux, hipStream_t st);
 hipError_t launch_line_ptr(const int* sorted_keys, const int* n_dev, int cap, int n_lines,
                            int keys_per_line, int* ptr, hipStream_t st);
 // linear node indices are pitched (row pitch nxp); the keys order by line

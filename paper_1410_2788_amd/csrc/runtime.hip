@@ -640,7 +640,8 @@ Layout make_layout(const npb_molecule* mol, const npb_grid* g, const npb_params*
   L.key_b = take((size_t)cap * 4);
   L.id_b = take((size_t)cap * 4);
   L.sval = take((size_t)cap * 8);
-  L.hist = take((size_t)256 * (nb > 0 ? nb : 1) * 4);
+  // radix histograms and, after them, the multi-block scan's tile totals
+  L.hist = take(((size_t)256 * (nb > 0 ? nb : 1) + (size_t)scan_aux_ints(256 * (nb > 0 ? nb : 1))) * 4);
   L.heads = take((size_t)cap * 4);
   L.q_idx = take((size_t)cap * 4);
   L.q_val = take((size_t)cap * 8);
@@ -1215,7 +1216,8 @@ struct Engine {
       const double pref = P.fields() ? 1.0 : 4.0 * M_PI * P.lB / (P.g->h * P.g->h * P.g->h);
       e = launch_merge_charges(P.at<int>(L.key_a), P.at<int>(L.id_a), P.at<double>(L.sval),
                                P.at<int>(L.heads), L.cap, ints, P.at<int>(L.q_idx),
-                               P.at<double>(L.q_val), P.at<double>(L.q_rho), pref, st);
+                               P.at<double>(L.q_val), P.at<double>(L.q_rho), pref,
+                               P.at<int>(L.hist), st);
       if (e != hipSuccess) return e;
       e = launch_line_ptr(P.at<int>(L.q_idx), ints, L.cap, ny * nz, nxp, P.at<int>(L.xptr), st);
       if (e != hipSuccess) return e;

@@ -315,7 +315,65 @@ __global__ __launch_bounds__(1024) void scan_lds_kernel(int* data, int n, int ti
   if (tid == 0 && total) *total = carry;
 }
 
-hipError_t launch_exclusive_scan(int* data, int n, int* total, hipStream_t st) {
+// Multi-block exclusive scan for long arrays: every block scans one tile of
+// kScanTileN = 4096 entries (4 per thread) and leaves the tile's total in
+// aux; the tile totals are scanned by scan_lds_kernel (which also gives the
+// grand total); a last pass adds each tile's offset.  Integer sums, so the
+// result does not depend on scheduling.
+constexpr int kScanTileN = 4096;
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(int* data, int n, int* aux) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long long base = (long long)blockIdx.x * kScanTileN + 4LL * tid;
+  int v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = (base + q < n) ? data[base + q] : 0;
+  const int s = (v[0] + v[1]) + (v[2] + v[3]);
+  int inc = s;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += u;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    int t = lane < 16 ? wsum[lane] : 0;
+    for (int off = 1; off < 16; off <<= 1) {
+      const int u = __shfl_up(t, off, 64);
+      if (lane >= off) t += u;
+    }
+    if (lane < 16) wsum[lane] = t;
+  }
+  __syncthreads();
+  int run = (w > 0 ? wsum[w - 1] : 0) + inc - s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < n) data[base + q] = run;
+    run += v[q];
+  }
+  if (tid == 0) aux[blockIdx.x] = wsum[15];
+}
+__global__ __launch_bounds__(1024) void scan_add_kernel(int* data, int n, const int* aux) {
+  const long long base = (long long)blockIdx.x * kScanTileN + 4LL * threadIdx.x;
+  const int off = aux[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (base + q < n) data[base + q] += off;
+}
+
+int scan_aux_ints(int n) { return (n + kScanTileN - 1) / kScanTileN + 1; }
+
+hipError_t launch_exclusive_scan(int* data, int n, int* total, int* aux, hipStream_t st) {
+  if (aux != nullptr && n > 2 * kScanTileN) {
+    const int nt = (n + kScanTileN - 1) / kScanTileN;
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3(nt), dim3(1024), 0, st, data, n, aux);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan(aux, nt, total, nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_add_kernel, dim3(nt), dim3(1024), 0, st, data, n, aux);
+    return hipGetLastError();
+  }
   const int tile = n < kScanTile ? (n > 0 ? n : 1) : kScanTile;
   const size_t lds = (size_t)scan_pad(tile) * sizeof(int);
   if (lds > 64 * 1024) {
@@ -341,7 +399,7 @@ hipError_t radix_sort_pairs(int* key_a, int* id_a, int* key_b, int* id_b, int* h
     int shift = 8 * p;
     hipLaunchKernelGGL(radix_count_kernel, dim3(nblocks), dim3(256), 0, st, ka, n, shift,
                        nblocks, hist);
-    hipError_t e = launch_exclusive_scan(hist, 256 * nblocks, nullptr, st);
+    hipError_t e = launch_exclusive_scan(hist, 256 * nblocks, nullptr, hist + 256 * nblocks, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(256), 0, st, ka, ia, kb, ib, n,
                        shift, nblocks, hist);
@@ -383,11 +441,11 @@ __global__ void merge_kernel(const int* key, const int* id, const double* val, c
 
 hipError_t launch_merge_charges(const int* key, const int* id, const double* val, int* heads,
                                 int n, int* nq_dev, int* q_idx, double* q_val, double* q_rho,
-                                double rho_pref, hipStream_t st) {
+                                double rho_pref, int* scan_aux, hipStream_t st) {
   if (n <= 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(nq_dev), 1, 0u, st);
   int nb = (n + 255) / 256;
   hipLaunchKernelGGL(heads_kernel, dim3(nb), dim3(256), 0, st, key, n, heads);
-  hipError_t e = launch_exclusive_scan(heads, n, nq_dev, st);
+  hipError_t e = launch_exclusive_scan(heads, n, nq_dev, scan_aux, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(merge_kernel, dim3(nb), dim3(256), 0, st, key, id, val, heads, n, q_idx,
                      q_val, q_rho, rho_pref);
@@ -525,35 +583,6 @@ __device__ __forceinline__ void shell_node(long long s, int nx, int ny, int nz, 
 // per-term rounding of FP32 terms is of the same order); FP64 terms go
 // straight into FP64 sums.
 constexpr int kBcGroups = 64, kBcSlices = 4, kBcK = 8;
-
-// e^x for x <= 0 in FP64: Cody and Waite's range reduction x = k ln2 + r
-// (ln2 split into a head with 31 fraction bits, so that k * head is exact,
-// and the rest), |r| <= ln2 / 2, e^r by its Taylor series to degree 13
-// (truncation below 5e-18 relative), then the exponent k added back.
-__device__ __forceinline__ double exp_neg(double x) {
-  constexpr double kLog2e = 1.4426950408889634;
-  constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
-  constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
-  const double k = __builtin_rint(x * kLog2e);
-  double r = fma(-k, kLn2Hi, x);
-  r = fma(-k, kLn2Lo, r);
-  // 1/n!, n = 13 .. 0
-  double p = 1.0 / 6227020800.0;
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
-  return __builtin_ldexp(p, (int)k);
-}
 
 template <typename R>
 struct BcPair;
@@ -781,7 +810,28 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny,
   }
   const int j0 = p * M, j1 = p * M + M + 1;
   uint8_t c = 1;
-  if (j1 <= n - 1 && face_loc) {
+  if (dir == 0 && j1 <= n - 1) {
+    // x-lines: the chunk's bytes j0 .. j1 of one row, read as the 32-bit
+    // words that hold them (rows and j0 = p M are 4-byte aligned; the word
+    // of byte j1 ends inside the row's row4(nx) bytes)
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(mask + base);
+    const int w0 = j0 >> 2, w1 = j1 >> 2;
+    const uint32_t first = w[w0] & 0xffu;
+    const uint32_t ref = face_loc ? ((first >> 1) & 1u) : first;
+    bool same = true;
+    for (int q = w0; q <= w1; ++q) {
+      const uint32_t v = w[q];
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * q + b;
+        const uint32_t byte = (v >> (8 * b)) & 0xffu;
+        const uint32_t x = face_loc ? ((byte >> 1) & 1u) : byte;
+        // face rule by location: half points j0 .. j1 - 1; else nodes j0 .. j1
+        const bool in = face_loc ? (j >= j0 && j < j1) : (j >= j0 && j <= j1);
+        same = same && (!in || x == ref);
+      }
+    }
+    if (same) c = ref ? 2 : 0;
+  } else if (j1 <= n - 1 && face_loc) {
     const int v0 = mask[base + (long long)j0 * stride] & 2;
     bool same = true;
     for (int j = j0 + 1; j < j1; ++j) same = same && ((mask[base + (long long)j * stride] & 2) == v0);

@@ -43,7 +43,9 @@ namespace npb {
 // printed ratio divided by cosh(theta) becomes
 //   (kA + kB E) / (kB + kA E) = 1 + 2k m / (kB + kA E),
 // so  w = sign(u) * log1p(2k m / (kB + kA E)): odd in u, no overflow.
-// FP32 uses the hardware exp/log; FP64 the accurate expm1/log1p.
+// FP32 uses the hardware exp/log; FP64 the series-based exp_neg and
+// log1p_nonneg (m = 1 - E then loses relative accuracy as |u| -> 0 but keeps
+// an absolute error of ~1e-16, which is what the field sees).
 __device__ __forceinline__ float sinh_flow(float u, float kA, float kB) {
   const float E = __expf(-fabsf(u));
   const float m = 1.0f - E;
@@ -51,9 +53,9 @@ __device__ __forceinline__ float sinh_flow(float u, float kA, float kB) {
   return copysignf(__logf(1.0f + x), u);
 }
 __device__ __forceinline__ double sinh_flow(double u, double kA, double kB) {
-  const double mm = expm1(-fabs(u));  // = E - 1 = -m
-  const double E = 1.0 + mm;
-  return copysign(log1p((kA - kB) * (-mm) / fma(kA, E, kB)), u);
+  const double E = exp_neg(-fabs(u));
+  const double m = 1.0 - E;
+  return copysign(log1p_nonneg((kA - kB) * m * rcp_newton(fma(kA, E, kB))), u);
 }
 
 template <typename T>
