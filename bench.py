@@ -258,12 +258,13 @@ def bench_large(args):
         ref = _golden(gname)
         rec = {"precision": prec, "scheme": scheme, "dt": [dt, dt / 2], "steps": [n, 2 * n],
                "ms_per_solve": ms, "grid_point_updates_per_solve": rs[0]["grid_point_updates"],
-               "dG": rs[0]["dG"], "dG_plain": rs[0]["dG_plain"]}
+               "dG": rs[0]["dG"], "dG_plain": rs[0]["dG_plain"], "dG_err_est": rs[0]["dG_err_est"]}
         good = len(rs)
         if ref:
             errs = [abs(r["dG"] - ref["dG"]) for r in rs]
             good = sum(e <= _energy_tol(ref["dG"]) for e in errs)
-            rec.update(oracle_dG=ref["dG"], abs_err=errs[0], tolerance=_energy_tol(ref["dG"]))
+            rec.update(oracle_dG=ref["dG"], abs_err=errs[0], tolerance=_energy_tol(ref["dG"]),
+                       within_estimate=bool(errs[0] <= rs[0]["dG_err_est"]))
         # ms is per solve: count the fraction of solves within tolerance
         rec["solves_within_tolerance"] = f"{good}/{len(rs)}" if ref else None
         rec["grid_point_updates_per_s"] = rs[0]["grid_point_updates"] * (good / len(rs)) / (ms * 1e-3)
