@@ -277,8 +277,14 @@ npb_status npb_validate(const npb_molecule* mol, const npb_grid* grid,
 npb_status npb_workspace_bytes(const npb_molecule* mol, const npb_grid* grid,
                                const npb_params* params, size_t* bytes);
 
-/* Solve one problem.  Enqueues setup (solute mask, trilinear charges,
- * boundary data), the time loops, the FP64 energy reductions and
+/* Solve one problem: the NPB equation of Sec. 2.1 (Eqs. (NPB), (RhoEq),
+ * (DebyeHuckel), (BoundaryCond)) by pseudo-time stepping of Eq.
+ * (TimeDepNPB) with the splitting scheme params->scheme (Sec. 3.1-3.3;
+ * Eq. (SpatialOperators) in space, Eq. (ana3) for the nonlinear part),
+ * then the energies of Sec. 5.3 (Eq. (deltaG) per run, Eq. (rich) across
+ * dt and dt/2, Eq. (deltaG3) across the media).  Enqueues setup (solute
+ * mask, trilinear charges of Sec. 3.1, boundary data of Eq.
+ * (BoundaryCond)), the time loops, the FP64 energy reductions and
  * combinations on `stream`, then waits for that stream and fills *out.
  * The device work is captured once as a graph and replayed (see
  * npb_ctx_set_graph), except explicit Euler runs of more than 4096 step
@@ -294,7 +300,8 @@ npb_status npb_solve(npb_ctx* ctx, const npb_molecule* mol, const npb_grid* grid
                      const npb_params* params, void* d_ws, size_t ws_bytes,
                      double* d_field_out, void* stream, npb_result* out);
 
-/* npb_solve without the final wait: the device work and a last kernel that
+/* npb_solve without the final wait (the same operation: Sec. 2.1, the
+ * scheme of Sec. 3, the energies of Sec. 5.3): the device work and a last kernel that
  * writes the result are enqueued on `stream`, and the call returns.
  * pinned_out must be page-locked host memory the device can write (e.g.
  * hipHostMalloc, or a torch tensor with pin_memory); it holds the result
@@ -307,8 +314,9 @@ npb_status npb_solve_async(npb_ctx* ctx, const npb_molecule* mol, const npb_grid
                            double* d_field_out, void* stream, npb_result* pinned_out);
 
 /* Solve n independent problems together (molecules, grids and parameters
- * may all differ; one precision per batch).  Same semantics per problem as
- * npb_solve: problem i uses workspace d_ws[i] (ws_bytes[i] bytes, at least
+ * may all differ; one precision per batch).  Each problem is the operation
+ * of npb_solve (Sec. 2.1; the scheme of Sec. 3; the energies of Sec. 5.3),
+ * with the same semantics: problem i uses workspace d_ws[i] (ws_bytes[i] bytes, at least
  * npb_workspace_bytes of that problem, 256-byte aligned, no two problems
  * sharing one) and writes its field to d_field_out[i] when d_field_out is
  * not NULL and that entry is not NULL.  Every run of every problem advances
@@ -326,7 +334,8 @@ npb_status npb_solve_batch(npb_ctx* ctx, int n, const npb_molecule* mols,
 /* ---- no device allocation ------------------------------------------------
  * For callers that cannot allocate device memory at call time (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
- * npb_solve without a workspace argument.  The problem's workspace and its
+ * npb_solve (Sec. 2.1; the scheme of Sec. 3; the energies of Sec. 5.3)
+ * without a workspace argument.  The problem's workspace and its
  * launch tables live in a static device array of NPB_NOALLOC_BYTES that the
  * library's code object carries (each device the library runs on holds its
  * own copy until the process ends); the atoms are staged through pageable
@@ -425,7 +434,9 @@ typedef struct npb_server_stats {
 npb_status npb_server_create(npb_ctx* ctx, size_t hbm_budget, int max_batch, int max_queue,
                              npb_server** out);
 
-/* Queue one request; the molecule arrays are copied before returning.
+/* Queue one request: the solve of npb_solve (Sec. 2.1; the scheme of
+ * Sec. 3; the energies of Sec. 5.3, Eqs. (rich) and (deltaG3)) for this
+ * molecule, grid and parameters; the molecule arrays are copied before returning.
  * *ticket identifies it for npb_poll.  Errors: EINVAL / ERANGE (the checks
  * of npb_validate), EBUSY (its workspace exceeds the arena, or the queue is
  * full: admission refused). */
@@ -433,11 +444,13 @@ npb_status npb_submit(npb_server* server, const npb_molecule* mol, const npb_gri
                       const npb_params* params, uint64_t* ticket);
 
 /* *done = 0 while the request is queued or running.  Once done: *done = 1,
- * *out holds its result, the ticket is released, and the return value is
+ * *out holds its result (the energies of Sec. 5.3 as npb_solve reports them), the ticket is released, and the return value is
  * the request's own status (NPB_OK, EDIVERGED, or the batch's device
  * error).  Unknown or released ticket: EINVAL. */
 npb_status npb_poll(npb_server* server, uint64_t ticket, npb_result* out, int* done);
 
+/* Counters and latency percentiles of the request loop (host bookkeeping;
+ * no operation of the paper). */
 npb_status npb_server_get_stats(npb_server* server, npb_server_stats* out);
 
 /* Clear the counters and the latency record (e.g. after a warm-up or a

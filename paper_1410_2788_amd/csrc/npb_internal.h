@@ -365,9 +365,6 @@ hipError_t launch_field_init(T* u, const double* bc, int nx, int nxp, int ny, in
 template <typename T>
 hipError_t launch_field_from_dense(T* u, const double* src, int nx, int nxp, int ny, int nz,
                                    hipStream_t st);
-template <typename T>
-hipError_t launch_energy(const T* u, const int* q_idx, const double* q_val, const int* nq_dev,
-                         int cap, double* slot, hipStream_t st);
 // dense out[nz][ny][nx] = beta * out + gamma * u (pitched u)
 template <typename T>
 hipError_t launch_field_out(double* out, const T* u, int nx, int nxp, int ny, int nz, double beta,

@@ -245,32 +245,6 @@ hipError_t launch_field_from_dense(T* u, const double* src, int nx, int nxp, int
   return hipGetLastError();
 }
 
-// S = sum_k q_k u[idx_k] in double, fixed order (one block, tree reduction)
-template <typename T>
-__global__ __launch_bounds__(1024) void energy_kernel(const T* u, const int* q_idx,
-                                                      const double* q_val, const int* nq_dev,
-                                                      double* slot) {
-  __shared__ double part[1024];
-  const int nq = *nq_dev;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nq; k += 1024) s += q_val[k] * (double)u[q_idx[k]];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *slot = part[0];
-}
-
-template <typename T>
-hipError_t launch_energy(const T* u, const int* q_idx, const double* q_val, const int* nq_dev,
-                         int /*cap*/, double* slot, hipStream_t st) {
-  hipLaunchKernelGGL((energy_kernel<T>), dim3(1), dim3(1024), 0, st, u, q_idx, q_val, nq_dev,
-                     slot);
-  return hipGetLastError();
-}
-
 template <typename T>
 __global__ void field_out_kernel(double* out, const T* u, int nx, int nxp, long long n,
                                  double beta, double gamma) {
