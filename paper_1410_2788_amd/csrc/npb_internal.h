@@ -337,9 +337,11 @@ hipError_t launch_axis_keys(const int* q_idx, const int* nq_dev, int cap, int nx
 hipError_t launch_gather_entries(const int* id, const int* nq_dev, int cap, const int* q_idx,
                                  const double* q_rho, int* lin_out, double* rho_out,
                                  hipStream_t st);
-// Dirichlet values of the solvated (eps_s, kappa) and, if bc_v is not null,
-// the vacuum (eps_v, no screening) medium on the outer shell, in shell
-// order.  fp32_terms: per-pair terms in FP32 (sums stay FP64).
+// Dirichlet values of the solvated (eps_s, kappa; into bc_s) and the vacuum
+// (eps_v, no screening; into bc_v) medium on the outer shell, in shell
+// order; a null pointer skips that medium (either medium's values do not
+// depend on whether the other is computed in the same launch).
+// fp32_terms: per-pair terms in FP32 (sums stay FP64).
 hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, double eps_v,
                            double lB, double* bc_s, double* bc_v, bool fp32_terms,
                            hipStream_t st);

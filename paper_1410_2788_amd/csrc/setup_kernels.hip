@@ -586,27 +586,32 @@ constexpr int kBcGroups = 64, kBcSlices = 4, kBcK = 8;
 
 template <typename R>
 struct BcPair;
+// One atom-node pair: ts += q e^{-kappa d} / d (solvated, kMedia bit 0),
+// tv += q / d (vacuum, bit 1).  Either medium alone does the same arithmetic
+// as both together, so its sums are bit-identical.
 template <>
 struct BcPair<float> {
-  // c = -kappa log2(e); ts += q e^{-kappa d} / d, tv += q / d
+  // c = -kappa log2(e)
+  template <int kMedia>
   static __device__ __forceinline__ void add(float d2, float q, float c, float& ts, float& tv) {
     const float ri = __builtin_amdgcn_rsqf(d2);
     const float t = q * ri;
-    tv += t;
-    ts = fmaf(t, __builtin_amdgcn_exp2f(c * (d2 * ri)), ts);
+    if constexpr ((kMedia & 2) != 0) tv += t;
+    if constexpr ((kMedia & 1) != 0) ts = fmaf(t, __builtin_amdgcn_exp2f(c * (d2 * ri)), ts);
   }
 };
 template <>
 struct BcPair<double> {
   // c = -kappa
+  template <int kMedia>
   static __device__ __forceinline__ void add(double d2, double q, double c, double& ts,
                                              double& tv) {
     double ri = __builtin_amdgcn_rsq(d2);
     ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
     ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
     const double t = q * ri;
-    tv += t;
-    ts = fma(t, exp_neg(c * (d2 * ri)), ts);
+    if constexpr ((kMedia & 2) != 0) tv += t;
+    if constexpr ((kMedia & 1) != 0) ts = fma(t, exp_neg(c * (d2 * ri)), ts);
   }
 };
 
@@ -620,7 +625,8 @@ __device__ __forceinline__ BcSeg bc_segments(int nx, int ny, int nz) {
   return BcSeg{2LL * ny * sx, 2LL * (nz - 2) * sx, 2LL * (nz - 2) * sy};
 }
 
-template <typename R>
+// kMedia: 1 solvated values only, 2 vacuum only, 3 both
+template <typename R, int kMedia>
 __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double scale_s,
                                                             double c_exp, double scale_v,
                                                             double* bc_s, double* bc_v) {
@@ -707,7 +713,7 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
 #pragma unroll
         for (int q = 0; q < kBcK; ++q) {
           const R dv = V[q] - av;
-          BcPair<R>::add(dv * dv + b2, at.w, c, ps[q], pv[q]);
+          BcPair<R>::template add<kMedia>(dv * dv + b2, at.w, c, ps[q], pv[q]);
         }
       }
 #pragma unroll
@@ -720,8 +726,8 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
   }
 #pragma unroll
   for (int t = 0; t < kBcK; ++t) {
-    rs[sl][g * kBcK + t] = acc_s[t];
-    rv[sl][g * kBcK + t] = acc_v[t];
+    if constexpr ((kMedia & 1) != 0) rs[sl][g * kBcK + t] = acc_s[t];
+    if constexpr ((kMedia & 2) != 0) rv[sl][g * kBcK + t] = acc_v[t];
   }
   __syncthreads();
   if (sl == 0) {
@@ -735,11 +741,11 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
       double ts = 0.0, tv = 0.0;
 #pragma unroll
       for (int q = 0; q < kBcSlices; ++q) {
-        ts += rs[q][g * kBcK + t];
-        tv += rv[q][g * kBcK + t];
+        if constexpr ((kMedia & 1) != 0) ts += rs[q][g * kBcK + t];
+        if constexpr ((kMedia & 2) != 0) tv += rv[q][g * kBcK + t];
       }
-      bc_s[si] = scale_s * ts;
-      if (bc_v) bc_v[si] = scale_v * tv;
+      if constexpr ((kMedia & 1) != 0) bc_s[si] = scale_s * ts;
+      if constexpr ((kMedia & 2) != 0) bc_v[si] = scale_v * tv;
     }
   }
 }
@@ -751,11 +757,27 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
   const long long nseg = 2LL * a.ny * sx + 2LL * (a.nz - 2) * sx + 2LL * (a.nz - 2) * sy;
   const dim3 g((unsigned)((nseg + kBcGroups - 1) / kBcGroups)), b(kBcGroups * kBcSlices);
   const double ss = lB / eps_s, sv = lB / eps_v;
-  if (fp32_terms)
-    hipLaunchKernelGGL(boundary_rows_kernel<float>, g, b, 0, st, a, ss, -kappa * 1.4426950408889634,
-                       sv, bc_s, bc_v);
-  else
-    hipLaunchKernelGGL(boundary_rows_kernel<double>, g, b, 0, st, a, ss, -kappa, sv, bc_s, bc_v);
+  const int media = (bc_s ? 1 : 0) | (bc_v ? 2 : 0);
+  const double cf = fp32_terms ? -kappa * 1.4426950408889634 : -kappa;
+  if (media == 0) return hipSuccess;
+#define NPB_BC_LAUNCH(R, M) \
+  hipLaunchKernelGGL((boundary_rows_kernel<R, M>), g, b, 0, st, a, ss, cf, sv, bc_s, bc_v)
+  if (fp32_terms) {
+    if (media == 3)
+      NPB_BC_LAUNCH(float, 3);
+    else if (media == 1)
+      NPB_BC_LAUNCH(float, 1);
+    else
+      NPB_BC_LAUNCH(float, 2);
+  } else {
+    if (media == 3)
+      NPB_BC_LAUNCH(double, 3);
+    else if (media == 1)
+      NPB_BC_LAUNCH(double, 1);
+    else
+      NPB_BC_LAUNCH(double, 2);
+  }
+#undef NPB_BC_LAUNCH
   return hipGetLastError();
 }
 
