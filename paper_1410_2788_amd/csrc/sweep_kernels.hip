@@ -498,13 +498,35 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   const bool uniform = (a.mask == nullptr);
   const bool aos = (a.mode == MODE_AOS_FIRST);
   const int tid = threadIdx.x;
+  // Line l is interior row y = l % nyi of interior plane zi = l / nyi.  The
+  // block's first line is split once (block-uniform); line l0 + q then has
+  // t = yb + q < nyi + L, whose quotient by nyi comes from a float
+  // reciprocal estimate (off by at most one below, for t a multiple of nyi)
+  // and one correction, branch-free, so no lane runs an integer division.
+  const int zb = l0 / nyi, yb = l0 - zb * nyi;
+  const float rnyi = 1.0f / (float)nyi;
+  auto line_yz = [&](int q, int& yi, int& zi) {
+    const int t = yb + q;
+    int w = (int)((float)t * rnyi);
+    int r = t - w * nyi;
+    if (r < 0) {
+      r += nyi;
+      --w;
+    }
+    if (r >= nyi) {
+      r -= nyi;
+      ++w;
+    }
+    yi = r;
+    zi = zb + w;
+  };
   // element offset of node 0 of block row q (line l0 + q), -1 past the last
   // line; offsets fit in 32 bits (n <= 514)
   auto row_base = [&](int q) -> int {
-    const int l = l0 + q;
-    if (q >= L || l >= nlines) return -1;
-    const int zi = l / nyi;
-    return ((1 + zi) * ny + 1 + (l - zi * nyi)) * nxp;
+    if (q >= L || l0 + q >= nlines) return -1;
+    int yi, zi;
+    line_yz(q, yi, zi);
+    return ((1 + zi) * ny + 1 + yi) * nxp;
   };
 
   size_t off = 16;
@@ -570,8 +592,9 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
       }
     }
     if (gr_line) {
-      const int l = l0 + tid, zi = l / nyi;
-      const int s = 2 * nx * ny + zi * (2 * nx + 2 * nyi) + 2 * nx + 2 * (l - zi * nyi) + 1;
+      int yi, zi;
+      line_yz(tid, yi, zi);
+      const int s = 2 * nx * ny + zi * (2 * nx + 2 * nyi) + 2 * nx + 2 * yi + 1;
       gRv = (A)(T)a.bcx[s];
     }
   };
