@@ -227,7 +227,10 @@ constexpr int kMaxChunk = 20;  // longest chunk compiled into the sweeps
 // (ga = -gam_k, al = -lam_k); rf_c, rf_l: gamma and leak of the reduced row
 // of x_0 (its alpha is re, or 0 with re added to the leak on a line's
 // first chunk); rl_a, rl_c, rl_l: alpha, gamma and leak of the reduced row
-// of x_{M-1}.  Computed in double by the leak recurrences of the sweeps.
+// of x_{M-1}.  rf_lt: leak of the reduced row of x_0 in a line's last chunk
+// when that chunk ends inside (its last real row kt = (nint - 1) mod M,
+// 1 <= kt <= M - 2, couples to the right Dirichlet node; its gamma is then
+// zero).  Computed in double by the leak recurrences of the sweeps.
 template <typename A>
 struct ChunkTab {
   A inv[2][kMaxChunk];
@@ -235,6 +238,7 @@ struct ChunkTab {
   A al[2][kMaxChunk];
   A re[2];
   A rf_c[2], rf_l[2], rl_a[2], rl_c[2], rl_l[2];
+  A rf_lt[2];
 };
 
 // Pick chunk length / chunk count and the block shape for a line length.
@@ -271,7 +275,7 @@ inline long long class_lines(int nx, int ny, int nz, int dir) {
 // Elimination constants for chunks of M rows whose faces all carry re_t
 // (t = 0: solvent or uniform medium, t = 1: solute), computed in double.
 template <typename A>
-void fill_chunk_tab(ChunkTab<A>& tb, double re_solvent, double re_solute, int M);
+void fill_chunk_tab(ChunkTab<A>& tb, double re_solvent, double re_solute, int M, int nint);
 
 // A sweep launch covers any set of fields (of any grids) that share a
 // launch shape: args is a device array of per-field arguments, already

@@ -1120,10 +1120,11 @@ struct Engine {
         for (int d = 0; d < 3; ++d) {
           ChunkTab<A>& tb =
               *reinterpret_cast<ChunkTab<A>*>(hb + P.tabs_pinned + kTabBytes * (3 * r + d));
+          const int nint = (d == 0 ? P.g->nx : d == 1 ? P.g->ny : P.g->nz) - 2;
           if (c.vacuum)
-            fill_chunk_tab(tb, c.re_uniform, c.re_uniform, P.L.shape[d].M);
+            fill_chunk_tab(tb, c.re_uniform, c.re_uniform, P.L.shape[d].M, nint);
           else
-            fill_chunk_tab(tb, c.re[0], c.re[2], P.L.shape[d].M);
+            fill_chunk_tab(tb, c.re[0], c.re[2], P.L.shape[d].M, nint);
         }
       }
       NPB_HIP(hipMemcpyAsync(P.ws + P.L.tabs, hb + P.tabs_pinned, kTabBytes * 3 * P.L.n_runs,
@@ -1784,10 +1785,11 @@ npb_status autotune_t(npb_ctx* ctx, std::vector<Problem>& pr, hipStream_t st,
           const Coefs c = run_coefs(P, P.L.runs[r]);
           ChunkTab<A>& tb =
               *reinterpret_cast<ChunkTab<A>*>(hb + P.tabs_pinned + kTabBytes * (3 * r + d));
+          const int nint = (d == 0 ? P.g->nx : d == 1 ? P.g->ny : P.g->nz) - 2;
           if (c.vacuum)
-            fill_chunk_tab(tb, c.re_uniform, c.re_uniform, sh.M);
+            fill_chunk_tab(tb, c.re_uniform, c.re_uniform, sh.M, nint);
           else
-            fill_chunk_tab(tb, c.re[0], c.re[2], sh.M);
+            fill_chunk_tab(tb, c.re[0], c.re[2], sh.M, nint);
           NPB_HIP(hipMemcpyAsync(P.ws + P.L.tabs + kTabBytes * (3 * r + d),
                                  hb + P.tabs_pinned + kTabBytes * (3 * r + d), kTabBytes,
                                  hipMemcpyHostToDevice, st));

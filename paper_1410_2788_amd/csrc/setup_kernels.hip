@@ -805,7 +805,10 @@ hipError_t launch_shell_from_dense(const double* u0, int nx, int ny, int nz, dou
 
 // Face class of every (chunk, line) of one sweep direction: 0 if all nodes
 // from the chunk's left neighbour to its right neighbour are solvent, 2 if
-// all are solute, 1 otherwise (and for chunks that reach the line end).
+// all are solute, 1 otherwise.  A line's last chunk, which ends at the last
+// interior node or before the chunk's end, is classed by the nodes up to
+// the right Dirichlet node (a chunk with no interior row past its first
+// stays 1).
 // Face rule by location (face_loc): 0 / 2 if the chunk's M + 1 half points
 // (bit 1 of the flags of the left neighbour .. the last row) are all
 // solvent / all solute.  Lines are numbered as class_lines describes.
@@ -830,7 +833,9 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny,
     stride = (dir == 1) ? nxp : (long long)nxp * ny;
     n = (dir == 1) ? ny : nz;
   }
-  const int j0 = p * M, j1 = p * M + M + 1;
+  const int j0 = p * M;
+  int j1 = p * M + M + 1;
+  if (j1 > n - 1 && j0 + 2 <= n - 2) j1 = n - 1;  // the last chunk: up to the Dirichlet node
   uint8_t c = 1;
   if (dir == 0 && j1 <= n - 1) {
     // x-lines: the chunk's bytes j0 .. j1 of one row, read as the 32-bit

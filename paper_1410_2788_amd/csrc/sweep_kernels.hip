@@ -279,26 +279,51 @@ __device__ __forceinline__ void cn_tile_rows(A* v, int vs, const uint8_t* f, int
 // right-hand side is eliminated.  tb: the table, t: its row (solvent /
 // solute).  The first chunk of a line has its left Dirichlet coupling in
 // the leak of row 0.
+//
+// A line's last chunk (tail: its last real row kt = (nint - 1) mod M, the
+// same for every line of the block, 1 <= kt <= M - 1, not also the first
+// chunk) takes the same path.  Row kt's right face goes to the Dirichlet
+// node gR: the caller has added re gR to that row's value, and row kt's
+// gamma drops to zero while its pivot stays (leak 1 + re and gamma 0 sum to
+// the same diagonal).  For kt = M - 1 that changes only the reduced row of
+// x_{M-1}: gamma 0, leak rl_l + rl_c.  For kt < M - 1 the rows past kt are
+// identity rows: the reduced row of x_{M-1} is the identity (decoupled; its
+// value and the rows past kt are never stored), the reduced row of x_0 has
+// gamma 0 and the tabulated leak rf_lt, and the recurrences that run down
+// through row kt drop its coupling to row kt + 1.  kt is block-uniform, so
+// the row test is a scalar branch.
 template <typename A, int M, typename TB>
 __device__ __forceinline__ void fast_eliminate(A (&d)[M], const TB& tb, int t, bool first,
-                                               RRow<A>& rf, RRow<A>& rl) {
+                                               bool tail, int kt, RRow<A>& rf, RRow<A>& rl) {
   const A re = tb.re[t];
   d[1] = d[1] * tb.inv[t][1];
 #pragma unroll
   for (int k = 2; k < M; ++k) d[k] = fma(re, d[k - 1], d[k]) * tb.inv[t][k];
-  rl = RRow<A>{tb.rl_a[t], tb.rl_c[t], tb.rl_l[t], d[M - 1]};
+  const bool tail_in = tail && kt < M - 1;
+  rl = RRow<A>{tail_in ? A(0) : tb.rl_a[t], tail ? A(0) : tb.rl_c[t],
+               tail_in ? A(1) : (tail ? tb.rl_l[t] + tb.rl_c[t] : tb.rl_l[t]), d[M - 1]};
   A dp = d[M - 2];
 #pragma unroll
-  for (int k = M - 3; k >= 1; --k) dp = fma(-tb.ga[t][k], dp, d[k]);
-  rf = RRow<A>{first ? A(0) : re, tb.rf_c[t], first ? tb.rf_l[t] + re : tb.rf_l[t],
+  for (int k = M - 3; k >= 1; --k) {
+    const A g = tb.ga[t][k];
+    dp = fma(k == kt ? (tail ? A(0) : -g) : -g, dp, d[k]);
+  }
+  const A lf = tail_in ? tb.rf_lt[t] : tb.rf_l[t];
+  rf = RRow<A>{first ? A(0) : re, tail_in ? A(0) : tb.rf_c[t], first ? lf + re : lf,
                fma(re, dp, d[0])};
 }
 
+// back substitution of a uniform chunk (a tail chunk as in fast_eliminate:
+// row kt takes nothing from row kt + 1)
 template <typename A, int M, typename Ptr>
-__device__ __forceinline__ void fast_finish(A (&d)[M], Ptr ga, Ptr al, A xf, A xl) {
+__device__ __forceinline__ void fast_finish(A (&d)[M], Ptr ga, Ptr al, A xf, A xl, bool tail,
+                                            int kt) {
   d[M - 1] = xl;
 #pragma unroll
-  for (int k = M - 2; k >= 1; --k) d[k] = fma(-ga[k], d[k + 1], fma(-al[k], xf, d[k]));
+  for (int k = M - 2; k >= 1; --k) {
+    const A g = ga[k];
+    d[k] = fma(k == kt ? (tail ? A(0) : -g) : -g, d[k + 1], fma(-al[k], xf, d[k]));
+  }
   d[0] = xf;
 }
 
@@ -577,6 +602,11 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   // the two z faces, then per interior z the y = 0 and y = ny-1 rows and
   // the x = 0, nx-1 pairs of each interior y).
   const bool gr_line = nxl < nx && tid < L && l0 + tid < nlines;
+  // the chunk class of lane (line tid % L, chunk tid / L), fetched ahead of
+  // the rows so that its latency overlaps theirs
+  int cls = 1;
+  if (l0 + tid % L < nlines)
+    cls = uniform ? 0 : (a.ccls ? (int)a.ccls[(size_t)(tid / L) * nlines + (l0 + tid % L)] : 1);
   A gRv = A(0);
   bool first_batch = true;
   // with the first batch of row loads in flight: the source entries and
@@ -696,31 +726,36 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   A* trow = tile + ql * S;
   A* col = trow + 1 + g0;  // row element of interior node g0 + k at col[k]
   const uint8_t* mrow = mt + ql * nx4;
+  const A gL = trow[0];
+  const A gR = trow[nx - 1];
+  const bool first = (g0 == 0);
+  const int kR = lvalid ? nint - 1 - g0 : -1;
+  // a line's last chunk (1 <= kR <= M - 1) takes the uniform path too,
+  // unless the explicit Crank-Nicolson half is formed in registers here
+  const int kt = (nint - 1) % M;
+  const bool tail = kR >= 1 && kR < M && !first && !(CN && a.cn == 1);
+  // lanes without a line follow whatever path their wave takes
+  const bool inner = cls != 1 && (kR >= M || tail);
+  const unsigned long long bv = __ballot(lvalid);
+  const unsigned long long bf = __ballot(lvalid && inner);
+  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
+  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
+  const int t = __builtin_amdgcn_readfirstlane((fast && bs != 0) ? 1 : 0);
+  // uniform tail chunk: the right Dirichlet term into the last real row
+  // (an LDS update of the lane's own node; the row is overwritten below)
+  if (fast && tail && lvalid) col[kR] = fma(tb.re[t], gR, col[kR]);
   A d[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     const A v = col[k];
     d[k] = (lvalid && g0 + k < nint) ? v : A(0);
   }
-  const A gL = trow[0];
-  const A gR = trow[nx - 1];
-  const bool first = (g0 == 0);
-  const int kR = lvalid ? nint - 1 - g0 : -1;
-  int cls = 1;
-  if (lvalid) cls = uniform ? 0 : (a.ccls ? (int)a.ccls[(size_t)p * nlines + (l0 + ql)] : 1);
-  // lanes without a line follow whatever path their wave takes
-  const bool inner = cls != 1 && kR >= M;
-  const unsigned long long bv = __ballot(lvalid);
-  const unsigned long long bf = __ballot(lvalid && inner);
-  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
-  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
-  const int t = __builtin_amdgcn_readfirstlane((fast && bs != 0) ? 1 : 0);
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
     if (CN && a.cn == 1) cn_rhs_uniform<A, M>(d, tb.re[t], col[-1], col[M]);
     if (first) d[0] = fma(tb.re[t], gL, d[0]);
-    fast_eliminate<A, M>(d, tb, t, first, rf, rl);
+    fast_eliminate<A, M>(d, tb, t, first, tail, kt, rf, rl);
   } else {
     const A re0 = (A)(uniform ? a.re_uniform : a.re[0]);
     const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
@@ -757,7 +792,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   const A xf = R[(4 * (2 * p) + 3) * (L + 1)];
   const A xl = R[(4 * (2 * p + 1) + 3) * (L + 1)];
   if (fast)
-    fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl);
+    fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl, tail, kt);
   else
     chunk_finish<A, M>(d, al, ga, xf, xl);
   // results back into the row; a full chunk stores without per-row checks.
@@ -830,30 +865,37 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
   const int g0 = p * M;
   A* col = tile + (1 + g0) * ts + ql;
   const uint8_t* mcol = mt + g0 * TW + ql;  // flag of along node g0 + k at mcol[k * TW]
+  const A gL = tile[ql];
+  const A gR = tile[(n - 1) * ts + ql];
+  const bool first = (g0 == 0);
+  const int kR = lvalid ? nint - 1 - g0 : -1;
+  // a line's last chunk (1 <= kR <= M - 1) takes the uniform path too,
+  // unless the explicit Crank-Nicolson half is formed in registers here
+  const int kt = (nint - 1) % M;
+  const bool tail = kR >= 1 && kR < M && !first && !(VAR == kYzGeneral && a.cn == 1);
+  // lanes without a line follow whatever path their wave takes
+  const bool inner = cls != 1 && (kR >= M || tail);
+  const unsigned long long bv = __ballot(lvalid);
+  const unsigned long long bf = __ballot(lvalid && inner);
+  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
+  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
+  const int t = __builtin_amdgcn_readfirstlane((fast && bs != 0) ? 1 : 0);
+  // uniform tail chunk: the right Dirichlet term into the last real row
+  // (an LDS update of the lane's own node; the row is overwritten below)
+  if (fast && tail && lvalid) col[kR * ts] = fma(tb.re[t], gR, col[kR * ts]);
   A d[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     const A v = col[k * ts];
     d[k] = (g0 + k < nint) ? v : A(0);
   }
-  const A gL = tile[ql];
-  const A gR = tile[(n - 1) * ts + ql];
-  const bool first = (g0 == 0);
-  const int kR = lvalid ? nint - 1 - g0 : -1;
-  // lanes without a line follow whatever path their wave takes
-  const bool inner = cls != 1 && kR >= M;
-  const unsigned long long bv = __ballot(lvalid);
-  const unsigned long long bf = __ballot(lvalid && inner);
-  const unsigned long long bs = __ballot(lvalid && inner && cls == 2);
-  const bool fast = bv != 0 && bf == bv && (bs == 0 || bs == bf);
-  const int t = __builtin_amdgcn_readfirstlane((fast && bs != 0) ? 1 : 0);
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
     if (VAR == kYzGeneral && a.cn == 1)
       cn_rhs_uniform<A, M>(d, tb.re[t], col[-ts], col[M * ts]);
     if (first) d[0] = fma(tb.re[t], gL, d[0]);
-    fast_eliminate<A, M>(d, tb, t, first, rf, rl);
+    fast_eliminate<A, M>(d, tb, t, first, tail, kt, rf, rl);
   } else {
     const A re0 = (A)(uniform ? a.re_uniform : a.re[0]);
     const A re1 = (A)(uniform ? a.re_uniform : a.re[1]);
@@ -890,7 +932,7 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
   const A xf = R[(4 * (2 * p) + 3) * (TW + 1)];
   const A xl = R[(4 * (2 * p + 1) + 3) * (TW + 1)];
   if (fast)
-    fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl);
+    fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl, tail, kt);
   else
     chunk_finish<A, M>(d, al, ga, xf, xl);
 
@@ -995,6 +1037,10 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
     fetch = false;
   };
 
+  // the lane's chunk class, fetched ahead of the rows so that its latency
+  // overlaps theirs
+  const int cls = yz_chunk_class<T, TW>(a, dir, o, xb, tid);
+
   // Node-row traffic: thread = (vector column cv, first row jr); rows step
   // by RS = nthreads / VPR.  Columns past row4(nx) stay untouched.
   const int cv = tid % VPR;
@@ -1073,7 +1119,6 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
     __syncthreads();
   }
 
-  const int cls = yz_chunk_class<T, TW>(a, dir, o, xb, tid);
   yz_solve_lines<T, A, M, VAR, TW>(a, tile, TS, mt, red, n, xb, cls, tid);
   __syncthreads();
   if (VAR == kYzGeneral && a.src_stage == 2) {
@@ -1214,7 +1259,7 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw)
 // Elimination constants of uniform chunks of M rows with face coefficient
 // re: the leak recurrences of chunk_eliminate in double, stored in A.
 template <typename A>
-static void fill_tab_row(ChunkTab<A>& tb, int t, double re, int M) {
+static void fill_tab_row(ChunkTab<A>& tb, int t, double re, int M, int nint) {
   double inv[kMaxChunk] = {0}, ga[kMaxChunk] = {0}, al[kMaxChunk] = {0};
   double lam = 1.0, tau = 0.0, s = 0.0, G = 1.0;
   for (int k = 1; k < M; ++k) {
@@ -1243,16 +1288,33 @@ static void fill_tab_row(ChunkTab<A>& tb, int t, double re, int M) {
   tb.re[t] = (A)re;
   tb.rf_c[t] = (A)(re * G);
   tb.rf_l[t] = (A)(1.0 + re * s);
+  // a line's last chunk ending at row kt < M - 1: the same rows up to kt,
+  // whose right face goes to the Dirichlet node (gamma 0, leak 1 + re);
+  // the rows past kt are identity rows and add nothing
+  const int kt = nint >= 1 ? (nint - 1) % M : 0;
+  tb.rf_lt[t] = tb.rf_l[t];
+  if (kt >= 1 && kt <= M - 2) {
+    double lm = 1.0, ta = 0.0, st = 0.0, Gt = 1.0;
+    for (int k = 1; k <= kt; ++k) {
+      const double iv = 1.0 / (1.0 + re + re * (ta + lm));
+      lm = re * lm * iv;
+      const double gm = k == kt ? 0.0 : re * iv;
+      ta = (1.0 + (k == kt ? re : 0.0) + re * ta) * iv;
+      st += ta * Gt;
+      Gt *= gm;
+    }
+    tb.rf_lt[t] = (A)(1.0 + re * st);
+  }
 }
 
 template <typename A>
-void fill_chunk_tab(ChunkTab<A>& tb, double re_solvent, double re_solute, int M) {
+void fill_chunk_tab(ChunkTab<A>& tb, double re_solvent, double re_solute, int M, int nint) {
   tb = ChunkTab<A>{};
-  fill_tab_row(tb, 0, re_solvent, M);
-  fill_tab_row(tb, 1, re_solute, M);
+  fill_tab_row(tb, 0, re_solvent, M, nint);
+  fill_tab_row(tb, 1, re_solute, M, nint);
 }
-template void fill_chunk_tab<float>(ChunkTab<float>&, double, double, int);
-template void fill_chunk_tab<double>(ChunkTab<double>&, double, double, int);
+template void fill_chunk_tab<float>(ChunkTab<float>&, double, double, int, int);
+template void fill_chunk_tab<double>(ChunkTab<double>&, double, double, int, int);
 
 template <typename T>
 void shape_args(SweepArgs<T>& a, int dir, const LaunchShape& s) {
