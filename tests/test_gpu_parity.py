@@ -147,6 +147,30 @@ def test_crank_nicolson_ragged_grid_fp64(scheme):
     _assert_f64(errs, fe)
 
 
+@pytest.mark.parametrize("precision,dims", [
+    ("f32", (42, 62, 50)),   # last chunks full (kt = M - 1) on x, y and z
+    ("f32", (51, 42, 62)),   # x: one-row last chunk (kt = 0, the general path)
+    ("f32", (52, 50, 34)),   # x: two-row last chunk (kt = 1)
+    ("f64", (42, 40, 39)),   # x full, y kt = 1, z kt = 0
+    ("f64", (52, 38, 51)),   # x kt = 1, y full, z kt = 0
+])
+def test_last_chunk_lengths(precision, dims):
+    """A line's last chunk on the tabulated path (uniform chunks, including
+    the uniform vacuum runs) and on the general path, for the last-chunk
+    lengths kt + 1 that the grid sizes give on each axis."""
+    npb = _npb()
+    nx, ny, nz = dims
+    w = inputs.small_globular(n=nx, ny=ny, nz=nz, n_atoms=60, n_steps=3, precision=precision)
+    shapes = npb.npb_launch_shapes(None, npb.make_grid(w.grid), npb.make_params(w.params))
+    kts = [((n - 3) % shapes[d][0], shapes[d][0]) for d, n in enumerate(dims)]
+    _say("last-chunk rows (kt, M) per axis:", kts)
+    g, o, errs, fe = _compare(w)
+    if precision == "f64":
+        _assert_f64(errs, fe)
+    else:
+        _assert_f32(errs, fe)
+
+
 def test_long_lines_many_chunks_fp64():
     # 131 nodes: 7 chunks per y/z line, 8 chunk slots on x
     w = inputs.small_globular(n=131, ny=21, nz=23, n_atoms=60, n_steps=2, richardson=False)
