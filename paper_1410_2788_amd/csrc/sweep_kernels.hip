@@ -927,7 +927,17 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
   A* R = red + ql;
   put_reduced(R, TW + 1, p, rf, rl);
   __syncthreads();
-  if (p == 0 && lvalid) reduced_solve(R, 2 * P, TW + 1);
+  // reduced systems: in FP32 arithmetic with a power-of-two chunk count the
+  // block's lanes solve them together by cyclic reduction (the P lanes of a
+  // line in one wave, as in the x sweep); otherwise one lane per line runs
+  // Thomas (FP64 keeps only Thomas: the cyclic reduction's registers would
+  // cost its kernels a wave per SIMD)
+  bool pcr = false;
+  if constexpr (sizeof(A) == 4) pcr = (P & (P - 1)) == 0 && P <= 64;
+  if (pcr)
+    pcr_reduced(red, TW + 1, P, tid);
+  else if (p == 0 && lvalid)
+    reduced_solve(R, 2 * P, TW + 1);
   __syncthreads();
   const A xf = R[(4 * (2 * p) + 3) * (TW + 1)];
   const A xl = R[(4 * (2 * p + 1) + 3) * (TW + 1)];
