@@ -32,6 +32,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "npb_internal.h"
 
@@ -628,7 +629,13 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
       gRv = (A)(T)a.bcx[s];
     }
   };
-  {
+  // When RQ is a multiple of L (P a multiple of 8), every item of a lane
+  // lies in the same block row q = rq mod L: its row base is then found once
+  // (a block-uniform choice between two compiled forms of the loops).
+  const bool qfix = (RQ % L) == 0;
+  auto load_rows = [&](auto fixq) {
+    constexpr bool kFix = decltype(fixq)::value;
+    const int rb0 = kFix ? row_base(rq % L) : 0;
     constexpr int kU = 8;
     for (int w0 = rq; w0 < nitems; w0 += kU * RQ) {
       T v[kU][VX];
@@ -639,9 +646,9 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
         lo[j] = -1;
         const int w = w0 + j * RQ;
         if (w < nitems) {
-          const int q = w % L, g = w / L;
+          const int q = kFix ? rq % L : w % L, g = w / L;
           const int c = (cv + 8 * g) * VX;
-          const int rb = row_base(q);
+          const int rb = kFix ? rb0 : row_base(q);
           if (c < nx4 && rb >= 0) {
             lo[j] = c < nxl ? q * S + c : -1;
             mo[j] = q * nx4 + c;
@@ -669,10 +676,14 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
         }
       }
     }
-    // lanes without row items
-    if (first_batch) fetch_first();
-    if (gr_line) tile[tid * S + nx - 1] = gRv;
-  }
+  };
+  if (qfix)
+    load_rows(std::true_type{});
+  else
+    load_rows(std::false_type{});
+  // lanes without row items
+  if (first_batch) fetch_first();
+  if (gr_line) tile[tid * S + nx - 1] = gRv;
   __syncthreads();
 
   // pointwise pre-operations on interior nodes: AOS W = flow(u) and the
@@ -813,17 +824,25 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
 
   // row stores (boundary columns carry their loaded values), same lane map
   T* out = aos ? a.acc : a.u;
-  for (int w = rq; w < nitems; w += RQ) {
-    const int q = w % L, g = w / L;
-    const int c = (cv + 8 * g) * VX;
-    const int rb = row_base(q);
-    if (c < nxl && rb >= 0) {
-      T v[VX];
+  auto store_rows = [&](auto fixq) {
+    constexpr bool kFix = decltype(fixq)::value;
+    const int rb0 = kFix ? row_base(rq % L) : 0;
+    for (int w = rq; w < nitems; w += RQ) {
+      const int q = kFix ? rq % L : w % L, g = w / L;
+      const int c = (cv + 8 * g) * VX;
+      const int rb = kFix ? rb0 : row_base(q);
+      if (c < nxl && rb >= 0) {
+        T v[VX];
 #pragma unroll
-      for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c + i];
-      VecIO<T, VX>::st(out + rb + c, v);
+        for (int i = 0; i < VX; ++i) v[i] = (T)tile[q * S + c + i];
+        VecIO<T, VX>::st(out + rb + c, v);
+      }
     }
-  }
+  };
+  if (qfix)
+    store_rows(std::true_type{});
+  else
+    store_rows(std::false_type{});
 }
 
 // Face class of lane tid's chunk (line x = xb + tid % TW, chunk tid / TW)
