@@ -375,10 +375,74 @@ __device__ __forceinline__ RRow<A> shfl_row_down(const RRow<A>& r, int delta, in
                  __shfl_down(r.l, delta, width), __shfl_down(r.d, delta, width)};
 }
 
+// Neighbour exchange inside 16-lane rows by DPP row shifts (one VALU move a
+// 32-bit word): kUp takes lane i - D's value, else lane i + D's; a lane whose
+// source lies outside its row gets zero (the cyclic reduction replaces such
+// neighbours by identity rows).  Valid when a line's P lanes lie in one row
+// (P <= 16, lines at multiples of P).
+template <int D, bool kUp>
+__device__ __forceinline__ float dpp_shift(float v) {
+  constexpr int ctl = (kUp ? 0x110 : 0x100) | D;  // row_shr:D / row_shl:D
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctl, 0xf, 0xf, false));
+}
+template <int D, bool kUp>
+__device__ __forceinline__ double dpp_shift(double v) {
+  constexpr int ctl = (kUp ? 0x110 : 0x100) | D;
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), ctl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctl, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int D, bool kUp, typename A>
+__device__ __forceinline__ RRow<A> dpp_row(const RRow<A>& r) {
+  return RRow<A>{dpp_shift<D, kUp>(r.a), dpp_shift<D, kUp>(r.c), dpp_shift<D, kUp>(r.l),
+                 dpp_shift<D, kUp>(r.d)};
+}
+// one reduction step at lane distance E (row distance 2E), E a constant
+template <int E, typename A>
+__device__ __forceinline__ void pcr_step_dpp(RRow<A>& r0, RRow<A>& r1, int p, int P) {
+  if (E >= P) return;
+  RRow<A> u0 = dpp_row<E, true>(r0), u1 = dpp_row<E, true>(r1);
+  RRow<A> d0 = dpp_row<E, false>(r0), d1 = dpp_row<E, false>(r1);
+  if (p < E) u0 = u1 = rrow_identity<A>();
+  if (p + E >= P) d0 = d1 = rrow_identity<A>();
+  const RRow<A> n0 = pcr_combine(r0, u0, d0);
+  const RRow<A> n1 = pcr_combine(r1, u1, d1);
+  r0 = n0;
+  r1 = n1;
+}
+
 // Solve the reduced systems of all lines of the block (every thread takes
 // part); the solution overwrites the d coefficients.
 template <typename A>
 __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
+  if (P <= 16) {
+    // the same steps with DPP row shifts for the neighbour exchange
+    const int p = tid & (P - 1);
+    A* R = red + tid / P;
+    auto get = [&](int r) {
+      return RRow<A>{R[(4 * r) * rs], R[(4 * r + 1) * rs], R[(4 * r + 2) * rs],
+                     R[(4 * r + 3) * rs]};
+    };
+    RRow<A> r0 = get(2 * p), r1 = get(2 * p + 1);
+    {
+      RRow<A> up = dpp_row<1, true>(r1);
+      RRow<A> dn = dpp_row<1, false>(r0);
+      if (p == 0) up = rrow_identity<A>();
+      if (p == P - 1) dn = rrow_identity<A>();
+      const RRow<A> n0 = pcr_combine(r0, up, r1);
+      const RRow<A> n1 = pcr_combine(r1, r0, dn);
+      r0 = n0;
+      r1 = n1;
+    }
+    pcr_step_dpp<1>(r0, r1, p, P);
+    pcr_step_dpp<2>(r0, r1, p, P);
+    pcr_step_dpp<4>(r0, r1, p, P);
+    pcr_step_dpp<8>(r0, r1, p, P);
+    R[(4 * (2 * p) + 3) * rs] = r0.d * rcp_pivot(rrow_b(r0));
+    R[(4 * (2 * p + 1) + 3) * rs] = r1.d * rcp_pivot(rrow_b(r1));
+    return;
+  }
   const int p = tid & (P - 1);
   A* R = red + tid / P;
   auto get = [&](int r) {
