@@ -398,16 +398,36 @@ __device__ __forceinline__ RRow<A> dpp_row(const RRow<A>& r) {
   return RRow<A>{dpp_shift<D, kUp>(r.a), dpp_shift<D, kUp>(r.c), dpp_shift<D, kUp>(r.l),
                  dpp_shift<D, kUp>(r.d)};
 }
-// one reduction step at lane distance E (row distance 2E), E a constant
+// pcr_combine with the neighbours' diagonal reciprocals given (iu, id)
+template <typename A>
+__device__ __forceinline__ RRow<A> pcr_combine_r(const RRow<A>& r, const RRow<A>& up, A iu,
+                                                 const RRow<A>& dn, A id) {
+  const A k1 = r.a * iu;
+  const A k2 = r.c * id;
+  return RRow<A>{up.a * k1, dn.c * k2, fma(up.l, k1, fma(dn.l, k2, r.l)),
+                 fma(up.d, k1, fma(dn.d, k2, r.d))};
+}
+// one reduction step at lane distance E (row distance 2E), E a constant:
+// each lane forms the reciprocals of its own two rows' diagonals and passes
+// them on with the rows (identity neighbours: diagonal 1)
 template <int E, typename A>
 __device__ __forceinline__ void pcr_step_dpp(RRow<A>& r0, RRow<A>& r1, int p, int P) {
   if (E >= P) return;
+  const A b0 = rcp_pivot(rrow_b(r0)), b1 = rcp_pivot(rrow_b(r1));
   RRow<A> u0 = dpp_row<E, true>(r0), u1 = dpp_row<E, true>(r1);
   RRow<A> d0 = dpp_row<E, false>(r0), d1 = dpp_row<E, false>(r1);
-  if (p < E) u0 = u1 = rrow_identity<A>();
-  if (p + E >= P) d0 = d1 = rrow_identity<A>();
-  const RRow<A> n0 = pcr_combine(r0, u0, d0);
-  const RRow<A> n1 = pcr_combine(r1, u1, d1);
+  A iu0 = dpp_shift<E, true>(b0), iu1 = dpp_shift<E, true>(b1);
+  A id0 = dpp_shift<E, false>(b0), id1 = dpp_shift<E, false>(b1);
+  if (p < E) {
+    u0 = u1 = rrow_identity<A>();
+    iu0 = iu1 = A(1);
+  }
+  if (p + E >= P) {
+    d0 = d1 = rrow_identity<A>();
+    id0 = id1 = A(1);
+  }
+  const RRow<A> n0 = pcr_combine_r(r0, u0, iu0, d0, id0);
+  const RRow<A> n1 = pcr_combine_r(r1, u1, iu1, d1, id1);
   r0 = n0;
   r1 = n1;
 }
@@ -426,12 +446,20 @@ __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
     };
     RRow<A> r0 = get(2 * p), r1 = get(2 * p + 1);
     {
+      const A b0 = rcp_pivot(rrow_b(r0)), b1 = rcp_pivot(rrow_b(r1));
       RRow<A> up = dpp_row<1, true>(r1);
       RRow<A> dn = dpp_row<1, false>(r0);
-      if (p == 0) up = rrow_identity<A>();
-      if (p == P - 1) dn = rrow_identity<A>();
-      const RRow<A> n0 = pcr_combine(r0, up, r1);
-      const RRow<A> n1 = pcr_combine(r1, r0, dn);
+      A iu = dpp_shift<1, true>(b1), id = dpp_shift<1, false>(b0);
+      if (p == 0) {
+        up = rrow_identity<A>();
+        iu = A(1);
+      }
+      if (p == P - 1) {
+        dn = rrow_identity<A>();
+        id = A(1);
+      }
+      const RRow<A> n0 = pcr_combine_r(r0, up, iu, r1, b1);
+      const RRow<A> n1 = pcr_combine_r(r1, r0, b0, dn, id);
       r0 = n0;
       r1 = n1;
     }
