@@ -810,11 +810,31 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
                        (A)a.re[2], (A)a.re_uniform);
   }
   if (src) {
-    // entries are distinct nodes: the adds do not collide
+    // entries are distinct nodes: the adds do not collide.  Quotients by the
+    // pitch (a multiple of 16, entries below 514 * 514 * 544) and by ny
+    // (rows below 514 * ny) from float reciprocal estimates with one
+    // correction each way, exact over those ranges
+    const float rnxp = 1.0f / (float)nxp, rny = 1.0f / (float)ny;
+    auto divmod = [](int n, int dv, float rdv, int& qo, int& ro) {
+      int w = (int)((float)n * rdv);
+      int r = n - w * dv;
+      if (r < 0) {
+        r += dv;
+        --w;
+      }
+      if (r >= dv) {
+        r -= dv;
+        ++w;
+      }
+      qo = w;
+      ro = r;
+    };
     auto add_entry = [&](int lin, double rho) {
-      const int row = lin / nxp;
-      const int q = (row / ny - 1) * nyi + (row % ny - 1) - l0;
-      tile[q * S + (lin - row * nxp)] += (A)(a.src_coef * rho);
+      int row, x, zr, yr;
+      divmod(lin, nxp, rnxp, row, x);
+      divmod(row, ny, rny, zr, yr);
+      const int q = (zr - 1) * nyi + (yr - 1) - l0;
+      tile[q * S + x] += (A)(a.src_coef * rho);
     };
     if (e_lin >= 0) add_entry(e_lin, e_rho);
     for (int e = eb + tid + nthreads; e < ee; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
