@@ -922,14 +922,19 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   // Additive modes: acc = ww W + wv V (the weights of the mean)
   const A ww = (A)a.aos_ww, wv = (A)a.aos_wv;
   if (lvalid) {
-    if (g0 + M <= nint) {
+    if (!aos) {
+      if (g0 + M <= nint) {
 #pragma unroll
-      for (int k = 0; k < M; ++k)
-        col[k] = aos ? fma(ww, wtile[ql * S + 1 + g0 + k], wv * d[k]) : d[k];
+        for (int k = 0; k < M; ++k) col[k] = d[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+          if (g0 + k < nint) col[k] = d[k];
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < M; ++k)
-        if (g0 + k < nint) col[k] = aos ? fma(ww, wtile[ql * S + 1 + g0 + k], wv * d[k]) : d[k];
+        if (g0 + k < nint) col[k] = fma(ww, wtile[ql * S + 1 + g0 + k], wv * d[k]);
     }
   }
   __syncthreads();
@@ -1272,6 +1277,7 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   const int mode = (VAR == kYzGeneral) ? a.mode : MODE_INPLACE;
   T* out = (mode == MODE_AOS_ADD) ? a.acc : a.u;
   bool bad = false;
+  const bool chk = a.nonfinite != nullptr;
   if (cok) {
     uint32_t pt = base + (uint32_t)(1 + jr) * stride + (uint32_t)(cv * VX);
     for (int j = 1 + jr; j <= nint; j += RS, pt += rstep) {
@@ -1293,8 +1299,10 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
 #pragma unroll
         for (int i = 0; i < VX; ++i) w[i] = (T)tile[j * TS + cv * VX + i];
       }
+      if (chk) {
 #pragma unroll
-      for (int i = 0; i < VX; ++i) bad |= !isfinite(w[i]);
+        for (int i = 0; i < VX; ++i) bad |= !isfinite(w[i]);
+      }
       VecIO<T, VX>::st(out + pt, w);
     }
   }
