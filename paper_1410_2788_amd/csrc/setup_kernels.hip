@@ -625,8 +625,27 @@ __device__ __forceinline__ BcSeg bc_segments(int nx, int ny, int nz) {
   return BcSeg{2LL * ny * sx, 2LL * (nz - 2) * sx, 2LL * (nz - 2) * sy};
 }
 
-// kMedia: 1 solvated values only, 2 vacuum only, 3 both
-template <typename R, int kMedia>
+// e^y for |y| <= 0.1 by its Taylor polynomial to degree 9 (remainder below
+// 3e-17 relative)
+__device__ __forceinline__ double exp_small(double y) {
+  double p = 1.0 / 362880.0;
+  p = fma(p, y, 1.0 / 40320.0);
+  p = fma(p, y, 1.0 / 5040.0);
+  p = fma(p, y, 1.0 / 720.0);
+  p = fma(p, y, 1.0 / 120.0);
+  p = fma(p, y, 1.0 / 24.0);
+  p = fma(p, y, 1.0 / 6.0);
+  p = fma(p, y, 0.5);
+  p = fma(p, y, 1.0);
+  return fma(p, y, 1.0);
+}
+
+// kMedia: 1 solvated values only, 2 vacuum only, 3 both.  kChain (FP64
+// terms, kappa h <= 0.1): along a row the screening factor of node q + 1
+// is that of node q times e^{-kappa (d_{q+1} - d_q)}, |kappa (d_{q+1} - d_q)|
+// <= kappa h, from exp_small (relative error of the chain below 1e-14 over
+// the row's eight nodes, from the rounding of the distance differences)
+template <typename R, int kMedia, bool kChain = false>
 __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double scale_s,
                                                             double c_exp, double scale_v,
                                                             double* bc_s, double* bc_v) {
@@ -710,10 +729,31 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
         const R d1 = F1 - (vy ? at.x : at.y), d3 = F2 - at.z;
         const R b2 = d1 * d1 + d3 * d3;
         const R av = vy ? at.y : at.x;
+        if constexpr (kChain) {
+          double dprev = 0.0, eprev = 0.0;
 #pragma unroll
-        for (int q = 0; q < kBcK; ++q) {
-          const R dv = V[q] - av;
-          BcPair<R>::template add<kMedia>(dv * dv + b2, at.w, c, ps[q], pv[q]);
+          for (int q = 0; q < kBcK; ++q) {
+            const double dv = V[q] - av;
+            const double d2 = dv * dv + b2;
+            double ri = __builtin_amdgcn_rsq(d2);
+            ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
+            ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
+            const double t = at.w * ri;
+            if constexpr ((kMedia & 2) != 0) pv[q] += t;
+            if constexpr ((kMedia & 1) != 0) {
+              const double dist = d2 * ri;
+              const double e = q == 0 ? exp_neg(c * dist) : eprev * exp_small(c * (dist - dprev));
+              ps[q] = fma(t, e, ps[q]);
+              dprev = dist;
+              eprev = e;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < kBcK; ++q) {
+            const R dv = V[q] - av;
+            BcPair<R>::template add<kMedia>(dv * dv + b2, at.w, c, ps[q], pv[q]);
+          }
         }
       }
 #pragma unroll
@@ -762,6 +802,10 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
   if (media == 0) return hipSuccess;
 #define NPB_BC_LAUNCH(R, M) \
   hipLaunchKernelGGL((boundary_rows_kernel<R, M>), g, b, 0, st, a, ss, cf, sv, bc_s, bc_v)
+#define NPB_BC_LAUNCH_CHAIN(M) \
+  hipLaunchKernelGGL((boundary_rows_kernel<double, M, true>), g, b, 0, st, a, ss, cf, sv, bc_s, bc_v)
+  // FP64 terms: the row-chained screening factor when kappa h <= 0.1
+  const bool chain = !fp32_terms && kappa * a.h <= 0.1;
   if (fp32_terms) {
     if (media == 3)
       NPB_BC_LAUNCH(float, 3);
@@ -769,6 +813,11 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
       NPB_BC_LAUNCH(float, 1);
     else
       NPB_BC_LAUNCH(float, 2);
+  } else if (chain && (media & 1) != 0) {
+    if (media == 3)
+      NPB_BC_LAUNCH_CHAIN(3);
+    else
+      NPB_BC_LAUNCH_CHAIN(1);
   } else {
     if (media == 3)
       NPB_BC_LAUNCH(double, 3);
@@ -777,6 +826,7 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
     else
       NPB_BC_LAUNCH(double, 2);
   }
+#undef NPB_BC_LAUNCH_CHAIN
 #undef NPB_BC_LAUNCH
   return hipGetLastError();
 }
