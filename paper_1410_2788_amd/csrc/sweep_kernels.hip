@@ -377,26 +377,29 @@ __device__ __forceinline__ RRow<A> shfl_row_down(const RRow<A>& r, int delta, in
 
 // Neighbour exchange inside 16-lane rows by DPP row shifts (one VALU move a
 // 32-bit word): kUp takes lane i - D's value, else lane i + D's; a lane whose
-// source lies outside its row gets zero (the cyclic reduction replaces such
-// neighbours by identity rows).  Valid when a line's P lanes lie in one row
-// (P <= 16, lines at multiples of P).
+// source lies outside its row gets `fill`.  With the fills of an identity
+// row (alpha, gamma, d 0, leak 1, diagonal reciprocal 1) a line that fills
+// a whole row (P = 16) needs no further selects; smaller P select the
+// identity for the lanes whose source belongs to the neighbouring line.
 template <int D, bool kUp>
-__device__ __forceinline__ float dpp_shift(float v) {
+__device__ __forceinline__ float dpp_shift(float v, float fill) {
   constexpr int ctl = (kUp ? 0x110 : 0x100) | D;  // row_shr:D / row_shl:D
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctl, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), ctl,
+                                                    0xf, 0xf, false));
 }
 template <int D, bool kUp>
-__device__ __forceinline__ double dpp_shift(double v) {
+__device__ __forceinline__ double dpp_shift(double v, double fill) {
   constexpr int ctl = (kUp ? 0x110 : 0x100) | D;
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), ctl, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctl, 0xf, 0xf, false);
+  const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
+  const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffLL), (int)(b & 0xffffffffLL), ctl,
+                                             0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), ctl, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <int D, bool kUp, typename A>
 __device__ __forceinline__ RRow<A> dpp_row(const RRow<A>& r) {
-  return RRow<A>{dpp_shift<D, kUp>(r.a), dpp_shift<D, kUp>(r.c), dpp_shift<D, kUp>(r.l),
-                 dpp_shift<D, kUp>(r.d)};
+  return RRow<A>{dpp_shift<D, kUp>(r.a, A(0)), dpp_shift<D, kUp>(r.c, A(0)),
+                 dpp_shift<D, kUp>(r.l, A(1)), dpp_shift<D, kUp>(r.d, A(0))};
 }
 // pcr_combine with the neighbours' diagonal reciprocals given (iu, id)
 template <typename A>
@@ -416,15 +419,17 @@ __device__ __forceinline__ void pcr_step_dpp(RRow<A>& r0, RRow<A>& r1, int p, in
   const A b0 = rcp_pivot(rrow_b(r0)), b1 = rcp_pivot(rrow_b(r1));
   RRow<A> u0 = dpp_row<E, true>(r0), u1 = dpp_row<E, true>(r1);
   RRow<A> d0 = dpp_row<E, false>(r0), d1 = dpp_row<E, false>(r1);
-  A iu0 = dpp_shift<E, true>(b0), iu1 = dpp_shift<E, true>(b1);
-  A id0 = dpp_shift<E, false>(b0), id1 = dpp_shift<E, false>(b1);
-  if (p < E) {
-    u0 = u1 = rrow_identity<A>();
-    iu0 = iu1 = A(1);
-  }
-  if (p + E >= P) {
-    d0 = d1 = rrow_identity<A>();
-    id0 = id1 = A(1);
+  A iu0 = dpp_shift<E, true>(b0, A(1)), iu1 = dpp_shift<E, true>(b1, A(1));
+  A id0 = dpp_shift<E, false>(b0, A(1)), id1 = dpp_shift<E, false>(b1, A(1));
+  if (P < 16) {
+    if (p < E) {
+      u0 = u1 = rrow_identity<A>();
+      iu0 = iu1 = A(1);
+    }
+    if (p + E >= P) {
+      d0 = d1 = rrow_identity<A>();
+      id0 = id1 = A(1);
+    }
   }
   const RRow<A> n0 = pcr_combine_r(r0, u0, iu0, d0, id0);
   const RRow<A> n1 = pcr_combine_r(r1, u1, iu1, d1, id1);
@@ -449,14 +454,16 @@ __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
       const A b0 = rcp_pivot(rrow_b(r0)), b1 = rcp_pivot(rrow_b(r1));
       RRow<A> up = dpp_row<1, true>(r1);
       RRow<A> dn = dpp_row<1, false>(r0);
-      A iu = dpp_shift<1, true>(b1), id = dpp_shift<1, false>(b0);
-      if (p == 0) {
-        up = rrow_identity<A>();
-        iu = A(1);
-      }
-      if (p == P - 1) {
-        dn = rrow_identity<A>();
-        id = A(1);
+      A iu = dpp_shift<1, true>(b1, A(1)), id = dpp_shift<1, false>(b0, A(1));
+      if (P < 16) {
+        if (p == 0) {
+          up = rrow_identity<A>();
+          iu = A(1);
+        }
+        if (p == P - 1) {
+          dn = rrow_identity<A>();
+          id = A(1);
+        }
       }
       const RRow<A> n0 = pcr_combine_r(r0, up, iu, r1, b1);
       const RRow<A> n1 = pcr_combine_r(r1, r0, b0, dn, id);
