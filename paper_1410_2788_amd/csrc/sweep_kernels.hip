@@ -783,6 +783,17 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   // lanes without row items
   if (first_batch) fetch_first();
   if (gr_line) tile[tid * S + nx - 1] = gRv;
+  // A line's last chunk reads past the right Dirichlet node: into the row's
+  // padding columns [z0, S), then (when P M + 1 > S) into the next row's
+  // loaded values or, after the last row, the P M + 2 spare elements.  The
+  // padding and the spare elements hold zeros, so every such read is finite.
+  {
+    const int z0 = nxl < nx ? nx : nx4;
+    const int nzc = S - z0;
+    if (nzc > 0)
+      for (int e = tid; e < L * nzc; e += nthreads) tile[(e / nzc) * S + z0 + e % nzc] = A(0);
+    for (int e = tid; e < P * M + 2; e += nthreads) tile[L * S + e] = A(0);
+  }
   __syncthreads();
 
   // pointwise pre-operations on interior nodes: AOS W = flow(u) and the
@@ -874,12 +885,12 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   // uniform tail chunk: the right Dirichlet term into the last real row
   // (an LDS update of the lane's own node; the row is overwritten below)
   if (fast && tail && lvalid) col[kR] = fma(tb.re[t], gR, col[kR]);
+  // rows past a line's end read zeros or the Dirichlet value (finite; their
+  // results are never stored), lanes without a line whatever their rows
+  // hold (their results stay in their own lanes and lines)
   A d[M];
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const A v = col[k];
-    d[k] = (lvalid && g0 + k < nint) ? v : A(0);
-  }
+  for (int k = 0; k < M; ++k) d[k] = col[k];
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
@@ -1026,12 +1037,11 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
   // uniform tail chunk: the right Dirichlet term into the last real row
   // (an LDS update of the lane's own node; the row is overwritten below)
   if (fast && tail && lvalid) col[kR * ts] = fma(tb.re[t], gR, col[kR * ts]);
+  // rows past the line's end read zeros or the Dirichlet value (finite;
+  // their results are never stored)
   A d[M];
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const A v = col[k * ts];
-    d[k] = (g0 + k < nint) ? v : A(0);
-  }
+  for (int k = 0; k < M; ++k) d[k] = col[k * ts];
   A al[M], ga[M];
   RRow<A> rf, rl;
   if (fast) {
@@ -1234,6 +1244,9 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   }
   // lanes without node rows to move
   if (fetch) fetch_entries();
+  // tile rows past the line's end up to the last chunk row hold zeros, so
+  // that a line's last chunk reads finite values past its end
+  for (int e = tid; e < (P * M + 1 - n) * TS; e += nthreads) tile[n * TS + e] = A(0);
   __syncthreads();
 
   auto add_entry = [&](int lin, double rho) {
