@@ -335,10 +335,11 @@ __device__ __forceinline__ void fast_finish(A (&d)[M], Ptr ga, Ptr al, A xf, A x
 // the 2P rows of a line form a tridiagonal system in the form above, whose
 // first alpha and last gamma are zero.  Both solvers keep it in that form.
 //
-// x sweeps: parallel cyclic reduction with the P lanes of a line side by
-// side in one wave (lane t: line t / P, rows 2p and 2p+1 of p = t % P, P a
-// power of two).  Each step eliminates a row's couplings to the rows at
-// distance d using those rows (from the neighbour lanes): with
+// x sweeps (and FP32 y/z sweeps with P a power of two): parallel cyclic
+// reduction with the P lanes of a line side by side in one wave (lane t:
+// line t / P, rows 2p and 2p+1 of p = t % P).  Each step eliminates a row's
+// couplings to the rows at distance d using those rows (from the neighbour
+// lanes): with
 // B = leak + alpha + gamma of each row, k1 = alpha_r / B_up, k2 = gamma_r / B_dn,
 //   alpha' = alpha_up k1,  gamma' = gamma_dn k2,
 //   leak'  = leak_r + leak_up k1 + leak_dn k2,  d' = d_r + d_up k1 + d_dn k2,
@@ -377,29 +378,31 @@ __device__ __forceinline__ RRow<A> shfl_row_down(const RRow<A>& r, int delta, in
 
 // Neighbour exchange inside 16-lane rows by DPP row shifts (one VALU move a
 // 32-bit word): kUp takes lane i - D's value, else lane i + D's; a lane whose
-// source lies outside its row gets `fill`.  With the fills of an identity
-// row (alpha, gamma, d 0, leak 1, diagonal reciprocal 1) a line that fills
-// a whole row (P = 16) needs no further selects; smaller P select the
-// identity for the lanes whose source belongs to the neighbouring line.
+// source lies outside its row reads zero.  A zero row in place of the
+// identity is exact wherever it can reach a result: a row whose neighbour
+// at the current distance lies before the start (after the end) of its
+// line has alpha (gamma) exactly zero, so k1 (k2) = 0 * 0 and the zero row
+// drops out; by induction over the steps this holds from the first alpha and
+// last gamma of the system, which are zero.  A line that fills a whole row
+// (P = 16) therefore needs no selects; smaller P select the identity for the
+// lanes whose source belongs to the neighbouring line.
 template <int D, bool kUp>
-__device__ __forceinline__ float dpp_shift(float v, float fill) {
+__device__ __forceinline__ float dpp_shift(float v) {
   constexpr int ctl = (kUp ? 0x110 : 0x100) | D;  // row_shr:D / row_shl:D
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), ctl,
-                                                    0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctl, 0xf, 0xf, true));
 }
 template <int D, bool kUp>
-__device__ __forceinline__ double dpp_shift(double v, double fill) {
+__device__ __forceinline__ double dpp_shift(double v) {
   constexpr int ctl = (kUp ? 0x110 : 0x100) | D;
-  const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
-  const int lo = __builtin_amdgcn_update_dpp((int)(f & 0xffffffffLL), (int)(b & 0xffffffffLL), ctl,
-                                             0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), ctl, 0xf, 0xf, false);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), ctl, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctl, 0xf, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <int D, bool kUp, typename A>
 __device__ __forceinline__ RRow<A> dpp_row(const RRow<A>& r) {
-  return RRow<A>{dpp_shift<D, kUp>(r.a, A(0)), dpp_shift<D, kUp>(r.c, A(0)),
-                 dpp_shift<D, kUp>(r.l, A(1)), dpp_shift<D, kUp>(r.d, A(0))};
+  return RRow<A>{dpp_shift<D, kUp>(r.a), dpp_shift<D, kUp>(r.c), dpp_shift<D, kUp>(r.l),
+                 dpp_shift<D, kUp>(r.d)};
 }
 // pcr_combine with the neighbours' diagonal reciprocals given (iu, id)
 template <typename A>
@@ -410,31 +413,64 @@ __device__ __forceinline__ RRow<A> pcr_combine_r(const RRow<A>& r, const RRow<A>
   return RRow<A>{up.a * k1, dn.c * k2, fma(up.l, k1, fma(dn.l, k2, r.l)),
                  fma(up.d, k1, fma(dn.d, k2, r.d))};
 }
-// one reduction step at lane distance E (row distance 2E), E a constant:
-// each lane forms the reciprocals of its own two rows' diagonals and passes
-// them on with the rows (identity neighbours: diagonal 1)
-template <int E, typename A>
-__device__ __forceinline__ void pcr_step_dpp(RRow<A>& r0, RRow<A>& r1, int p, int P) {
-  if (E >= P) return;
-  const A b0 = rcp_pivot(rrow_b(r0)), b1 = rcp_pivot(rrow_b(r1));
-  RRow<A> u0 = dpp_row<E, true>(r0), u1 = dpp_row<E, true>(r1);
-  RRow<A> d0 = dpp_row<E, false>(r0), d1 = dpp_row<E, false>(r1);
-  A iu0 = dpp_shift<E, true>(b0, A(1)), iu1 = dpp_shift<E, true>(b1, A(1));
-  A id0 = dpp_shift<E, false>(b0, A(1)), id1 = dpp_shift<E, false>(b1, A(1));
-  if (P < 16) {
+// One reduction step at lane distance E, E a constant, over one row per
+// lane: each lane forms the reciprocal of its row's diagonal and passes it
+// on with the row.  kFull: the line fills the whole 16-lane row (zero rows
+// from outside it); else lanes whose source lies outside the line take the
+// identity row.
+template <int E, bool kFull, typename A>
+__device__ __forceinline__ void pcr_step_dpp(RRow<A>& r, int p, int P) {
+  if (!kFull && E >= P) return;
+  const A b = rcp_pivot(rrow_b(r));
+  RRow<A> u = dpp_row<E, true>(r), d = dpp_row<E, false>(r);
+  A iu = dpp_shift<E, true>(b), id = dpp_shift<E, false>(b);
+  if constexpr (!kFull) {
     if (p < E) {
-      u0 = u1 = rrow_identity<A>();
-      iu0 = iu1 = A(1);
+      u = rrow_identity<A>();
+      iu = A(1);
     }
     if (p + E >= P) {
-      d0 = d1 = rrow_identity<A>();
-      id0 = id1 = A(1);
+      d = rrow_identity<A>();
+      id = A(1);
     }
   }
-  const RRow<A> n0 = pcr_combine_r(r0, u0, iu0, d0, id0);
-  const RRow<A> n1 = pcr_combine_r(r1, u1, iu1, d1, id1);
-  r0 = n0;
-  r1 = n1;
+  r = pcr_combine_r(r, u, iu, d, id);
+}
+
+// Reduced system of a line with its P <= 16 lanes in one 16-lane row (lane
+// p: rows 2p and 2p+1).  One step of cyclic reduction first: the odd row
+// 2p+1 takes in the even rows 2p (its own lane) and 2p+2 (lane p+1), after
+// which the odd rows alone form a tridiagonal system, one row per lane,
+// solved by the DPP steps above.  Each even row then follows from its
+// original equation and the odd neighbours:
+//   x_{2p} = (d_{2p} + alpha_{2p} x_{2p-1} + gamma_{2p} x_{2p+1}) / B_{2p}.
+template <bool kFull, typename A>
+__device__ __forceinline__ void pcr_dpp(A* R, int rs, int p, int P) {
+  auto get = [&](int r) {
+    return RRow<A>{R[(4 * r) * rs], R[(4 * r + 1) * rs], R[(4 * r + 2) * rs],
+                   R[(4 * r + 3) * rs]};
+  };
+  const RRow<A> r0 = get(2 * p);
+  RRow<A> o = get(2 * p + 1);
+  const A b0 = rcp_pivot(rrow_b(r0));
+  {
+    RRow<A> dn = dpp_row<1, false>(r0);
+    A id = dpp_shift<1, false>(b0);
+    if (!kFull && p == P - 1) {
+      dn = rrow_identity<A>();
+      id = A(1);
+    }
+    o = pcr_combine_r(o, r0, b0, dn, id);
+  }
+  pcr_step_dpp<1, kFull>(o, p, P);
+  pcr_step_dpp<2, kFull>(o, p, P);
+  pcr_step_dpp<4, kFull>(o, p, P);
+  pcr_step_dpp<8, kFull>(o, p, P);
+  const A xo = o.d * rcp_pivot(rrow_b(o));
+  A xm = dpp_shift<1, true>(xo);  // x_{2p-1}; alpha_0 = 0 for p = 0
+  if (!kFull && p == 0) xm = A(0);
+  R[(4 * (2 * p) + 3) * rs] = fma(r0.a, xm, fma(r0.c, xo, r0.d)) * b0;
+  R[(4 * (2 * p + 1) + 3) * rs] = xo;
 }
 
 // Solve the reduced systems of all lines of the block (every thread takes
@@ -442,40 +478,12 @@ __device__ __forceinline__ void pcr_step_dpp(RRow<A>& r0, RRow<A>& r1, int p, in
 template <typename A>
 __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
   if (P <= 16) {
-    // the same steps with DPP row shifts for the neighbour exchange
     const int p = tid & (P - 1);
     A* R = red + tid / P;
-    auto get = [&](int r) {
-      return RRow<A>{R[(4 * r) * rs], R[(4 * r + 1) * rs], R[(4 * r + 2) * rs],
-                     R[(4 * r + 3) * rs]};
-    };
-    RRow<A> r0 = get(2 * p), r1 = get(2 * p + 1);
-    {
-      const A b0 = rcp_pivot(rrow_b(r0)), b1 = rcp_pivot(rrow_b(r1));
-      RRow<A> up = dpp_row<1, true>(r1);
-      RRow<A> dn = dpp_row<1, false>(r0);
-      A iu = dpp_shift<1, true>(b1, A(1)), id = dpp_shift<1, false>(b0, A(1));
-      if (P < 16) {
-        if (p == 0) {
-          up = rrow_identity<A>();
-          iu = A(1);
-        }
-        if (p == P - 1) {
-          dn = rrow_identity<A>();
-          id = A(1);
-        }
-      }
-      const RRow<A> n0 = pcr_combine_r(r0, up, iu, r1, b1);
-      const RRow<A> n1 = pcr_combine_r(r1, r0, b0, dn, id);
-      r0 = n0;
-      r1 = n1;
-    }
-    pcr_step_dpp<1>(r0, r1, p, P);
-    pcr_step_dpp<2>(r0, r1, p, P);
-    pcr_step_dpp<4>(r0, r1, p, P);
-    pcr_step_dpp<8>(r0, r1, p, P);
-    R[(4 * (2 * p) + 3) * rs] = r0.d * rcp_pivot(rrow_b(r0));
-    R[(4 * (2 * p + 1) + 3) * rs] = r1.d * rcp_pivot(rrow_b(r1));
+    if (P == 16)
+      pcr_dpp<true>(R, rs, p, P);
+    else
+      pcr_dpp<false>(R, rs, p, P);
     return;
   }
   const int p = tid & (P - 1);
