@@ -306,8 +306,9 @@ __device__ __forceinline__ void fast_eliminate(A (&d)[M], const TB& tb, int t, b
   A dp = d[M - 2];
 #pragma unroll
   for (int k = M - 3; k >= 1; --k) {
-    const A g = tb.ga[t][k];
-    dp = fma(k == kt ? (tail ? A(0) : -g) : -g, dp, d[k]);
+    // row kt of a tail chunk takes nothing from row kt + 1 (a select of the
+    // value, not of the table coefficient: one VALU op)
+    dp = fma(-tb.ga[t][k], (tail && k == kt) ? A(0) : dp, d[k]);
   }
   const A lf = tail_in ? tb.rf_lt[t] : tb.rf_l[t];
   rf = RRow<A>{first ? A(0) : re, tail_in ? A(0) : tb.rf_c[t], first ? lf + re : lf,
@@ -322,8 +323,7 @@ __device__ __forceinline__ void fast_finish(A (&d)[M], Ptr ga, Ptr al, A xf, A x
   d[M - 1] = xl;
 #pragma unroll
   for (int k = M - 2; k >= 1; --k) {
-    const A g = ga[k];
-    d[k] = fma(k == kt ? (tail ? A(0) : -g) : -g, d[k + 1], fma(-al[k], xf, d[k]));
+    d[k] = fma(-ga[k], (tail && k == kt) ? A(0) : d[k + 1], fma(-al[k], xf, d[k]));
   }
   d[0] = xf;
 }
@@ -1304,9 +1304,8 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   // step) notes a stored value that is not finite (Sec. 4.2: a diverged run)
   const int mode = (VAR == kYzGeneral) ? a.mode : MODE_INPLACE;
   T* out = (mode == MODE_AOS_ADD) ? a.acc : a.u;
-  bool bad = false;
-  const bool chk = a.nonfinite != nullptr;
-  if (cok) {
+  T nz = T(0);  // stays zero while every stored value is finite (0 * inf, 0 * nan: nan)
+  auto store_rows = [&](auto check) {
     uint32_t pt = base + (uint32_t)(1 + jr) * stride + (uint32_t)(cv * VX);
     for (int j = 1 + jr; j <= nint; j += RS, pt += rstep) {
       T w[VX];
@@ -1327,14 +1326,21 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
 #pragma unroll
         for (int i = 0; i < VX; ++i) w[i] = (T)tile[j * TS + cv * VX + i];
       }
-      if (chk) {
+      if constexpr (decltype(check)::value) {
 #pragma unroll
-        for (int i = 0; i < VX; ++i) bad |= !isfinite(w[i]);
+        for (int i = 0; i < VX; ++i) nz = fma(w[i], T(0), nz);
       }
       VecIO<T, VX>::st(out + pt, w);
     }
+  };
+  const bool chk = a.nonfinite != nullptr;
+  if (cok) {
+    if (chk)
+      store_rows(std::true_type{});
+    else
+      store_rows(std::false_type{});
   }
-  if (bad && a.nonfinite != nullptr) atomicOr(a.nonfinite, 1);
+  if (chk && nz != nz) atomicOr(a.nonfinite, 1);
 }
 
 // ---------------------------------------------------------------------------
