@@ -591,19 +591,22 @@ struct BcPair;
 // as both together, so its sums are bit-identical.
 template <>
 struct BcPair<float> {
-  // c = -kappa log2(e)
-  template <int kMedia>
+  // c = -kappa log2(e).  kUnit: the coordinates come scaled by kappa log2(e)
+  // (the sums then carry a factor 1 / (kappa log2(e)), taken out at the end),
+  // so the exponent is the scaled distance itself
+  template <int kMedia, bool kUnit>
   static __device__ __forceinline__ void add(float d2, float q, float c, float& ts, float& tv) {
     const float ri = __builtin_amdgcn_rsqf(d2);
     const float t = q * ri;
     if constexpr ((kMedia & 2) != 0) tv += t;
-    if constexpr ((kMedia & 1) != 0) ts = fmaf(t, __builtin_amdgcn_exp2f(c * (d2 * ri)), ts);
+    if constexpr ((kMedia & 1) != 0)
+      ts = fmaf(t, __builtin_amdgcn_exp2f(kUnit ? -(d2 * ri) : c * (d2 * ri)), ts);
   }
 };
 template <>
 struct BcPair<double> {
   // c = -kappa
-  template <int kMedia>
+  template <int kMedia, bool kUnit>
   static __device__ __forceinline__ void add(double d2, double q, double c, double& ts,
                                              double& tv) {
     double ri = __builtin_amdgcn_rsq(d2);
@@ -644,11 +647,14 @@ __device__ __forceinline__ double exp_small(double y) {
 // terms, kappa h <= 0.1): along a row the screening factor of node q + 1
 // is that of node q times e^{-kappa (d_{q+1} - d_q)}, |kappa (d_{q+1} - d_q)|
 // <= kappa h, from exp_small (relative error of the chain below 1e-14 over
-// the row's eight nodes, from the rounding of the distance differences)
-template <typename R, int kMedia, bool kChain = false>
+// the row's eight nodes, from the rounding of the distance differences).
+// xs: factor of every coordinate (1, or kappa log2(e) with kUnit; the sums
+// then carry a factor 1 / xs, which scale_s and scale_v take out).
+template <typename R, int kMedia, bool kChain = false, bool kUnit = false>
 __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double scale_s,
                                                             double c_exp, double scale_v,
-                                                            double* bc_s, double* bc_v) {
+                                                            double xs, double* bc_s,
+                                                            double* bc_v) {
   using R4 = typename std::conditional<std::is_same<R, float>::value, float4, double4>::type;
   __shared__ R4 sa[256];
   __shared__ double rs[kBcSlices][kBcGroups * kBcK], rv[kBcSlices][kBcGroups * kBcK];
@@ -684,20 +690,21 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
   int cnt = 0;
   if (face >= 0) {
     const int kz = face < 2 ? (face == 1 ? nz - 1 : 0) : row + 1;
-    F2 = (R)(a.oz + (double)kz * a.h);
+    F2 = (R)((a.oz + (double)kz * a.h) * xs);
     if (face < 2)
-      F1 = (R)(a.oy + (double)row * a.h);
+      F1 = (R)((a.oy + (double)row * a.h) * xs);
     else if (face < 4)
-      F1 = (R)(a.oy + (double)(face == 3 ? ny - 1 : 0) * a.h);
+      F1 = (R)((a.oy + (double)(face == 3 ? ny - 1 : 0) * a.h) * xs);
     else
-      F1 = (R)(a.ox + (double)(face == 5 ? nx - 1 : 0) * a.h);
+      F1 = (R)((a.ox + (double)(face == 5 ? nx - 1 : 0) * a.h) * xs);
     cnt = min(kBcK, len - u0);
   }
 #pragma unroll
   for (int t = 0; t < kBcK; ++t) {
     const int u = u0 + t;
     V[t] = R(1e4);
-    if (t < cnt) V[t] = vy ? (R)(a.oy + (double)(1 + u) * a.h) : (R)(a.ox + (double)u * a.h);
+    if (t < cnt)
+      V[t] = vy ? (R)((a.oy + (double)(1 + u) * a.h) * xs) : (R)((a.ox + (double)u * a.h) * xs);
   }
   const int na = a.n_atoms;
   const R c = (R)c_exp;
@@ -708,9 +715,9 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
     const int t = t0 + (int)threadIdx.x;
     if (t < na) {
       R4 at;
-      at.x = (R)a.atoms[t];
-      at.y = (R)a.atoms[na + t];
-      at.z = (R)a.atoms[2 * na + t];
+      at.x = (R)(a.atoms[t] * xs);
+      at.y = (R)(a.atoms[na + t] * xs);
+      at.z = (R)(a.atoms[2 * na + t] * xs);
       at.w = (R)a.atoms[3 * na + t];
       sa[threadIdx.x] = at;
     }
@@ -752,7 +759,7 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
 #pragma unroll
           for (int q = 0; q < kBcK; ++q) {
             const R dv = V[q] - av;
-            BcPair<R>::template add<kMedia>(dv * dv + b2, at.w, c, ps[q], pv[q]);
+            BcPair<R>::template add<kMedia, kUnit>(dv * dv + b2, at.w, c, ps[q], pv[q]);
           }
         }
       }
@@ -800,13 +807,29 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
   const int media = (bc_s ? 1 : 0) | (bc_v ? 2 : 0);
   const double cf = fp32_terms ? -kappa * 1.4426950408889634 : -kappa;
   if (media == 0) return hipSuccess;
-#define NPB_BC_LAUNCH(R, M) \
-  hipLaunchKernelGGL((boundary_rows_kernel<R, M>), g, b, 0, st, a, ss, cf, sv, bc_s, bc_v)
-#define NPB_BC_LAUNCH_CHAIN(M) \
-  hipLaunchKernelGGL((boundary_rows_kernel<double, M, true>), g, b, 0, st, a, ss, cf, sv, bc_s, bc_v)
+  // FP32 terms with screening: coordinates scaled by kappa log2(e), so that
+  // the exponent needs no multiply (the same for either medium alone)
+  const bool unit = fp32_terms && kappa > 0.0;
+  const double xs = unit ? kappa * 1.4426950408889634 : 1.0;
+#define NPB_BC_LAUNCH(R, M)                                                               \
+  hipLaunchKernelGGL((boundary_rows_kernel<R, M>), g, b, 0, st, a, ss, cf, sv, 1.0, bc_s, \
+                     bc_v)
+#define NPB_BC_LAUNCH_UNIT(M)                                                            \
+  hipLaunchKernelGGL((boundary_rows_kernel<float, M, false, true>), g, b, 0, st, a, ss * xs, \
+                     cf, sv * xs, xs, bc_s, bc_v)
+#define NPB_BC_LAUNCH_CHAIN(M)                                                             \
+  hipLaunchKernelGGL((boundary_rows_kernel<double, M, true>), g, b, 0, st, a, ss, cf, sv, 1.0, \
+                     bc_s, bc_v)
   // FP64 terms: the row-chained screening factor when kappa h <= 0.1
   const bool chain = !fp32_terms && kappa * a.h <= 0.1;
-  if (fp32_terms) {
+  if (unit) {
+    if (media == 3)
+      NPB_BC_LAUNCH_UNIT(3);
+    else if (media == 1)
+      NPB_BC_LAUNCH_UNIT(1);
+    else
+      NPB_BC_LAUNCH_UNIT(2);
+  } else if (fp32_terms) {
     if (media == 3)
       NPB_BC_LAUNCH(float, 3);
     else if (media == 1)
@@ -827,6 +850,7 @@ hipError_t launch_boundary(const SetupArgs& a, double eps_s, double kappa, doubl
       NPB_BC_LAUNCH(double, 2);
   }
 #undef NPB_BC_LAUNCH_CHAIN
+#undef NPB_BC_LAUNCH_UNIT
 #undef NPB_BC_LAUNCH
   return hipGetLastError();
 }
