@@ -576,33 +576,47 @@ __device__ __forceinline__ void put_reduced(A* R, int nl, int p, const RRow<A>& 
 // the address must be 16-byte aligned.
 template <typename T, int V>
 struct VecIO;
+// Fields and flags live in device global memory.  Accesses through
+// address-space-1 pointers compile to global_* instructions, which count
+// only against vmcnt; through generic pointers they become flat_* ones,
+// which count against lgkmcnt as well, so that every wait for a scalar load
+// or an LDS access would also wait for the field loads in flight.
+#define NPB_GLOBAL __attribute__((address_space(1)))
+template <typename U>
+__device__ __forceinline__ U ldg(const U* p) {
+  return *(const NPB_GLOBAL U*)p;
+}
+// (native vector types: HIP's float4 is a class, whose member functions
+// would take the address back to the generic space)
+typedef float npb_f4 __attribute__((ext_vector_type(4)));
+typedef double npb_d2 __attribute__((ext_vector_type(2)));
 template <>
 struct VecIO<float, 4> {
   static __device__ __forceinline__ void ld(const float* p, float (&o)[4]) {
-    float4 v = *reinterpret_cast<const float4*>(p);
+    const npb_f4 v = *(const NPB_GLOBAL npb_f4*)p;
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
   static __device__ __forceinline__ void st(float* p, const float (&o)[4]) {
-    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+    *(NPB_GLOBAL npb_f4*)p = npb_f4{o[0], o[1], o[2], o[3]};
   }
 };
 template <>
 struct VecIO<double, 2> {
   static __device__ __forceinline__ void ld(const double* p, double (&o)[2]) {
-    double2 v = *reinterpret_cast<const double2*>(p);
+    const npb_d2 v = *(const NPB_GLOBAL npb_d2*)p;
     o[0] = v.x; o[1] = v.y;
   }
   static __device__ __forceinline__ void st(double* p, const double (&o)[2]) {
-    *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
+    *(NPB_GLOBAL npb_d2*)p = npb_d2{o[0], o[1]};
   }
 };
 
 // solute flags of V consecutive nodes, one byte each
 template <int V>
 __device__ __forceinline__ uint32_t ld_mask(const uint8_t* p) {
-  if constexpr (V == 4) return *reinterpret_cast<const uint32_t*>(p);
-  if constexpr (V == 2) return *reinterpret_cast<const uint16_t*>(p);
-  return *p;
+  if constexpr (V == 4) return *(const NPB_GLOBAL uint32_t*)p;
+  if constexpr (V == 2) return *(const NPB_GLOBAL uint16_t*)p;
+  return *(const NPB_GLOBAL uint8_t*)p;
 }
 
 // ---------------------------------------------------------------------------
@@ -714,7 +728,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   // the rows so that its latency overlaps theirs
   int cls = 1;
   if (l0 + tid % L < nlines)
-    cls = uniform ? 0 : (a.ccls ? (int)a.ccls[(size_t)(tid / L) * nlines + (l0 + tid % L)] : 1);
+    cls = uniform ? 0 : (a.ccls ? (int)ldg(a.ccls + (size_t)(tid / L) * nlines + (l0 + tid % L)) : 1);
   A gRv = A(0);
   bool first_batch = true;
   // with the first batch of row loads in flight: the source entries and
@@ -722,18 +736,18 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   auto fetch_first = [&]() {
     first_batch = false;
     if (src) {
-      eb = a.src_ptr[row_base(0) / nxp];
-      ee = a.src_ptr[row_base(min(L, nlines - l0) - 1) / nxp + 1];
+      eb = ldg(a.src_ptr + row_base(0) / nxp);
+      ee = ldg(a.src_ptr + row_base(min(L, nlines - l0) - 1) / nxp + 1);
       if (eb + tid < ee) {
-        e_lin = a.src_lin[eb + tid];
-        e_rho = a.src_rho[eb + tid];
+        e_lin = ldg(a.src_lin + eb + tid);
+        e_rho = ldg(a.src_rho + eb + tid);
       }
     }
     if (gr_line) {
       int yi, zi;
       line_yz(tid, yi, zi);
       const int s = 2 * nx * ny + zi * (2 * nx + 2 * nyi) + 2 * nx + 2 * yi + 1;
-      gRv = (A)(T)a.bcx[s];
+      gRv = (A)(T)ldg(a.bcx + s);
     }
   };
   // When RQ is a multiple of L (P a multiple of 8), every item of a lane
@@ -743,6 +757,8 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   auto load_rows = [&](auto fixq) {
     constexpr bool kFix = decltype(fixq)::value;
     const int rb0 = kFix ? row_base(rq % L) : 0;
+    const T* const ug = a.u;
+    const uint8_t* const mg = a.mask;
     constexpr int kU = 8;
     for (int w0 = rq; w0 < nitems; w0 += kU * RQ) {
       T v[kU][VX];
@@ -759,8 +775,8 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
           if (c < nx4 && rb >= 0) {
             lo[j] = c < nxl ? q * S + c : -1;
             mo[j] = q * nx4 + c;
-            if (c < nxl) VecIO<T, VX>::ld(a.u + rb + c, v[j]);
-            if (!uniform) m[j] = ld_mask<VX>(a.mask + rb + c);
+            if (c < nxl) VecIO<T, VX>::ld(ug + rb + c, v[j]);
+            if (!uniform) m[j] = ld_mask<VX>(mg + rb + c);
           } else {
             mo[j] = -1;
           }
@@ -796,10 +812,13 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   // loaded values or, after the last row, the P M + 2 spare elements.  The
   // padding and the spare elements hold zeros, so every such read is finite.
   {
+    // nzc = S - z0 <= 35 (S exceeds row4(nx) by at most 32), so 64 slots a
+    // row cover it without a division
     const int z0 = nxl < nx ? nx : nx4;
     const int nzc = S - z0;
     if (nzc > 0)
-      for (int e = tid; e < L * nzc; e += nthreads) tile[(e / nzc) * S + z0 + e % nzc] = A(0);
+      for (int e = tid; e < L * 64; e += nthreads)
+        if ((e & 63) < nzc) tile[(e >> 6) * S + z0 + (e & 63)] = A(0);
     for (int e = tid; e < P * M + 2; e += nthreads) tile[L * S + e] = A(0);
   }
   __syncthreads();
@@ -863,7 +882,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
       tile[q * S + x] += (A)(a.src_coef * rho);
     };
     if (e_lin >= 0) add_entry(e_lin, e_rho);
-    for (int e = eb + tid + nthreads; e < ee; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
+    for (int e = eb + tid + nthreads; e < ee; e += nthreads) add_entry(ldg(a.src_lin + e), ldg(a.src_rho + e));
     __syncthreads();
   }
 
@@ -1000,8 +1019,7 @@ __device__ __forceinline__ int yz_chunk_class(const SweepArgs<T>& a, int dir, in
   if (a.mask == nullptr) return 0;
   if (!a.ccls) return 1;
   const long long nl = (long long)(nx - 2) * ((dir == 1 ? a.nz : a.ny) - 2);
-  const auto* cc = (const __attribute__((address_space(1))) uint8_t*)a.ccls;
-  return (int)cc[(size_t)(tid / TW) * nl + (size_t)(o - 1) * (nx - 2) + (x - 1)];
+  return (int)ldg(a.ccls + (size_t)(tid / TW) * nl + (size_t)(o - 1) * (nx - 2) + (x - 1));
 }
 
 // Line solves of one y/z tile held in LDS: tile[row * ts + q] is node row
@@ -1199,11 +1217,11 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   bool fetch = src;
   auto fetch_entries = [&]() {
     const int xlo = max(xb, 1), xhi = min(xb + TW - 1, nx - 2);
-    sb = a.src_ptr[o * nx + xlo];
-    se = a.src_ptr[o * nx + xhi + 1];
+    sb = ldg(a.src_ptr + o * nx + xlo);
+    se = ldg(a.src_ptr + o * nx + xhi + 1);
     if (sb + tid < se) {
-      e_lin = a.src_lin[sb + tid];
-      e_rho = a.src_rho[sb + tid];
+      e_lin = ldg(a.src_lin + sb + tid);
+      e_rho = ldg(a.src_rho + sb + tid);
     }
     fetch = false;
   };
@@ -1265,7 +1283,7 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   };
   auto add_sources = [&]() {
     if (e_lin >= 0) add_entry(e_lin, e_rho);
-    for (int e = sb + tid + nthreads; e < se; e += nthreads) add_entry(a.src_lin[e], a.src_rho[e]);
+    for (int e = sb + tid + nthreads; e < se; e += nthreads) add_entry(ldg(a.src_lin + e), ldg(a.src_rho + e));
   };
   // general variant: the leading nonlinear sub-step on the input (Sec. 3.3)
   // and the Crank-Nicolson explicit half before the sources (additive schemes)
