@@ -44,14 +44,16 @@ namespace npb {
 // printed ratio divided by cosh(theta) becomes
 //   (kA + kB E) / (kB + kA E) = 1 + 2k m / (kB + kA E),
 // so  w = sign(u) * log1p(2k m / (kB + kA E)): odd in u, no overflow.
-// FP32 uses the hardware exp/log; FP64 the series-based exp_neg and
+// FP32 uses the hardware exp2/log2 (1 + x >= 1 is a normal number, so
+// the log needs none of a library log's range handling; the rounding of
+// 1 + x dominates its error either way); FP64 the series-based exp_neg and
 // log1p_nonneg (m = 1 - E then loses relative accuracy as |u| -> 0 but keeps
 // an absolute error of ~1e-16, which is what the field sees).
 __device__ __forceinline__ float sinh_flow(float u, float kA, float kB) {
   const float E = __expf(-fabsf(u));
   const float m = 1.0f - E;
   const float x = (kA - kB) * m * __builtin_amdgcn_rcpf(fmaf(kA, E, kB));
-  return copysignf(__logf(1.0f + x), u);
+  return copysignf(__builtin_amdgcn_logf(1.0f + x) * 0.693147180559945f, u);
 }
 __device__ __forceinline__ double sinh_flow(double u, double kA, double kB) {
   const double E = exp_neg(-fabs(u));
