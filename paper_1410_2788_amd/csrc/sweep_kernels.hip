@@ -331,9 +331,12 @@ __device__ __forceinline__ void fast_finish(A (&d)[M], Ptr ga, Ptr al, A xf, A x
 }
 
 // Reduced systems in LDS: entry (line l, row r, coefficient c) at
-// R[(4 r + c) * rs + l], c = alpha, gamma, leak, d; rs = lines + 1, so
-// that the lanes of one wave writing them (different lines, same row) touch
-// distinct banks.  Row 2p is the first row of chunk p, row 2p+1 its last;
+// R[r (4 rs + 1) + c rs + l] (red_at), c = alpha, gamma, leak, d;
+// rs = lines + 1.  The lanes of one wave that write them (different lines,
+// same row) touch distinct banks, and so do the lanes that read them for the
+// cyclic reduction (one line's rows 2p, p = 0..15, 2p (4 rs + 1) apart: an
+// odd row stride spreads them over the banks).  Row 2p is the first row of
+// chunk p, row 2p+1 its last;
 // the 2P rows of a line form a tridiagonal system in the form above, whose
 // first alpha and last gamma are zero.  Both solvers keep it in that form.
 //
@@ -348,6 +351,9 @@ __device__ __forceinline__ void fast_finish(A (&d)[M], Ptr ga, Ptr al, A xf, A x
 // after which the row couples to the rows at distance 2d; after steps
 // d = 1, 2, ..., P every row stands alone and x_r = d_r / B_r.  Rows outside
 // the system act as identity rows (their coupling is already zero).
+__host__ __device__ constexpr int red_at(int r, int c, int rs) { return r * (4 * rs + 1) + c * rs; }
+// elements of the reduced systems of a block
+__host__ __device__ constexpr int red_size(int P, int rs) { return 2 * P * (4 * rs + 1); }
 template <typename A>
 __device__ __forceinline__ RRow<A> rrow_identity() {
   return RRow<A>{A(0), A(0), A(1), A(0)};
@@ -449,8 +455,8 @@ __device__ __forceinline__ void pcr_step_dpp(RRow<A>& r, int p, int P) {
 template <bool kFull, typename A>
 __device__ __forceinline__ void pcr_dpp(A* R, int rs, int p, int P) {
   auto get = [&](int r) {
-    return RRow<A>{R[(4 * r) * rs], R[(4 * r + 1) * rs], R[(4 * r + 2) * rs],
-                   R[(4 * r + 3) * rs]};
+    return RRow<A>{R[red_at(r, 0, rs)], R[red_at(r, 1, rs)], R[red_at(r, 2, rs)],
+                   R[red_at(r, 3, rs)]};
   };
   const RRow<A> r0 = get(2 * p);
   RRow<A> o = get(2 * p + 1);
@@ -471,8 +477,8 @@ __device__ __forceinline__ void pcr_dpp(A* R, int rs, int p, int P) {
   const A xo = o.d * rcp_pivot(rrow_b(o));
   A xm = dpp_shift<1, true>(xo);  // x_{2p-1}; alpha_0 = 0 for p = 0
   if (!kFull && p == 0) xm = A(0);
-  R[(4 * (2 * p) + 3) * rs] = fma(r0.a, xm, fma(r0.c, xo, r0.d)) * b0;
-  R[(4 * (2 * p + 1) + 3) * rs] = xo;
+  R[red_at(2 * p, 3, rs)] = fma(r0.a, xm, fma(r0.c, xo, r0.d)) * b0;
+  R[red_at(2 * p + 1, 3, rs)] = xo;
 }
 
 // Solve the reduced systems of all lines of the block (every thread takes
@@ -491,8 +497,8 @@ __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
   const int p = tid & (P - 1);
   A* R = red + tid / P;
   auto get = [&](int r) {
-    return RRow<A>{R[(4 * r) * rs], R[(4 * r + 1) * rs], R[(4 * r + 2) * rs],
-                   R[(4 * r + 3) * rs]};
+    return RRow<A>{R[red_at(r, 0, rs)], R[red_at(r, 1, rs)], R[red_at(r, 2, rs)],
+                   R[red_at(r, 3, rs)]};
   };
   RRow<A> r0 = get(2 * p), r1 = get(2 * p + 1);
   {
@@ -517,8 +523,8 @@ __device__ __forceinline__ void pcr_reduced(A* red, int rs, int P, int tid) {
     r0 = n0;
     r1 = n1;
   }
-  R[(4 * (2 * p) + 3) * rs] = r0.d * rcp_pivot(rrow_b(r0));
-  R[(4 * (2 * p + 1) + 3) * rs] = r1.d * rcp_pivot(rrow_b(r1));
+  R[red_at(2 * p, 3, rs)] = r0.d * rcp_pivot(rrow_b(r0));
+  R[red_at(2 * p + 1, 3, rs)] = r1.d * rcp_pivot(rrow_b(r1));
 }
 
 // y/z sweeps (chunk counts need not be powers of two): Thomas on the 2P
@@ -536,42 +542,41 @@ __device__ __forceinline__ void reduced_solve(A* R, int n2, int nl) {
   for (int r = 0; r < n2; ++r) {
     const A ar = an, cr = cn, lr = ln, dr = dn;
     if (r + 1 < n2) {
-      an = R[(4 * r + 4) * nl];
-      cn = R[(4 * r + 5) * nl];
-      ln = R[(4 * r + 6) * nl];
-      dn = R[(4 * r + 7) * nl];
+      an = R[red_at(r + 1, 0, nl)];
+      cn = R[red_at(r + 1, 1, nl)];
+      ln = R[red_at(r + 1, 2, nl)];
+      dn = R[red_at(r + 1, 3, nl)];
     }
     const A inv = rcp_pivot(fma(ar, u, lr + cr));
     dp = fma(ar, dp, dr) * inv;
     u = fma(ar, u, lr) * inv;
-    R[(4 * r + 1) * nl] = cr * inv;
-    R[(4 * r + 3) * nl] = dp;
+    R[red_at(r, 1, nl)] = cr * inv;
+    R[red_at(r, 3, nl)] = dp;
   }
   A xn = dp;
-  A cq = R[(4 * (n2 - 2) + 1) * nl], dq = R[(4 * (n2 - 2) + 3) * nl];
+  A cq = R[red_at(n2 - 2, 1, nl)], dq = R[red_at(n2 - 2, 3, nl)];
   for (int r = n2 - 2; r >= 0; --r) {
     const A cr = cq, dr = dq;
     if (r > 0) {
-      cq = R[(4 * r - 3) * nl];
-      dq = R[(4 * r - 1) * nl];
+      cq = R[red_at(r - 1, 1, nl)];
+      dq = R[red_at(r - 1, 3, nl)];
     }
     xn = fma(cr, xn, dr);
-    R[(4 * r + 3) * nl] = xn;
+    R[red_at(r, 3, nl)] = xn;
   }
 }
 
 template <typename A>
 __device__ __forceinline__ void put_reduced(A* R, int nl, int p, const RRow<A>& rf,
                                             const RRow<A>& rl) {
-  const int f = 4 * (2 * p), l = 4 * (2 * p + 1);
-  R[(f + 0) * nl] = rf.a;
-  R[(f + 1) * nl] = rf.c;
-  R[(f + 2) * nl] = rf.l;
-  R[(f + 3) * nl] = rf.d;
-  R[(l + 0) * nl] = rl.a;
-  R[(l + 1) * nl] = rl.c;
-  R[(l + 2) * nl] = rl.l;
-  R[(l + 3) * nl] = rl.d;
+  R[red_at(2 * p, 0, nl)] = rf.a;
+  R[red_at(2 * p, 1, nl)] = rf.c;
+  R[red_at(2 * p, 2, nl)] = rf.l;
+  R[red_at(2 * p, 3, nl)] = rf.d;
+  R[red_at(2 * p + 1, 0, nl)] = rl.a;
+  R[red_at(2 * p + 1, 1, nl)] = rl.c;
+  R[red_at(2 * p + 1, 2, nl)] = rl.l;
+  R[red_at(2 * p + 1, 3, nl)] = rl.d;
 }
 
 // 16-byte vector access of V consecutive elements (V * sizeof(T) == 16);
@@ -680,7 +685,7 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
 
   size_t off = 16;
   A* red = reinterpret_cast<A*>(smem + off);  // reduced systems
-  off += sizeof(A) * (size_t)(L + 1) * 2 * P * 4;
+  off += sizeof(A) * (size_t)red_size(P, L + 1);
   // the tile and the mask rows carry P*M+2 spare elements at their end:
   // a chunk's reads may run past the last row (values selected away)
   A* tile = reinterpret_cast<A*>(smem + off);
@@ -959,8 +964,8 @@ __global__ __launch_bounds__(L * 8 > 512 ? 512 : (L * 8 < 256 ? 256 : L * 8)) vo
   __syncthreads();
   pcr_reduced(red, L + 1, P, tid);
   __syncthreads();
-  const A xf = R[(4 * (2 * p) + 3) * (L + 1)];
-  const A xl = R[(4 * (2 * p + 1) + 3) * (L + 1)];
+  const A xf = R[red_at(2 * p, 3, L + 1)];
+  const A xl = R[red_at(2 * p + 1, 3, L + 1)];
   if (fast)
     fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl, tail, kt);
   else
@@ -1120,8 +1125,8 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
   else if (p == 0 && lvalid)
     reduced_solve(R, 2 * P, TW + 1);
   __syncthreads();
-  const A xf = R[(4 * (2 * p) + 3) * (TW + 1)];
-  const A xl = R[(4 * (2 * p + 1) + 3) * (TW + 1)];
+  const A xf = R[red_at(2 * p, 3, TW + 1)];
+  const A xl = R[red_at(2 * p + 1, 3, TW + 1)];
   if (fast)
     fast_finish<A, M>(d, &tb.ga[t][0], &tb.al[t][0], xf, xl, tail, kt);
   else
@@ -1205,7 +1210,7 @@ __global__ __launch_bounds__(512) void sweep_yz_kernel(const SweepArgs<T>* __res
   const bool uniform = (a.mask == nullptr);
 
   A* red = reinterpret_cast<A*>(smem);  // reduced systems
-  A* tile = red + (size_t)(TW + 1) * 2 * P * 4;
+  A* tile = red + (size_t)red_size(P, TW + 1);
   uint8_t* mt = reinterpret_cast<uint8_t*>(tile + (size_t)nrow * TS);  // [nrow][TW]
 
   // Trilinear sources of the tile's lines form one contiguous range
@@ -1397,7 +1402,7 @@ LaunchShape plan_x(int nx, int ny, int nz, bool fp64, bool aos, bool uniform, in
   if (L < 8) return s;
   auto lds = [&](int Lc) {
     size_t off = 16;
-    off += (size_t)es * (Lc + 1) * 2 * P * 4;
+    off += (size_t)es * red_size(P, Lc + 1);
     off += (size_t)es * ((size_t)Lc * S + P * M + 2);
     if (aos) off += (size_t)es * Lc * S;
     off = (off + 15) & ~size_t(15);
@@ -1435,8 +1440,7 @@ LaunchShape plan_yz(int nx, int n_along, int n_other, bool fp64, int mt, int tw)
   P = (nint + M - 1) / M;
   const int nrow = std::max(n_along, P * M + 2);  // LDS tile rows
   auto lds = [&](int tw) {
-    return (size_t)es * (tw + 1) * 2 * P * 4 + (size_t)es * nrow * (tw + 1) + (size_t)nrow * tw +
-           16;
+    return (size_t)es * red_size(P, tw + 1) + (size_t)es * nrow * (tw + 1) + (size_t)nrow * tw + 16;
   };
   // Tile width (measured on 161^3 batches): FP32 arithmetic runs best with
   // 32 x per tile (one 128-byte line per node row) when that fits 512
