@@ -890,8 +890,12 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny,
                                    int M, int P, long long nlines, int face_loc, uint8_t* out) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nlines * P) return;
-  const int p = (int)(idx / nlines);
-  const long long l = idx - (long long)p * nlines;
+  // x lines: the P chunks of a line on consecutive lanes, so that a wave's
+  // word loads fall in a few cache lines of four rows (the output keeps its
+  // (chunk, line) order); y / z lines: consecutive lines on consecutive
+  // lanes, whose loads are contiguous along x
+  const int p = dir == 0 ? (int)(idx % P) : (int)(idx / nlines);
+  const long long l = dir == 0 ? idx / P : idx - (long long)p * nlines;
   long long base, stride;
   int n;
   if (dir == 0) {
@@ -943,7 +947,7 @@ __global__ void chunk_class_kernel(const uint8_t* mask, int nx, int nxp, int ny,
     for (int j = j0 + 1; j <= j1; ++j) same = same && (mask[base + (long long)j * stride] == v0);
     if (same) c = v0 ? 2 : 0;
   }
-  out[idx] = c;
+  out[(long long)p * nlines + l] = c;
 }
 
 hipError_t launch_chunk_classes(const uint8_t* mask, int nx, int nxp, int ny, int nz, int dir,
