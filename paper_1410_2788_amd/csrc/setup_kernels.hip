@@ -40,6 +40,31 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Visit the nodes (lo[0] + i, lo[1] + j, lo[2] + k) of a bx x by x bz box
+// with one block: lane t & 31 walks x in passes of 32, t >> 5 the (j, k)
+// rows in steps of blockDim / 32, carried by subtraction (no integer
+// division per node).
+template <typename F>
+__device__ __forceinline__ void box_walk(const int (&lo)[3], int bx, int by, int bz, F&& f) {
+  const int lane = (int)threadIdx.x & 31, r0 = (int)threadIdx.x >> 5;
+  const int rstep = (int)blockDim.x >> 5;
+  for (int i = lane; i < bx; i += 32) {
+    int j = r0, k = 0;
+    while (j >= by) {
+      j -= by;
+      ++k;
+    }
+    while (k < bz) {
+      f(lo[0] + i, lo[1] + j, lo[2] + k);
+      j += rstep;
+      while (j >= by) {
+        j -= by;
+        ++k;
+      }
+    }
+  }
+}
+
 // Solute region = union of atomic balls, a node on a sphere counts as
 // solute (Sec. 2.1: eps_m on/inside the surface).  One block per atom walks
 // the atom's bounding box of nodes.
@@ -60,12 +85,9 @@ __global__ __launch_bounds__(256) void mask_raster_kernel(SetupArgs a, uint8_t* 
     if (lo[d] > hi[d]) return;
   }
   const int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
-  const long long tot = (long long)bx * by * bz;
   const double R2 = R * R;
-  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
-    int i = lo[0] + (int)(e % bx);
-    int j = lo[1] + (int)((e / bx) % by);
-    int k = lo[2] + (int)(e / ((long long)bx * by));
+  box_walk(lo, bx, by, bz, [&](int i, int j, int k) {
+#pragma clang fp contract(off)
     double X = (double)i * a.h;
     X = a.ox + X;
     double Y = (double)j * a.h;
@@ -76,7 +98,7 @@ __global__ __launch_bounds__(256) void mask_raster_kernel(SetupArgs a, uint8_t* 
     double d2 = dx * dx + dy * dy;
     d2 = d2 + dz * dz;
     if (d2 <= R2) mask[((long long)k * a.ny + j) * a.nxp + i] = 1;
-  }
+  });
 }
 
 // Face rule by location (Sec. 3.1, text after Eq. (SpatialOperators)):
@@ -105,11 +127,10 @@ __global__ __launch_bounds__(256) void face_raster_kernel(SetupArgs a, int dir, 
     if (lo[d] > hi[d]) return;
   }
   const int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
-  const long long tot = (long long)bx * by * bz;
   const double R2 = R * R;
-  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int idx[3] = {lo[0] + (int)(e % bx), lo[1] + (int)((e / bx) % by),
-                        lo[2] + (int)(e / ((long long)bx * by))};
+  box_walk(lo, bx, by, bz, [&](int i, int j, int k) {
+#pragma clang fp contract(off)
+    const int idx[3] = {i, j, k};
     double p[3];
     for (int d = 0; d < 3; ++d) {
       double t = d == dir ? ((double)idx[d] + 0.5) * a.h : (double)idx[d] * a.h;
@@ -122,7 +143,7 @@ __global__ __launch_bounds__(256) void face_raster_kernel(SetupArgs a, int dir, 
       const long long g = ((long long)idx[2] * a.ny + idx[1]) * a.nxp + idx[0];
       fmask[g] = (uint8_t)(mask[g] | 2u);
     }
-  }
+  });
 }
 
 hipError_t launch_face_raster(const SetupArgs& a, int dir, const uint8_t* mask, uint8_t* fmask,
