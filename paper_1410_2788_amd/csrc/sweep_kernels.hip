@@ -1143,9 +1143,19 @@ __device__ __forceinline__ void yz_solve_lines(const SweepArgs<T>& a, A* tile, i
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < M; ++k)
-        if (VAR == kYzGeneral ? (mcol[(k + 1) * TW] & 1) == 0 : mcol[(k + 1) * TW] == 0)
-          d[k] = sinh_flow(d[k], ka, kb);
+      for (int k = 0; k < M; ++k) {
+        const bool solv =
+            VAR == kYzGeneral ? (mcol[(k + 1) * TW] & 1) == 0 : mcol[(k + 1) * TW] == 0;
+        if constexpr (sizeof(A) == 4) {
+          // FP32: every node's flow (ten instructions), kept on the solvent
+          // ones by a select: no branch per node, and the flag reads need
+          // not wait one by one
+          const A w = sinh_flow(d[k], ka, kb);
+          d[k] = solv ? w : d[k];
+        } else {
+          if (solv) d[k] = sinh_flow(d[k], ka, kb);
+        }
+      }
     }
   }
   // rows past the line end land in rows n-1.. of the tile, which are
