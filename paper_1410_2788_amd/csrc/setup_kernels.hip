@@ -732,66 +732,85 @@ __global__ __launch_bounds__(256) void boundary_rows_kernel(SetupArgs a, double 
   double acc_s[kBcK], acc_v[kBcK];
 #pragma unroll
   for (int t = 0; t < kBcK; ++t) acc_s[t] = acc_v[t] = 0.0;
-  for (int t0 = 0; t0 < na; t0 += 256) {
-    const int t = t0 + (int)threadIdx.x;
-    if (t < na) {
-      R4 at;
-      at.x = (R)(a.atoms[t] * xs);
-      at.y = (R)(a.atoms[na + t] * xs);
-      at.z = (R)(a.atoms[2 * na + t] * xs);
-      at.w = (R)a.atoms[3 * na + t];
-      sa[threadIdx.x] = at;
-    }
-    __syncthreads();
-    const int n = min(256, na - t0);
-    // FP32: partial sums over 32 atoms of the slice; FP64: one run
-    constexpr int kRun = std::is_same<R, float>::value ? 32 * kBcSlices : 256;
-    for (int j0 = sl; j0 < n; j0 += kRun) {
-      R ps[kBcK], pv[kBcK];
+  // Segments run z faces, y faces, then x faces (rows along y): the block's
+  // rows are all along x or all along y except in the block that holds the
+  // last y-face and first x-face segments.
+  const long long sb0 = (long long)blockIdx.x * kBcGroups, yb = sg.nz2 + sg.ny2;
+  const long long sall = sg.nz2 + sg.ny2 + sg.nx2;
+  const long long sb1 = (sb0 + kBcGroups < sall ? sb0 + kBcGroups : sall) - 1;
+  auto sum_atoms = [&](auto mode) {
+    constexpr int kMode = decltype(mode)::value;
+    for (int t0 = 0; t0 < na; t0 += 256) {
+      const int t = t0 + (int)threadIdx.x;
+      if (t < na) {
+        R4 at;
+        at.x = (R)(a.atoms[t] * xs);
+        at.y = (R)(a.atoms[na + t] * xs);
+        at.z = (R)(a.atoms[2 * na + t] * xs);
+        at.w = (R)a.atoms[3 * na + t];
+        sa[threadIdx.x] = at;
+      }
+      __syncthreads();
+      const int n = min(256, na - t0);
+      // FP32: partial sums over 32 atoms of the slice; FP64: one run
+      constexpr int kRun = std::is_same<R, float>::value ? 32 * kBcSlices : 256;
+      for (int j0 = sl; j0 < n; j0 += kRun) {
+        R ps[kBcK], pv[kBcK];
 #pragma unroll
-      for (int q = 0; q < kBcK; ++q) ps[q] = pv[q] = R(0);
-      const int je = min(j0 + kRun, n);
+        for (int q = 0; q < kBcK; ++q) ps[q] = pv[q] = R(0);
+        const int je = min(j0 + kRun, n);
 #pragma unroll 2
-      for (int jj = j0; jj < je; jj += kBcSlices) {
-        const R4 at = sa[jj];
-        const R d1 = F1 - (vy ? at.x : at.y), d3 = F2 - at.z;
-        const R b2 = d1 * d1 + d3 * d3;
-        const R av = vy ? at.y : at.x;
-        if constexpr (kChain) {
-          double dprev = 0.0, eprev = 0.0;
+        for (int jj = j0; jj < je; jj += kBcSlices) {
+          const R4 at = sa[jj];
+          // the row's direction: block-uniform (kMode 0: x, 1: y) but for the
+          // one block that holds rows of both kinds (kMode 2)
+          const bool rv_y = kMode == 2 ? vy : kMode == 1;
+          const R d1 = F1 - (rv_y ? at.x : at.y), d3 = F2 - at.z;
+          const R b2 = d1 * d1 + d3 * d3;
+          const R av = rv_y ? at.y : at.x;
+          if constexpr (kChain) {
+            double dprev = 0.0, eprev = 0.0;
 #pragma unroll
-          for (int q = 0; q < kBcK; ++q) {
-            const double dv = V[q] - av;
-            const double d2 = dv * dv + b2;
-            double ri = __builtin_amdgcn_rsq(d2);
-            ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
-            ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
-            const double t = at.w * ri;
-            if constexpr ((kMedia & 2) != 0) pv[q] += t;
-            if constexpr ((kMedia & 1) != 0) {
-              const double dist = d2 * ri;
-              const double e = q == 0 ? exp_neg(c * dist) : eprev * exp_small(c * (dist - dprev));
-              ps[q] = fma(t, e, ps[q]);
-              dprev = dist;
-              eprev = e;
+            for (int q = 0; q < kBcK; ++q) {
+              const double dv = V[q] - av;
+              const double d2 = dv * dv + b2;
+              double ri = __builtin_amdgcn_rsq(d2);
+              ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
+              ri = fma(0.5 * ri, fma(-d2 * ri, ri, 1.0), ri);
+              const double t = at.w * ri;
+              if constexpr ((kMedia & 2) != 0) pv[q] += t;
+              if constexpr ((kMedia & 1) != 0) {
+                const double dist = d2 * ri;
+                const double e =
+                    q == 0 ? exp_neg(c * dist) : eprev * exp_small(c * (dist - dprev));
+                ps[q] = fma(t, e, ps[q]);
+                dprev = dist;
+                eprev = e;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < kBcK; ++q) {
+              const R dv = V[q] - av;
+              BcPair<R>::template add<kMedia, kUnit>(dv * dv + b2, at.w, c, ps[q], pv[q]);
             }
           }
-        } else {
+        }
 #pragma unroll
-          for (int q = 0; q < kBcK; ++q) {
-            const R dv = V[q] - av;
-            BcPair<R>::template add<kMedia, kUnit>(dv * dv + b2, at.w, c, ps[q], pv[q]);
-          }
+        for (int q = 0; q < kBcK; ++q) {
+          acc_s[q] += (double)ps[q];
+          acc_v[q] += (double)pv[q];
         }
       }
-#pragma unroll
-      for (int q = 0; q < kBcK; ++q) {
-        acc_s[q] += (double)ps[q];
-        acc_v[q] += (double)pv[q];
-      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  };
+  if (sb0 >= yb)
+    sum_atoms(std::integral_constant<int, 1>{});
+  else if (sb1 < yb)
+    sum_atoms(std::integral_constant<int, 0>{});
+  else
+    sum_atoms(std::integral_constant<int, 2>{});
 #pragma unroll
   for (int t = 0; t < kBcK; ++t) {
     if constexpr ((kMedia & 1) != 0) rs[sl][g * kBcK + t] = acc_s[t];
